@@ -1,0 +1,233 @@
+"""FP64 CPU oracle for the VANSE Carreau-Yasuda lattice Boltzmann step.
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+benchmark's CPU-baseline leg use this package; the product path never imports
+it.  It shares no code with the GPU path: the C++ in ``lbm_oracle.cpp`` is a
+plain per-cell FP64 implementation written from the paper's method section,
+and ``bruteforce.py`` is a second, dense-array NumPy transcription used to
+cross-check it on tiny lattices.
+"""
+
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lbm_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+Q = 19
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle into ``oracle/liboracle.so`` (g++, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-o", _LIB + ".tmp", _SRC]
+        subprocess.check_call(cmd)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class _Case(ct.Structure):
+    _fields_ = [
+        ("nx", ct.c_int), ("ny", ct.c_int), ("nz", ct.c_int),
+        ("periodic", ct.c_int * 3),
+        ("solid", ct.c_void_p), ("phi", ct.c_void_p), ("sac", ct.c_void_p),
+        ("inlet", ct.c_int), ("outlet", ct.c_int),
+        ("inlet_shape", ct.c_void_p),
+        ("a0", ct.c_double), ("a1", ct.c_double), ("period", ct.c_double),
+        ("rho_out", ct.c_double),
+        ("nu0", ct.c_double), ("nu_inf", ct.c_double), ("lam", ct.c_double), ("n", ct.c_double), ("a", ct.c_double),
+        ("nu_d", ct.c_double), ("kc", ct.c_double), ("d", ct.c_double),
+        ("forchheimer", ct.c_int),
+        ("g", ct.c_double * 3),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = ct.CDLL(_LIB)
+        vp, i32, i64, dbl = ct.c_void_p, ct.c_int, ct.c_int64, ct.c_double
+        L.oracle_new.restype = vp
+        L.oracle_new.argtypes = [ct.POINTER(_Case)]
+        L.oracle_free.argtypes = [vp]
+        L.oracle_nfluid.restype = i64
+        L.oracle_nfluid.argtypes = [vp]
+        L.oracle_cells.argtypes = [vp, vp]
+        L.oracle_neighbours.argtypes = [vp, vp]
+        L.oracle_amplitude.restype = dbl
+        L.oracle_amplitude.argtypes = [vp, i32]
+        L.oracle_set_phi.argtypes = [vp, vp]
+        L.oracle_init.argtypes = [vp, vp, vp]
+        L.oracle_run.argtypes = [vp, vp, vp, i32, i32, vp]
+        L.oracle_moments.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp]
+        L.oracle_cell.argtypes = [ct.POINTER(_Case), vp, dbl, dbl, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.oracle_zouhe_inlet.argtypes = [vp, dbl, dbl, dbl]
+        L.oracle_zouhe_outlet.argtypes = [vp, dbl]
+        L.oracle_lattice.argtypes = [vp, vp]
+        L.oracle_objective.restype = dbl
+        L.oracle_objective.argtypes = [vp, i32, i32, i32]
+        L.oracle_grad_dual.argtypes = [vp, i32, i32, i32, vp, i32, vp, vp]
+        L.oracle_grad_reverse.argtypes = [vp, i32, i32, i32, i32, vp, vp]
+        L.oracle_threads.restype = i32
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ct.c_void_p) if a is not None else None
+
+
+def make_struct(case, keep: list, **override) -> _Case:
+    """Fill the C case description from a ``synth.Case``; ``keep`` holds the
+    arrays so they outlive the struct."""
+    solid = np.ascontiguousarray(case.solid.reshape(-1), dtype=np.uint8)
+    phi = np.ascontiguousarray(override.get("phi", case.phi).reshape(-1), dtype=np.float64)
+    sac = np.ascontiguousarray(case.sac.reshape(-1), dtype=np.uint8)
+    shape = None
+    if case.inlet_shape is not None:
+        shape = np.ascontiguousarray(case.inlet_shape.reshape(-1), dtype=np.float64)
+    keep.extend([solid, phi, sac, shape])
+    s = _Case()
+    s.nx, s.ny, s.nz = case.nx, case.ny, case.nz
+    for a in range(3):
+        s.periodic[a] = int(bool(case.periodic[a]))
+    s.solid, s.phi, s.sac = _ptr(solid), _ptr(phi), _ptr(sac)
+    s.inlet, s.outlet = int(case.inlet), int(case.outlet)
+    s.inlet_shape = _ptr(shape)
+    s.a0, s.a1, s.period = (float(v) for v in case.wave)
+    s.rho_out = float(case.rho_out)
+    rh = case.rheology
+    s.nu0, s.nu_inf, s.lam, s.n, s.a = rh["nu0"], rh["nu_inf"], rh["lam"], rh["n"], rh["a"]
+    po = case.porous
+    s.nu_d, s.kc, s.d = po["nu_d"], po["kc"], po["d"]
+    s.forchheimer = int(po.get("forchheimer", 0))
+    for a in range(3):
+        s.g[a] = float(po["g"][a])
+    return s
+
+
+class Oracle:
+    """One case on the CPU.  State arrays: ``f`` of shape (19, n_fluid) with the
+    pre-collision populations in canonical D3Q19 order (rest, +x, -x, +y, -y,
+    +z, -z, then the 12 edge directions in opposite pairs), ``omega`` of shape
+    (n_fluid,) with the previous step's relaxation rate."""
+
+    def __init__(self, case, phi=None):
+        self.case = case
+        self._keep = []
+        kw = {} if phi is None else dict(phi=phi)
+        self._struct = make_struct(case, self._keep, **kw)
+        self.h = lib().oracle_new(ct.byref(self._struct))
+        self.nf = int(lib().oracle_nfluid(self.h))
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().oracle_free(self.h)
+            self.h = None
+
+    def cells(self) -> np.ndarray:
+        out = np.empty(self.nf, np.int64)
+        lib().oracle_cells(self.h, _ptr(out))
+        return out
+
+    def neighbours(self) -> np.ndarray:
+        out = np.empty((Q, self.nf), np.int32)
+        lib().oracle_neighbours(self.h, _ptr(out))
+        return out
+
+    def amplitude(self, t: int) -> float:
+        return float(lib().oracle_amplitude(self.h, int(t)))
+
+    def set_phi(self, phi_box: np.ndarray):
+        p = np.ascontiguousarray(phi_box.reshape(-1), dtype=np.float64)
+        lib().oracle_set_phi(self.h, _ptr(p))
+
+    def init(self):
+        f = np.empty((Q, self.nf), np.float64)
+        om = np.empty(self.nf, np.float64)
+        lib().oracle_init(self.h, _ptr(f), _ptr(om))
+        return f, om
+
+    def run(self, f, omega, t0: int, nsteps: int, want_ke: bool = False):
+        """Advance ``nsteps`` steps from step index ``t0`` (in place)."""
+        assert f.dtype == np.float64 and f.flags.c_contiguous and f.shape == (Q, self.nf)
+        assert omega.dtype == np.float64 and omega.flags.c_contiguous
+        ke = np.empty(nsteps, np.float64) if want_ke else None
+        lib().oracle_run(self.h, _ptr(f), _ptr(omega), int(t0), int(nsteps), _ptr(ke))
+        return ke
+
+    def moments(self, f, omega, t: int):
+        nf = self.nf
+        rho = np.empty(nf)
+        u = np.empty((3, nf))
+        shear = np.empty(nf)
+        om = np.empty(nf)
+        sigma = np.empty((6, nf))
+        lib().oracle_moments(self.h, _ptr(np.ascontiguousarray(f)), _ptr(np.ascontiguousarray(omega)), int(t),
+                             _ptr(rho), _ptr(u), _ptr(shear), _ptr(om), _ptr(sigma))
+        return dict(rho=rho, u=u, shear=shear, omega=om, sigma=sigma)
+
+    def objective(self, T: int, tb: int, te: int) -> float:
+        return float(lib().oracle_objective(self.h, int(T), int(tb), int(te)))
+
+    def grad_dual(self, T: int, tb: int, te: int, box_cells):
+        cells = np.ascontiguousarray(np.asarray(box_cells, dtype=np.int64))
+        assert cells.size <= 16
+        J = np.zeros(1)
+        g = np.zeros(cells.size)
+        lib().oracle_grad_dual(self.h, int(T), int(tb), int(te), _ptr(cells), int(cells.size), _ptr(J), _ptr(g))
+        return float(J[0]), g
+
+    def grad_reverse(self, T: int, tb: int, te: int, ckpt: int):
+        J = np.zeros(1)
+        g = np.zeros(self.case.n_box)
+        lib().oracle_grad_reverse(self.h, int(T), int(tb), int(te), int(ckpt), _ptr(J), _ptr(g))
+        return float(J[0]), g.reshape(self.case.nz, self.case.ny, self.case.nx)
+
+
+def cell(case, f, omega_prev, phi, phit):
+    """Evaluate one cell's update (no open-face fill).  Returns a dict with rho,
+    u, F, feq, Pi (xx yy zz xy xz yz), shear, nu, omega and q."""
+    keep = []
+    s = make_struct(case, keep)
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    phit = np.ascontiguousarray(phit, dtype=np.float64)
+    out = {k: np.zeros(n) for k, n in dict(rho=1, u=3, F=3, feq=Q, Pi=6, shear=1, nu=1, omega=1, q=Q).items()}
+    lib().oracle_cell(ct.byref(s), _ptr(f), float(omega_prev), float(phi), _ptr(phit),
+                      *[_ptr(out[k]) for k in ("rho", "u", "F", "feq", "Pi", "shear", "nu", "omega", "q")])
+    for k in ("rho", "shear", "nu", "omega"):
+        out[k] = float(out[k][0])
+    return out
+
+
+def zouhe_inlet(f, ux, uy=0.0, uz=0.0):
+    f = np.array(f, dtype=np.float64)
+    lib().oracle_zouhe_inlet(_ptr(f), float(ux), float(uy), float(uz))
+    return f
+
+
+def zouhe_outlet(f, rho_out):
+    f = np.array(f, dtype=np.float64)
+    lib().oracle_zouhe_outlet(_ptr(f), float(rho_out))
+    return f
+
+
+def lattice():
+    c = np.zeros((Q, 3), np.int32)
+    w = np.zeros(Q, np.float64)
+    lib().oracle_lattice(_ptr(c), _ptr(w))
+    return c, w
+
+
+def threads() -> int:
+    return int(lib().oracle_threads())

@@ -1,0 +1,169 @@
+"""Dense-array NumPy transcription of one lattice Boltzmann step.
+
+TEST INFRASTRUCTURE ONLY.  A second FP64 implementation of the paper's method
+section, written over whole (nz, ny, nx) arrays with explicit shifts instead of
+the C++ oracle's compact cell list and neighbour table, so that indexing, wall
+and open-face mistakes in either show up as a mismatch on tiny lattices.
+
+State layout here: ``f`` of shape (19, nz, ny, nx), pre-collision populations,
+0 on solid voxels and on the unknown links of open-face cells.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+# D3Q19: rest, +-x, +-y, +-z, then xy, xz, yz edges, each followed by its opposite
+C = np.array([(0, 0, 0),
+              (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1),
+              (1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0),
+              (1, 0, 1), (-1, 0, -1), (1, 0, -1), (-1, 0, 1),
+              (0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1)], dtype=np.int64)
+W = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+OPP = np.array([int(np.flatnonzero((C == -C[i]).all(axis=1))[0]) for i in range(19)])
+CS2 = 1.0 / 3.0
+
+
+def _shift(a, c, periodic, fill):
+    """b[x] = a[x - c] along the three axes (array axes are z, y, x)."""
+    b = a
+    for ax_xyz, s in enumerate(c):
+        if s == 0:
+            continue
+        axis = 2 - ax_xyz
+        if periodic[ax_xyz]:
+            b = np.roll(b, s, axis=axis)
+        else:
+            b = np.roll(b, s, axis=axis)
+            idx = [slice(None)] * b.ndim
+            idx[axis] = slice(0, s) if s > 0 else slice(b.shape[axis] + s, None)
+            b = b.copy()
+            b[tuple(idx)] = fill
+    return b
+
+
+def _link_kinds(case):
+    """For each direction i and cell x: 0 if x + c_i is a fluid cell, 1 if it is
+    a wall (solid voxel or outside a wall face), 2 if it is outside an open face."""
+    fluid = case.solid == 0
+    nz, ny, nx = fluid.shape
+    kinds = np.zeros((19,) + fluid.shape, np.int8)
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    for i in range(19):
+        cx, cy, cz = C[i]
+        tx, ty, tz = xx + cx, yy + cy, zz + cz
+        out_wall = np.zeros_like(fluid)
+        out_open = np.zeros_like(fluid)
+        coords = []
+        for a, (t, n) in enumerate(((tx, nx), (ty, ny), (tz, nz))):
+            outside = (t < 0) | (t >= n)
+            if case.periodic[a]:
+                t = t % n
+            else:
+                if a == 0:
+                    opn = ((t < 0) & case.inlet) | ((t >= n) & case.outlet)
+                    out_open |= opn
+                    out_wall |= outside & ~opn
+                else:
+                    out_wall |= outside
+                t = np.clip(t, 0, n - 1)
+            coords.append(t)
+        tgt_fluid = fluid[coords[2], coords[1], coords[0]]
+        k = np.where(out_wall, 1, np.where(out_open, 2, np.where(tgt_fluid, 0, 1)))
+        kinds[i] = k
+    return kinds
+
+
+def step(case, f, omega_prev, t):
+    """One step on dense arrays; returns (f_next, omega_new, fields)."""
+    fluid = case.solid == 0
+    phi = np.where(fluid, case.phi.astype(np.float64), 1.0)
+    nz, ny, nx = fluid.shape
+    kinds = _link_kinds(case)
+    f = f.copy()
+    # open-face fill: Zou-He inflow on x = 0, constant-density outflow on x = nx-1
+    if case.inlet:
+        a0, a1, period = case.wave
+        amp = a0 * (1.0 + a1 * np.sin(2.0 * np.pi * t / period))
+        fx = f[:, :, :, 0]
+        ux = amp * case.inlet_shape.astype(np.float64)
+        zero = C[:, 0] == 0
+        neg = C[:, 0] == -1
+        rho = (fx[zero].sum(0) + 2 * fx[neg].sum(0)) / (1 - ux)
+        ny_ = 0.5 * (fx[zero] * C[zero, 1][:, None, None]).sum(0)
+        nz_ = 0.5 * (fx[zero] * C[zero, 2][:, None, None]).sum(0)
+        fx[1] = fx[2] + rho * ux / 3
+        fx[7] = fx[8] + rho * ux / 6 - ny_
+        fx[9] = fx[10] + rho * ux / 6 + ny_
+        fx[11] = fx[12] + rho * ux / 6 - nz_
+        fx[13] = fx[14] + rho * ux / 6 + nz_
+        m = fluid[:, :, 0]
+        f[:, :, :, 0] = np.where(m[None], fx, f[:, :, :, 0])
+    if case.outlet:
+        fx = f[:, :, :, nx - 1]
+        ro = case.rho_out
+        zero = C[:, 0] == 0
+        pos = C[:, 0] == 1
+        ux = (fx[zero].sum(0) + 2 * fx[pos].sum(0)) / ro - 1
+        ny_ = 0.5 * (fx[zero] * C[zero, 1][:, None, None]).sum(0)
+        nz_ = 0.5 * (fx[zero] * C[zero, 2][:, None, None]).sum(0)
+        fx[2] = fx[1] - ro * ux / 3
+        fx[8] = fx[7] - ro * ux / 6 + ny_
+        fx[10] = fx[9] - ro * ux / 6 - ny_
+        fx[12] = fx[11] - ro * ux / 6 + nz_
+        fx[14] = fx[13] - ro * ux / 6 - nz_
+        m = fluid[:, :, nx - 1]
+        f[:, :, :, nx - 1] = np.where(m[None], fx, f[:, :, :, nx - 1])
+
+    rp = case.rheology
+    po = case.porous
+    g = np.array(po["g"], dtype=np.float64)
+    sumf = f.sum(0)
+    sumf = np.where(fluid, sumf, 1.0)
+    rho = sumf / phi
+    mom = np.einsum("iz...,ia->az...", f, C.astype(np.float64))
+    v = mom / (phi * rho)[None] + g[:, None, None, None] / (2 * phi)[None]
+    invk = po["kc"] * (1 - phi) ** 2 / (po["d"] ** 2 * phi ** 3)
+    cf = 1.75 / np.sqrt(150 * phi ** 3) if po.get("forchheimer", 0) else np.zeros_like(phi)
+    c0 = 0.5 + phi * po["nu_d"] * invk / 4
+    c1 = phi ** 2 * cf * np.sqrt(invk) / 2
+    vn = np.sqrt((v ** 2).sum(0))
+    u = v / (c0 + np.sqrt(c0 ** 2 + c1 * vn))[None]
+    un = np.sqrt((u ** 2).sum(0))
+    F = rho[None] * (g[:, None, None, None] - (phi ** 2 * po["nu_d"] * invk)[None] * u
+                     - (phi ** 3 * cf * np.sqrt(invk) * un)[None] * u)
+    cu = np.einsum("ia,az...->iz...", C.astype(np.float64), u)
+    uu = (u ** 2).sum(0)
+    feq = W[:, None, None, None] * (phi * rho)[None] * (1 + cu / CS2 + cu ** 2 / (2 * CS2 ** 2) - uu[None] / (2 * CS2))
+    neq = f - feq
+    Pi = np.zeros((3, 3) + fluid.shape)
+    for a in range(3):
+        for b in range(3):
+            Pi[a, b] = (neq * (C[:, a] * C[:, b])[:, None, None, None]).sum(0) + 0.5 * (F[a] * u[b] + u[a] * F[b])
+    pn = np.sqrt((Pi ** 2).sum((0, 1)))
+    shear = omega_prev * pn / (CS2 * rho)
+    lam_s = rp["lam"] * shear
+    nu = rp["nu_inf"] + (rp["nu0"] - rp["nu_inf"]) * (1 + np.where(lam_s > 0, lam_s, 0.0) ** rp["a"]) ** ((rp["n"] - 1) / rp["a"])
+    omega = 2 * rho * CS2 / (2 * nu + rho * CS2)
+    phi_t = np.empty((19,) + fluid.shape)
+    for i in range(19):
+        # porosity at x + c_i, or phi(x) across walls and open faces
+        nb = _shift(phi, -C[i], case.periodic, 0.0)
+        phi_t[i] = np.where(kinds[i] == 0, nb, phi)
+    guo = np.zeros_like(f)
+    for i in range(19):
+        s = np.zeros(fluid.shape)
+        for a in range(3):
+            s += ((C[i, a] - u[a]) / CS2 + cu[i] * C[i, a] / CS2 ** 2) * F[a]
+        guo[i] = W[i] * (1 - omega / 2) * s
+    q = f + W[:, None, None, None] * rho[None] * (phi_t - phi[None]) + guo - omega[None] * neq
+    q = np.where(fluid[None], q, 0.0)
+    # push streaming with halfway bounce-back; open-face links are dropped
+    fn = np.zeros_like(f)
+    for i in range(19):
+        moved = _shift(np.where(kinds[i] == 0, q[i], 0.0), C[i], case.periodic, 0.0)
+        fn[i] += moved
+        fn[OPP[i]] += np.where(kinds[i] == 1, q[i], 0.0)
+    fn = np.where(fluid[None], fn, 0.0)
+    fields = dict(rho=rho, u=u, shear=shear, omega=omega, Pi=Pi)
+    return fn, np.where(fluid, omega, 0.0), fields

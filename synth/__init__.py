@@ -1,0 +1,20 @@
+"""Seeded synthetic inputs for the VANSE Carreau-Yasuda lattice Boltzmann step.
+
+This package only builds geometry, porosity and boundary-condition inputs
+(voxel masks, porosity fields, inlet shapes, parameter sets).  It holds none of
+the method's arithmetic and is imported by both the FP64 oracle's tests and the
+GPU path's tests and benchmark.
+"""
+
+from .cases import (  # noqa: F401
+    Case,
+    channel_case,
+    aneurysm_case,
+    coarsen2,
+    coil_cases,
+    periodic_box_case,
+    tiny_case,
+    fd_voxels,
+    CONFIGS,
+    make_config,
+)

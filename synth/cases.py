@@ -1,0 +1,345 @@
+"""Seeded synthetic cases: channel, tube-plus-sac aneurysm, coil, periodic box.
+
+Conventions (all arrays are C-ordered with shape (nz, ny, nx), so the flat box
+index is ``x + nx * (y + ny * z)``):
+
+* ``solid`` is ``uint8``: 1 for a solid voxel, 0 for fluid.
+* ``phi`` is ``float32`` porosity, in (0, 1] on fluid and 0 on solid voxels.
+* ``sac`` is a ``bool`` mask of the aneurysm sac (sphere minus tube).
+* ``inlet_shape`` has shape (nz, ny): the normalised Hagen-Poiseuille profile
+  ``1 - r^2/R^2`` of the inflow (the paper's inflow-profile paragraph in its
+  simulation-setup section) on inlet cells of the x = 0 face, 0 elsewhere.
+* the inlet amplitude is ``a0 * (1 + a1 * sin(2 pi t / period))`` with t the
+  step index; only the three numbers travel with the case.
+
+Geometry recipe of the aneurysm cases: cell centres at integer coordinates,
+tube axis at (y_c, z_c) = (ny/2 - 1/2, nz/2 - 1/2), tube fluid where
+(y - y_c)^2 + (z - z_c)^2 < R^2 (strict) for every x; sac = sphere of radius
+R_s centred at (nx/2 - 1/2, y_c + D, z_c) with D = R + round(0.7 R_s), minus the
+tube.  Sac porosity comes from a Gaussian random field: i.i.d. N(0, 1) noise from
+``numpy.random.default_rng(seed)`` over the sphere's bounding box, a Gaussian
+filter of standard deviation ``ell``, standardisation over the sac voxels to xi,
+then phi = 0.65 + 0.30 * Phi(xi)^beta with Phi the standard normal CDF and
+beta = 0.30/0.13 - 1, so that E[phi] = 0.78 on the range (0.65, 0.95).
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Dict, Optional, Tuple
+
+import numpy as np
+from scipy import ndimage, special
+
+# Lattice-unit Carreau-Yasuda parameters shared by every configuration.
+CY_DEFAULT = dict(nu0=0.1, nu_inf=0.01, lam=50.0, n=0.36, a=2.0)
+BETA_PHI = 0.30 / 0.13 - 1.0
+
+
+@dataclasses.dataclass
+class Case:
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    periodic: Tuple[bool, bool, bool]
+    solid: np.ndarray
+    phi: np.ndarray
+    sac: np.ndarray
+    inlet: bool = False
+    outlet: bool = False
+    inlet_shape: Optional[np.ndarray] = None
+    wave: Tuple[float, float, float] = (0.0, 0.0, 1.0)
+    rho_out: float = 1.0
+    rheology: Dict[str, float] = dataclasses.field(default_factory=lambda: dict(CY_DEFAULT))
+    # Darcy/Forchheimer drag parameters: nu_d (kinematic viscosity in the
+    # porous medium), kc (Kozeny-Carman constant), d (grain size), forchheimer
+    # (0 = off, 1 = Ergun constant), g (body force per unit mass).
+    porous: Dict[str, object] = dataclasses.field(
+        default_factory=lambda: dict(nu_d=0.1, kc=180.0, d=2.0, forchheimer=0, g=(0.0, 0.0, 0.0)))
+    steps: int = 0
+    extra: Dict[str, object] = dataclasses.field(default_factory=dict)
+
+    @property
+    def n_box(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    @property
+    def fluid(self) -> np.ndarray:
+        return self.solid == 0
+
+    @property
+    def n_fluid(self) -> int:
+        return int(np.count_nonzero(self.solid == 0))
+
+    def fluid_index(self) -> np.ndarray:
+        """Flat box indices of the fluid cells in ascending (z, y, x) order."""
+        return np.flatnonzero(self.solid.reshape(-1) == 0)
+
+    def with_(self, **kw) -> "Case":
+        return dataclasses.replace(self, **kw)
+
+
+def _zeros(nz, ny, nx, dtype):
+    return np.zeros((nz, ny, nx), dtype=dtype)
+
+
+def channel_case(n: int = 32, g: float = 1e-6, rheology=None, steps: int = 2000,
+                 ny: Optional[int] = None, nx: Optional[int] = None, nz: Optional[int] = None,
+                 phi: float = 1.0, nu_d: float = 0.1, kc: float = 180.0, d: float = 2.0,
+                 forchheimer: int = 0) -> Case:
+    """Plane channel: solid node layers at y = 0 and y = ny - 1, periodic x and z,
+    body force g along x, uniform porosity ``phi`` (1 by default).
+
+    With ny = 32 the fluid occupies y = 1 .. 30 and the halfway bounce-back walls
+    sit at y = 0.5 and y = 30.5 (channel width 30).
+    """
+    nx = n if nx is None else nx
+    ny = n if ny is None else ny
+    nz = n if nz is None else nz
+    solid = _zeros(nz, ny, nx, np.uint8)
+    solid[:, 0, :] = 1
+    solid[:, ny - 1, :] = 1
+    ph = np.where(solid == 0, np.float32(phi), np.float32(0.0)).astype(np.float32)
+    return Case(name=f"channel{nx}x{ny}x{nz}", nx=nx, ny=ny, nz=nz, periodic=(True, False, True),
+                solid=solid, phi=ph, sac=np.zeros_like(solid, dtype=bool),
+                rheology=dict(CY_DEFAULT if rheology is None else rheology),
+                porous=dict(nu_d=nu_d, kc=kc, d=d, forchheimer=forchheimer, g=(g, 0.0, 0.0)),
+                steps=steps)
+
+
+def _grf_phi(shape, ell: float, rng: np.random.Generator, region: np.ndarray) -> np.ndarray:
+    noise = rng.standard_normal(shape)
+    field = ndimage.gaussian_filter(noise, sigma=ell, mode="reflect", truncate=4.0)
+    vals = field[region]
+    xi = (field - vals.mean()) / vals.std()
+    u = special.ndtr(xi)
+    return (0.65 + 0.30 * np.power(u, BETA_PHI)).astype(np.float32)
+
+
+def aneurysm_case(nx: int, ny: int, nz: int, R: float, Rs: float, ell: float, seed: int,
+                  steps: int = 20000, name: str = "aneurysm", wave=(0.05, 0.5, 4000.0),
+                  kc: float = 180.0, d: float = 2.0, rheology=None) -> Case:
+    """Straight tube along x with a spherical sac off its side (module docstring
+    gives the recipe); GRF porosity in the sac; velocity inlet at x = 0, constant
+    density outlet at x = nx - 1, walls elsewhere."""
+    yc = ny / 2.0 - 0.5
+    zc = nz / 2.0 - 0.5
+    D = R + round(0.7 * Rs)
+    cx, cy, cz = nx / 2.0 - 0.5, yc + D, zc
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    tube = (y - yc) ** 2 + (z - zc) ** 2 < R * R
+    sphere = (x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2 < Rs * Rs
+    fluid = tube | sphere
+    sac = sphere & ~tube
+    solid = (~fluid).astype(np.uint8)
+
+    phi = np.where(fluid, np.float32(1.0), np.float32(0.0)).astype(np.float32)
+    # GRF over the sphere's bounding box (clipped to the domain).
+    lo = [max(0, int(math.floor(c - Rs))) for c in (cz, cy, cx)]
+    hi = [min(nn, int(math.ceil(c + Rs)) + 1) for c, nn in zip((cz, cy, cx), (nz, ny, nx))]
+    sl = tuple(slice(a, b) for a, b in zip(lo, hi))
+    rng = np.random.default_rng(seed)
+    sub = _grf_phi(tuple(b - a for a, b in zip(lo, hi)), ell, rng, sac[sl])
+    phi_sub = phi[sl]
+    phi_sub[sac[sl]] = sub[sac[sl]]
+    phi[sl] = phi_sub
+
+    r2 = (y[0, :, 0][None, :] - yc) ** 2 + (np.arange(nz)[:, None] - zc) ** 2
+    shape = np.where(r2 < R * R, 1.0 - r2 / (R * R), 0.0).astype(np.float32)
+    shape = np.where(solid[:, :, 0] == 0, shape, 0.0).astype(np.float32)
+    return Case(name=name, nx=nx, ny=ny, nz=nz, periodic=(False, False, False), solid=solid,
+                phi=phi, sac=sac, inlet=True, outlet=True, inlet_shape=shape, wave=tuple(wave),
+                rho_out=1.0, rheology=dict(CY_DEFAULT if rheology is None else rheology),
+                porous=dict(nu_d=0.1, kc=kc, d=d, forchheimer=0, g=(0.0, 0.0, 0.0)), steps=steps,
+                extra=dict(R=R, Rs=Rs, D=D, ell=ell, seed=seed))
+
+
+def coarsen2(case: Case, name: Optional[str] = None) -> Case:
+    """2x-coarsened copy of an aneurysm case: same recipe at half the radii, with
+    the sac porosity taken as the 2x2x2 block mean of the fine porosity."""
+    e = case.extra
+    nx, ny, nz = case.nx // 2, case.ny // 2, case.nz // 2
+    c = aneurysm_case(nx, ny, nz, R=e["R"] / 2.0, Rs=e["Rs"] / 2.0, ell=e["ell"] / 2.0, seed=e["seed"],
+                      steps=case.steps, name=name or case.name + "_coarse", wave=case.wave,
+                      kc=case.porous["kc"], d=case.porous["d"], rheology=case.rheology)
+    fine = case.phi.astype(np.float64)
+    fine_fluid = (case.solid == 0).astype(np.float64)
+    blk_sum = fine.reshape(nz, 2, ny, 2, nx, 2).sum(axis=(1, 3, 5))
+    blk_cnt = fine_fluid.reshape(nz, 2, ny, 2, nx, 2).sum(axis=(1, 3, 5))
+    mean = np.where(blk_cnt > 0, blk_sum / np.maximum(blk_cnt, 1), 1.0)
+    phi = c.phi.copy()
+    phi[c.sac] = np.clip(mean[c.sac], 0.05, 1.0).astype(np.float32)
+    return c.with_(phi=phi)
+
+
+def _coil_mask(case: Case, packing: float, wire_d: float, loop_r: Tuple[float, float], seed: int) -> np.ndarray:
+    """Voxelised coil: a seeded random walk of helical loops inside the sac.
+
+    Each loop picks a random axis through the current point, a radius drawn from
+    ``loop_r`` and sweeps one helical turn with a pitch of one wire diameter;
+    centreline samples (spacing 0.5 voxel) that would put the wire outside the
+    sphere are skipped.  Voxels within wire_d/2 of a sample become coil.  Loops
+    are added until the coil covers ``packing`` of the sac voxels.
+    """
+    e = case.extra
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = case.nx, case.ny, case.nz
+    yc, zc = ny / 2.0 - 0.5, nz / 2.0 - 0.5
+    centre = np.array([nx / 2.0 - 0.5, yc + e["D"], zc])
+    Rs = float(e["Rs"])
+    rw = wire_d / 2.0
+    coil = np.zeros((nz, ny, nx), dtype=bool)
+    n_sac = int(np.count_nonzero(case.sac))
+    target = packing * n_sac
+    pos = centre.copy()
+    offs = np.arange(-int(math.ceil(rw)), int(math.ceil(rw)) + 1)
+    oz, oy, ox = np.meshgrid(offs, offs, offs, indexing="ij")
+    ball = (ox ** 2 + oy ** 2 + oz ** 2) <= rw * rw + 1e-9
+    bx, by, bz = ox[ball], oy[ball], oz[ball]
+    count = 0
+    loops = 0
+    while count < target and loops < 100000:
+        loops += 1
+        axis = rng.standard_normal(3)
+        axis /= np.linalg.norm(axis)
+        tmp = np.array([1.0, 0.0, 0.0]) if abs(axis[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+        e1 = np.cross(axis, tmp)
+        e1 /= np.linalg.norm(e1)
+        e2 = np.cross(axis, e1)
+        r = rng.uniform(*loop_r)
+        # the loop passes through the current point: its centre sits r away along e1
+        lc = pos - r * e1
+        nsamp = max(8, int(2 * math.pi * r / 0.5))
+        last = pos
+        for k in range(nsamp + 1):
+            th = 2 * math.pi * k / nsamp
+            p = lc + r * (math.cos(th) * e1 + math.sin(th) * e2) + axis * wire_d * th / (2 * math.pi)
+            if np.linalg.norm(p - centre) > Rs - rw - 0.5:
+                continue
+            last = p
+            ix = np.rint(p[0] + bx).astype(int)
+            iy = np.rint(p[1] + by).astype(int)
+            iz = np.rint(p[2] + bz).astype(int)
+            ok = (ix >= 0) & (ix < nx) & (iy >= 0) & (iy < ny) & (iz >= 0) & (iz < nz)
+            coil[iz[ok], iy[ok], ix[ok]] = True
+        pos = last
+        if loops % 8 == 0:
+            count = int(np.count_nonzero(coil & case.sac))
+    coil &= case.sac
+    return coil
+
+
+def coil_cases(nx=384, ny=256, nz=256, R=24.0, Rs=40.0, packing=0.22, wire_d=3.0,
+               loop_r=(6.0, 12.0), seed=3, window=8, steps=20000):
+    """Fully resolved coil (coil voxels solid, porosity 1) and its volume-averaged
+    twin (vessel mask only, porosity 1 - box-filter of the coil indicator over a
+    window of ``window`` voxels with offsets -window/2 .. window/2 - 1)."""
+    base = aneurysm_case(nx, ny, nz, R, Rs, ell=4.0, seed=seed, steps=steps, name="coil_base")
+    coil = _coil_mask(base, packing, wire_d, loop_r, seed)
+    solid_res = (base.solid.astype(bool) | coil).astype(np.uint8)
+    phi_res = np.where(solid_res == 0, np.float32(1.0), np.float32(0.0)).astype(np.float32)
+    resolved = base.with_(name="coil_resolved", solid=solid_res, phi=phi_res,
+                          sac=base.sac & ~coil)
+    frac = ndimage.uniform_filter(coil.astype(np.float64), size=window, mode="constant", origin=0)
+    phi_avg = np.where(base.solid == 0, 1.0 - frac, 0.0)
+    phi_avg = np.where(base.solid == 0, np.clip(phi_avg, 0.05, 1.0), 0.0).astype(np.float32)
+    # inflow and outflow cells keep porosity 1
+    phi_avg[:, :, 0] = np.where(base.solid[:, :, 0] == 0, 1.0, 0.0)
+    phi_avg[:, :, -1] = np.where(base.solid[:, :, -1] == 0, 1.0, 0.0)
+    averaged = base.with_(name="coil_averaged", phi=phi_avg)
+    packing_got = float(np.count_nonzero(coil)) / max(1, int(np.count_nonzero(base.sac)))
+    resolved.extra = dict(base.extra, packing=packing_got)
+    averaged.extra = dict(base.extra, packing=packing_got)
+    return resolved, averaged
+
+
+def periodic_box_case(nx=512, ny=320, nz=320, ell=10.0, seed=5, g=1e-6, steps=2000) -> Case:
+    """All-fluid box, periodic in every axis, body force along x, GRF porosity in
+    every cell (the HBM-scale throughput case)."""
+    rng = np.random.default_rng(seed)
+    region = np.ones((nz, ny, nx), dtype=bool)
+    phi = _grf_phi((nz, ny, nx), ell, rng, region)
+    return Case(name=f"periodic{nx}x{ny}x{nz}", nx=nx, ny=ny, nz=nz, periodic=(True, True, True),
+                solid=np.zeros((nz, ny, nx), np.uint8), phi=phi,
+                sac=np.zeros((nz, ny, nx), bool),
+                porous=dict(nu_d=0.1, kc=180.0, d=2.0, forchheimer=0, g=(g, 0.0, 0.0)), steps=steps)
+
+
+def tiny_case(kind: str = "open", seed: int = 0, nx: int = 9, ny: int = 7, nz: int = 6) -> Case:
+    """Small lattices with every cell type, for brute-force and parity checks.
+
+    ``open``: non-periodic box, random solid voxels (about 15 %), velocity inlet
+    on x = 0 and density outlet on x = nx - 1 (porosity 1 there), random porosity
+    in [0.6, 1] elsewhere, fluid cells also touching the y/z faces (treated as
+    walls).  ``periodic``: periodic x and z, solid layers at y = 0 and ny - 1 plus
+    random solid voxels, random porosity, body force.
+    """
+    rng = np.random.default_rng(1000 + seed)
+    solid = (rng.random((nz, ny, nx)) < 0.15).astype(np.uint8)
+    phi = rng.uniform(0.6, 1.0, (nz, ny, nx)).astype(np.float32)
+    sac = rng.random((nz, ny, nx)) < 0.5
+    if kind == "open":
+        solid[:, :, 0] = 0
+        solid[:, :, nx - 1] = 0
+        solid[0, :, 0] = 1  # a few solid voxels on the open faces too
+        solid[:, 0, nx - 1] = 1
+        phi[:, :, 0] = 1.0
+        phi[:, :, nx - 1] = 1.0
+        shape = rng.uniform(0.2, 1.0, (nz, ny)).astype(np.float32)
+        shape = np.where(solid[:, :, 0] == 0, shape, 0.0).astype(np.float32)
+        case = Case(name=f"tiny_open{seed}", nx=nx, ny=ny, nz=nz, periodic=(False, False, False),
+                    solid=solid, phi=phi, sac=sac, inlet=True, outlet=True, inlet_shape=shape,
+                    wave=(0.03, 0.5, 40.0), rho_out=1.0,
+                    porous=dict(nu_d=0.1, kc=180.0, d=2.0, forchheimer=0, g=(0.0, 0.0, 0.0)))
+    elif kind == "periodic":
+        solid[:, 0, :] = 1
+        solid[:, ny - 1, :] = 1
+        case = Case(name=f"tiny_periodic{seed}", nx=nx, ny=ny, nz=nz, periodic=(True, False, True),
+                    solid=solid, phi=phi, sac=sac,
+                    porous=dict(nu_d=0.1, kc=180.0, d=2.0, forchheimer=0, g=(2e-5, -1e-5, 5e-6)))
+    else:
+        raise ValueError(kind)
+    case.phi = np.where(case.solid == 0, case.phi, 0.0).astype(np.float32)
+    case.sac = case.sac & (case.solid == 0)
+    return case
+
+
+def fd_voxels(case: Case, count: int = 16, seed: int = 16) -> np.ndarray:
+    """Flat box indices of ``count`` sac voxels drawn by default_rng(seed)."""
+    cand = np.flatnonzero(case.sac.reshape(-1))
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(cand, size=min(count, cand.size), replace=False))
+
+
+CONFIGS = {
+    "c0": dict(kind="channel"),
+    "c1": dict(kind="aneurysm", nx=192, ny=128, nz=128, R=12, Rs=20, ell=4, seed=1, steps=20000),
+    "c2": dict(kind="aneurysm", nx=512, ny=320, nz=320, R=32, Rs=56, ell=10, seed=2, steps=20000),
+    "c2c": dict(kind="coarse", of="c2"),
+    "c3": dict(kind="coil"),
+    "c4": dict(kind="aneurysm", nx=128, ny=96, nz=96, R=8, Rs=14, ell=4, seed=4, steps=4000),
+    "hbm": dict(kind="periodic"),
+}
+
+
+def make_config(key: str):
+    """Build one of the named workloads: c0 (32^3 channel), c1 (192x128x128
+    aneurysm), c2 (512x320x320 aneurysm), c2c (c2 coarsened 2x), c3 (coil pair:
+    returns (resolved, averaged)), c4 (128x96x96 aneurysm for gradients), hbm
+    (512x320x320 periodic all-fluid box)."""
+    cfg = CONFIGS[key]
+    kind = cfg["kind"]
+    if kind == "channel":
+        return channel_case(32)
+    if kind == "aneurysm":
+        return aneurysm_case(cfg["nx"], cfg["ny"], cfg["nz"], cfg["R"], cfg["Rs"], cfg["ell"], cfg["seed"],
+                             steps=cfg["steps"], name=key)
+    if kind == "coarse":
+        return coarsen2(make_config(cfg["of"]), name=key)
+    if kind == "coil":
+        return coil_cases()
+    if kind == "periodic":
+        return periodic_box_case()
+    raise KeyError(key)

@@ -1,0 +1,147 @@
+"""Pins of the FP64 oracle's full step: brute-force agreement on tiny lattices,
+the rest state, mass and momentum budgets, and translation invariance."""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import bruteforce as bf
+from synth import channel_case, tiny_case
+
+
+def _random_state(o, seed, amp=0.1):
+    rng = np.random.default_rng(seed)
+    f0, om0 = o.init()
+    known = f0 != 0
+    f = np.ascontiguousarray(f0 * (1 + amp * rng.standard_normal(f0.shape)) * known)
+    om = np.ascontiguousarray(om0 * (1 + 0.2 * rng.random(o.nf)))
+    return f, om
+
+
+def _dense(case, cells, f, om):
+    fd = np.zeros((19, case.n_box))
+    fd[:, cells] = f
+    od = np.zeros(case.n_box)
+    od[cells] = om
+    return fd.reshape(19, case.nz, case.ny, case.nx), od.reshape(case.nz, case.ny, case.nx)
+
+
+@pytest.mark.parametrize("kind", ["open", "periodic"])
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_matches_dense_bruteforce(kind, seed):
+    """Compact-list C++ oracle vs dense-array NumPy transcription: 1 and 10 steps
+    from a random non-equilibrium state with walls, open faces, periodic wrap and
+    heterogeneous porosity."""
+    case = tiny_case(kind, seed=seed)
+    o = oracle.Oracle(case)
+    cells = o.cells()
+    f, om = _random_state(o, seed)
+    fd, od = _dense(case, cells, f, om)
+    t0 = 7
+    f1, o1 = f.copy(), om.copy()
+    o.run(f1, o1, t0, 1)
+    fd1, od1, _ = bf.step(case, fd, od, t0)
+    assert np.abs(fd1.reshape(19, -1)[:, cells] - f1).max() < 1e-14
+    assert np.abs(od1.reshape(-1)[cells] - o1).max() < 1e-13
+    o.run(f1, o1, t0 + 1, 9)
+    for s in range(1, 10):
+        fd1, od1, _ = bf.step(case, fd1, od1, t0 + s)
+    assert np.abs(fd1.reshape(19, -1)[:, cells] - f1).max() < 1e-13
+    # moments of the state agree too
+    m = o.moments(f1, o1, t0 + 10)
+    _, _, fields = bf.step(case, fd1, od1, t0 + 10)
+    assert np.abs(fields["u"].reshape(3, -1)[:, cells] - m["u"]).max() < 1e-13
+    assert np.abs(fields["shear"].reshape(-1)[cells] - m["shear"]).max() < 1e-12
+
+
+@pytest.mark.parametrize("kind", ["open", "periodic"])
+def test_rest_state_is_stationary(kind):
+    """Fluid at rest with heterogeneous porosity, walls and (zero-velocity)
+    open faces stays at rest: the porosity-jump term, the porosity-shifted
+    equilibrium and bounce-back are mutually consistent."""
+    case = tiny_case(kind, seed=3)
+    case.porous = dict(case.porous, g=(0.0, 0.0, 0.0))
+    case.wave = (0.0, 0.0, 1.0)
+    o = oracle.Oracle(case)
+    f, om = o.init()
+    f1, o1 = f.copy(), om.copy()
+    o.run(f1, o1, 0, 25)
+    assert np.abs(f1 - f).max() < 1e-15
+    m = o.moments(f1, o1, 25)
+    assert np.abs(m["u"]).max() < 1e-15
+    assert np.abs(m["rho"] - 1).max() < 1e-14
+
+
+def test_mass_exact_for_uniform_porosity():
+    case = tiny_case("periodic", seed=4)
+    case.phi = np.where(case.solid == 0, 0.8, 0.0).astype(np.float32)
+    o = oracle.Oracle(case)
+    f, om = _random_state(o, 4)
+    m0 = f.sum()
+    o.run(f, om, 0, 300)
+    assert abs(f.sum() - m0) / m0 < 1e-13
+
+
+def test_mass_budget_heterogeneous_porosity():
+    """Closed domain: each step changes the mass by exactly
+    sum_x rho(x) sum_i w_i (phi~(x + c_i) - phi(x))."""
+    case = tiny_case("periodic", seed=5)
+    o = oracle.Oracle(case)
+    cells = o.cells()
+    kinds = bf._link_kinds(case)
+    phi = np.where(case.solid == 0, case.phi.astype(np.float64), 1.0)
+    jump = np.zeros(case.phi.shape)
+    for i in range(19):
+        nb = np.roll(phi, shift=tuple(-int(c) for c in bf.C[i][::-1]), axis=(0, 1, 2))
+        jump += bf.W[i] * np.where(kinds[i] == 0, nb - phi, 0.0)
+    jump = jump.reshape(-1)[cells]
+    f, om = _random_state(o, 5)
+    for t in range(20):
+        rho = o.moments(f, om, t)["rho"]
+        before = f.sum()
+        o.run(f, om, t, 1)
+        assert abs(f.sum() - before - (rho * jump).sum()) < 1e-15 * before
+
+
+def test_momentum_gain_equals_body_force():
+    """Periodic box without walls, porosity 1: total momentum grows by
+    g * sum_x rho(x) per step."""
+    case = channel_case(6, g=3e-5)
+    case.solid[:] = 0
+    case.periodic = (True, True, True)
+    case.phi = np.ones(case.phi.shape, np.float32)
+    case.porous = dict(case.porous, g=(3e-5, -1e-5, 2e-5))
+    o = oracle.Oracle(case)
+    f, om = _random_state(o, 6, amp=0.05)
+    c, _ = oracle.lattice()
+    g = np.array(case.porous["g"])
+    for t in range(10):
+        rho = o.moments(f, om, t)["rho"]
+        p0 = (f.T @ c).sum(0)
+        o.run(f, om, t, 1)
+        p1 = (f.T @ c).sum(0)
+        assert np.abs(p1 - p0 - g * rho.sum()).max() < 1e-15
+
+
+def test_channel_translation_invariance():
+    """The 32^3 channel from rest equals the 1x32x1 channel in every column."""
+    big = channel_case(32)
+    small = channel_case(32, nx=1, nz=1)
+    ob, os_ = oracle.Oracle(big), oracle.Oracle(small)
+    fb, omb = ob.init()
+    fs, oms = os_.init()
+    ob.run(fb, omb, 0, 60)
+    os_.run(fs, oms, 0, 60)
+    ub = ob.moments(fb, omb, 60)["u"][0].reshape(32, 30, 32)
+    us = os_.moments(fs, oms, 60)["u"][0]
+    assert np.abs(ub - us[None, :, None]).max() < 1e-17 + 1e-12 * np.abs(us).max()
+
+
+def test_deterministic():
+    case = tiny_case("open", seed=6)
+    o = oracle.Oracle(case)
+    f, om = _random_state(o, 6)
+    a, b = (f.copy(), om.copy()), (f.copy(), om.copy())
+    o.run(*a, 0, 15)
+    o.run(*b, 0, 15)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
