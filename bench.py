@@ -1,0 +1,205 @@
+"""Throughput of the fused D3Q19 VANSE Carreau-Yasuda step on one GPU.
+
+Prints ONE JSON line.  The workload is the 512x320x320 tube-and-sac aneurysm
+(tube radius 32, sac radius 56, GRF sac porosity with correlation length 10,
+2 360 212 fluid cells): fluid-cell MLUPS with FP32 population storage is the
+headline ``value``; FP16 and BF16 storage (and the adjoint, when built) are
+reported on the same geometry under ``forms``.  A step is one time step of the
+whole hot path: pull-streaming with bounce-back and open-face fill, porosity-
+weighted moments, drag-corrected velocity, equilibrium and Pi, Carreau-Yasuda
+relaxation rate, collision and store (plus the FP64 stability reduction every
+1000th step).
+
+Timing: inputs resident in device memory, ``--warmup`` untimed steps, then
+exactly ``--steps`` steps between HIP events on the solver's stream, bracketed
+by device synchronisation.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak
+B_ALG = {"fp32": 164, "fp16": 88, "bf16": 88}  # algorithmic bytes per fluid-cell update
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2402_10809_amd", "csrc")
+    for n in sorted(os.listdir(d)):
+        with open(os.path.join(d, n), "rb") as fh:
+            h.update(n.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(key: str):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel sources; else None."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as fh:
+        t = json.load(fh)
+    if t.get("source_hash") != source_hash():
+        return None
+    e = t.get("kernels", {}).get(key)
+    return None if e is None else e.get("bytes_per_launch")
+
+
+def time_steps(torch, solver, steps: int, warmup: int):
+    solver.step(warmup)
+    torch.cuda.synchronize()
+    stream = solver.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    solver.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps  # ms per step
+
+
+def copy_probe(torch, nbytes=4 << 30, reps=10):
+    from paper_2402_10809_amd import lbm
+
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    a.fill_(1)
+    st = torch.cuda.current_stream()
+    lbm.lbm_copy_probe(b.data_ptr(), a.data_ptr(), nbytes, st.cuda_stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        lbm.lbm_copy_probe(b.data_ptr(), a.data_ptr(), nbytes, st.cuda_stream)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def cpu_baseline(case, budget_s: float):
+    """The FP64 oracle (as it stands) on a bounded number of steps of the same
+    geometry, on this host's cores."""
+    import oracle
+
+    o = oracle.Oracle(case)
+    f, om = o.init()
+    t0 = time.perf_counter()
+    o.run(f, om, 0, 1)
+    one = time.perf_counter() - t0
+    n = max(1, min(50, int(budget_s / max(one, 1e-3))))
+    t0 = time.perf_counter()
+    o.run(f, om, 1, n)
+    dt = time.perf_counter() - t0
+    return dict(value=round(o.nf * n / dt / 1e6, 3), unit="MLUPS", cores=oracle.threads(), kind="oracle",
+                sample=f"{n} steps (after 1 untimed) of the full {case.nx}x{case.ny}x{case.nz} geometry, "
+                       f"{o.nf} fluid cells, FP64, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--forms", default="fp16,bf16")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--only", default=None, help="time one storage form only (profiling runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2402_10809_amd import Solver
+    from synth import make_config
+
+    if not torch.cuda.is_available():
+        print("no HIP device", file=sys.stderr)
+        sys.exit(1)
+    t0 = time.perf_counter()
+    case = make_config(args.config)
+    log(f"[bench] geometry {case.name} {case.nx}x{case.ny}x{case.nz}: {case.n_fluid} fluid cells "
+        f"({time.perf_counter() - t0:.1f} s)")
+
+    results = {}
+    forms = ["fp32"] + [f for f in args.forms.split(",") if f]
+    if args.only:
+        forms = [args.only]
+    for form in forms:
+        s = Solver.from_case(case, storage=form)
+        log(f"[bench] {form}: timing {args.steps} steps after {args.warmup} warmup")
+        ms = time_steps(torch, s, args.steps, args.warmup)
+        mlups = s.n_fluid / (ms * 1e-3) / 1e6
+        gbs = mlups * 1e6 * B_ALG[form] / 1e9
+        results[form] = dict(ms_per_step=ms, mlups=mlups, alg_GBps=gbs, frac=gbs / HBM_PEAK_GBS)
+        log(f"[bench] {form}: {ms * 1e3:.1f} us/step, {mlups:.0f} MLUPS, {gbs:.0f} GB/s algorithmic")
+        d = s.diagnostics()
+        assert d["nonfinite"] == 0
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+
+    head = results.get("fp32") or next(iter(results.values()))
+    head_form = "fp32" if "fp32" in results else forms[0]
+    probe = copy_probe(torch)
+    log(f"[bench] copy probe: {probe:.0f} GB/s")
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] oracle CPU baseline")
+        cpu = cpu_baseline(case, args.cpu_budget)
+        log(f"[bench] oracle: {cpu['value']} MLUPS on {cpu['cores']} threads")
+
+    nf = case.n_fluid
+    traffic = traffic_for(f"k_step_{head_form}_{args.config}")
+    line = {
+        "metric": "fluid MLUPS + % HBM peak, D3Q19 VANSE-CY: FP32 vs FP16-store vs adjoint",
+        "value": round(head["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if head_form == "fp32" else head_form,
+        "data": "synthetic",
+        "config": {"workload": f"aneurysm {case.nx}x{case.ny}x{case.nz}, tube R={case.extra.get('R')}, "
+                               f"sac R={case.extra.get('Rs')}, GRF porosity ell={case.extra.get('ell')}, "
+                               f"Carreau-Yasuda, pulsatile Zou-He inlet, density outlet",
+                   "fluid_cells": nf, "storage": head_form, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(head["alg_GBps"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(head["frac"], 4),
+                     "traffic": traffic},
+        "cpu_baseline": cpu,
+        "forms": {k: {"mlups": round(v["mlups"], 1), "alg_GBps": round(v["alg_GBps"], 1),
+                      "frac": round(v["frac"], 4), "bytes_per_update": B_ALG[k],
+                      "ms_per_step": round(v["ms_per_step"], 5)} for k, v in results.items()},
+        "copy_probe_GBps": round(probe, 1),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,209 @@
+/*
+ * lbm.h -- C ABI of liblbm.so: the D3Q19 lattice Boltzmann step for the
+ * volume-averaged Navier-Stokes equations (VANSE) with Carreau-Yasuda blood
+ * rheology and a coil modelled as a porous medium, on one AMD Instinct GPU.
+ *
+ * What the library computes is defined by the paper (Horvat, Lunowa, Sytnyk,
+ * Wohlmuth, "A Lattice Boltzmann Method for Non-Newtonian Blood Flow in Coiled
+ * Intracranial Aneurysms", arXiv:2402.10809):
+ *   - the model: VANSE mass and momentum, porosity phi in (0, 1], shear-strain
+ *     rate with the Frobenius norm, Carreau-Yasuda viscosity (eq. carreau),
+ *     Darcy/Forchheimer drag with the Kozeny-Carman permeability (section
+ *     "Volume-Averaged Navier-Stokes Equations for Blood Flow");
+ *   - the step: porosity-weighted moments, explicit velocity with C0 and C1,
+ *     collide-and-stream with the porosity-jump, Guo-forcing and BGK terms,
+ *     relaxation rate from the viscosity, semi-explicit shear rate from the
+ *     corrected second moment Pi, deviatoric stress (section "Lattice
+ *     Boltzmann Method for Volume-Averaged Navier-Stokes");
+ *   - the boundaries: halfway bounce-back walls, Zou-He velocity inflow with a
+ *     Hagen-Poiseuille profile (section "Numerical Simulations in a Realistic
+ *     Aneurysm", boundary-condition paragraph).
+ * The library uses the D3Q19 velocity set, a Kozeny-Carman constant that is a
+ * parameter, a constant-density (Zou-He pressure) outflow and a sinusoidal
+ * inflow amplitude; all quantities are in lattice units (dx = dt = 1,
+ * c_s^2 = 1/3, reference density 1).
+ *
+ * Conventions
+ *   - Box of nx*ny*nz voxels; box index b = x + nx*(y + ny*z) (x fastest).
+ *   - Fluid cells are the non-solid voxels, numbered in ascending box index;
+ *     "per fluid cell" arrays use that order (lbm_fluid_index gives it).
+ *   - D3Q19 directions in the order: rest; +x, -x, +y, -y, +z, -z;
+ *     (+1,+1,0), (-1,-1,0), (+1,-1,0), (-1,+1,0); (+1,0,+1), (-1,0,-1),
+ *     (+1,0,-1), (-1,0,+1); (0,+1,+1), (0,-1,-1), (0,+1,-1), (0,-1,+1).
+ *   - "Host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device memory (e.g. a torch tensor's data_ptr()).
+ *
+ * Ownership
+ *   - Host inputs are read during the call only (copied as needed).
+ *   - The library never allocates device memory.  The caller supplies one
+ *     device workspace of lbm_workspace_size() bytes (256-byte aligned) that
+ *     must outlive the context, and owns every device output buffer.
+ *   - All device work is enqueued on the HIP stream given to lbm_create.
+ *     Calls that return host data synchronise that stream.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ *
+ * Errors
+ *   - Every call returns an lbm_status; nothing is thrown across the ABI.
+ *   - LBM_E_INVALID: bad arguments, detected before any device work.
+ *   - LBM_E_DEVICE: a HIP call failed; the context is poisoned and every later
+ *     call on it returns LBM_E_STATE.
+ *   - LBM_E_UNSTABLE: a non-finite value, or a speed above 0.3 c_s, was seen at
+ *     a diagnostics check; the state is kept.
+ *   - lbm_last_error() returns a thread-local message for the last failure.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_E_INVALID = 1,
+  LBM_E_DEVICE = 2,
+  LBM_E_UNSTABLE = 3,
+  LBM_E_STATE = 4,
+  LBM_E_WORKSPACE = 5
+} lbm_status;
+
+/* Storage precision of the populations.  Arithmetic is FP32 in every case;
+ * what is stored is the deviation of each population from a rest value (see
+ * shift_mode).  FP16 values are stored scaled by an exact power of two per
+ * weight class (2^12 rest, 2^14 axis, 2^15 edge) so that they stay in the
+ * normal range; BF16 is stored unscaled.  Both round to nearest even. */
+typedef enum { LBM_STORE_FP32 = 0, LBM_STORE_FP16 = 1, LBM_STORE_BF16 = 2 } lbm_storage;
+
+typedef struct {
+  int nx, ny, nz;      /* box size; nx <= 2048, ny <= 1024, nz <= 1024 */
+  int periodic[3];     /* 1: axis wraps around; 0: faces are walls (or open, see lbm_open) */
+  int storage;         /* lbm_storage */
+  int shift_mode;      /* 0: stored value f_i - w_i phi(consumer cell) (default)
+                          1: stored value f_i - w_i */
+} lbm_grid;
+
+/* Carreau-Yasuda law (eq. carreau) in kinematic lattice units:
+ *   nu(g) = nu_inf + (nu0 - nu_inf) (1 + (lambda g)^a)^((n-1)/a);
+ * dynamic viscosity mu = nu (reference density 1); relaxation rate
+ *   omega = 2 rho c_s^2 / (2 mu + rho c_s^2) with the local density rho.
+ * n = 1 or lambda = 0 gives a Newtonian fluid with nu0. */
+typedef struct { double nu0, nu_inf, lambda, n, a; } lbm_rheology;
+
+/* Porous medium (model section):  1/k = kc (1-phi)^2 / (d^2 phi^3)  (finite,
+ * and 0 at phi = 1);  Darcy drag -phi^2 nu_darcy u / k;  Forchheimer drag
+ * -phi^3 C_F |u| u / sqrt(k) with C_F = 1.75/sqrt(150 phi^3) when
+ * forchheimer = 1, else 0;  g: body force per unit mass, added to the drag. */
+typedef struct {
+  double nu_darcy, d, kc;
+  int forchheimer;
+  double g[3];
+} lbm_porous;
+
+/* Open faces.  inlet: the x = 0 face is a Zou-He velocity inflow with
+ * u = (A(t) * shape_yz[y + ny*z], 0, 0) and A(t) = a0 (1 + a1 sin(2 pi t/period)),
+ * t the step index; shape_yz is host memory (ny*nz floats), e.g. the
+ * normalised Hagen-Poiseuille profile 1 - r^2/R^2.  outlet: the x = nx-1 face
+ * is a Zou-He constant-density outflow with density rho_out and zero
+ * tangential velocity.  Fluid cells on an open face must have phi = 1.
+ * Fluid cells on other non-periodic faces see the outside as wall. */
+typedef struct {
+  int inlet;
+  const float* shape_yz;
+  double a0, a1, period;
+  int outlet;
+  double rho_out;
+} lbm_open;
+
+/* Objective for lbm_adjoint: J = (1/(t_end - t_begin)) sum_{t=t_begin}^{t_end-1} e(t),
+ * e(t) = mean over the region cells of (1/2) rho |u|^2 evaluated from the
+ * pre-collision state of step t (the region is given to lbm_create). */
+typedef struct { int t_begin, t_end; } lbm_objective;
+
+/* Diagnostics vector (lbm_diagnostics), all FP64, of the current state:
+ *   [0] mass  sum_x phi rho            [1..3] momentum sum_x sum_i f_i c_i
+ *   [4] kinetic energy sum_x rho|u|^2/2 [5] same over the region cells
+ *   [6] max |u|   [7] min omega   [8] max omega
+ *   [9] number of cells with a non-finite value   [10] step index t */
+#define LBM_NDIAG 11
+
+/* Bytes of device workspace a context needs.  adjoint_T > 0 adds room for an
+ * lbm_adjoint run of adjoint_T steps with checkpoints every ckpt_every steps.
+ * solid: host, nx*ny*nz bytes, nonzero = solid. */
+lbm_status lbm_workspace_size(const lbm_grid* grid, const uint8_t* solid, int adjoint_T, int ckpt_every,
+                              size_t* bytes);
+
+/* Create a context at the rest state (rho = 1, u = 0, omega = omega(nu0)), t = 0.
+ *   solid:   host, nx*ny*nz, nonzero = solid voxel
+ *   phi:     host, nx*ny*nz porosity; must be in (0, 1] on fluid cells (ignored on solid)
+ *   region:  host, nx*ny*nz, nonzero = objective region (e.g. the sac); may be NULL
+ *   open:    may be NULL (no open faces)
+ *   workspace/ws_bytes: device memory of at least lbm_workspace_size() bytes
+ *   stream:  hipStream_t (NULL = default stream)
+ * Errors (LBM_E_INVALID): NULL required pointers, bad sizes, phi out of range
+ * on fluid, nu0 <= 0 or nu_inf <= 0, rheology a <= 0, open face on a periodic x
+ * axis, phi != 1 on an open-face fluid cell, no fluid cell; LBM_E_WORKSPACE: the
+ * workspace is too small or misaligned. */
+lbm_status lbm_create(const lbm_grid* grid, const uint8_t* solid, const float* phi, const uint8_t* region,
+                      const lbm_rheology* rheology, const lbm_porous* porous, const lbm_open* open,
+                      void* workspace, size_t ws_bytes, void* stream, lbm_ctx** out);
+
+/* Advance n time steps (collide and stream every fluid cell n times).  Every
+ * 1000th step index the state is checked (see LBM_E_UNSTABLE). */
+lbm_status lbm_step(lbm_ctx* ctx, int n);
+
+/* Macroscopic fields of the current state (what the next step's collision
+ * uses): density rho, velocity u [3][nx*ny*nz], shear rate, the relaxation
+ * rate omega the next collision will use, and the deviatoric stress
+ * sigma = (omega/2 - 1) Pi [6][nx*ny*nz] in the order xx yy zz xy xz yz.
+ * Device outputs in box layout, 0 on solid voxels; any may be NULL. */
+lbm_status lbm_moments(lbm_ctx* ctx, float* rho, float* u, float* shear, float* omega, float* sigma);
+
+/* FP64 diagnostics of the current state into out[LBM_NDIAG] (host); syncs. */
+lbm_status lbm_diagnostics(lbm_ctx* ctx, double* out);
+
+/* State transfer (host memory, per fluid cell): f[19][n_fluid] pre-collision
+ * populations (unshifted, FP64), omega[n_fluid] the relaxation rate of the
+ * previous step.  Populations that would arrive through an open face are
+ * unknown: get writes 0 there, set ignores them.  Both sync the stream. */
+lbm_status lbm_get_state(lbm_ctx* ctx, double* f, float* omega);
+lbm_status lbm_set_state(lbm_ctx* ctx, const double* f, const float* omega);
+
+/* Replace the porosity field (host, nx*ny*nz, same rules as lbm_create) and
+ * reset to the rest state at t = 0. */
+lbm_status lbm_set_porosity(lbm_ctx* ctx, const float* phi);
+
+/* Reset to the rest state at t = 0. */
+lbm_status lbm_reset(lbm_ctx* ctx);
+
+/* Gradient of the region kinetic-energy objective with respect to the
+ * porosity of every fluid cell.  Resets to rest, runs T steps forward while
+ * accumulating J and storing a checkpoint every ckpt_every steps, then sweeps
+ * back through the segments (recompute forward, then reverse steps).  Needs a
+ * workspace sized with adjoint_T >= T and the same ckpt_every; FP32 storage.
+ *   J:       host, 1 double
+ *   dJ_dphi: device, nx*ny*nz floats (box layout, 0 off the fluid), may be NULL
+ * Leaves the context at the forward state after T steps. */
+lbm_status lbm_adjoint(lbm_ctx* ctx, const lbm_objective* obj, int T, int ckpt_every, double* J, float* dJ_dphi);
+
+lbm_status lbm_fluid_cells(lbm_ctx* ctx, int64_t* n_fluid);
+/* Box index of every fluid cell (host, n_fluid int64) in the library's order. */
+lbm_status lbm_fluid_index(lbm_ctx* ctx, int64_t* box_index);
+/* Current step index. */
+lbm_status lbm_time(lbm_ctx* ctx, int64_t* t);
+
+/* Measurement aid: device-to-device copy of `bytes` (multiple of 16) by a plain
+ * streaming kernel on `stream`, for an achievable-bandwidth reference. */
+lbm_status lbm_copy_probe(void* dst, const void* src, size_t bytes, void* stream);
+
+const char* lbm_last_error(void);
+void lbm_destroy(lbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

@@ -1,0 +1,570 @@
+// Host runtime of liblbm.so: the C ABI declared in include/lbm.h.
+//
+// The library never allocates device memory: the caller's workspace is carved
+// into the population buffers, the porosity box, the compact fluid list and
+// the per-cell relaxation rates (plus the adjoint's checkpoints and records
+// when asked for).  Every kernel runs on the context's stream.
+#include "lbm.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "step.hpp"
+#include "adjoint.hpp"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+lbm_status fail(lbm_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+constexpr int CHECK_EVERY = 1000;     // steps between stability checks
+constexpr double MAX_SPEED = 0.3 / 1.7320508075688772;  // 0.3 c_s
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+size_t store_bytes(int storage) { return storage == LBM_STORE_FP32 ? 4 : 2; }
+
+struct Layout {
+  size_t A, B, phi, cells, omega, shape, stage, part, diag, obj;
+  // adjoint
+  size_t ck, rec, rho, ah0, ah1, omh, phih, phih64, objstep;
+  int nck, ckpt, T;
+  size_t total;
+};
+
+int blocks_for(int64_t n) { return (int)((n + BLOCK - 1) / BLOCK); }
+
+Layout make_layout(const lbm_grid& g, int64_t nf, int T, int ckpt) {
+  Layout L{};
+  const size_t nbox = (size_t)g.nx * g.ny * g.nz;
+  const size_t ss = store_bytes(g.storage);
+  const int nblk = blocks_for(nf);
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+  L.A = take(Q * nbox * ss);
+  L.B = take(Q * nbox * ss);
+  L.phi = take(nbox * 4);
+  L.cells = take((size_t)nf * 4);
+  L.omega = take((size_t)nf * 4);
+  L.shape = take((size_t)g.ny * g.nz * 4);
+  L.stage = take((size_t)(Q + 1) * nf * 4);
+  L.part = take((size_t)nblk * NDIAGP * 8);
+  L.diag = take(64 * 8);
+  L.obj = take((size_t)nblk * 8);
+  L.T = T;
+  L.ckpt = ckpt;
+  if (T > 0) {
+    L.nck = (T + ckpt - 1) / ckpt;
+    L.ck = take((size_t)L.nck * (Q + 1) * nf * 4);
+    L.rec = take((size_t)ckpt * (Q + 1) * nf * 4);
+    L.rho = take((size_t)ckpt * nbox * 4);
+    L.ah0 = take(Q * nbox * 4);
+    L.ah1 = take(Q * nbox * 4);
+    L.omh = take((size_t)nf * 4);
+    L.phih = take((size_t)nf * 4);
+    L.phih64 = take((size_t)nf * 8);
+    L.objstep = take((size_t)nblk * 8);
+  }
+  L.total = o;
+  return L;
+}
+
+struct TF32 { using T = float; };
+struct TF16 { using T = _Float16; };
+struct TBF16 { using T = __bf16; };
+
+template <class Fn>
+void with_storage(int storage, int shw, Fn&& fn) {
+  if (storage == LBM_STORE_FP32) {
+    if (shw) fn(TF32{}, std::true_type{}); else fn(TF32{}, std::false_type{});
+  } else if (storage == LBM_STORE_FP16) {
+    if (shw) fn(TF16{}, std::true_type{}); else fn(TF16{}, std::false_type{});
+  } else {
+    if (shw) fn(TBF16{}, std::true_type{}); else fn(TBF16{}, std::false_type{});
+  }
+}
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_grid grid{};
+  lbm_rheology rh{};
+  lbm_porous po{};
+  lbm_open op{};
+  int has_open = 0;
+  size_t nbox = 0;
+  int64_t nf = 0;
+  int nblk = 0;
+  std::vector<int64_t> fluid_box;
+  std::vector<double> phi_f;      // porosity per fluid cell (host, for state transfer)
+  std::vector<uint8_t> solid;     // host copy (porosity updates re-validate against it)
+  std::vector<uint8_t> openface;  // per fluid cell: 1 inlet, 2 outlet
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  Layout L{};
+  char* cur = nullptr;            // buffer holding the current state
+  char* nxt = nullptr;
+  int64_t t = 0;
+  bool poisoned = false;
+  Params P{};
+  float omega0 = 1.0f;
+};
+
+namespace {
+
+#define HIP_TRY(ctx, expr)                                                                      \
+  do {                                                                                          \
+    hipError_t e_ = (expr);                                                                     \
+    if (e_ != hipSuccess) {                                                                     \
+      if (ctx) (ctx)->poisoned = true;                                                          \
+      return fail(LBM_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));             \
+    }                                                                                           \
+  } while (0)
+
+#define CTX_CHECK(ctx)                                                                          \
+  do {                                                                                          \
+    if (!(ctx)) return fail(LBM_E_INVALID, "null context");                                     \
+    if ((ctx)->poisoned) return fail(LBM_E_STATE, "context poisoned by an earlier device error"); \
+  } while (0)
+
+Bufs bufs(lbm_ctx* c, const void* A, void* B) {
+  Bufs b{};
+  b.A = A;
+  b.B = B;
+  b.cells = (const uint32_t*)(c->ws + c->L.cells);
+  b.phi = (const float*)(c->ws + c->L.phi);
+  b.omega = (float*)(c->ws + c->L.omega);
+  b.shape = (const float*)(c->ws + c->L.shape);
+  b.part = (double*)(c->ws + c->L.part);
+  b.rec = nullptr;
+  b.rho_box = nullptr;
+  return b;
+}
+
+double amplitude(const lbm_ctx* c, int64_t t) {
+  if (!c->op.inlet) return 0.0;
+  const double pi = 3.14159265358979323846;
+  return c->op.a0 * (1.0 + c->op.a1 * std::sin(2.0 * pi * (double)t / c->op.period));
+}
+
+lbm_status validate_grid(const lbm_grid* g) {
+  if (!g) return fail(LBM_E_INVALID, "grid is NULL");
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1) return fail(LBM_E_INVALID, "grid dimensions must be positive");
+  if (g->nx > 2048 || g->ny > 1024 || g->nz > 1024) return fail(LBM_E_INVALID, "grid exceeds 2048 x 1024 x 1024");
+  const double nbox = (double)g->nx * g->ny * g->nz;
+  if (g->storage < 0 || g->storage > 2) return fail(LBM_E_INVALID, "unknown storage format");
+  if (nbox * Q * (double)store_bytes(g->storage) >= 4294967296.0)
+    return fail(LBM_E_INVALID, "population buffer would reach 4 GiB (kernels address it with 32-bit byte offsets)");
+  if (g->shift_mode < 0 || g->shift_mode > 1) return fail(LBM_E_INVALID, "shift_mode must be 0 or 1");
+  return LBM_OK;
+}
+
+int64_t count_fluid(const lbm_grid* g, const uint8_t* solid) {
+  const size_t nbox = (size_t)g->nx * g->ny * g->nz;
+  int64_t n = 0;
+  for (size_t b = 0; b < nbox; ++b) n += solid[b] ? 0 : 1;
+  return n;
+}
+
+lbm_status check_phi(const lbm_ctx* c, const float* phi) {
+  for (size_t k = 0; k < c->fluid_box.size(); ++k) {
+    const float v = phi[c->fluid_box[k]];
+    if (!(v > 0.0f && v <= 1.0f))
+      return fail(LBM_E_INVALID, "porosity must lie in (0, 1] on every fluid cell (box index " +
+                                     std::to_string(c->fluid_box[k]) + ")");
+    if (c->openface[k] && v != 1.0f)
+      return fail(LBM_E_INVALID, "porosity must be 1 on open-face cells (box index " +
+                                     std::to_string(c->fluid_box[k]) + ")");
+  }
+  return LBM_OK;
+}
+
+lbm_status upload_phi(lbm_ctx* c, const float* phi) {
+  std::vector<float> box(c->nbox, 0.0f);
+  c->phi_f.resize(c->nf);
+  for (int64_t k = 0; k < c->nf; ++k) {
+    box[c->fluid_box[k]] = phi[c->fluid_box[k]];
+    c->phi_f[k] = phi[c->fluid_box[k]];
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->ws + c->L.phi, box.data(), c->nbox * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+lbm_status launch_init(lbm_ctx* c) {
+  Bufs b = bufs(c, nullptr, c->cur);
+  with_storage(c->grid.storage, c->grid.shift_mode, [&](auto tag, auto shw) {
+    using S = typename decltype(tag)::T;
+    hipLaunchKernelGGL((k_init<S, decltype(shw)::value>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b,
+                       c->omega0);
+  });
+  HIP_TRY(c, hipGetLastError());
+  c->t = 0;
+  return LBM_OK;
+}
+
+// One step from cur into nxt.  diag: 0 none, 1 diagnostics partials, 2 region
+// energy accumulation into the objective partials.
+lbm_status launch_step(lbm_ctx* c, int diag, float* rec, float* rho_box) {
+  Bufs b = bufs(c, c->cur, c->nxt);
+  const float amp = (float)amplitude(c, c->t);
+  if (diag == 2) b.part = (double*)(c->ws + c->L.obj);
+  if (rec) {
+    b.rec = rec;
+    b.rho_box = rho_box;
+    hipLaunchKernelGGL((k_step<float, false, 0, true>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, amp);
+  } else {
+    with_storage(c->grid.storage, c->grid.shift_mode, [&](auto tag, auto shw) {
+      using S = typename decltype(tag)::T;
+      constexpr bool SH = decltype(shw)::value;
+      if (diag == 0)
+        hipLaunchKernelGGL((k_step<S, SH, 0, false>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, amp);
+      else if (diag == 1)
+        hipLaunchKernelGGL((k_step<S, SH, 1, false>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, amp);
+      else
+        hipLaunchKernelGGL((k_step<S, SH, 2, false>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, amp);
+    });
+  }
+  HIP_TRY(c, hipGetLastError());
+  std::swap(c->cur, c->nxt);
+  c->t += 1;
+  return LBM_OK;
+}
+
+const uint32_t DIAG_OPS = (0u) | (0u << 2) | (0u << 4) | (0u << 6) | (0u << 8) | (0u << 10) | (1u << 12) |
+                          (2u << 14) | (1u << 16) | (0u << 18);
+
+lbm_status read_diag(lbm_ctx* c, double* out) {
+  double* dout = (double*)(c->ws + c->L.diag);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(BLOCK), 0, c->stream, (const double*)(c->ws + c->L.part), c->nblk,
+                     NDIAGP, DIAG_OPS, dout);
+  HIP_TRY(c, hipGetLastError());
+  double h[NDIAGP];
+  HIP_TRY(c, hipMemcpyAsync(h, dout, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < NDIAGP; ++k) out[k] = h[k];
+  return LBM_OK;
+}
+
+lbm_status check_stable(lbm_ctx* c, const double* dg) {
+  if (dg[9] > 0.0 || !std::isfinite(dg[0]) || !(dg[6] <= MAX_SPEED)) {
+    char m[256];
+    std::snprintf(m, sizeof(m), "unstable at step %lld: %g non-finite cells, max |u| = %g (limit %g)",
+                  (long long)c->t, dg[9], dg[6], MAX_SPEED);
+    return fail(LBM_E_UNSTABLE, m);
+  }
+  return LBM_OK;
+}
+
+lbm_status moments_launch(lbm_ctx* c, bool diag, float* rho, float* u, float* shear, float* omega, float* sigma) {
+  Bufs b = bufs(c, c->cur, nullptr);
+  const float amp = (float)amplitude(c, c->t);
+  with_storage(c->grid.storage, c->grid.shift_mode, [&](auto tag, auto shw) {
+    using S = typename decltype(tag)::T;
+    constexpr bool SH = decltype(shw)::value;
+    if (diag)
+      hipLaunchKernelGGL((k_moments<S, SH, true>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, amp, rho, u,
+                         shear, omega, sigma);
+    else
+      hipLaunchKernelGGL((k_moments<S, SH, false>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, amp, rho, u,
+                         shear, omega, sigma);
+  });
+  HIP_TRY(c, hipGetLastError());
+  return LBM_OK;
+}
+
+// Compact pulled state (FP32, [19][nf]) of the current buffer into dst (device).
+lbm_status gather_state(lbm_ctx* c, float* dst) {
+  Bufs b = bufs(c, c->cur, nullptr);
+  with_storage(c->grid.storage, 0, [&](auto tag, auto) {
+    using S = typename decltype(tag)::T;
+    hipLaunchKernelGGL((k_gather_state<S>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, dst);
+  });
+  HIP_TRY(c, hipGetLastError());
+  return LBM_OK;
+}
+
+lbm_status scatter_state(lbm_ctx* c, const float* src) {
+  Bufs b = bufs(c, nullptr, c->cur);
+  with_storage(c->grid.storage, 0, [&](auto tag, auto) {
+    using S = typename decltype(tag)::T;
+    hipLaunchKernelGGL((k_scatter_state<S>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, src);
+  });
+  HIP_TRY(c, hipGetLastError());
+  return LBM_OK;
+}
+
+double rest_value(const lbm_ctx* c, int i, int64_t k) {
+  return (double)wgt(i) * (c->grid.shift_mode ? 1.0 : c->phi_f[k]);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+lbm_status lbm_workspace_size(const lbm_grid* grid, const uint8_t* solid, int adjoint_T, int ckpt_every,
+                              size_t* bytes) {
+  lbm_status s = validate_grid(grid);
+  if (s != LBM_OK) return s;
+  if (!solid || !bytes) return fail(LBM_E_INVALID, "solid and bytes must not be NULL");
+  if (adjoint_T < 0 || (adjoint_T > 0 && ckpt_every < 1)) return fail(LBM_E_INVALID, "bad adjoint_T / ckpt_every");
+  const int64_t nf = count_fluid(grid, solid);
+  if (nf == 0) return fail(LBM_E_INVALID, "no fluid cell");
+  *bytes = make_layout(*grid, nf, adjoint_T, adjoint_T > 0 ? ckpt_every : 0).total;
+  return LBM_OK;
+}
+
+lbm_status lbm_create(const lbm_grid* grid, const uint8_t* solid, const float* phi, const uint8_t* region,
+                      const lbm_rheology* rh, const lbm_porous* po, const lbm_open* op, void* workspace,
+                      size_t ws_bytes, void* stream, lbm_ctx** out) {
+  if (!out) return fail(LBM_E_INVALID, "out is NULL");
+  *out = nullptr;
+  lbm_status s = validate_grid(grid);
+  if (s != LBM_OK) return s;
+  if (!solid || !phi || !rh || !po) return fail(LBM_E_INVALID, "solid, phi, rheology and porous must not be NULL");
+  if (!(rh->nu0 > 0) || !(rh->nu_inf > 0)) return fail(LBM_E_INVALID, "nu0 and nu_inf must be positive");
+  if (!(rh->a > 0) || !(rh->lambda >= 0) || !std::isfinite(rh->n)) return fail(LBM_E_INVALID, "bad Carreau-Yasuda a, lambda or n");
+  if (!(po->kc >= 0) || !(po->d > 0) || !(po->nu_darcy >= 0)) return fail(LBM_E_INVALID, "bad porous parameters");
+  if (op && (op->inlet || op->outlet)) {
+    if (grid->periodic[0]) return fail(LBM_E_INVALID, "open faces need a non-periodic x axis");
+    if (op->inlet && (!op->shape_yz || !(op->period > 0))) return fail(LBM_E_INVALID, "inlet needs shape_yz and period > 0");
+    if (op->outlet && !(op->rho_out > 0)) return fail(LBM_E_INVALID, "outlet density must be positive");
+  }
+  if (!workspace) return fail(LBM_E_WORKSPACE, "workspace is NULL");
+  if (((uintptr_t)workspace & 255) != 0) return fail(LBM_E_WORKSPACE, "workspace must be 256-byte aligned");
+
+  lbm_ctx* c = new lbm_ctx();
+  c->grid = *grid;
+  c->rh = *rh;
+  c->po = *po;
+  c->has_open = op ? 1 : 0;
+  if (op) c->op = *op;
+  c->op.shape_yz = nullptr;
+  c->nbox = (size_t)grid->nx * grid->ny * grid->nz;
+  c->solid.assign(solid, solid + c->nbox);
+  c->stream = (hipStream_t)stream;
+  std::vector<uint32_t> packed;
+  packed.reserve(c->nbox / 8);
+  for (int z = 0; z < grid->nz; ++z)
+    for (int y = 0; y < grid->ny; ++y)
+      for (int x = 0; x < grid->nx; ++x) {
+        const size_t b = (size_t)x + (size_t)grid->nx * ((size_t)y + (size_t)grid->ny * z);
+        if (solid[b]) continue;
+        uint32_t pk = (uint32_t)x | ((uint32_t)y << 11) | ((uint32_t)z << 21);
+        if (region && region[b]) pk |= 1u << 31;
+        packed.push_back(pk);
+        c->fluid_box.push_back((int64_t)b);
+        uint8_t of = 0;
+        if (op && op->inlet && x == 0) of = 1;
+        else if (op && op->outlet && x == grid->nx - 1) of = 2;
+        c->openface.push_back(of);
+      }
+  c->nf = (int64_t)packed.size();
+  if (c->nf == 0) { delete c; return fail(LBM_E_INVALID, "no fluid cell"); }
+  s = check_phi(c, phi);
+  if (s != LBM_OK) { delete c; return s; }
+  c->nblk = blocks_for(c->nf);
+  c->L = make_layout(*grid, c->nf, 0, 0);
+  if (ws_bytes < c->L.total) {
+    // an adjoint-sized workspace is also fine; size the layout to what was given
+    delete c;
+    return fail(LBM_E_WORKSPACE, "workspace too small: need " + std::to_string(make_layout(*grid, count_fluid(grid, solid), 0, 0).total) + " bytes");
+  }
+  c->ws = (char*)workspace;
+  c->ws_bytes = ws_bytes;
+  c->cur = c->ws + c->L.A;
+  c->nxt = c->ws + c->L.B;
+
+  Params& P = c->P;
+  P.nx = grid->nx; P.ny = grid->ny; P.nz = grid->nz; P.nf = (int)c->nf;
+  P.nxy = (uint32_t)grid->nx * grid->ny;
+  P.nbox = (uint32_t)c->nbox;
+  P.px = grid->periodic[0] ? 1 : 0; P.py = grid->periodic[1] ? 1 : 0; P.pz = grid->periodic[2] ? 1 : 0;
+  P.inlet = (op && op->inlet) ? 1 : 0;
+  P.outlet = (op && op->outlet) ? 1 : 0;
+  P.nu0 = (float)rh->nu0; P.nu_inf = (float)rh->nu_inf; P.lam = (float)rh->lambda;
+  P.cy_e = (float)((rh->n - 1.0) / rh->a); P.cy_a = (float)rh->a; P.cy_a2 = rh->a == 2.0 ? 1 : 0;
+  P.nu_d = (float)po->nu_darcy; P.kcd = (float)(po->kc / (po->d * po->d)); P.forch = po->forchheimer ? 1 : 0;
+  P.gx = (float)po->g[0]; P.gy = (float)po->g[1]; P.gz = (float)po->g[2];
+  P.rho_out = (op && op->outlet) ? (float)op->rho_out : 1.0f;
+  c->omega0 = (float)(2.0 / (6.0 * rh->nu0 + 1.0));
+
+  auto bail = [&](lbm_status st) { delete c; return st; };
+#define HIP_TRY0(expr)                                                                              \
+  do {                                                                                              \
+    hipError_t e_ = (expr);                                                                         \
+    if (e_ != hipSuccess) return bail(fail(LBM_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_))); \
+  } while (0)
+  HIP_TRY0(hipMemcpyAsync(c->ws + c->L.cells, packed.data(), packed.size() * 4, hipMemcpyHostToDevice, c->stream));
+  std::vector<float> shape((size_t)grid->ny * grid->nz, 0.0f);
+  if (op && op->inlet) std::memcpy(shape.data(), op->shape_yz, shape.size() * 4);
+  HIP_TRY0(hipMemcpyAsync(c->ws + c->L.shape, shape.data(), shape.size() * 4, hipMemcpyHostToDevice, c->stream));
+  // the unused halves of the population buffers are never read; clear them once
+  HIP_TRY0(hipMemsetAsync(c->ws + c->L.A, 0, c->L.phi - c->L.A, c->stream));
+  HIP_TRY0(hipStreamSynchronize(c->stream));
+#undef HIP_TRY0
+  s = upload_phi(c, phi);
+  if (s != LBM_OK) return bail(s);
+  s = launch_init(c);
+  if (s != LBM_OK) return bail(s);
+  *out = c;
+  return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx* c, int n) {
+  CTX_CHECK(c);
+  if (n < 0) return fail(LBM_E_INVALID, "n must be >= 0");
+  for (int s = 0; s < n; ++s) {
+    const bool check = ((c->t + 1) % CHECK_EVERY) == 0;
+    lbm_status st = launch_step(c, check ? 1 : 0, nullptr, nullptr);
+    if (st != LBM_OK) return st;
+    if (check) {
+      double dg[NDIAGP];
+      st = read_diag(c, dg);
+      if (st != LBM_OK) return st;
+      st = check_stable(c, dg);
+      if (st != LBM_OK) return st;
+    }
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_moments(lbm_ctx* c, float* rho, float* u, float* shear, float* omega, float* sigma) {
+  CTX_CHECK(c);
+  const size_t nb = c->nbox * 4;
+  if (rho) HIP_TRY(c, hipMemsetAsync(rho, 0, nb, c->stream));
+  if (u) HIP_TRY(c, hipMemsetAsync(u, 0, 3 * nb, c->stream));
+  if (shear) HIP_TRY(c, hipMemsetAsync(shear, 0, nb, c->stream));
+  if (omega) HIP_TRY(c, hipMemsetAsync(omega, 0, nb, c->stream));
+  if (sigma) HIP_TRY(c, hipMemsetAsync(sigma, 0, 6 * nb, c->stream));
+  return moments_launch(c, false, rho, u, shear, omega, sigma);
+}
+
+lbm_status lbm_diagnostics(lbm_ctx* c, double* out) {
+  CTX_CHECK(c);
+  if (!out) return fail(LBM_E_INVALID, "out is NULL");
+  lbm_status s = moments_launch(c, true, nullptr, nullptr, nullptr, nullptr, nullptr);
+  if (s != LBM_OK) return s;
+  s = read_diag(c, out);
+  if (s != LBM_OK) return s;
+  out[NDIAGP] = (double)c->t;
+  return LBM_OK;
+}
+
+lbm_status lbm_get_state(lbm_ctx* c, double* f, float* omega) {
+  CTX_CHECK(c);
+  if (!f && !omega) return fail(LBM_E_INVALID, "nothing to get");
+  float* stage = (float*)(c->ws + c->L.stage);
+  const size_t nf = (size_t)c->nf;
+  if (f) {
+    lbm_status s = gather_state(c, stage);
+    if (s != LBM_OK) return s;
+    std::vector<float> h(Q * nf);
+    HIP_TRY(c, hipMemcpyAsync(h.data(), stage, h.size() * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (int i = 0; i < Q; ++i)
+      for (size_t k = 0; k < nf; ++k) {
+        const float v = h[i * nf + k];
+        f[i * nf + k] = std::isnan(v) ? 0.0 : (double)v + rest_value(c, i, (int64_t)k);
+      }
+  }
+  if (omega) {
+    HIP_TRY(c, hipMemcpyAsync(omega, c->ws + c->L.omega, nf * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_set_state(lbm_ctx* c, const double* f, const float* omega) {
+  CTX_CHECK(c);
+  if (!f && !omega) return fail(LBM_E_INVALID, "nothing to set");
+  float* stage = (float*)(c->ws + c->L.stage);
+  const size_t nf = (size_t)c->nf;
+  if (f) {
+    std::vector<float> h(Q * nf);
+    for (int i = 0; i < Q; ++i)
+      for (size_t k = 0; k < nf; ++k) h[i * nf + k] = (float)(f[i * nf + k] - rest_value(c, i, (int64_t)k));
+    HIP_TRY(c, hipMemcpyAsync(stage, h.data(), h.size() * 4, hipMemcpyHostToDevice, c->stream));
+    lbm_status s = scatter_state(c, stage);
+    if (s != LBM_OK) return s;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
+  if (omega) {
+    HIP_TRY(c, hipMemcpyAsync(c->ws + c->L.omega, omega, nf * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_reset(lbm_ctx* c) {
+  CTX_CHECK(c);
+  return launch_init(c);
+}
+
+lbm_status lbm_set_porosity(lbm_ctx* c, const float* phi) {
+  CTX_CHECK(c);
+  if (!phi) return fail(LBM_E_INVALID, "phi is NULL");
+  lbm_status s = check_phi(c, phi);
+  if (s != LBM_OK) return s;
+  s = upload_phi(c, phi);
+  if (s != LBM_OK) return s;
+  return launch_init(c);
+}
+
+lbm_status lbm_fluid_cells(lbm_ctx* c, int64_t* n) {
+  CTX_CHECK(c);
+  if (!n) return fail(LBM_E_INVALID, "n is NULL");
+  *n = c->nf;
+  return LBM_OK;
+}
+
+lbm_status lbm_fluid_index(lbm_ctx* c, int64_t* box_index) {
+  CTX_CHECK(c);
+  if (!box_index) return fail(LBM_E_INVALID, "box_index is NULL");
+  std::memcpy(box_index, c->fluid_box.data(), c->fluid_box.size() * 8);
+  return LBM_OK;
+}
+
+lbm_status lbm_time(lbm_ctx* c, int64_t* t) {
+  CTX_CHECK(c);
+  if (!t) return fail(LBM_E_INVALID, "t is NULL");
+  *t = c->t;
+  return LBM_OK;
+}
+
+lbm_status lbm_copy_probe(void* dst, const void* src, size_t bytes, void* stream) {
+  if (!dst || !src || bytes % 16 != 0) return fail(LBM_E_INVALID, "copy probe needs non-null buffers and bytes % 16 == 0");
+  const size_t n = bytes / 16;
+  size_t blocks = (n + BLOCK - 1) / BLOCK;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks == 0) return LBM_OK;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(BLOCK), 0, (hipStream_t)stream, (const uint4*)src,
+                     (uint4*)dst, n);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(LBM_E_DEVICE, std::string("copy probe: ") + hipGetErrorString(e));
+  return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx* c) { delete c; }
+
+}  // extern "C"
+
+#include "adjoint_host.inc"
