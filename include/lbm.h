@@ -72,12 +72,21 @@ typedef enum {
   LBM_E_WORKSPACE = 5
 } lbm_status;
 
-/* Storage precision of the populations.  Arithmetic is FP32 in every case;
- * what is stored is the deviation of each population from a rest value (see
- * shift_mode).  FP16 values are stored scaled by an exact power of two per
- * weight class (2^12 rest, 2^14 axis, 2^15 edge) so that they stay in the
- * normal range; BF16 is stored unscaled.  Both round to nearest even. */
+/* Storage precision of the populations.  What is stored is U times the
+ * deviation of each population from a rest value (see shift_mode), with
+ * U = 36 (so that U w_i is an exact integer for every direction) and an extra
+ * factor 2^10 for FP16 (keeps typical deviations in the normal range).  FP16
+ * and BF16 round to nearest even. */
 typedef enum { LBM_STORE_FP32 = 0, LBM_STORE_FP16 = 1, LBM_STORE_BF16 = 2 } lbm_storage;
+
+/* Arithmetic of the moments, velocity, force and collision (the Carreau-Yasuda
+ * transcendentals are FP32 in every mode).  FP32 rounding of the per-cell
+ * scalars (velocity, relaxation rate) is common to all 19 directions and acts
+ * as a small persistent momentum source; in slowly evolving flows it
+ * accumulates to ~1e-5 of the velocity, so FP32 storage computes in FP64 by
+ * default (same issue rate as unpacked FP32 on CDNA).  Reduced-precision
+ * storage is limited by its own rounding and computes in FP32. */
+typedef enum { LBM_ARITH_AUTO = 0, LBM_ARITH_FP32 = 1, LBM_ARITH_FP64 = 2 } lbm_arith;
 
 typedef struct {
   int nx, ny, nz;      /* box size; nx <= 2048, ny <= 1024, nz <= 1024 */
@@ -85,6 +94,8 @@ typedef struct {
   int storage;         /* lbm_storage */
   int shift_mode;      /* 0: stored value f_i - w_i phi(consumer cell) (default)
                           1: stored value f_i - w_i */
+  int arith;           /* lbm_arith: AUTO = FP64 with FP32 storage, FP32 with FP16/BF16
+                          storage; FP64 is only available with FP32 storage */
 } lbm_grid;
 
 /* Carreau-Yasuda law (eq. carreau) in kinematic lattice units:
@@ -184,10 +195,11 @@ lbm_status lbm_reset(lbm_ctx* ctx);
  * porosity of every fluid cell.  Resets to rest, runs T steps forward while
  * accumulating J and storing a checkpoint every ckpt_every steps, then sweeps
  * back through the segments (recompute forward, then reverse steps).  Needs a
- * workspace sized with adjoint_T >= T and the same ckpt_every; FP32 storage.
+ * workspace sized for (T, ckpt_every) or larger; FP32 storage, shift mode 0,
+ * no Forchheimer drag, a non-empty region, 0 <= t_begin < t_end <= T.
  *   J:       host, 1 double
  *   dJ_dphi: device, nx*ny*nz floats (box layout, 0 off the fluid), may be NULL
- * Leaves the context at the forward state after T steps. */
+ * Leaves the context at the rest state (t = 0); syncs the stream. */
 lbm_status lbm_adjoint(lbm_ctx* ctx, const lbm_objective* obj, int T, int ckpt_every, double* J, float* dJ_dphi);
 
 lbm_status lbm_fluid_cells(lbm_ctx* ctx, int64_t* n_fluid);

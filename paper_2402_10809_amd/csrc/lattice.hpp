@@ -17,20 +17,6 @@ constexpr int CZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1
 constexpr int OPP[Q] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
 
 __host__ __device__ constexpr float wgt(int i) { return i == 0 ? 1.0f / 3.0f : (i < 7 ? 1.0f / 18.0f : 1.0f / 36.0f); }
-// Rounding remainder of each weight: w_i = wgt(i) + wlo(i) to ~1e-16.  Applying
-// both parts keeps the collision's mass and momentum free of the systematic
-// 7e-9 relative bias that the FP32-rounded 1/18 would otherwise inject every
-// step.
-__host__ __device__ constexpr double wexact(int i) { return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
-__host__ __device__ constexpr float wlo(int i) { return (float)(wexact(i) - (double)wgt(i)); }
-// x * w_i + y with the two-part weight.
-__device__ __forceinline__ float wfma(int i, float x, float y) { return __builtin_fmaf(wgt(i), x, __builtin_fmaf(wlo(i), x, y)); }
-
-// FP16 storage keeps each deviation scaled by an exact power of two per weight
-// class so that small deviations stay out of the subnormal range.
-__host__ __device__ constexpr float f16_scale(int i) { return i == 0 ? 4096.0f : (i < 7 ? 16384.0f : 32768.0f); }
-__host__ __device__ constexpr float f16_unscale(int i) { return 1.0f / f16_scale(i); }
-
 // Element access through a 32-bit byte offset from a uniform base (the whole
 // population buffer is kept below 4 GiB), so loads and stores address as
 // scalar base + vector offset.
@@ -49,21 +35,13 @@ template <> struct Store<float> {
   static __device__ __forceinline__ void st(float* b, uint32_t e, float v, int) { sto(b, e, v); }
 };
 template <> struct Store<_Float16> {
-  static __device__ __forceinline__ float ld(const _Float16* b, uint32_t e, int i) { return (float)ldo(b, e) * f16_unscale(i); }
-  static __device__ __forceinline__ void st(_Float16* b, uint32_t e, float v, int i) { sto(b, e, (_Float16)(v * f16_scale(i))); }
+  static __device__ __forceinline__ float ld(const _Float16* b, uint32_t e, int) { return (float)ldo(b, e); }
+  static __device__ __forceinline__ void st(_Float16* b, uint32_t e, float v, int) { sto(b, e, (_Float16)v); }
 };
 template <> struct Store<__bf16> {
   static __device__ __forceinline__ float ld(const __bf16* b, uint32_t e, int) { return (float)ldo(b, e); }
   static __device__ __forceinline__ void st(__bf16* b, uint32_t e, float v, int) { sto(b, e, (__bf16)v); }
 };
-
-// Packed fluid-cell entry: x (11 bits) | y (10) << 11 | z (10) << 21 | region << 31.
-__device__ __forceinline__ void unpack(uint32_t pk, int& x, int& y, int& z, bool& reg) {
-  x = (int)(pk & 0x7FFu);
-  y = (int)((pk >> 11) & 0x3FFu);
-  z = (int)((pk >> 21) & 0x3FFu);
-  reg = (pk >> 31) != 0;
-}
 
 // Consecutive workgroups are dispatched round-robin over the 8 XCDs; remap so
 // that each XCD works on one contiguous slice of the fluid list (neighbouring

@@ -1,9 +1,10 @@
 // Host runtime of liblbm.so: the C ABI declared in include/lbm.h.
 //
 // The library never allocates device memory: the caller's workspace is carved
-// into the population buffers, the porosity box, the compact fluid list and
-// the per-cell relaxation rates (plus the adjoint's checkpoints and records
-// when asked for).  Every kernel runs on the context's stream.
+// into the population buffers, the porosity box, the compact fluid list with
+// its link words and the per-cell relaxation rates (plus the adjoint's
+// checkpoints and records when asked for).  Every kernel runs on the context's
+// stream.
 #include "lbm.h"
 
 #include <hip/hip_runtime.h>
@@ -29,17 +30,19 @@ lbm_status fail(lbm_status s, const std::string& msg) {
   return s;
 }
 
-constexpr int CHECK_EVERY = 1000;     // steps between stability checks
+constexpr int CHECK_EVERY = 1000;                       // steps between stability checks
 constexpr double MAX_SPEED = 0.3 / 1.7320508075688772;  // 0.3 c_s
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
-
 size_t store_bytes(int storage) { return storage == LBM_STORE_FP32 ? 4 : 2; }
+// Storage unit U: stored value = U (f - rest).  36 w_i is an integer; FP16 adds
+// 2^10 so that typical deviations sit in the normal range.
+double storage_unit(int storage) { return storage == LBM_STORE_FP16 ? 36.0 * 1024.0 : 36.0; }
 
 struct Layout {
-  size_t A, B, phi, cells, omega, shape, stage, part, diag, obj;
+  size_t A, B, phi, cells, links, omega, shape, stage, part, diag, obj;
   // adjoint
-  size_t ck, rec, rho, ah0, ah1, omh, phih, phih64, objstep;
+  size_t ck, rec, rho, ah0, ah1, omh, phih;
   int nck, ckpt, T;
   size_t total;
 };
@@ -57,6 +60,7 @@ Layout make_layout(const lbm_grid& g, int64_t nf, int T, int ckpt) {
   L.B = take(Q * nbox * ss);
   L.phi = take(nbox * 4);
   L.cells = take((size_t)nf * 4);
+  L.links = take((size_t)nf * 4);
   L.omega = take((size_t)nf * 4);
   L.shape = take((size_t)g.ny * g.nz * 4);
   L.stage = take((size_t)(Q + 1) * nf * 4);
@@ -68,14 +72,12 @@ Layout make_layout(const lbm_grid& g, int64_t nf, int T, int ckpt) {
   if (T > 0) {
     L.nck = (T + ckpt - 1) / ckpt;
     L.ck = take((size_t)L.nck * (Q + 1) * nf * 4);
-    L.rec = take((size_t)ckpt * (Q + 1) * nf * 4);
-    L.rho = take((size_t)ckpt * nbox * 4);
+    L.rec = take((size_t)(ckpt + 1) * (Q + 1) * nf * 4);
+    L.rho = take((size_t)(ckpt + 1) * nbox * 4);
     L.ah0 = take(Q * nbox * 4);
     L.ah1 = take(Q * nbox * 4);
     L.omh = take((size_t)nf * 4);
-    L.phih = take((size_t)nf * 4);
-    L.phih64 = take((size_t)nf * 8);
-    L.objstep = take((size_t)nblk * 8);
+    L.phih = take((size_t)nf * 8);
   }
   L.total = o;
   return L;
@@ -84,6 +86,8 @@ Layout make_layout(const lbm_grid& g, int64_t nf, int T, int ckpt) {
 struct TF32 { using T = float; };
 struct TF16 { using T = _Float16; };
 struct TBF16 { using T = __bf16; };
+struct RF32 { using T = float; };
+struct RF64 { using T = double; };
 
 template <class Fn>
 void with_storage(int storage, int shw, Fn&& fn) {
@@ -96,6 +100,29 @@ void with_storage(int storage, int shw, Fn&& fn) {
   }
 }
 
+// Storage type, shift mode and arithmetic type: FP64 arithmetic only with FP32 storage.
+template <class Fn>
+void with_config(int storage, int shw, bool f64, Fn&& fn) {
+  with_storage(storage, shw, [&](auto tag, auto sh) {
+    using S = typename decltype(tag)::T;
+    if constexpr (std::is_same<S, float>::value) {
+      if (f64) fn(tag, sh, RF64{}); else fn(tag, sh, RF32{});
+    } else {
+      fn(tag, sh, RF32{});
+    }
+  });
+}
+
+// Granlund-Montgomery constants for unsigned division by d (d >= 1).
+void div_magic(uint32_t d, uint32_t& m, uint32_t& s1, uint32_t& s2) {
+  uint32_t l = 0;
+  while (((uint64_t)1 << l) < d) ++l;
+  const uint64_t mm = (((uint64_t)1 << 32) * (((uint64_t)1 << l) - d)) / d + 1;
+  m = (uint32_t)mm;
+  s1 = l < 1 ? l : 1;
+  s2 = l > 1 ? l - 1 : 0;
+}
+
 }  // namespace
 
 struct lbm_ctx {
@@ -103,13 +130,15 @@ struct lbm_ctx {
   lbm_rheology rh{};
   lbm_porous po{};
   lbm_open op{};
-  int has_open = 0;
   size_t nbox = 0;
   int64_t nf = 0;
   int nblk = 0;
+  int64_t nreg = 0;
+  double U = 36.0;
   std::vector<int64_t> fluid_box;
   std::vector<double> phi_f;      // porosity per fluid cell (host, for state transfer)
-  std::vector<uint8_t> solid;     // host copy (porosity updates re-validate against it)
+  std::vector<uint8_t> solid;     // host copy of the mask
+  std::vector<uint8_t> region_f;  // per fluid cell
   std::vector<uint8_t> openface;  // per fluid cell: 1 inlet, 2 outlet
   hipStream_t stream = nullptr;
   char* ws = nullptr;
@@ -121,6 +150,7 @@ struct lbm_ctx {
   bool poisoned = false;
   Params P{};
   float omega0 = 1.0f;
+  bool f64 = true;                // FP64 arithmetic for the collision
 };
 
 namespace {
@@ -145,6 +175,7 @@ Bufs bufs(lbm_ctx* c, const void* A, void* B) {
   b.A = A;
   b.B = B;
   b.cells = (const uint32_t*)(c->ws + c->L.cells);
+  b.links = (const uint32_t*)(c->ws + c->L.links);
   b.phi = (const float*)(c->ws + c->L.phi);
   b.omega = (float*)(c->ws + c->L.omega);
   b.shape = (const float*)(c->ws + c->L.shape);
@@ -169,6 +200,9 @@ lbm_status validate_grid(const lbm_grid* g) {
   if (nbox * Q * (double)store_bytes(g->storage) >= 4294967296.0)
     return fail(LBM_E_INVALID, "population buffer would reach 4 GiB (kernels address it with 32-bit byte offsets)");
   if (g->shift_mode < 0 || g->shift_mode > 1) return fail(LBM_E_INVALID, "shift_mode must be 0 or 1");
+  if (g->arith < 0 || g->arith > 2) return fail(LBM_E_INVALID, "unknown arithmetic mode");
+  if (g->arith == LBM_ARITH_FP64 && g->storage != LBM_STORE_FP32)
+    return fail(LBM_E_INVALID, "FP64 arithmetic is only available with FP32 storage");
   return LBM_OK;
 }
 
@@ -192,6 +226,53 @@ lbm_status check_phi(const lbm_ctx* c, const float* phi) {
   return LBM_OK;
 }
 
+// Link word of every fluid cell (see step.hpp): bounce-back mask of the pulls,
+// uniform-neighbour-porosity flag, open-face role, region, periodic faces.
+void build_links(const lbm_ctx* c, const std::vector<float>& phib, std::vector<uint32_t>& links) {
+  const int nx = c->grid.nx, ny = c->grid.ny, nz = c->grid.nz;
+  const int per[3] = {c->grid.periodic[0] != 0, c->grid.periodic[1] != 0, c->grid.periodic[2] != 0};
+  const int dims[3] = {nx, ny, nz};
+  links.assign(c->nf, 0u);
+  for (int64_t k = 0; k < c->nf; ++k) {
+    const int64_t b = c->fluid_box[k];
+    const int X[3] = {(int)(b % nx), (int)((b / nx) % ny), (int)(b / ((int64_t)nx * ny))};
+    uint32_t lk = 0;
+    bool uni = true;
+    const float ph = phib[b];
+    for (int i = 1; i < Q; ++i) {
+      const int cv[3] = {CX[i], CY[i], CZ[i]};
+      for (int sgn = -1; sgn <= 1; sgn += 2) {  // -1: pull source x - c_i; +1: neighbour x + c_i
+        int s[3];
+        bool out = false;
+        for (int a = 0; a < 3; ++a) {
+          s[a] = X[a] + sgn * cv[a];
+          if (s[a] < 0 || s[a] >= dims[a]) {
+            if (per[a]) s[a] = (s[a] + dims[a]) % dims[a];
+            else out = true;
+          }
+        }
+        const int64_t sb = out ? -1 : (int64_t)s[0] + (int64_t)nx * ((int64_t)s[1] + (int64_t)ny * s[2]);
+        const bool wall = out || c->solid[sb];
+        if (sgn < 0) { if (wall) lk |= 1u << i; }
+        else if (!wall && phib[sb] != ph) uni = false;
+      }
+    }
+    if (uni) lk |= LK_UNI;
+    if (c->openface[k] == 1) lk |= LK_IN;
+    if (c->openface[k] == 2) lk |= LK_OUT;
+    if (c->region_f[k]) lk |= LK_REG;
+    uint32_t faces = 0;
+    for (int a = 0; a < 3; ++a) {
+      if (!per[a]) continue;
+      if (X[a] == 0) faces |= 1u << (2 * a);
+      if (X[a] == dims[a] - 1) faces |= 1u << (2 * a + 1);
+    }
+    if (faces) lk |= LK_WRAP | (faces << LK_FACE);
+    links[k] = lk;
+  }
+}
+
+// Upload the porosity box and the link words (which depend on it).
 lbm_status upload_phi(lbm_ctx* c, const float* phi) {
   std::vector<float> box(c->nbox, 0.0f);
   c->phi_f.resize(c->nf);
@@ -199,7 +280,10 @@ lbm_status upload_phi(lbm_ctx* c, const float* phi) {
     box[c->fluid_box[k]] = phi[c->fluid_box[k]];
     c->phi_f[k] = phi[c->fluid_box[k]];
   }
+  std::vector<uint32_t> links;
+  build_links(c, box, links);
   HIP_TRY(c, hipMemcpyAsync(c->ws + c->L.phi, box.data(), c->nbox * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->ws + c->L.links, links.data(), links.size() * 4, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return LBM_OK;
 }
@@ -217,7 +301,8 @@ lbm_status launch_init(lbm_ctx* c) {
 }
 
 // One step from cur into nxt.  diag: 0 none, 1 diagnostics partials, 2 region
-// energy accumulation into the objective partials.
+// energy accumulation into the objective partials.  rec: record the step for
+// the adjoint (FP32, shift mode 0 only).
 lbm_status launch_step(lbm_ctx* c, int diag, float* rec, float* rho_box) {
   Bufs b = bufs(c, c->cur, c->nxt);
   const float amp = (float)amplitude(c, c->t);
@@ -225,38 +310,46 @@ lbm_status launch_step(lbm_ctx* c, int diag, float* rec, float* rho_box) {
   if (rec) {
     b.rec = rec;
     b.rho_box = rho_box;
-    hipLaunchKernelGGL((k_step<float, false, 0, true>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, amp);
-  } else {
-    with_storage(c->grid.storage, c->grid.shift_mode, [&](auto tag, auto shw) {
-      using S = typename decltype(tag)::T;
-      constexpr bool SH = decltype(shw)::value;
-      if (diag == 0)
-        hipLaunchKernelGGL((k_step<S, SH, 0, false>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, amp);
-      else if (diag == 1)
-        hipLaunchKernelGGL((k_step<S, SH, 1, false>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, amp);
-      else
-        hipLaunchKernelGGL((k_step<S, SH, 2, false>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, amp);
-    });
   }
+  with_config(c->grid.storage, c->grid.shift_mode, c->f64, [&](auto tag, auto shw, auto rt) {
+    using S = typename decltype(tag)::T;
+    using R = typename decltype(rt)::T;
+    constexpr bool SH = decltype(shw)::value;
+    auto go = [&](auto per) {
+      constexpr bool PER = decltype(per)::value;
+      if (rec) {
+        if constexpr (std::is_same<S, float>::value && !SH)
+          hipLaunchKernelGGL((k_step<S, false, PER, 0, true, R>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b,
+                             amp);
+      } else if (diag == 0) {
+        hipLaunchKernelGGL((k_step<S, SH, PER, 0, false, R>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, amp);
+      } else if (diag == 1) {
+        hipLaunchKernelGGL((k_step<S, SH, PER, 1, false, R>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, amp);
+      } else {
+        hipLaunchKernelGGL((k_step<S, SH, PER, 2, false, R>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, amp);
+      }
+    };
+    if (c->P.anyper) go(std::true_type{}); else go(std::false_type{});
+  });
   HIP_TRY(c, hipGetLastError());
   std::swap(c->cur, c->nxt);
   c->t += 1;
   return LBM_OK;
 }
 
-const uint32_t DIAG_OPS = (0u) | (0u << 2) | (0u << 4) | (0u << 6) | (0u << 8) | (0u << 10) | (1u << 12) |
-                          (2u << 14) | (1u << 16) | (0u << 18);
+const uint32_t DIAG_OPS = (1u << 12) | (2u << 14) | (1u << 16);  // max |u|, min omega, max omega; rest sums
+
+lbm_status finalize(lbm_ctx* c, const double* part, int n, uint32_t ops, double* host_out) {
+  double* dout = (double*)(c->ws + c->L.diag);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(BLOCK), 0, c->stream, part, c->nblk, n, ops, dout);
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipMemcpyAsync(host_out, dout, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
 
 lbm_status read_diag(lbm_ctx* c, double* out) {
-  double* dout = (double*)(c->ws + c->L.diag);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(BLOCK), 0, c->stream, (const double*)(c->ws + c->L.part), c->nblk,
-                     NDIAGP, DIAG_OPS, dout);
-  HIP_TRY(c, hipGetLastError());
-  double h[NDIAGP];
-  HIP_TRY(c, hipMemcpyAsync(h, dout, sizeof(h), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  for (int k = 0; k < NDIAGP; ++k) out[k] = h[k];
-  return LBM_OK;
+  return finalize(c, (const double*)(c->ws + c->L.part), NDIAGP, DIAG_OPS, out);
 }
 
 lbm_status check_stable(lbm_ctx* c, const double* dg) {
@@ -272,21 +365,23 @@ lbm_status check_stable(lbm_ctx* c, const double* dg) {
 lbm_status moments_launch(lbm_ctx* c, bool diag, float* rho, float* u, float* shear, float* omega, float* sigma) {
   Bufs b = bufs(c, c->cur, nullptr);
   const float amp = (float)amplitude(c, c->t);
-  with_storage(c->grid.storage, c->grid.shift_mode, [&](auto tag, auto shw) {
+  with_config(c->grid.storage, c->grid.shift_mode, c->f64, [&](auto tag, auto shw, auto rt) {
     using S = typename decltype(tag)::T;
+    using R = typename decltype(rt)::T;
     constexpr bool SH = decltype(shw)::value;
     if (diag)
-      hipLaunchKernelGGL((k_moments<S, SH, true>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, amp, rho, u,
+      hipLaunchKernelGGL((k_moments<S, SH, true, R>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, amp, rho, u,
                          shear, omega, sigma);
     else
-      hipLaunchKernelGGL((k_moments<S, SH, false>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, amp, rho, u,
+      hipLaunchKernelGGL((k_moments<S, SH, false, R>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, amp, rho, u,
                          shear, omega, sigma);
   });
   HIP_TRY(c, hipGetLastError());
   return LBM_OK;
 }
 
-// Compact pulled state (FP32, [19][nf]) of the current buffer into dst (device).
+// Compact pulled state (raw stored values as FP32, [19][nf]) of the current
+// buffer into dst (device).
 lbm_status gather_state(lbm_ctx* c, float* dst) {
   Bufs b = bufs(c, c->cur, nullptr);
   with_storage(c->grid.storage, 0, [&](auto tag, auto) {
@@ -308,7 +403,8 @@ lbm_status scatter_state(lbm_ctx* c, const float* src) {
 }
 
 double rest_value(const lbm_ctx* c, int i, int64_t k) {
-  return (double)wgt(i) * (c->grid.shift_mode ? 1.0 : c->phi_f[k]);
+  const double w = i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+  return w * (c->grid.shift_mode ? 1.0 : c->phi_f[k]);
 }
 
 }  // namespace
@@ -341,53 +437,53 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* solid, const float* p
   if (s != LBM_OK) return s;
   if (!solid || !phi || !rh || !po) return fail(LBM_E_INVALID, "solid, phi, rheology and porous must not be NULL");
   if (!(rh->nu0 > 0) || !(rh->nu_inf > 0)) return fail(LBM_E_INVALID, "nu0 and nu_inf must be positive");
-  if (!(rh->a > 0) || !(rh->lambda >= 0) || !std::isfinite(rh->n)) return fail(LBM_E_INVALID, "bad Carreau-Yasuda a, lambda or n");
+  if (!(rh->a > 0) || !(rh->lambda >= 0) || !std::isfinite(rh->n))
+    return fail(LBM_E_INVALID, "bad Carreau-Yasuda a, lambda or n");
   if (!(po->kc >= 0) || !(po->d > 0) || !(po->nu_darcy >= 0)) return fail(LBM_E_INVALID, "bad porous parameters");
   if (op && (op->inlet || op->outlet)) {
     if (grid->periodic[0]) return fail(LBM_E_INVALID, "open faces need a non-periodic x axis");
-    if (op->inlet && (!op->shape_yz || !(op->period > 0))) return fail(LBM_E_INVALID, "inlet needs shape_yz and period > 0");
+    if (op->inlet && (!op->shape_yz || !(op->period > 0)))
+      return fail(LBM_E_INVALID, "inlet needs shape_yz and period > 0");
     if (op->outlet && !(op->rho_out > 0)) return fail(LBM_E_INVALID, "outlet density must be positive");
   }
   if (!workspace) return fail(LBM_E_WORKSPACE, "workspace is NULL");
   if (((uintptr_t)workspace & 255) != 0) return fail(LBM_E_WORKSPACE, "workspace must be 256-byte aligned");
+  const int64_t nf0 = count_fluid(grid, solid);
+  if (nf0 == 0) return fail(LBM_E_INVALID, "no fluid cell");
+  const Layout L0 = make_layout(*grid, nf0, 0, 0);
+  if (ws_bytes < L0.total)
+    return fail(LBM_E_WORKSPACE, "workspace too small: need " + std::to_string(L0.total) + " bytes");
 
   lbm_ctx* c = new lbm_ctx();
   c->grid = *grid;
   c->rh = *rh;
   c->po = *po;
-  c->has_open = op ? 1 : 0;
   if (op) c->op = *op;
   c->op.shape_yz = nullptr;
   c->nbox = (size_t)grid->nx * grid->ny * grid->nz;
   c->solid.assign(solid, solid + c->nbox);
   c->stream = (hipStream_t)stream;
-  std::vector<uint32_t> packed;
-  packed.reserve(c->nbox / 8);
-  for (int z = 0; z < grid->nz; ++z)
-    for (int y = 0; y < grid->ny; ++y)
-      for (int x = 0; x < grid->nx; ++x) {
-        const size_t b = (size_t)x + (size_t)grid->nx * ((size_t)y + (size_t)grid->ny * z);
-        if (solid[b]) continue;
-        uint32_t pk = (uint32_t)x | ((uint32_t)y << 11) | ((uint32_t)z << 21);
-        if (region && region[b]) pk |= 1u << 31;
-        packed.push_back(pk);
-        c->fluid_box.push_back((int64_t)b);
-        uint8_t of = 0;
-        if (op && op->inlet && x == 0) of = 1;
-        else if (op && op->outlet && x == grid->nx - 1) of = 2;
-        c->openface.push_back(of);
-      }
-  c->nf = (int64_t)packed.size();
-  if (c->nf == 0) { delete c; return fail(LBM_E_INVALID, "no fluid cell"); }
+  c->U = storage_unit(grid->storage);
+  std::vector<uint32_t> cells;
+  cells.reserve(nf0);
+  c->fluid_box.reserve(nf0);
+  for (size_t b = 0; b < c->nbox; ++b) {
+    if (solid[b]) continue;
+    const int x = (int)(b % grid->nx);
+    cells.push_back((uint32_t)b);
+    c->fluid_box.push_back((int64_t)b);
+    c->region_f.push_back(region && region[b] ? 1 : 0);
+    uint8_t of = 0;
+    if (op && op->inlet && x == 0) of = 1;
+    else if (op && op->outlet && x == grid->nx - 1) of = 2;
+    c->openface.push_back(of);
+    c->nreg += (region && region[b]) ? 1 : 0;
+  }
+  c->nf = (int64_t)cells.size();
   s = check_phi(c, phi);
   if (s != LBM_OK) { delete c; return s; }
   c->nblk = blocks_for(c->nf);
-  c->L = make_layout(*grid, c->nf, 0, 0);
-  if (ws_bytes < c->L.total) {
-    // an adjoint-sized workspace is also fine; size the layout to what was given
-    delete c;
-    return fail(LBM_E_WORKSPACE, "workspace too small: need " + std::to_string(make_layout(*grid, count_fluid(grid, solid), 0, 0).total) + " bytes");
-  }
+  c->L = L0;
   c->ws = (char*)workspace;
   c->ws_bytes = ws_bytes;
   c->cur = c->ws + c->L.A;
@@ -398,13 +494,18 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* solid, const float* p
   P.nxy = (uint32_t)grid->nx * grid->ny;
   P.nbox = (uint32_t)c->nbox;
   P.px = grid->periodic[0] ? 1 : 0; P.py = grid->periodic[1] ? 1 : 0; P.pz = grid->periodic[2] ? 1 : 0;
+  P.anyper = P.px | P.py | P.pz;
   P.inlet = (op && op->inlet) ? 1 : 0;
   P.outlet = (op && op->outlet) ? 1 : 0;
-  P.nu0 = (float)rh->nu0; P.nu_inf = (float)rh->nu_inf; P.lam = (float)rh->lambda;
-  P.cy_e = (float)((rh->n - 1.0) / rh->a); P.cy_a = (float)rh->a; P.cy_a2 = rh->a == 2.0 ? 1 : 0;
-  P.nu_d = (float)po->nu_darcy; P.kcd = (float)(po->kc / (po->d * po->d)); P.forch = po->forchheimer ? 1 : 0;
-  P.gx = (float)po->g[0]; P.gy = (float)po->g[1]; P.gz = (float)po->g[2];
-  P.rho_out = (op && op->outlet) ? (float)op->rho_out : 1.0f;
+  div_magic((uint32_t)grid->nx, P.dmag, P.dsh1, P.dsh2);
+  for (int i = 0; i < Q; ++i) P.plb[i] = (uint32_t)((size_t)i * c->nbox * store_bytes(grid->storage));
+  P.U = c->U; P.iU = 1.0 / c->U; P.ks = c->U / 36.0;
+  P.nu0 = rh->nu0; P.nu_inf = rh->nu_inf; P.lam = rh->lambda;
+  P.cy_e = (rh->n - 1.0) / rh->a; P.cy_a = rh->a; P.cy_a2 = rh->a == 2.0 ? 1 : 0;
+  P.nu_d = po->nu_darcy; P.kcd = po->kc / (po->d * po->d); P.forch = po->forchheimer ? 1 : 0;
+  P.gx = po->g[0]; P.gy = po->g[1]; P.gz = po->g[2];
+  P.rho_out = (op && op->outlet) ? op->rho_out : 1.0;
+  c->f64 = grid->arith == LBM_ARITH_FP64 || (grid->arith == LBM_ARITH_AUTO && grid->storage == LBM_STORE_FP32);
   c->omega0 = (float)(2.0 / (6.0 * rh->nu0 + 1.0));
 
   auto bail = [&](lbm_status st) { delete c; return st; };
@@ -413,11 +514,11 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* solid, const float* p
     hipError_t e_ = (expr);                                                                         \
     if (e_ != hipSuccess) return bail(fail(LBM_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_))); \
   } while (0)
-  HIP_TRY0(hipMemcpyAsync(c->ws + c->L.cells, packed.data(), packed.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY0(hipMemcpyAsync(c->ws + c->L.cells, cells.data(), cells.size() * 4, hipMemcpyHostToDevice, c->stream));
   std::vector<float> shape((size_t)grid->ny * grid->nz, 0.0f);
   if (op && op->inlet) std::memcpy(shape.data(), op->shape_yz, shape.size() * 4);
   HIP_TRY0(hipMemcpyAsync(c->ws + c->L.shape, shape.data(), shape.size() * 4, hipMemcpyHostToDevice, c->stream));
-  // the unused halves of the population buffers are never read; clear them once
+  // slots that no consumer reads are never written by the kernels; clear them once
   HIP_TRY0(hipMemsetAsync(c->ws + c->L.A, 0, c->L.phi - c->L.A, c->stream));
   HIP_TRY0(hipStreamSynchronize(c->stream));
 #undef HIP_TRY0
@@ -480,10 +581,11 @@ lbm_status lbm_get_state(lbm_ctx* c, double* f, float* omega) {
     std::vector<float> h(Q * nf);
     HIP_TRY(c, hipMemcpyAsync(h.data(), stage, h.size() * 4, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const double iU = 1.0 / c->U;
     for (int i = 0; i < Q; ++i)
       for (size_t k = 0; k < nf; ++k) {
         const float v = h[i * nf + k];
-        f[i * nf + k] = std::isnan(v) ? 0.0 : (double)v + rest_value(c, i, (int64_t)k);
+        f[i * nf + k] = std::isnan(v) ? 0.0 : (double)v * iU + rest_value(c, i, (int64_t)k);
       }
   }
   if (omega) {
@@ -501,7 +603,7 @@ lbm_status lbm_set_state(lbm_ctx* c, const double* f, const float* omega) {
   if (f) {
     std::vector<float> h(Q * nf);
     for (int i = 0; i < Q; ++i)
-      for (size_t k = 0; k < nf; ++k) h[i * nf + k] = (float)(f[i * nf + k] - rest_value(c, i, (int64_t)k));
+      for (size_t k = 0; k < nf; ++k) h[i * nf + k] = (float)((f[i * nf + k] - rest_value(c, i, (int64_t)k)) * c->U);
     HIP_TRY(c, hipMemcpyAsync(stage, h.data(), h.size() * 4, hipMemcpyHostToDevice, c->stream));
     lbm_status s = scatter_state(c, stage);
     if (s != LBM_OK) return s;

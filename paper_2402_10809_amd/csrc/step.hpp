@@ -5,145 +5,209 @@
 // populations live in two structure-of-arrays buffers over the dense box
 // (plane stride nbox); a step pulls from A at x - c_i and writes B at x.
 //
-// Stored values are deviations from a rest value.  With shift mode 0 the
-// producer at x stores q_i(x) - w_i phi~(x + c_i), where phi~ is the porosity of
-// the consumer cell (its own porosity when the link bounces back), so every
-// consumer reads delta_i = f_i - w_i phi(x) and the whole collision runs on
-// deltas:
-//   rho - 1 = sum(delta)/phi,  m = sum(delta c),
-//   delta_eq_i = w_i phi [(rho - 1) + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u)],
-//   stored_i = delta_i - omega (delta_i - delta_eq_i) + G_i + w_i (rho - 1)(phi~_i - phi).
+// Stored values are scaled deviations from a rest value: with shift mode 0 the
+// producer at x stores U (q_i(x) - w_i phi~(x + c_i)), where phi~ is the
+// porosity of the consumer cell (its own porosity when the link bounces back),
+// so every consumer reads v_i = U (f_i - w_i phi(x)).  U = 36 (times 2^10 for
+// FP16) makes U w_i an exact integer (12, 2, 1 times 2^k) for every direction,
+// so the per-direction arithmetic carries no rounded weight: the collision
+// conserves mass and momentum up to unbiased rounding only.  The whole
+// collision runs on these deviations:
+//   rho - 1 = sum(v) / (U phi),  m = sum(v c) / U,
+//   v_eq_i = U w_i phi [(rho - 1) + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u)],
+//   out_i = v_i - omega (v_i - v_eq_i) + U G_i + U w_i (rho - 1)(phi~_i - phi).
 // This is the paper's collide-and-stream update (method section) with f_eq,
 // Omega^phi, Guo's Omega^f and Omega^SRT expanded around the rest state, which
 // keeps the O(u) signal far above FP32/FP16 rounding of the O(1) rest value.
-// Shift mode 1 stores f_i - w_i instead and converts on load and store.
+// Shift mode 1 stores U (f_i - w_i) instead and converts on load and store.
+//
+// Each fluid cell carries a link word: bit i (1..18) = the pull of direction i
+// bounces back (x - c_i is solid or outside a non-periodic face), plus flags
+// (uniform neighbour porosity, open-face role, region, periodic-face bits).
+// Waves whose cells all have uniform neighbour porosity skip the neighbour
+// porosity loads and the porosity-jump arithmetic.
 #pragma once
+#include <type_traits>
+
 #include "lattice.hpp"
 
 namespace lbm {
 
+constexpr uint32_t LK_UNI = 1u << 19;   // every fluid neighbour has the cell's porosity
+constexpr uint32_t LK_IN = 1u << 20;    // inflow cell (x = 0)
+constexpr uint32_t LK_OUT = 1u << 21;   // outflow cell (x = nx - 1)
+constexpr uint32_t LK_REG = 1u << 22;   // objective region
+constexpr uint32_t LK_WRAP = 1u << 23;  // on a periodic face
+constexpr int LK_FACE = 24;             // 6 bits: x-, x+, y-, y+, z-, z+ periodic faces
+
+// 36 w_i: 12 (rest), 2 (axis), 1 (edge).
+__host__ __device__ constexpr float kw(int i) { return i == 0 ? 12.0f : (i < 7 ? 2.0f : 1.0f); }
+
 struct Params {
   int nx, ny, nz, nf;
   uint32_t nxy, nbox;
-  int px, py, pz;
+  int px, py, pz, anyper;
   int inlet, outlet;
-  float nu0, nu_inf, lam, cy_e, cy_a;  // Carreau-Yasuda; cy_e = (n-1)/a
-  int cy_a2;                           // a == 2: (lambda g)^a is one multiply
-  float nu_d, kcd;                     // Darcy viscosity, kc/d^2
+  uint32_t dmag, dsh1, dsh2;  // division by nx (Granlund-Montgomery)
+  uint32_t plb[Q];            // byte offset of population plane i (i * nbox * sizeof(storage))
+  // physical constants (converted to the kernel's arithmetic type on use)
+  double U, iU, ks;            // storage unit, 1/U, U/36
+  double nu0, nu_inf, lam, cy_e, cy_a;  // Carreau-Yasuda; cy_e = (n-1)/a
+  int cy_a2;                            // a == 2: (lambda g)^a is one multiply
+  double nu_d, kcd;                     // Darcy viscosity, kc/d^2
   int forch;
-  float gx, gy, gz;
-  float rho_out;
+  double gx, gy, gz;
+  double rho_out;
 };
 
 struct Bufs {
   const void* A;
   void* B;
-  const uint32_t* cells;
+  const uint32_t* cells;  // box index per fluid cell
+  const uint32_t* links;  // link word per fluid cell
   const float* phi;       // dense box porosity, 0 = solid
   float* omega;           // per fluid cell, previous relaxation rate
   const float* shape;     // inflow profile, ny*nz
   double* part;           // per-block partials
-  float* rec;             // recompute record: [20][nf] (pulled deltas, omega_prev)
+  float* rec;             // recompute record: [20][nf] (pulled values, omega_prev)
   float* rho_box;         // recompute record: dense rho of the step
-};
-
-// Per-axis offsets from a cell to its -1 / +1 neighbour, with periodic wrap,
-// and whether that neighbour lies outside a non-periodic face.
-struct Nb {
-  int oxm, oxp, oym, oyp, ozm, ozp;
-  bool nxm, nxp, nym, nyp, nzm, nzp;
-  __device__ __forceinline__ Nb(const Params& p, int x, int y, int z) {
-    nxm = (x == 0) && !p.px;
-    nxp = (x == p.nx - 1) && !p.px;
-    nym = (y == 0) && !p.py;
-    nyp = (y == p.ny - 1) && !p.py;
-    nzm = (z == 0) && !p.pz;
-    nzp = (z == p.nz - 1) && !p.pz;
-    oxm = x > 0 ? -1 : (p.px ? p.nx - 1 : 0);
-    oxp = x < p.nx - 1 ? 1 : (p.px ? -(p.nx - 1) : 0);
-    const int sy = p.nx, sz = (int)p.nxy;
-    oym = y > 0 ? -sy : (p.py ? (p.ny - 1) * sy : 0);
-    oyp = y < p.ny - 1 ? sy : (p.py ? -(p.ny - 1) * sy : 0);
-    ozm = z > 0 ? -sz : (p.pz ? (p.nz - 1) * sz : 0);
-    ozp = z < p.nz - 1 ? sz : (p.pz ? -(p.nz - 1) * sz : 0);
-  }
-  // Offset and outside flag of x + s (s a lattice vector with entries in {-1,0,1}).
-  template <int SX, int SY, int SZ>
-  __device__ __forceinline__ int off(bool& out) const {
-    int o = 0;
-    out = false;
-    if (SX == -1) { o += oxm; out |= nxm; }
-    if (SX == 1) { o += oxp; out |= nxp; }
-    if (SY == -1) { o += oym; out |= nym; }
-    if (SY == 1) { o += oyp; out |= nyp; }
-    if (SZ == -1) { o += ozm; out |= nzm; }
-    if (SZ == 1) { o += ozp; out |= nzp; }
-    return o;
-  }
-  // Whether x + s is outside the open x face only (not also outside a wall face).
-  template <int SX, int SY, int SZ>
-  __device__ __forceinline__ bool open_only(const Params& p, int x) const {
-    bool ox = (SX == -1 && x == 0 && p.inlet) || (SX == 1 && x == p.nx - 1 && p.outlet);
-    bool wall = (SY == -1 && nym) || (SY == 1 && nyp) || (SZ == -1 && nzm) || (SZ == 1 && nzp);
-    return ox && !wall;
-  }
 };
 
 template <int I> struct Dir {
   static constexpr int cx = CX[I], cy = CY[I], cz = CZ[I], opp = OPP[I];
 };
 
-// Pull: delta_i(x) = stored value at x - c_i, or the cell's own opposite value
-// when x - c_i is solid or outside a wall/open face (halfway bounce-back; the
-// open-face unknowns are replaced by the Zou-He fill afterwards).  Also returns
-// pt[j] = porosity of x + c_j (phi(x) across walls), for the producer side.
-template <class S, bool SHW>
-__device__ __forceinline__ void pull(const Params& p, const S* __restrict__ A, const float* __restrict__ phi,
-                                     uint32_t idx, const Nb& nb, float phx, float d[Q], float pt[Q]) {
-  pt[0] = phx;
-  d[0] = Store<S>::ld(A, idx, 0);
-#define LBM_PULL(I)                                                                   \
-  {                                                                                   \
-    bool out;                                                                         \
-    const int o = nb.template off<-Dir<I>::cx, -Dir<I>::cy, -Dir<I>::cz>(out);        \
-    const uint32_t src = idx + (uint32_t)o;                                           \
-    const float pn = ldo(phi, src);                                                   \
-    const bool bb = out || (pn == 0.0f);                                              \
-    pt[Dir<I>::opp] = bb ? phx : pn;                                                  \
-    const uint32_t e = bb ? (uint32_t)Dir<I>::opp * p.nbox + idx : (uint32_t)I * p.nbox + src; \
-    d[I] = Store<S>::ld(A, e, I);                                                     \
+template <int A, int B, class F>
+__device__ __forceinline__ void sfor(F&& f) {
+  if constexpr (A < B) {
+    f(std::integral_constant<int, A>{});
+    sfor<A + 1, B>(f);
   }
-  LBM_PULL(1) LBM_PULL(2) LBM_PULL(3) LBM_PULL(4) LBM_PULL(5) LBM_PULL(6)
-  LBM_PULL(7) LBM_PULL(8) LBM_PULL(9) LBM_PULL(10) LBM_PULL(11) LBM_PULL(12)
-  LBM_PULL(13) LBM_PULL(14) LBM_PULL(15) LBM_PULL(16) LBM_PULL(17) LBM_PULL(18)
-#undef LBM_PULL
+}
+
+__device__ __forceinline__ uint32_t div_nx(const Params& p, uint32_t n) {
+  const uint32_t t = __umulhi(p.dmag, n);
+  return (t + ((n - t) >> p.dsh1)) >> p.dsh2;
+}
+
+// Hardware reciprocal refined by Newton steps (the raw v_rcp result is biased
+// by up to an ulp, which accumulates over thousands of steps).
+__device__ __forceinline__ float fast_rcp(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return __builtin_fmaf(r, __builtin_fmaf(-x, r, 1.0f), r);
+}
+__device__ __forceinline__ double fast_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+  return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ float rsqrt_(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ double rsqrt_(double x) { return __builtin_sqrt(x); }
+__device__ __forceinline__ float rfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double rfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Offset from x to x + s for the lattice vector s = (SX, SY, SZ), including the
+// periodic wrap corrections of cells on a periodic face (wc: x-, x+, y-, y+, z-, z+).
+template <int SX, int SY, int SZ, bool PER = true>
+__device__ __forceinline__ int nb_off(const Params& p, const int (&wc)[6]) {
+  int o = SX + SY * p.nx + SZ * (int)p.nxy;
+  if (PER) {
+    if (SX == -1) o += wc[0];
+    if (SX == 1) o += wc[1];
+    if (SY == -1) o += wc[2];
+    if (SY == 1) o += wc[3];
+    if (SZ == -1) o += wc[4];
+    if (SZ == 1) o += wc[5];
+  }
+  return o;
+}
+
+// Load through a byte offset from a uniform base.
+template <class T>
+__device__ __forceinline__ T ldb(const T* base, uint32_t byte_off) {
+  return *(const T*)((const char*)base + byte_off);
+}
+template <class T>
+__device__ __forceinline__ void stb(T* base, uint32_t byte_off, T v) {
+  *(T*)((char*)base + byte_off) = v;
+}
+template <class S>
+__device__ __forceinline__ float ld_pop(const S* base, uint32_t byte_off) {
+  if constexpr (std::is_same<S, float>::value) return ldb(base, byte_off);
+  else return (float)ldb(base, byte_off);
+}
+template <class S>
+__device__ __forceinline__ void st_pop(S* base, uint32_t byte_off, float v) {
+  if constexpr (std::is_same<S, float>::value) stb(base, byte_off, v);
+  else stb(base, byte_off, (S)v);
+}
+
+__device__ __forceinline__ void wrap_corr(const Params& p, uint32_t lk, int (&wc)[6]) {
+  const int nxy = (int)p.nxy;
+  wc[0] = (lk >> (LK_FACE + 0)) & 1 ? p.nx : 0;
+  wc[1] = (lk >> (LK_FACE + 1)) & 1 ? -p.nx : 0;
+  wc[2] = (lk >> (LK_FACE + 2)) & 1 ? p.ny * p.nx : 0;
+  wc[3] = (lk >> (LK_FACE + 3)) & 1 ? -p.ny * p.nx : 0;
+  wc[4] = (lk >> (LK_FACE + 4)) & 1 ? p.nz * nxy : 0;
+  wc[5] = (lk >> (LK_FACE + 5)) & 1 ? -p.nz * nxy : 0;
+}
+
+// Pull: v_i(x) = stored value at x - c_i, or the cell's own opposite value when
+// that link bounces back (solid or outside; the open-face unknowns are then
+// replaced by the Zou-He fill).  Unless UNI, also pt[j] = porosity of x + c_j
+// (phi(x) across walls) for the producer side.
+template <class S, bool SHW, bool UNI, bool PER>
+__device__ __forceinline__ void pull(const Params& p, const S* __restrict__ A, const float* __restrict__ phi,
+                                     uint32_t idx, uint32_t lk, const int (&wc)[6], float phx, float v[Q],
+                                     float pt[Q]) {
+  constexpr uint32_t SB = sizeof(S);
+  const uint32_t ib = idx * SB;
+  v[0] = ld_pop(A, ib);
+  pt[0] = phx;
+  sfor<1, Q>([&](auto ic) {
+    constexpr int I = decltype(ic)::value;
+    constexpr int J = OPP[I];
+    const bool bb = (lk >> I) & 1u;
+    const int o = nb_off<-CX[I], -CY[I], -CZ[I], PER>(p, wc);
+    const uint32_t a_bb = p.plb[J] + ib;
+    const uint32_t a_nb = p.plb[I] + ib + (uint32_t)(o * (int)SB);
+    v[I] = ld_pop(A, bb ? a_bb : a_nb);
+    if (!UNI) {
+      // a bounced link reads the cell's own porosity, which is what phi~ is then
+      const uint32_t pidx = idx + (bb ? 0u : (uint32_t)o);
+      pt[J] = ldo(phi, pidx);
+    } else {
+      pt[J] = phx;
+    }
+  });
   if (SHW) {
-    const float s = phx - 1.0f;
+    const float s = (float)p.ks * (phx - 1.0f);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) d[i] -= wgt(i) * s;
+    for (int i = 0; i < Q; ++i) v[i] -= kw(i) * s;
   }
 }
 
 // Zou-He fill of the unknown populations on the open faces (phi = 1 there, so
-// delta = f - w and the closures hold for deltas as for populations).
-__device__ __forceinline__ void open_fill(const Params& p, int x, int y, int z, float amp,
+// the closures hold for the deviations as for the populations).
+__device__ __forceinline__ void open_fill(const Params& p, uint32_t idx, uint32_t lk, float amp,
                                           const float* __restrict__ shape, float d[Q]) {
-  const bool in = p.inlet && x == 0;
-  const bool outl = p.outlet && x == p.nx - 1;
+  const bool in = (lk & LK_IN) != 0;
+  const bool outl = (lk & LK_OUT) != 0;
   if (!(in || outl)) return;
+  const float U = (float)p.U, iU = (float)p.iU;
   const float s0 = d[0] + d[3] + d[4] + d[5] + d[6] + d[15] + d[16] + d[17] + d[18];
   const float ny_ = 0.5f * (d[3] - d[4] + d[15] - d[16] + d[17] - d[18]);
   const float nz_ = 0.5f * (d[5] - d[6] + d[15] - d[16] - d[17] + d[18]);
   // inflow: prescribed u = (ux, 0, 0); density from mass and normal momentum
-  const float uin = in ? amp * shape[y + p.ny * z] : 0.0f;
+  const float uin = in ? amp * shape[div_nx(p, idx)] : 0.0f;
   const float sm = d[2] + d[8] + d[10] + d[12] + d[14];
-  const float rin = (1.0f + s0 + 2.0f * sm) / (1.0f - uin);
+  const float rin = (1.0f + (s0 + 2.0f * sm) * iU) / (1.0f - uin);
   // outflow: prescribed density, normal velocity from mass and the known half
   const float sp = d[1] + d[7] + d[9] + d[11] + d[13];
-  const float ro = p.rho_out;
-  const float uout = (1.0f + s0 + 2.0f * sp) / ro - 1.0f;
-  const float r3i = rin * uin * (1.0f / 3.0f), r6i = rin * uin * (1.0f / 6.0f);
-  const float r3o = ro * uout * (1.0f / 3.0f), r6o = ro * uout * (1.0f / 6.0f);
+  const float ro = (float)p.rho_out;
+  const float uout = (1.0f + (s0 + 2.0f * sp) * iU) / ro - 1.0f;
+  const float r3i = U * rin * uin * (1.0f / 3.0f), r6i = U * rin * uin * (1.0f / 6.0f);
+  const float r3o = U * ro * uout * (1.0f / 3.0f), r6o = U * ro * uout * (1.0f / 6.0f);
   const float i1 = d[2] + r3i, i7 = d[8] + r6i - ny_, i9 = d[10] + r6i + ny_, i11 = d[12] + r6i - nz_,
               i13 = d[14] + r6i + nz_;
   const float o2 = d[1] - r3o, o8 = d[7] - r6o + ny_, o10 = d[9] - r6o - ny_, o12 = d[11] - r6o + nz_,
@@ -160,88 +224,108 @@ __device__ __forceinline__ void open_fill(const Params& p, int x, int y, int z, 
   d[14] = outl ? o14 : d[14];
 }
 
-// Macroscopic state of one cell for one step.
-struct Macro {
-  float rho, rm1;         // density and rho - 1
-  float ux, uy, uz, uu;   // velocity
-  float Fx, Fy, Fz;       // force density rho f(u)
-  float P[6];             // corrected second moment Pi (xx yy zz xy xz yz)
-  float shear, omega;
+// Moment sums of the 19 values from opposite-pair sums and differences, in
+// the arithmetic type R.
+template <class R>
+struct Sums {
+  R s, mx, my, mz, xx, yy, zz, xy, xz, yz;
 };
-
-// Hardware reciprocal refined by one Newton step (the raw v_rcp_f32 result is
-// biased by up to an ulp, which accumulates over thousands of steps).
-__device__ __forceinline__ float fast_rcp(float x) {
-  const float r = __builtin_amdgcn_rcpf(x);
-  return __builtin_fmaf(r, __builtin_fmaf(-x, r, 1.0f), r);
+template <class R>
+__device__ __forceinline__ Sums<R> moment_sums(const float d[Q]) {
+  auto x = [&](int i) { return (R)d[i]; };
+  const R P1 = x(1) + x(2), P3 = x(3) + x(4), P5 = x(5) + x(6), P7 = x(7) + x(8), P9 = x(9) + x(10),
+          P11 = x(11) + x(12), P13 = x(13) + x(14), P15 = x(15) + x(16), P17 = x(17) + x(18);
+  const R M1 = x(1) - x(2), M3 = x(3) - x(4), M5 = x(5) - x(6), M7 = x(7) - x(8), M9 = x(9) - x(10),
+          M11 = x(11) - x(12), M13 = x(13) - x(14), M15 = x(15) - x(16), M17 = x(17) - x(18);
+  Sums<R> r;
+  r.s = x(0) + ((P1 + P3) + (P5 + P7)) + ((P9 + P11) + (P13 + (P15 + P17)));
+  r.mx = M1 + M7 + M9 + M11 + M13;
+  r.my = M3 + M7 - M9 + M15 + M17;
+  r.mz = M5 + M11 - M13 + M15 - M17;
+  r.xx = P1 + P7 + P9 + P11 + P13;
+  r.yy = P3 + P7 + P9 + P15 + P17;
+  r.zz = P5 + P11 + P13 + P15 + P17;
+  r.xy = P7 - P9;
+  r.xz = P11 - P13;
+  r.yz = P15 - P17;
+  return r;
 }
 
+// Macroscopic state of one cell for one step.
+template <class R>
+struct Macro {
+  R rho, rm1;         // density and rho - 1
+  R ux, uy, uz, uu;   // velocity
+  R Fx, Fy, Fz;       // force density rho f(u)
+  R P[6];             // corrected second moment Pi (xx yy zz xy xz yz)
+  float shear;        // shear rate (the rheology runs in FP32)
+  R omega;
+};
+
 // Moments, explicit velocity with drag, force, Pi, shear rate and the new
-// relaxation rate from the Carreau-Yasuda viscosity.
-__device__ __forceinline__ void macro(const Params& p, float phx, const float d[Q], float omega_prev, Macro& M) {
-  float sd = 0.f;
-#pragma unroll
-  for (int i = 0; i < Q; ++i) sd += d[i];
-  const float mx = (d[1] + d[7] + d[9] + d[11] + d[13]) - (d[2] + d[8] + d[10] + d[12] + d[14]);
-  const float my = (d[3] + d[7] + d[10] + d[15] + d[17]) - (d[4] + d[8] + d[9] + d[16] + d[18]);
-  const float mz = (d[5] + d[11] + d[14] + d[15] + d[18]) - (d[6] + d[12] + d[13] + d[16] + d[17]);
-  const float iphi = fast_rcp(phx);
-  const float sumf = phx + sd;                 // phi rho
-  const float rm1 = sd * iphi;                 // rho - 1
-  const float rho = 1.0f + rm1;
-  const float isum = fast_rcp(sumf);
-  const float hg = 0.5f * iphi;
-  const float vx = mx * isum + p.gx * hg, vy = my * isum + p.gy * hg, vz = mz * isum + p.gz * hg;
+// relaxation rate from the Carreau-Yasuda viscosity.  R is the arithmetic
+// type of everything that feeds the collision's mass and momentum: with FP32
+// storage it is FP64, because FP32 rounding of these per-cell scalars is
+// common to all 19 directions and acts as a persistent momentum source.
+template <class R>
+__device__ __forceinline__ void macro(const Params& p, float phx_f, const float d[Q], float omega_prev, Macro<R>& M) {
+  const Sums<R> s = moment_sums<R>(d);
+  const R phx = (R)phx_f;
+  const R one = (R)1;
+  const R iphi = fast_rcp(phx);
+  const R rm1 = s.s * fast_rcp((R)p.U * phx);  // rho - 1
+  const R rho = one + rm1;
+  const R pr = phx * rho;                      // phi rho = sum f
+  const R iUS = fast_rcp((R)p.U * pr);
+  const R hg = (R)0.5 * iphi;
+  const R gx = (R)p.gx, gy = (R)p.gy, gz = (R)p.gz;
+  const R vx = s.mx * iUS + gx * hg, vy = s.my * iUS + gy * hg, vz = s.mz * iUS + gz * hg;
   // 1/k = (kc/d^2) (1 - phi)^2 / phi^3
-  const float om = 1.0f - phx;
-  const float invk = p.kcd * om * om * iphi * iphi * iphi;
-  const float dark = phx * p.nu_d * invk;      // phi nu / k
-  const float C0 = 0.5f + 0.25f * dark;
-  float den, fcoef;
+  const R om = one - phx;
+  const R invk = (R)p.kcd * om * om * iphi * iphi * iphi;
+  const R dark = phx * (R)p.nu_d * invk;      // phi nu / k
+  const R C0 = (R)0.5 + (R)0.25 * dark;
+  R den, fcoef;
   if (p.forch) {
-    const float sik = __builtin_sqrtf(invk);
-    const float cf = 1.75f * __builtin_sqrtf(iphi * iphi * iphi * (1.0f / 150.0f));
-    const float C1 = 0.5f * phx * phx * cf * sik;
-    const float vn = __builtin_sqrtf(vx * vx + vy * vy + vz * vz);
-    den = C0 + __builtin_sqrtf(C0 * C0 + C1 * vn);
+    const R sik = rsqrt_(invk);
+    const R cf = (R)1.75 * rsqrt_(iphi * iphi * iphi * (R)(1.0 / 150.0));
+    const R C1 = (R)0.5 * phx * phx * cf * sik;
+    const R vn = rsqrt_(vx * vx + vy * vy + vz * vz);
+    den = C0 + rsqrt_(C0 * C0 + C1 * vn);
     fcoef = phx * phx * phx * cf * sik;        // times |u| below
   } else {
-    den = 2.0f * C0;
-    fcoef = 0.0f;
+    den = (R)2 * C0;
+    fcoef = (R)0;
   }
-  const float iden = fast_rcp(den);
-  const float ux = vx * iden, uy = vy * iden, uz = vz * iden;
-  const float uu = ux * ux + uy * uy + uz * uz;
-  const float drag = phx * dark + (p.forch ? fcoef * __builtin_sqrtf(uu) : 0.0f);  // phi^2 nu/k + phi^3 C_F |u|/sqrt(k)
-  const float Fx = rho * (p.gx - drag * ux), Fy = rho * (p.gy - drag * uy), Fz = rho * (p.gz - drag * uz);
-  // Pi = sum delta c c - [phi (rho-1)/3 I + phi rho u u] + (F u + u F)/2
-  const float pr = phx * rho;
-  const float iso = phx * rm1 * (1.0f / 3.0f);
-  const float Sxx = d[1] + d[2] + d[7] + d[8] + d[9] + d[10] + d[11] + d[12] + d[13] + d[14];
-  const float Syy = d[3] + d[4] + d[7] + d[8] + d[9] + d[10] + d[15] + d[16] + d[17] + d[18];
-  const float Szz = d[5] + d[6] + d[11] + d[12] + d[13] + d[14] + d[15] + d[16] + d[17] + d[18];
-  const float Sxy = (d[7] + d[8]) - (d[9] + d[10]);
-  const float Sxz = (d[11] + d[12]) - (d[13] + d[14]);
-  const float Syz = (d[15] + d[16]) - (d[17] + d[18]);
-  M.P[0] = Sxx - iso - pr * ux * ux + Fx * ux;
-  M.P[1] = Syy - iso - pr * uy * uy + Fy * uy;
-  M.P[2] = Szz - iso - pr * uz * uz + Fz * uz;
-  M.P[3] = Sxy - pr * ux * uy + 0.5f * (Fx * uy + ux * Fy);
-  M.P[4] = Sxz - pr * ux * uz + 0.5f * (Fx * uz + ux * Fz);
-  M.P[5] = Syz - pr * uy * uz + 0.5f * (Fy * uz + uy * Fz);
-  const float pn2 = M.P[0] * M.P[0] + M.P[1] * M.P[1] + M.P[2] * M.P[2] +
-                    2.0f * (M.P[3] * M.P[3] + M.P[4] * M.P[4] + M.P[5] * M.P[5]);
-  const float irho = fast_rcp(rho);
-  const float shear = 3.0f * omega_prev * __builtin_sqrtf(pn2) * irho;
+  const R iden = fast_rcp(den);
+  const R ux = vx * iden, uy = vy * iden, uz = vz * iden;
+  const R uu = ux * ux + uy * uy + uz * uz;
+  const R drag = phx * dark + (p.forch ? fcoef * rsqrt_(uu) : (R)0);  // phi^2 nu/k + phi^3 C_F |u|/sqrt(k)
+  const R Fx = rho * (gx - drag * ux), Fy = rho * (gy - drag * uy), Fz = rho * (gz - drag * uz);
+  // Pi = sum (f - f_eq) c c + (F u + u F)/2
+  //    = sum(v c c)/U - [phi (rho-1)/3 I + phi rho u u] + (F u + u F)/2
+  const R iso = phx * rm1 * (R)(1.0 / 3.0);
+  const R iU = (R)p.iU;
+  const R h = (R)0.5;
+  M.P[0] = s.xx * iU - iso - pr * ux * ux + Fx * ux;
+  M.P[1] = s.yy * iU - iso - pr * uy * uy + Fy * uy;
+  M.P[2] = s.zz * iU - iso - pr * uz * uz + Fz * uz;
+  M.P[3] = s.xy * iU - pr * ux * uy + h * (Fx * uy + ux * Fy);
+  M.P[4] = s.xz * iU - pr * ux * uz + h * (Fx * uz + ux * Fz);
+  M.P[5] = s.yz * iU - pr * uy * uz + h * (Fy * uz + uy * Fz);
+  const float pn2 = (float)(M.P[0] * M.P[0] + M.P[1] * M.P[1] + M.P[2] * M.P[2] +
+                            (R)2 * (M.P[3] * M.P[3] + M.P[4] * M.P[4] + M.P[5] * M.P[5]));
+  const float rhof = (float)rho;
+  const float shear = 3.0f * omega_prev * __builtin_sqrtf(pn2) * fast_rcp(rhof);
   // Carreau-Yasuda: nu = nu_inf + (nu0 - nu_inf) (1 + (lambda g)^a)^((n-1)/a)
-  const float lg = p.lam * shear;
+  const float lg = (float)p.lam * shear;
   float la;
   if (p.cy_a2) la = lg * lg;
-  else la = lg > 0.0f ? __builtin_amdgcn_exp2f(p.cy_a * __builtin_amdgcn_logf(lg)) : 0.0f;
-  const float fac = __builtin_amdgcn_exp2f(p.cy_e * __builtin_amdgcn_logf(1.0f + la));
-  const float nu = p.nu_inf + (p.nu0 - p.nu_inf) * fac;
+  else la = lg > 0.0f ? __builtin_amdgcn_exp2f((float)p.cy_a * __builtin_amdgcn_logf(lg)) : 0.0f;
+  const float fac = __builtin_amdgcn_exp2f((float)p.cy_e * __builtin_amdgcn_logf(1.0f + la));
+  const R nu = (R)p.nu_inf + (R)(p.nu0 - p.nu_inf) * (R)fac;
   // omega = 2 rho c_s^2 / (2 mu + rho c_s^2) = 2 rho / (6 nu + rho)
-  M.omega = 2.0f * rho * fast_rcp(6.0f * nu + rho);
+  M.omega = (R)2 * rho * fast_rcp((R)6 * nu + rho);
   M.rho = rho;
   M.rm1 = rm1;
   M.ux = ux; M.uy = uy; M.uz = uz; M.uu = uu;
@@ -252,49 +336,56 @@ __device__ __forceinline__ void macro(const Params& p, float phx, const float d[
 // BGK + Guo + porosity-jump collision, stored as deviations for the consumer.
 // Directions come in opposite pairs: with e = c.u and h = c.F the even part
 // (omega (A0 + C e^2) - K3 u.F + K9 e h) is shared and the odd part
-// (omega B e + K3 h) flips sign.
-template <class S, bool SHW>
-__device__ __forceinline__ void collide_store(const Params& p, S* __restrict__ B, uint32_t idx, float phx,
-                                              const float d[Q], const float pt[Q], const Macro& M) {
-  const float om = M.omega;
-  const float pr = phx * M.rho;
-  const float A0 = phx * M.rm1 - 1.5f * pr * M.uu;
-  const float Bc = 3.0f * pr, Cc = 4.5f * pr;
-  const float K = 1.0f - 0.5f * om;
-  const float K3 = 3.0f * K, K9 = 9.0f * K;
-  const float uF = M.ux * M.Fx + M.uy * M.Fy + M.uz * M.Fz;
-  const float keep = 1.0f - om;
-  const float ev0 = om * A0 - K3 * uF;
-  const float shw = phx - 1.0f;
-  // rest direction
+// (omega B e + K3 h) flips sign; both are per unit weight, scaled by the exact
+// U w_i.
+template <class S, bool SHW, bool UNI, class R>
+__device__ __forceinline__ void collide_store(const Params& p, S* __restrict__ B, uint32_t idx, float phx_f,
+                                              const float d[Q], const float pt[Q], const Macro<R>& M) {
+  const R phx = (R)phx_f;
+  const R om = M.omega;
+  const R pr = phx * M.rho;
+  const R A0 = phx * M.rm1 - (R)1.5 * pr * M.uu;
+  const R Bc = (R)3 * pr, Cc = (R)4.5 * pr;
+  const R K = (R)1 - (R)0.5 * om;
+  const R K3 = (R)3 * K, K9 = (R)9 * K;
+  const R uF = M.ux * M.Fx + M.uy * M.Fy + M.uz * M.Fz;
+  const R keep = (R)1 - om;
+  const R ev0 = om * A0 - K3 * uF;
+  const R shw = phx - (R)1;
+  const R ks = (R)p.ks;
+  const R omC = om * Cc, omB = om * Bc;
+  // uniform porosity: no jump; the shift-mode-1 term is the same for every link
+  const R ev0u = SHW && UNI ? ev0 + shw : ev0;
+  const uint32_t ib = idx * (uint32_t)sizeof(S);
   {
-    float v = wfma(0, ev0 + M.rm1 * (pt[0] - phx), keep * d[0]);
-    if (SHW) v += wgt(0) * shw;
-    Store<S>::st(B, idx, v, 0);
+    R t = ev0u;
+    if (!UNI) t += M.rm1 * ((R)pt[0] - phx) + (SHW ? shw : (R)0);
+    st_pop(B, ib, (float)rfma(ks * (R)kw(0), t, keep * (R)d[0]));
   }
-#define LBM_PAIR(I, EX, HX)                                                              \
-  {                                                                                      \
-    constexpr int J = Dir<I>::opp;                                                       \
-    const float e = (EX), h = (HX);                                                      \
-    const float ev = ev0 + om * Cc * e * e + K9 * e * h;                                 \
-    const float od = om * Bc * e + K3 * h;                                               \
-    float vi = wfma(I, ev + od + M.rm1 * (pt[I] - phx), keep * d[I]);                    \
-    float vj = wfma(J, ev - od + M.rm1 * (pt[J] - phx), keep * d[J]);                    \
-    if (SHW) { vi += wgt(I) * (pt[I] - 1.0f); vj += wgt(J) * (pt[J] - 1.0f); }           \
-    Store<S>::st(B, (uint32_t)I * p.nbox + idx, vi, I);                                  \
-    Store<S>::st(B, (uint32_t)J * p.nbox + idx, vj, J);                                  \
-  }
-  LBM_PAIR(1, M.ux, M.Fx)
-  LBM_PAIR(3, M.uy, M.Fy)
-  LBM_PAIR(5, M.uz, M.Fz)
-  LBM_PAIR(7, M.ux + M.uy, M.Fx + M.Fy)
-  LBM_PAIR(9, M.ux - M.uy, M.Fx - M.Fy)
-  LBM_PAIR(11, M.ux + M.uz, M.Fx + M.Fz)
-  LBM_PAIR(13, M.ux - M.uz, M.Fx - M.Fz)
-  LBM_PAIR(15, M.uy + M.uz, M.Fy + M.Fz)
-  LBM_PAIR(17, M.uy - M.uz, M.Fy - M.Fz)
-#undef LBM_PAIR
-  (void)shw;
+  auto pair = [&](auto ic, R e, R h) {
+    constexpr int I = decltype(ic)::value;
+    constexpr int J = OPP[I];
+    const R ev = ev0u + omC * e * e + K9 * e * h;
+    const R od = omB * e + K3 * h;
+    R ti = ev + od, tj = ev - od;
+    if (!UNI) {
+      ti += M.rm1 * ((R)pt[I] - phx);
+      tj += M.rm1 * ((R)pt[J] - phx);
+      if (SHW) { ti += (R)pt[I] - (R)1; tj += (R)pt[J] - (R)1; }
+    }
+    const R kk = ks * (R)kw(I);
+    st_pop(B, p.plb[I] + ib, (float)rfma(kk, ti, keep * (R)d[I]));
+    st_pop(B, p.plb[J] + ib, (float)rfma(kk, tj, keep * (R)d[J]));
+  };
+  pair(std::integral_constant<int, 1>{}, M.ux, M.Fx);
+  pair(std::integral_constant<int, 3>{}, M.uy, M.Fy);
+  pair(std::integral_constant<int, 5>{}, M.uz, M.Fz);
+  pair(std::integral_constant<int, 7>{}, M.ux + M.uy, M.Fx + M.Fy);
+  pair(std::integral_constant<int, 9>{}, M.ux - M.uy, M.Fx - M.Fy);
+  pair(std::integral_constant<int, 11>{}, M.ux + M.uz, M.Fx + M.Fz);
+  pair(std::integral_constant<int, 13>{}, M.ux - M.uz, M.Fx - M.Fz);
+  pair(std::integral_constant<int, 15>{}, M.uy + M.uz, M.Fy + M.Fz);
+  pair(std::integral_constant<int, 17>{}, M.uy - M.uz, M.Fy - M.Fz);
 }
 
 // ---------------------------------------------------------------------------
@@ -327,75 +418,86 @@ __device__ __forceinline__ void block_reduce(double (&v)[N], const int (&op)[N],
 
 // Per-cell diagnostic contributions: mass, momentum, energy, region energy,
 // max |u|, min/max omega, non-finite count.
-__device__ __forceinline__ void diag_terms(float phx, const float d[Q], const Macro& M, bool reg, bool active,
-                                           double (&v)[NDIAGP]) {
+template <class R>
+__device__ __forceinline__ void diag_terms(const Params& p, float phx, const float d[Q], const Macro<R>& M, bool reg,
+                                           bool active, double (&v)[NDIAGP]) {
   if (!active) {
     v[0] = v[1] = v[2] = v[3] = v[4] = v[5] = v[9] = 0.0;
     v[6] = 0.0; v[7] = 1e300; v[8] = -1e300;
     return;
   }
-  float sd = 0.f;
-#pragma unroll
-  for (int i = 0; i < Q; ++i) sd += d[i];
-  v[0] = (double)phx + (double)sd;
-  v[1] = (double)((d[1] + d[7] + d[9] + d[11] + d[13]) - (d[2] + d[8] + d[10] + d[12] + d[14]));
-  v[2] = (double)((d[3] + d[7] + d[10] + d[15] + d[17]) - (d[4] + d[8] + d[9] + d[16] + d[18]));
-  v[3] = (double)((d[5] + d[11] + d[14] + d[15] + d[18]) - (d[6] + d[12] + d[13] + d[16] + d[17]));
+  const Sums<double> s = moment_sums<double>(d);
+  v[0] = (double)phx + s.s * p.iU;
+  v[1] = s.mx * p.iU;
+  v[2] = s.my * p.iU;
+  v[3] = s.mz * p.iU;
   const double ke = 0.5 * (double)M.rho * (double)M.uu;
   v[4] = ke;
   v[5] = reg ? ke : 0.0;
-  v[6] = (double)__builtin_sqrtf(M.uu);
+  v[6] = __builtin_sqrt((double)M.uu);
   v[7] = (double)M.omega;
   v[8] = (double)M.omega;
-  const bool bad = !(__builtin_isfinite(M.rho) && __builtin_isfinite(M.uu) && __builtin_isfinite(M.omega) &&
-                     __builtin_isfinite(M.shear));
+  const bool bad = !(__builtin_isfinite((double)M.rho) && __builtin_isfinite((double)M.uu) &&
+                     __builtin_isfinite((double)M.omega) && __builtin_isfinite(M.shear));
   v[9] = bad ? 1.0 : 0.0;
   if (bad) { v[6] = 1e300; }
+}
+
+// Body of the step for one cell (UNI: the whole wave has uniform neighbour
+// porosity).
+template <class S, bool SHW, bool UNI, bool PER, int DIAG, bool REC, class R>
+__device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32_t c, float amp,
+                                          double (&dv)[NDIAGP], float& ke_reg) {
+  const uint32_t idx = b.cells[c];
+  const uint32_t lk = b.links[c];
+  const float phx = ldo(b.phi, idx);
+  int wc[6] = {0, 0, 0, 0, 0, 0};
+  if (PER) wrap_corr(p, lk, wc);
+  float d[Q], pt[Q];
+  pull<S, SHW, UNI, PER>(p, (const S*)b.A, b.phi, idx, lk, wc, phx, d, pt);
+  if (REC) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) b.rec[(size_t)i * p.nf + c] = d[i];
+  }
+  open_fill(p, idx, lk, amp, b.shape, d);
+  const float omp = b.omega[c];
+  Macro<R> M;
+  macro<R>(p, phx, d, omp, M);
+  b.omega[c] = (float)M.omega;
+  if (REC) {
+    b.rec[(size_t)Q * p.nf + c] = omp;
+    b.rho_box[idx] = (float)M.rho;
+  }
+  const bool reg = (lk & LK_REG) != 0;
+  if (DIAG == 1) diag_terms<R>(p, phx, d, M, reg, true, dv);
+  if (DIAG == 2) ke_reg = reg ? (float)((R)0.5 * M.rho * M.uu) : 0.0f;
+  collide_store<S, SHW, UNI, R>(p, (S*)b.B, idx, phx, d, pt, M);
 }
 
 // ---------------------------------------------------------------------------
 // The step.  DIAG: 0 none, 1 diagnostics of the pre-collision state into
 // part[block][NDIAGP], 2 region kinetic energy accumulated into part[block].
-// REC: also record the pulled deltas and omega_prev ([20][nf]) and rho (box).
+// REC: also record the pulled values and omega_prev ([20][nf]) and rho (box).
 // ---------------------------------------------------------------------------
-template <class S, bool SHW, int DIAG, bool REC>
+template <class S, bool SHW, bool PER, int DIAG, bool REC, class R>
 __global__ __launch_bounds__(BLOCK) void k_step(Params p, Bufs b, float amp) {
   const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
   const uint32_t c = blk * BLOCK + threadIdx.x;
   const bool active = c < (uint32_t)p.nf;
   double dv[NDIAGP];
   float ke_reg = 0.0f;
-  if (active) {
-    int x, y, z;
-    bool reg;
-    unpack(b.cells[c], x, y, z, reg);
-    const uint32_t idx = (uint32_t)x + p.nx * ((uint32_t)y + p.ny * (uint32_t)z);
-    const float phx = ldo(b.phi, idx);
-    const Nb nb(p, x, y, z);
-    float d[Q], pt[Q];
-    pull<S, SHW>(p, (const S*)b.A, b.phi, idx, nb, phx, d, pt);
-    if (REC) {
-#pragma unroll
-      for (int i = 0; i < Q; ++i) b.rec[(size_t)i * p.nf + c] = d[i];
-    }
-    open_fill(p, x, y, z, amp, b.shape, d);
-    const float omp = b.omega[c];
-    Macro M;
-    macro(p, phx, d, omp, M);
-    b.omega[c] = M.omega;
-    if (REC) {
-      b.rec[(size_t)Q * p.nf + c] = omp;
-      b.rho_box[idx] = M.rho;
-    }
-    if (DIAG == 1) diag_terms(phx, d, M, reg, true, dv);
-    if (DIAG == 2) ke_reg = reg ? 0.5f * M.rho * M.uu : 0.0f;
-    collide_store<S, SHW>(p, (S*)b.B, idx, phx, d, pt, M);
-  } else if (DIAG == 1) {
-    float d[Q] = {};
-    Macro M{};
-    diag_terms(0.f, d, M, false, false, dv);
+  const bool uni = !active || (b.links[active ? c : 0] & LK_UNI);
+  if (__all(uni)) {
+    if (active) step_cell<S, SHW, true, PER, DIAG, REC, R>(p, b, c, amp, dv, ke_reg);
+  } else {
+    if (active) step_cell<S, SHW, false, PER, DIAG, REC, R>(p, b, c, amp, dv, ke_reg);
   }
   if (DIAG == 1) {
+    if (!active) {
+      float d[Q] = {};
+      Macro<R> M{};
+      diag_terms<R>(p, 0.f, d, M, false, false, dv);
+    }
     const int ops[NDIAGP] = {0, 0, 0, 0, 0, 0, 1, 2, 1, 0};
     block_reduce<NDIAGP>(dv, ops, b.part + (size_t)blockIdx.x * NDIAGP);
   }
@@ -410,38 +512,41 @@ __global__ __launch_bounds__(BLOCK) void k_step(Params p, Bufs b, float amp) {
 
 // Moments of the current state (no collision): dense outputs (any may be null)
 // and optionally the diagnostics partials.
-template <class S, bool SHW, bool DIAG>
+template <class S, bool SHW, bool DIAG, class R>
 __global__ __launch_bounds__(BLOCK) void k_moments(Params p, Bufs b, float amp, float* rho_o, float* u_o,
                                                     float* shear_o, float* omega_o, float* sigma_o) {
   const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
   const bool active = c < (uint32_t)p.nf;
   double dv[NDIAGP];
   if (active) {
-    int x, y, z;
-    bool reg;
-    unpack(b.cells[c], x, y, z, reg);
-    const uint32_t idx = (uint32_t)x + p.nx * ((uint32_t)y + p.ny * (uint32_t)z);
+    const uint32_t idx = b.cells[c];
+    const uint32_t lk = b.links[c];
     const float phx = ldo(b.phi, idx);
-    const Nb nb(p, x, y, z);
+    int wc[6] = {0, 0, 0, 0, 0, 0};
+    if (p.anyper) wrap_corr(p, lk, wc);
     float d[Q], pt[Q];
-    pull<S, SHW>(p, (const S*)b.A, b.phi, idx, nb, phx, d, pt);
-    open_fill(p, x, y, z, amp, b.shape, d);
-    Macro M;
-    macro(p, phx, d, b.omega[c], M);
-    if (rho_o) rho_o[idx] = M.rho;
-    if (u_o) { u_o[idx] = M.ux; u_o[(size_t)p.nbox + idx] = M.uy; u_o[2 * (size_t)p.nbox + idx] = M.uz; }
-    if (shear_o) shear_o[idx] = M.shear;
-    if (omega_o) omega_o[idx] = M.omega;
-    if (sigma_o) {
-      const float s = 0.5f * M.omega - 1.0f;
-#pragma unroll
-      for (int k = 0; k < 6; ++k) sigma_o[(size_t)k * p.nbox + idx] = s * M.P[k];
+    pull<S, SHW, true, true>(p, (const S*)b.A, b.phi, idx, lk, wc, phx, d, pt);
+    open_fill(p, idx, lk, amp, b.shape, d);
+    Macro<R> M;
+    macro<R>(p, phx, d, b.omega[c], M);
+    if (rho_o) rho_o[idx] = (float)M.rho;
+    if (u_o) {
+      u_o[idx] = (float)M.ux;
+      u_o[(size_t)p.nbox + idx] = (float)M.uy;
+      u_o[2 * (size_t)p.nbox + idx] = (float)M.uz;
     }
-    if (DIAG) diag_terms(phx, d, M, reg, true, dv);
+    if (shear_o) shear_o[idx] = M.shear;
+    if (omega_o) omega_o[idx] = (float)M.omega;
+    if (sigma_o) {
+      const R s = (R)0.5 * M.omega - (R)1;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) sigma_o[(size_t)k * p.nbox + idx] = (float)(s * M.P[k]);
+    }
+    if (DIAG) diag_terms<R>(p, phx, d, M, (lk & LK_REG) != 0, true, dv);
   } else if (DIAG) {
     float d[Q] = {};
-    Macro M{};
-    diag_terms(0.f, d, M, false, false, dv);
+    Macro<R> M{};
+    diag_terms<R>(p, 0.f, d, M, false, false, dv);
   }
   if (DIAG) {
     const int ops[NDIAGP] = {0, 0, 0, 0, 0, 0, 1, 2, 1, 0};
@@ -479,56 +584,58 @@ template <class S, bool SHW>
 __global__ __launch_bounds__(BLOCK) void k_init(Params p, Bufs b, float omega0) {
   const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
   if (c >= (uint32_t)p.nf) return;
-  int x, y, z;
-  bool reg;
-  unpack(b.cells[c], x, y, z, reg);
-  const uint32_t idx = (uint32_t)x + p.nx * ((uint32_t)y + p.ny * (uint32_t)z);
+  const uint32_t idx = b.cells[c];
+  const uint32_t lk = b.links[c];
   const float phx = ldo(b.phi, idx);
-  const Nb nb(p, x, y, z);
-  float pt[Q];
-  pt[0] = phx;
-#define LBM_PT(I)                                                               \
-  {                                                                             \
-    bool out;                                                                   \
-    const int o = nb.template off<Dir<I>::cx, Dir<I>::cy, Dir<I>::cz>(out);     \
-    const float pn = ldo(b.phi, idx + (uint32_t)o);                             \
-    pt[I] = (out || pn == 0.0f) ? phx : pn;                                     \
-  }
-  LBM_PT(1) LBM_PT(2) LBM_PT(3) LBM_PT(4) LBM_PT(5) LBM_PT(6) LBM_PT(7) LBM_PT(8) LBM_PT(9)
-  LBM_PT(10) LBM_PT(11) LBM_PT(12) LBM_PT(13) LBM_PT(14) LBM_PT(15) LBM_PT(16) LBM_PT(17) LBM_PT(18)
-#undef LBM_PT
+  int wc[6] = {0, 0, 0, 0, 0, 0};
+  if (p.anyper) wrap_corr(p, lk, wc);
   S* B = (S*)b.B;
-#pragma unroll
-  for (int i = 0; i < Q; ++i) Store<S>::st(B, (uint32_t)i * p.nbox + idx, SHW ? wgt(i) * (pt[i] - 1.0f) : 0.0f, i);
+  const float ks = (float)p.ks;
+  Store<S>::st(B, idx, SHW ? ks * kw(0) * (phx - 1.0f) : 0.0f, 0);
+  sfor<1, Q>([&](auto ic) {
+    constexpr int I = decltype(ic)::value;
+    // porosity of x + c_I (phi(x) when that link bounces, i.e. when the pull of
+    // the opposite direction bounces)
+    const bool bb = (lk >> OPP[I]) & 1u;
+    const float pn = bb ? phx : ldo(b.phi, idx + (uint32_t)nb_off<CX[I], CY[I], CZ[I]>(p, wc));
+    Store<S>::st(B, (uint32_t)I * p.nbox + idx, SHW ? ks * kw(I) * (pn - 1.0f) : 0.0f, I);
+  });
   b.omega[c] = omega0;
 }
 
+// Whether the pull of direction I at this cell reads an open-face unknown
+// (source outside the inflow/outflow face and not outside a wall face).
+template <int I>
+__device__ __forceinline__ bool open_unknown(const Params& p, uint32_t idx, uint32_t lk) {
+  if (CX[I] == 0) return false;
+  if (CX[I] == 1 && !(lk & LK_IN)) return false;
+  if (CX[I] == -1 && !(lk & LK_OUT)) return false;
+  const uint32_t q = div_nx(p, idx);  // y + ny z
+  const uint32_t z = q / (uint32_t)p.ny, y = q - z * (uint32_t)p.ny;
+  const int sy = (int)y - CY[I], sz = (int)z - CZ[I];
+  const bool wall = (!p.py && (sy < 0 || sy >= p.ny)) || (!p.pz && (sz < 0 || sz >= p.nz));
+  return !wall;
+}
+
 // State out: the pulled (pre-collision) stored values as FP32, [19][nf]; the
-// host adds the rest value back in FP64.  Open-face unknowns are written as NaN.
+// host converts them back to populations in FP64.  Open-face unknowns are NaN.
 template <class S>
 __global__ __launch_bounds__(BLOCK) void k_gather_state(Params p, Bufs b, float* out) {
   const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
   if (c >= (uint32_t)p.nf) return;
-  int x, y, z;
-  bool reg;
-  unpack(b.cells[c], x, y, z, reg);
-  const uint32_t idx = (uint32_t)x + p.nx * ((uint32_t)y + p.ny * (uint32_t)z);
-  const Nb nb(p, x, y, z);
+  const uint32_t idx = b.cells[c];
+  const uint32_t lk = b.links[c];
+  int wc[6] = {0, 0, 0, 0, 0, 0};
+  if (p.anyper) wrap_corr(p, lk, wc);
   const S* A = (const S*)b.A;
   out[c] = Store<S>::ld(A, idx, 0);
-#define LBM_G(I)                                                                          \
-  {                                                                                       \
-    bool o_;                                                                              \
-    const int o = nb.template off<-Dir<I>::cx, -Dir<I>::cy, -Dir<I>::cz>(o_);             \
-    const uint32_t src = idx + (uint32_t)o;                                               \
-    const bool bb = o_ || ldo(b.phi, src) == 0.0f;                                        \
-    const bool unk = nb.template open_only<-Dir<I>::cx, -Dir<I>::cy, -Dir<I>::cz>(p, x);  \
-    const uint32_t e = bb ? (uint32_t)Dir<I>::opp * p.nbox + idx : (uint32_t)I * p.nbox + src; \
-    out[(size_t)I * p.nf + c] = unk ? __builtin_nanf("") : Store<S>::ld(A, e, I);         \
-  }
-  LBM_G(1) LBM_G(2) LBM_G(3) LBM_G(4) LBM_G(5) LBM_G(6) LBM_G(7) LBM_G(8) LBM_G(9)
-  LBM_G(10) LBM_G(11) LBM_G(12) LBM_G(13) LBM_G(14) LBM_G(15) LBM_G(16) LBM_G(17) LBM_G(18)
-#undef LBM_G
+  sfor<1, Q>([&](auto ic) {
+    constexpr int I = decltype(ic)::value;
+    const bool bb = (lk >> I) & 1u;
+    const uint32_t src = idx + (uint32_t)nb_off<-CX[I], -CY[I], -CZ[I]>(p, wc);
+    const uint32_t e = bb ? (uint32_t)OPP[I] * p.nbox + idx : (uint32_t)I * p.nbox + src;
+    out[(size_t)I * p.nf + c] = open_unknown<I>(p, idx, lk) ? __builtin_nanf("") : Store<S>::ld(A, e, I);
+  });
 }
 
 // State in: inverse of k_gather_state; each stored slot that some consumer
@@ -537,26 +644,19 @@ template <class S>
 __global__ __launch_bounds__(BLOCK) void k_scatter_state(Params p, Bufs b, const float* in) {
   const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
   if (c >= (uint32_t)p.nf) return;
-  int x, y, z;
-  bool reg;
-  unpack(b.cells[c], x, y, z, reg);
-  const uint32_t idx = (uint32_t)x + p.nx * ((uint32_t)y + p.ny * (uint32_t)z);
-  const Nb nb(p, x, y, z);
+  const uint32_t idx = b.cells[c];
+  const uint32_t lk = b.links[c];
+  int wc[6] = {0, 0, 0, 0, 0, 0};
+  if (p.anyper) wrap_corr(p, lk, wc);
   S* A = (S*)b.B;
   Store<S>::st(A, idx, in[c], 0);
-#define LBM_S(I)                                                                          \
-  {                                                                                       \
-    bool o_;                                                                              \
-    const int o = nb.template off<-Dir<I>::cx, -Dir<I>::cy, -Dir<I>::cz>(o_);             \
-    const uint32_t src = idx + (uint32_t)o;                                               \
-    const bool bb = o_ || ldo(b.phi, src) == 0.0f;                                        \
-    const bool unk = nb.template open_only<-Dir<I>::cx, -Dir<I>::cy, -Dir<I>::cz>(p, x);  \
-    const uint32_t e = bb ? (uint32_t)Dir<I>::opp * p.nbox + idx : (uint32_t)I * p.nbox + src; \
-    if (!unk) Store<S>::st(A, e, in[(size_t)I * p.nf + c], I);                            \
-  }
-  LBM_S(1) LBM_S(2) LBM_S(3) LBM_S(4) LBM_S(5) LBM_S(6) LBM_S(7) LBM_S(8) LBM_S(9)
-  LBM_S(10) LBM_S(11) LBM_S(12) LBM_S(13) LBM_S(14) LBM_S(15) LBM_S(16) LBM_S(17) LBM_S(18)
-#undef LBM_S
+  sfor<1, Q>([&](auto ic) {
+    constexpr int I = decltype(ic)::value;
+    const bool bb = (lk >> I) & 1u;
+    const uint32_t src = idx + (uint32_t)nb_off<-CX[I], -CY[I], -CZ[I]>(p, wc);
+    const uint32_t e = bb ? (uint32_t)OPP[I] * p.nbox + idx : (uint32_t)I * p.nbox + src;
+    if (!open_unknown<I>(p, idx, lk)) Store<S>::st(A, e, in[(size_t)I * p.nf + c], I);
+  });
 }
 
 // Plain streaming copy (16-byte vectors), the achievable-bandwidth reference.

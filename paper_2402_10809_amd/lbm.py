@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 
 LBM_OK, LBM_E_INVALID, LBM_E_DEVICE, LBM_E_UNSTABLE, LBM_E_STATE, LBM_E_WORKSPACE = range(6)
 STORAGE = {"fp32": 0, "fp16": 1, "bf16": 2}
+ARITH = {"auto": 0, "fp32": 1, "fp64": 2}
 NDIAG = 11
 DIAG_NAMES = ["mass", "mom_x", "mom_y", "mom_z", "ke", "ke_region", "max_u", "min_omega", "max_omega",
               "nonfinite", "t"]
@@ -27,7 +28,7 @@ DIAG_NAMES = ["mass", "mom_x", "mom_y", "mom_z", "ke", "ke_region", "max_u", "mi
 
 class lbm_grid(ct.Structure):
     _fields_ = [("nx", ct.c_int), ("ny", ct.c_int), ("nz", ct.c_int), ("periodic", ct.c_int * 3),
-                ("storage", ct.c_int), ("shift_mode", ct.c_int)]
+                ("storage", ct.c_int), ("shift_mode", ct.c_int), ("arith", ct.c_int)]
 
 
 class lbm_rheology(ct.Structure):
@@ -129,7 +130,7 @@ class Solver:
     adjoint_T/ckpt: reserve workspace for lbm_adjoint runs of up to adjoint_T steps.
     """
 
-    def __init__(self, solid, phi, *, periodic=(False, False, False), storage="fp32", shift_mode=0,
+    def __init__(self, solid, phi, *, periodic=(False, False, False), storage="fp32", shift_mode=0, arith="auto",
                  region=None, rheology=None, porous=None, inlet=None, outlet=None, adjoint_T=0, ckpt=64,
                  device=None, stream=None):
         import torch
@@ -147,6 +148,7 @@ class Solver:
             g.periodic[a] = int(bool(periodic[a]))
         g.storage = STORAGE[storage]
         g.shift_mode = int(shift_mode)
+        g.arith = ARITH[arith]
         self.grid = g
         self.storage = storage
         rh = dict(nu0=0.1, nu_inf=0.01, lam=50.0, n=0.36, a=2.0) if rheology is None else rheology
