@@ -83,9 +83,12 @@ typedef enum { LBM_STORE_FP32 = 0, LBM_STORE_FP16 = 1, LBM_STORE_BF16 = 2 } lbm_
  * transcendentals are FP32 in every mode).  FP32 rounding of the per-cell
  * scalars (velocity, relaxation rate) is common to all 19 directions and acts
  * as a small persistent momentum source; in slowly evolving flows it
- * accumulates to ~1e-5 of the velocity, so FP32 storage computes in FP64 by
- * default (same issue rate as unpacked FP32 on CDNA).  Reduced-precision
- * storage is limited by its own rounding and computes in FP32. */
+ * accumulates to ~1e-5 of the velocity.  AUTO with FP32 storage therefore
+ * computes in FP32 and then projects each cell's output onto the intended
+ * momentum, evaluated in FP64 on the FP32 values (exact conservation up to the
+ * final rounding of each stored value).  FP32 = plain FP32, FP64 = the whole
+ * collision in FP64 (FP32 storage only).  Reduced-precision storage is limited
+ * by its own rounding and computes in plain FP32. */
 typedef enum { LBM_ARITH_AUTO = 0, LBM_ARITH_FP32 = 1, LBM_ARITH_FP64 = 2 } lbm_arith;
 
 typedef struct {
@@ -94,8 +97,8 @@ typedef struct {
   int storage;         /* lbm_storage */
   int shift_mode;      /* 0: stored value f_i - w_i phi(consumer cell) (default)
                           1: stored value f_i - w_i */
-  int arith;           /* lbm_arith: AUTO = FP64 with FP32 storage, FP32 with FP16/BF16
-                          storage; FP64 is only available with FP32 storage */
+  int arith;           /* lbm_arith: AUTO = projected FP32 with FP32 storage, FP32 with
+                          FP16/BF16 storage; FP64 is only available with FP32 storage */
 } lbm_grid;
 
 /* Carreau-Yasuda law (eq. carreau) in kinematic lattice units:

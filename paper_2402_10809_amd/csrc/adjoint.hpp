@@ -71,11 +71,12 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, float am
   const R phx = (R)phx_f;
   const R iphi = fast_rcp(phx);
   const Sums<R> sm = moment_sums<R>(d);
-  const R iU = (R)p.iU;
+  const auto& kc = p.d;
+  const R iU = kc.iU;
   const R S = phx + sm.s * iU;  // sum f = phi rho
   const R mx = sm.mx * iU, my = sm.my * iU, mz = sm.mz * iU;
   const R om1 = 1.0 - phx;
-  const R kn = (R)p.kcd * (R)p.nu_d;
+  const R kn = kc.kcd * kc.nu_d;
   const R dark = kn * om1 * om1 * iphi * iphi;  // phi nu / k
   const R C0 = 0.5 + 0.25 * dark;
   const R D = phx * dark;                       // phi^2 nu / k
@@ -85,17 +86,17 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, float am
   const R Nn = rsqrt_(M.P[0] * M.P[0] + M.P[1] * M.P[1] + M.P[2] * M.P[2] +
                       2.0 * (M.P[3] * M.P[3] + M.P[4] * M.P[4] + M.P[5] * M.P[5]));
   const float shear = M.shear;
-  const float lg = (float)p.lam * shear;
+  const float lg = p.f.lam * shear;
   float la, dla;  // (lambda g)^a and its derivative in g
-  if (p.cy_a2) { la = lg * lg; dla = 2.0f * (float)p.lam * lg; }
+  if (p.cy_a2) { la = lg * lg; dla = 2.0f * p.f.lam * lg; }
   else {
-    la = lg > 0.0f ? __builtin_amdgcn_exp2f((float)p.cy_a * __builtin_amdgcn_logf(lg)) : 0.0f;
-    dla = (lg > 0.0f && shear > 0.0f) ? (float)p.cy_a * la / shear : 0.0f;
+    la = lg > 0.0f ? __builtin_amdgcn_exp2f(p.f.cy_a * __builtin_amdgcn_logf(lg)) : 0.0f;
+    dla = (lg > 0.0f && shear > 0.0f) ? p.f.cy_a * la / shear : 0.0f;
   }
   const float hh = 1.0f + la;
-  const float fac = __builtin_amdgcn_exp2f((float)p.cy_e * __builtin_amdgcn_logf(hh));
-  const R nu = (R)p.nu_inf + (R)(p.nu0 - p.nu_inf) * (R)fac;
-  const R dnu = (R)(p.nu0 - p.nu_inf) * (R)p.cy_e * (R)fac / (R)hh * (R)dla;
+  const float fac = __builtin_amdgcn_exp2f(p.f.cy_e * __builtin_amdgcn_logf(hh));
+  const R nu = kc.nu_inf + kc.dnu * (R)fac;
+  const R dnu = kc.dnu * kc.cy_e * (R)fac / (R)hh * (R)dla;
 
   // ---- gather the adjoint of the post-collision populations --------------
   R qh[Q];
@@ -205,7 +206,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, float am
   const R iS = fast_rcp(S);
   const R mhx = vhx * iS, mhy = vhy * iS, mhz = vhz * iS;
   R Sh = -(vhx * mx + vhy * my + vhz * mz) * iS * iS;
-  phh -= (vhx * (R)p.gx + vhy * (R)p.gy + vhz * (R)p.gz) * 0.5 * iphi * iphi;
+  phh -= (vhx * kc.gx + vhy * kc.gy + vhz * kc.gz) * 0.5 * iphi * iphi;
   // rho = S / phi
   Sh += rhoh * iphi;
   phh -= rhoh * rho * iphi;
@@ -236,7 +237,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, float am
     fh[5] += nzh; fh[6] -= nzh; fh[15] += nzh; fh[16] -= nzh; fh[17] -= nzh; fh[18] += nzh;
     fh[1] = 0.0; fh[7] = 0.0; fh[9] = 0.0; fh[11] = 0.0; fh[13] = 0.0;
   } else if (outl) {
-    const R ro = (R)p.rho_out;
+    const R ro = kc.rho_out;
     fh[1] += fh[2]; fh[7] += fh[8]; fh[9] += fh[10]; fh[11] += fh[12]; fh[13] += fh[14];
     const R uxh = -ro * (1.0 / 3.0) * fh[2] - ro * (1.0 / 6.0) * (fh[8] + fh[10] + fh[12] + fh[14]);
     const R nyh = 0.5 * (fh[8] - fh[10]), nzh = 0.5 * (fh[12] - fh[14]);

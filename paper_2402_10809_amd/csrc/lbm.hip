@@ -86,8 +86,11 @@ Layout make_layout(const lbm_grid& g, int64_t nf, int T, int ckpt) {
 struct TF32 { using T = float; };
 struct TF16 { using T = _Float16; };
 struct TBF16 { using T = __bf16; };
-struct RF32 { using T = float; };
-struct RF64 { using T = double; };
+// Arithmetic of the collision: FP32, FP32 with the FP64 momentum projection,
+// or FP64.
+struct RF32 { using T = float; static constexpr bool proj = false; };
+struct RF32P { using T = float; static constexpr bool proj = true; };
+struct RF64 { using T = double; static constexpr bool proj = false; };
 
 template <class Fn>
 void with_storage(int storage, int shw, Fn&& fn) {
@@ -100,13 +103,16 @@ void with_storage(int storage, int shw, Fn&& fn) {
   }
 }
 
-// Storage type, shift mode and arithmetic type: FP64 arithmetic only with FP32 storage.
+// Storage type, shift mode and arithmetic: the FP64 and projected forms only
+// exist for FP32 storage.  mode: 0 FP32, 1 FP32 + projection, 2 FP64.
 template <class Fn>
-void with_config(int storage, int shw, bool f64, Fn&& fn) {
+void with_config(int storage, int shw, int mode, Fn&& fn) {
   with_storage(storage, shw, [&](auto tag, auto sh) {
     using S = typename decltype(tag)::T;
     if constexpr (std::is_same<S, float>::value) {
-      if (f64) fn(tag, sh, RF64{}); else fn(tag, sh, RF32{});
+      if (mode == 2) fn(tag, sh, RF64{});
+      else if (mode == 1) fn(tag, sh, RF32P{});
+      else fn(tag, sh, RF32{});
     } else {
       fn(tag, sh, RF32{});
     }
@@ -150,7 +156,7 @@ struct lbm_ctx {
   bool poisoned = false;
   Params P{};
   float omega0 = 1.0f;
-  bool f64 = true;                // FP64 arithmetic for the collision
+  int amode = 1;                  // collision arithmetic: 0 FP32, 1 FP32 + projection, 2 FP64
 };
 
 namespace {
@@ -311,22 +317,26 @@ lbm_status launch_step(lbm_ctx* c, int diag, float* rec, float* rho_box) {
     b.rec = rec;
     b.rho_box = rho_box;
   }
-  with_config(c->grid.storage, c->grid.shift_mode, c->f64, [&](auto tag, auto shw, auto rt) {
+  with_config(c->grid.storage, c->grid.shift_mode, c->amode, [&](auto tag, auto shw, auto rt) {
     using S = typename decltype(tag)::T;
     using R = typename decltype(rt)::T;
+    constexpr bool PJ = decltype(rt)::proj;
     constexpr bool SH = decltype(shw)::value;
     auto go = [&](auto per) {
       constexpr bool PER = decltype(per)::value;
       if (rec) {
         if constexpr (std::is_same<S, float>::value && !SH)
-          hipLaunchKernelGGL((k_step<S, false, PER, 0, true, R>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b,
-                             amp);
+          hipLaunchKernelGGL((k_step<S, false, PER, 0, true, R, PJ>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P,
+                             b, amp);
       } else if (diag == 0) {
-        hipLaunchKernelGGL((k_step<S, SH, PER, 0, false, R>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, amp);
+        hipLaunchKernelGGL((k_step<S, SH, PER, 0, false, R, PJ>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b,
+                           amp);
       } else if (diag == 1) {
-        hipLaunchKernelGGL((k_step<S, SH, PER, 1, false, R>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, amp);
+        hipLaunchKernelGGL((k_step<S, SH, PER, 1, false, R, PJ>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b,
+                           amp);
       } else {
-        hipLaunchKernelGGL((k_step<S, SH, PER, 2, false, R>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, amp);
+        hipLaunchKernelGGL((k_step<S, SH, PER, 2, false, R, PJ>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b,
+                           amp);
       }
     };
     if (c->P.anyper) go(std::true_type{}); else go(std::false_type{});
@@ -365,7 +375,7 @@ lbm_status check_stable(lbm_ctx* c, const double* dg) {
 lbm_status moments_launch(lbm_ctx* c, bool diag, float* rho, float* u, float* shear, float* omega, float* sigma) {
   Bufs b = bufs(c, c->cur, nullptr);
   const float amp = (float)amplitude(c, c->t);
-  with_config(c->grid.storage, c->grid.shift_mode, c->f64, [&](auto tag, auto shw, auto rt) {
+  with_config(c->grid.storage, c->grid.shift_mode, c->amode == 2 ? 2 : 0, [&](auto tag, auto shw, auto rt) {
     using S = typename decltype(tag)::T;
     using R = typename decltype(rt)::T;
     constexpr bool SH = decltype(shw)::value;
@@ -499,13 +509,23 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* solid, const float* p
   P.outlet = (op && op->outlet) ? 1 : 0;
   div_magic((uint32_t)grid->nx, P.dmag, P.dsh1, P.dsh2);
   for (int i = 0; i < Q; ++i) P.plb[i] = (uint32_t)((size_t)i * c->nbox * store_bytes(grid->storage));
-  P.U = c->U; P.iU = 1.0 / c->U; P.ks = c->U / 36.0;
-  P.nu0 = rh->nu0; P.nu_inf = rh->nu_inf; P.lam = rh->lambda;
-  P.cy_e = (rh->n - 1.0) / rh->a; P.cy_a = rh->a; P.cy_a2 = rh->a == 2.0 ? 1 : 0;
-  P.nu_d = po->nu_darcy; P.kcd = po->kc / (po->d * po->d); P.forch = po->forchheimer ? 1 : 0;
-  P.gx = po->g[0]; P.gy = po->g[1]; P.gz = po->g[2];
-  P.rho_out = (op && op->outlet) ? op->rho_out : 1.0;
-  c->f64 = grid->arith == LBM_ARITH_FP64 || (grid->arith == LBM_ARITH_AUTO && grid->storage == LBM_STORE_FP32);
+  {
+    Params::K<double> k{};
+    k.U = c->U; k.iU = 1.0 / c->U; k.ks = c->U / 36.0;
+    k.nu0 = rh->nu0; k.nu_inf = rh->nu_inf; k.dnu = rh->nu0 - rh->nu_inf;
+    k.lam = rh->lambda; k.cy_e = (rh->n - 1.0) / rh->a; k.cy_a = rh->a;
+    k.nu_d = po->nu_darcy; k.kcd = po->kc / (po->d * po->d);
+    k.gx = po->g[0]; k.gy = po->g[1]; k.gz = po->g[2];
+    k.rho_out = (op && op->outlet) ? op->rho_out : 1.0;
+    P.d = k;
+    P.f = Params::K<float>{(float)k.U, (float)k.iU, (float)k.ks, (float)k.nu0, (float)k.nu_inf, (float)k.dnu,
+                           (float)k.lam, (float)k.cy_e, (float)k.cy_a, (float)k.nu_d, (float)k.kcd,
+                           (float)k.gx, (float)k.gy, (float)k.gz, (float)k.rho_out};
+  }
+  P.cy_a2 = rh->a == 2.0 ? 1 : 0;
+  P.forch = po->forchheimer ? 1 : 0;
+  c->amode = grid->arith == LBM_ARITH_FP64 ? 2
+             : (grid->arith == LBM_ARITH_AUTO && grid->storage == LBM_STORE_FP32) ? 1 : 0;
   c->omega0 = (float)(2.0 / (6.0 * rh->nu0 + 1.0));
 
   auto bail = [&](lbm_status st) { delete c; return st; };

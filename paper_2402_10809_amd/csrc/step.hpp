@@ -50,14 +50,26 @@ struct Params {
   int inlet, outlet;
   uint32_t dmag, dsh1, dsh2;  // division by nx (Granlund-Montgomery)
   uint32_t plb[Q];            // byte offset of population plane i (i * nbox * sizeof(storage))
-  // physical constants (converted to the kernel's arithmetic type on use)
-  double U, iU, ks;            // storage unit, 1/U, U/36
-  double nu0, nu_inf, lam, cy_e, cy_a;  // Carreau-Yasuda; cy_e = (n-1)/a
-  int cy_a2;                            // a == 2: (lambda g)^a is one multiply
-  double nu_d, kcd;                     // Darcy viscosity, kc/d^2
-  int forch;
-  double gx, gy, gz;
-  double rho_out;
+  int cy_a2;                   // a == 2: (lambda g)^a is one multiply
+  int forch;                   // Forchheimer drag on
+  // physical constants in both precisions (the kernels read the one they
+  // compute in, straight from the kernel arguments)
+  template <class T>
+  struct K {
+    T U, iU, ks;                 // storage unit, 1/U, U/36
+    T nu0, nu_inf, dnu;          // Carreau-Yasuda limits, nu0 - nu_inf
+    T lam, cy_e, cy_a;           // lambda, (n-1)/a, a
+    T nu_d, kcd;                 // Darcy viscosity, kc/d^2
+    T gx, gy, gz;                // body force
+    T rho_out;
+  };
+  K<float> f;
+  K<double> d;
+  template <class T>
+  __device__ __forceinline__ const K<T>& k() const {
+    if constexpr (std::is_same<T, double>::value) return d;
+    else return f;
+  }
 };
 
 struct Bufs {
@@ -181,7 +193,7 @@ __device__ __forceinline__ void pull(const Params& p, const S* __restrict__ A, c
     }
   });
   if (SHW) {
-    const float s = (float)p.ks * (phx - 1.0f);
+    const float s = p.f.ks * (phx - 1.0f);
 #pragma unroll
     for (int i = 0; i < Q; ++i) v[i] -= kw(i) * s;
   }
@@ -194,7 +206,7 @@ __device__ __forceinline__ void open_fill(const Params& p, uint32_t idx, uint32_
   const bool in = (lk & LK_IN) != 0;
   const bool outl = (lk & LK_OUT) != 0;
   if (!(in || outl)) return;
-  const float U = (float)p.U, iU = (float)p.iU;
+  const float U = p.f.U, iU = p.f.iU;
   const float s0 = d[0] + d[3] + d[4] + d[5] + d[6] + d[15] + d[16] + d[17] + d[18];
   const float ny_ = 0.5f * (d[3] - d[4] + d[15] - d[16] + d[17] - d[18]);
   const float nz_ = 0.5f * (d[5] - d[6] + d[15] - d[16] - d[17] + d[18]);
@@ -204,7 +216,7 @@ __device__ __forceinline__ void open_fill(const Params& p, uint32_t idx, uint32_
   const float rin = (1.0f + (s0 + 2.0f * sm) * iU) / (1.0f - uin);
   // outflow: prescribed density, normal velocity from mass and the known half
   const float sp = d[1] + d[7] + d[9] + d[11] + d[13];
-  const float ro = (float)p.rho_out;
+  const float ro = p.f.rho_out;
   const float uout = (1.0f + (s0 + 2.0f * sp) * iU) / ro - 1.0f;
   const float r3i = U * rin * uin * (1.0f / 3.0f), r6i = U * rin * uin * (1.0f / 6.0f);
   const float r3o = U * ro * uout * (1.0f / 3.0f), r6o = U * ro * uout * (1.0f / 6.0f);
@@ -270,20 +282,21 @@ struct Macro {
 template <class R>
 __device__ __forceinline__ void macro(const Params& p, float phx_f, const float d[Q], float omega_prev, Macro<R>& M) {
   const Sums<R> s = moment_sums<R>(d);
+  const auto& kc = p.k<R>();
   const R phx = (R)phx_f;
   const R one = (R)1;
   const R iphi = fast_rcp(phx);
-  const R rm1 = s.s * fast_rcp((R)p.U * phx);  // rho - 1
+  const R rm1 = s.s * fast_rcp(kc.U * phx);  // rho - 1
   const R rho = one + rm1;
   const R pr = phx * rho;                      // phi rho = sum f
-  const R iUS = fast_rcp((R)p.U * pr);
+  const R iUS = fast_rcp(kc.U * pr);
   const R hg = (R)0.5 * iphi;
-  const R gx = (R)p.gx, gy = (R)p.gy, gz = (R)p.gz;
+  const R gx = kc.gx, gy = kc.gy, gz = kc.gz;
   const R vx = s.mx * iUS + gx * hg, vy = s.my * iUS + gy * hg, vz = s.mz * iUS + gz * hg;
   // 1/k = (kc/d^2) (1 - phi)^2 / phi^3
   const R om = one - phx;
-  const R invk = (R)p.kcd * om * om * iphi * iphi * iphi;
-  const R dark = phx * (R)p.nu_d * invk;      // phi nu / k
+  const R invk = kc.kcd * om * om * iphi * iphi * iphi;
+  const R dark = phx * kc.nu_d * invk;      // phi nu / k
   const R C0 = (R)0.5 + (R)0.25 * dark;
   R den, fcoef;
   if (p.forch) {
@@ -305,7 +318,7 @@ __device__ __forceinline__ void macro(const Params& p, float phx_f, const float 
   // Pi = sum (f - f_eq) c c + (F u + u F)/2
   //    = sum(v c c)/U - [phi (rho-1)/3 I + phi rho u u] + (F u + u F)/2
   const R iso = phx * rm1 * (R)(1.0 / 3.0);
-  const R iU = (R)p.iU;
+  const R iU = kc.iU;
   const R h = (R)0.5;
   M.P[0] = s.xx * iU - iso - pr * ux * ux + Fx * ux;
   M.P[1] = s.yy * iU - iso - pr * uy * uy + Fy * uy;
@@ -318,12 +331,12 @@ __device__ __forceinline__ void macro(const Params& p, float phx_f, const float 
   const float rhof = (float)rho;
   const float shear = 3.0f * omega_prev * __builtin_sqrtf(pn2) * fast_rcp(rhof);
   // Carreau-Yasuda: nu = nu_inf + (nu0 - nu_inf) (1 + (lambda g)^a)^((n-1)/a)
-  const float lg = (float)p.lam * shear;
+  const float lg = p.f.lam * shear;
   float la;
   if (p.cy_a2) la = lg * lg;
-  else la = lg > 0.0f ? __builtin_amdgcn_exp2f((float)p.cy_a * __builtin_amdgcn_logf(lg)) : 0.0f;
-  const float fac = __builtin_amdgcn_exp2f((float)p.cy_e * __builtin_amdgcn_logf(1.0f + la));
-  const R nu = (R)p.nu_inf + (R)(p.nu0 - p.nu_inf) * (R)fac;
+  else la = lg > 0.0f ? __builtin_amdgcn_exp2f(p.f.cy_a * __builtin_amdgcn_logf(lg)) : 0.0f;
+  const float fac = __builtin_amdgcn_exp2f(p.f.cy_e * __builtin_amdgcn_logf(1.0f + la));
+  const R nu = kc.nu_inf + kc.dnu * (R)fac;
   // omega = 2 rho c_s^2 / (2 mu + rho c_s^2) = 2 rho / (6 nu + rho)
   M.omega = (R)2 * rho * fast_rcp((R)6 * nu + rho);
   M.rho = rho;
@@ -338,7 +351,16 @@ __device__ __forceinline__ void macro(const Params& p, float phx_f, const float 
 // (omega (A0 + C e^2) - K3 u.F + K9 e h) is shared and the odd part
 // (omega B e + K3 h) flips sign; both are per unit weight, scaled by the exact
 // U w_i.
-template <class S, bool SHW, bool UNI, class R>
+//
+// PROJ (FP32 arithmetic with FP32 storage): rounding of the per-cell scalars
+// (u, omega, ...) is common to all 19 directions, so the collision's momentum
+// change picks up a small relative error that repeats every step and
+// accumulates in slowly evolving flows.  The projection evaluates, in FP64 on
+// the FP32 values, the momentum the outputs actually carry and moves the
+// difference to the intended momentum (input momentum + force + porosity-jump
+// momentum) onto the three axis pairs, leaving only the final rounding of
+// each stored value.
+template <class S, bool SHW, bool UNI, class R, bool PROJ>
 __device__ __forceinline__ void collide_store(const Params& p, S* __restrict__ B, uint32_t idx, float phx_f,
                                               const float d[Q], const float pt[Q], const Macro<R>& M) {
   const R phx = (R)phx_f;
@@ -351,31 +373,20 @@ __device__ __forceinline__ void collide_store(const Params& p, S* __restrict__ B
   const R uF = M.ux * M.Fx + M.uy * M.Fy + M.uz * M.Fz;
   const R keep = (R)1 - om;
   const R ev0 = om * A0 - K3 * uF;
-  const R shw = phx - (R)1;
-  const R ks = (R)p.ks;
+  const R ks = p.k<R>().ks;
   const R omC = om * Cc, omB = om * Bc;
-  // uniform porosity: no jump; the shift-mode-1 term is the same for every link
-  const R ev0u = SHW && UNI ? ev0 + shw : ev0;
-  const uint32_t ib = idx * (uint32_t)sizeof(S);
-  {
-    R t = ev0u;
-    if (!UNI) t += M.rm1 * ((R)pt[0] - phx) + (SHW ? shw : (R)0);
-    st_pop(B, ib, (float)rfma(ks * (R)kw(0), t, keep * (R)d[0]));
-  }
+  // porosity-jump term per unit weight: (rho - 1)(phi~_i - phi)
+  auto jump = [&](int i) -> R { return UNI ? (R)0 : M.rm1 * ((R)pt[i] - phx); };
+  float o[Q];
+  o[0] = (float)rfma(ks * (R)kw(0), ev0 + jump(0), keep * (R)d[0]);
   auto pair = [&](auto ic, R e, R h) {
     constexpr int I = decltype(ic)::value;
     constexpr int J = OPP[I];
-    const R ev = ev0u + omC * e * e + K9 * e * h;
+    const R ev = ev0 + omC * e * e + K9 * e * h;
     const R od = omB * e + K3 * h;
-    R ti = ev + od, tj = ev - od;
-    if (!UNI) {
-      ti += M.rm1 * ((R)pt[I] - phx);
-      tj += M.rm1 * ((R)pt[J] - phx);
-      if (SHW) { ti += (R)pt[I] - (R)1; tj += (R)pt[J] - (R)1; }
-    }
     const R kk = ks * (R)kw(I);
-    st_pop(B, p.plb[I] + ib, (float)rfma(kk, ti, keep * (R)d[I]));
-    st_pop(B, p.plb[J] + ib, (float)rfma(kk, tj, keep * (R)d[J]));
+    o[I] = (float)rfma(kk, ev + od + jump(I), keep * (R)d[I]);
+    o[J] = (float)rfma(kk, ev - od + jump(J), keep * (R)d[J]);
   };
   pair(std::integral_constant<int, 1>{}, M.ux, M.Fx);
   pair(std::integral_constant<int, 3>{}, M.uy, M.Fy);
@@ -386,6 +397,41 @@ __device__ __forceinline__ void collide_store(const Params& p, S* __restrict__ B
   pair(std::integral_constant<int, 13>{}, M.ux - M.uz, M.Fx - M.Fz);
   pair(std::integral_constant<int, 15>{}, M.uy + M.uz, M.Fy + M.Fz);
   pair(std::integral_constant<int, 17>{}, M.uy - M.uz, M.Fy - M.Fz);
+  if constexpr (PROJ) {
+    // momentum in and out (pair differences are exact in FP64)
+    const Sums<double> si = moment_sums<double>(d);
+    const Sums<double> so = moment_sums<double>(o);
+    const double U = p.d.U;
+    double tx = si.mx + U * (double)M.Fx, ty = si.my + U * (double)M.Fy, tz = si.mz + U * (double)M.Fz;
+    if (!UNI) {
+      const double rm1 = (double)M.rm1, ph = (double)phx_f;
+      double jx = 0.0, jy = 0.0, jz = 0.0;
+      sfor<1, Q>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        const double jt = (double)kw(I) * ((double)pt[I] - ph);
+        if (CX[I]) jx += CX[I] * jt;
+        if (CY[I]) jy += CY[I] * jt;
+        if (CZ[I]) jz += CZ[I] * jt;
+      });
+      const double kr = p.d.ks * rm1;
+      tx += kr * jx; ty += kr * jy; tz += kr * jz;
+    }
+    // the axis pairs carry 2 (U w) = 2 ks * 2 per unit change of f_i - f_opp
+    const double rx = 0.5 * (tx - so.mx), ry = 0.5 * (ty - so.my), rz = 0.5 * (tz - so.mz);
+    o[1] = (float)((double)o[1] + rx); o[2] = (float)((double)o[2] - rx);
+    o[3] = (float)((double)o[3] + ry); o[4] = (float)((double)o[4] - ry);
+    o[5] = (float)((double)o[5] + rz); o[6] = (float)((double)o[6] - rz);
+  }
+  const uint32_t ib = idx * (uint32_t)sizeof(S);
+  if (SHW) {
+    // stored relative to w_i instead of w_i phi~_i
+    const float ksf = p.f.ks;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) o[i] += ksf * kw(i) * ((UNI ? phx_f : pt[i]) - 1.0f);
+  }
+  st_pop(B, ib, o[0]);
+#pragma unroll
+  for (int i = 1; i < Q; ++i) st_pop(B, p.plb[i] + ib, o[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -427,10 +473,10 @@ __device__ __forceinline__ void diag_terms(const Params& p, float phx, const flo
     return;
   }
   const Sums<double> s = moment_sums<double>(d);
-  v[0] = (double)phx + s.s * p.iU;
-  v[1] = s.mx * p.iU;
-  v[2] = s.my * p.iU;
-  v[3] = s.mz * p.iU;
+  v[0] = (double)phx + s.s * p.d.iU;
+  v[1] = s.mx * p.d.iU;
+  v[2] = s.my * p.d.iU;
+  v[3] = s.mz * p.d.iU;
   const double ke = 0.5 * (double)M.rho * (double)M.uu;
   v[4] = ke;
   v[5] = reg ? ke : 0.0;
@@ -445,7 +491,7 @@ __device__ __forceinline__ void diag_terms(const Params& p, float phx, const flo
 
 // Body of the step for one cell (UNI: the whole wave has uniform neighbour
 // porosity).
-template <class S, bool SHW, bool UNI, bool PER, int DIAG, bool REC, class R>
+template <class S, bool SHW, bool UNI, bool PER, int DIAG, bool REC, class R, bool PROJ>
 __device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32_t c, float amp,
                                           double (&dv)[NDIAGP], float& ke_reg) {
   const uint32_t idx = b.cells[c];
@@ -471,7 +517,7 @@ __device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32
   const bool reg = (lk & LK_REG) != 0;
   if (DIAG == 1) diag_terms<R>(p, phx, d, M, reg, true, dv);
   if (DIAG == 2) ke_reg = reg ? (float)((R)0.5 * M.rho * M.uu) : 0.0f;
-  collide_store<S, SHW, UNI, R>(p, (S*)b.B, idx, phx, d, pt, M);
+  collide_store<S, SHW, UNI, R, PROJ>(p, (S*)b.B, idx, phx, d, pt, M);
 }
 
 // ---------------------------------------------------------------------------
@@ -479,7 +525,7 @@ __device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32
 // part[block][NDIAGP], 2 region kinetic energy accumulated into part[block].
 // REC: also record the pulled values and omega_prev ([20][nf]) and rho (box).
 // ---------------------------------------------------------------------------
-template <class S, bool SHW, bool PER, int DIAG, bool REC, class R>
+template <class S, bool SHW, bool PER, int DIAG, bool REC, class R, bool PROJ>
 __global__ __launch_bounds__(BLOCK) void k_step(Params p, Bufs b, float amp) {
   const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
   const uint32_t c = blk * BLOCK + threadIdx.x;
@@ -488,9 +534,9 @@ __global__ __launch_bounds__(BLOCK) void k_step(Params p, Bufs b, float amp) {
   float ke_reg = 0.0f;
   const bool uni = !active || (b.links[active ? c : 0] & LK_UNI);
   if (__all(uni)) {
-    if (active) step_cell<S, SHW, true, PER, DIAG, REC, R>(p, b, c, amp, dv, ke_reg);
+    if (active) step_cell<S, SHW, true, PER, DIAG, REC, R, PROJ>(p, b, c, amp, dv, ke_reg);
   } else {
-    if (active) step_cell<S, SHW, false, PER, DIAG, REC, R>(p, b, c, amp, dv, ke_reg);
+    if (active) step_cell<S, SHW, false, PER, DIAG, REC, R, PROJ>(p, b, c, amp, dv, ke_reg);
   }
   if (DIAG == 1) {
     if (!active) {
@@ -590,7 +636,7 @@ __global__ __launch_bounds__(BLOCK) void k_init(Params p, Bufs b, float omega0) 
   int wc[6] = {0, 0, 0, 0, 0, 0};
   if (p.anyper) wrap_corr(p, lk, wc);
   S* B = (S*)b.B;
-  const float ks = (float)p.ks;
+  const float ks = p.f.ks;
   Store<S>::st(B, idx, SHW ? ks * kw(0) * (phx - 1.0f) : 0.0f, 0);
   sfor<1, Q>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
