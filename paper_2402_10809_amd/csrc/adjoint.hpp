@@ -24,14 +24,15 @@
 namespace lbm {
 
 struct AdjBufs {
-  const uint32_t* cells;  // box index per fluid cell
-  const uint32_t* links;  // link word per fluid cell
-  const float* phi;       // dense box porosity
-  const float* shape;     // inflow profile
-  const float* rec;       // record of step n: [19][nf] pulled values (before the fill), [nf] omega_prev
-  const float* rho_prev;  // dense density of step n-1 (null for n = 0)
-  const float* ph_next;   // adjoint of the pulled populations of step n+1, [19][nbox]
-  float* ph_out;          // adjoint of the pulled populations of step n, [19][nbox]
+  const uint32_t* code;   // (row << xbits) | x per compact cell
+  const uint32_t* links;  // link word per compact cell
+  const int* delta;       // neighbour-row deltas
+  const float* phi;       // porosity per compact cell
+  const float* shape;     // inflow profile per row
+  const float* rec;       // record of step n: [19][nc] pulled values (before the fill), [nc] omega_prev
+  const float* rho_prev;  // density of step n-1 per compact cell (null for n = 0)
+  const float* ph_next;   // adjoint of the pulled populations of step n+1, [19][nc]
+  float* ph_out;          // adjoint of the pulled populations of step n, [19][nc]
   float* omh;             // per cell: in adjoint of omega_n, out adjoint of omega_{n-1}
   double* phih;           // per cell: porosity adjoint accumulator
 };
@@ -50,22 +51,21 @@ __device__ __forceinline__ void sym_mv(const R s[6], R x, R y, R z, R& ox, R& oy
 // stored in FP32.
 __global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, float amp, float ew) {
   using R = double;
-  const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-  const uint32_t c = blk * BLOCK + threadIdx.x;
-  if (c >= (uint32_t)p.nf) return;
-  const uint32_t idx = a.cells[c];
+  const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
+  if (c >= (uint32_t)p.nc) return;
   const uint32_t lk = a.links[c];
+  if (lk & LK_DEAD) return;
+  Pos q = position(p, c, a.code[c]);
+  load_deltas(a.delta, q);
   const bool reg = (lk & LK_REG) != 0;
-  const float phx_f = ldo(a.phi, idx);
-  int wc[6] = {0, 0, 0, 0, 0, 0};
-  if (p.anyper) wrap_corr(p, lk, wc);
+  const float phx_f = ldo(a.phi, c);
 
   // ---- forward recompute from the record --------------------------------
   float d[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) d[i] = a.rec[(size_t)i * p.nf + c];
-  const float omp = a.rec[(size_t)Q * p.nf + c];
-  open_fill(p, idx, lk, amp, a.shape, d);
+  for (int i = 0; i < Q; ++i) d[i] = a.rec[(size_t)i * p.nc + c];
+  const float omp = a.rec[(size_t)Q * p.nc + c];
+  open_fill(p, q.row, lk, amp, a.shape, d);
   Macro<R> M;
   macro<R>(p, phx_f, d, omp, M);
   const R phx = (R)phx_f;
@@ -100,15 +100,15 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, float am
 
   // ---- gather the adjoint of the post-collision populations --------------
   R qh[Q];
-  qh[0] = (R)ldo(a.ph_next, idx);
+  qh[0] = (R)ldo(a.ph_next, c);
   uint32_t fmask = 0;
   R sfl = 0.0, sjump = 0.0;
   sfor<1, Q>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
     const bool fl = ((lk >> OPP[I]) & 1u) == 0;  // x + c_I is a fluid cell
-    const uint32_t tgt = idx + (uint32_t)nb_off<CX[I], CY[I], CZ[I]>(p, wc);
-    const R pn = (R)ldo(a.phi, fl ? tgt : idx);
-    const uint32_t e = fl ? (uint32_t)I * p.nbox + tgt : (uint32_t)OPP[I] * p.nbox + idx;
+    const uint32_t tgt = src_of<OPP[I]>(p, q);   // x + c_I
+    const R pn = (R)ldo(a.phi, fl ? tgt : c);
+    const uint32_t e = fl ? (uint32_t)I * (uint32_t)p.nc + tgt : (uint32_t)OPP[I] * (uint32_t)p.nc + c;
     qh[I] = (R)ldo(a.ph_next, e);
     const R ai = (R)wgt(I) * qh[I];
     sfl += fl ? ai : 0.0;
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, float am
   const bool in = (lk & LK_IN) != 0;
   const bool outl = (lk & LK_OUT) != 0;
   if (in) {
-    const R uin = (R)amp * (R)a.shape[div_nx(p, idx)];
+    const R uin = (R)amp * (R)a.shape[q.row];
     fh[2] += fh[1]; fh[8] += fh[7]; fh[10] += fh[9]; fh[12] += fh[11]; fh[14] += fh[13];
     const R rinh = uin * (1.0 / 3.0) * fh[1] + uin * (1.0 / 6.0) * (fh[7] + fh[9] + fh[11] + fh[13]);
     const R nyh = 0.5 * (fh[9] - fh[7]), nzh = 0.5 * (fh[13] - fh[11]);
@@ -249,7 +249,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, float am
     fh[2] = 0.0; fh[8] = 0.0; fh[10] = 0.0; fh[12] = 0.0; fh[14] = 0.0;
   }
 #pragma unroll
-  for (int i = 0; i < Q; ++i) sto(a.ph_out, (uint32_t)i * p.nbox + idx, (float)fh[i]);
+  for (int i = 0; i < Q; ++i) sto(a.ph_out, (uint32_t)i * (uint32_t)p.nc + c, (float)fh[i]);
   a.omh[c] = (float)omph;
 
   // porosity-jump term of step n-1: q_i(x - c_i) depends on phi(x) when
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, float am
     sfor<1, Q>([&](auto ic) {
       constexpr int J = decltype(ic)::value;
       if (fmask & (1u << J)) {
-        const uint32_t tgt = idx + (uint32_t)nb_off<CX[J], CY[J], CZ[J]>(p, wc);
+        const uint32_t tgt = src_of<OPP[J]>(p, q);   // x + c_J
         phh += (R)kw(J) * (1.0 / 36.0) * (R)ldo(a.rho_prev, tgt) * fh[OPP[J]];
       }
     });
@@ -268,15 +268,17 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, float am
 
 // Rest state f_i(0, x) = w_i phi(x) on the known links, then scatter the total
 // into the box-layout gradient.
-__global__ __launch_bounds__(BLOCK) void k_adj_final(Params p, const uint32_t* cells, const float* ph0,
-                                                     const double* total, float* grad) {
+__global__ __launch_bounds__(BLOCK) void k_adj_final(Params p, const uint32_t* code, const uint32_t* links,
+                                                     const uint32_t* rowbox, const float* ph0, const double* total,
+                                                     float* grad) {
   const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
-  if (c >= (uint32_t)p.nf) return;
-  const uint32_t idx = cells[c];
+  if (c >= (uint32_t)p.nc) return;
+  if (links[c] & LK_DEAD) return;
+  const Pos q = position(p, c, code[c]);
   double s = total[c];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) s += (double)kw(i) * (1.0 / 36.0) * (double)ldo(ph0, (uint32_t)i * p.nbox + idx);
-  grad[idx] = (float)s;
+  for (int i = 0; i < Q; ++i) s += (double)kw(i) * (1.0 / 36.0) * (double)ldo(ph0, (uint32_t)i * (uint32_t)p.nc + c);
+  grad[(size_t)rowbox[q.row] + (size_t)q.x] = (float)s;
 }
 
 }  // namespace lbm

@@ -29,26 +29,22 @@ __device__ __forceinline__ void sto(T* base, uint32_t e, T v) {
   *(T*)((char*)base + (uint32_t)(e * (uint32_t)sizeof(T))) = v;
 }
 
-template <class S> struct Store;
-template <> struct Store<float> {
-  static __device__ __forceinline__ float ld(const float* b, uint32_t e, int) { return ldo(b, e); }
-  static __device__ __forceinline__ void st(float* b, uint32_t e, float v, int) { sto(b, e, v); }
-};
-template <> struct Store<_Float16> {
-  static __device__ __forceinline__ float ld(const _Float16* b, uint32_t e, int) { return (float)ldo(b, e); }
-  static __device__ __forceinline__ void st(_Float16* b, uint32_t e, float v, int) { sto(b, e, (_Float16)v); }
-};
-template <> struct Store<__bf16> {
-  static __device__ __forceinline__ float ld(const __bf16* b, uint32_t e, int) { return (float)ldo(b, e); }
-  static __device__ __forceinline__ void st(__bf16* b, uint32_t e, float v, int) { sto(b, e, (__bf16)v); }
-};
-
-// Consecutive workgroups are dispatched round-robin over the 8 XCDs; remap so
-// that each XCD works on one contiguous slice of the fluid list (neighbouring
-// cells then share that XCD's L2).
-__device__ __forceinline__ uint32_t xcd_block(uint32_t bid, uint32_t nb) {
-  const uint32_t q = nb >> 3, r = nb & 7u, k = bid & 7u;
-  return k * q + (k < r ? k : r) + (bid >> 3);
+// Neighbour-row pairs (cy, cz): the pull source x - c_i lies in the row
+// (y - cy, z - cz); PK[i] is the index of that pair, 0 for the cell's own row.
+constexpr int NPAIR = 9;
+constexpr int PCY[NPAIR] = {0, 1, -1, 0, 0, 1, -1, 1, -1};
+constexpr int PCZ[NPAIR] = {0, 0, 0, 1, -1, 1, -1, -1, 1};
+__host__ __device__ constexpr int pair_of(int cy, int cz) {
+  int k = 0;
+  while (k < NPAIR && !(PCY[k] == cy && PCZ[k] == cz)) ++k;
+  return k;
 }
+constexpr int PK[Q] = {pair_of(CY[0], CZ[0]),   pair_of(CY[1], CZ[1]),   pair_of(CY[2], CZ[2]),
+                       pair_of(CY[3], CZ[3]),   pair_of(CY[4], CZ[4]),   pair_of(CY[5], CZ[5]),
+                       pair_of(CY[6], CZ[6]),   pair_of(CY[7], CZ[7]),   pair_of(CY[8], CZ[8]),
+                       pair_of(CY[9], CZ[9]),   pair_of(CY[10], CZ[10]), pair_of(CY[11], CZ[11]),
+                       pair_of(CY[12], CZ[12]), pair_of(CY[13], CZ[13]), pair_of(CY[14], CZ[14]),
+                       pair_of(CY[15], CZ[15]), pair_of(CY[16], CZ[16]), pair_of(CY[17], CZ[17]),
+                       pair_of(CY[18], CZ[18])};
 
 }  // namespace lbm

@@ -1,10 +1,11 @@
 // Host runtime of liblbm.so: the C ABI declared in include/lbm.h.
 //
 // The library never allocates device memory: the caller's workspace is carved
-// into the population buffers, the porosity box, the compact fluid list with
-// its link words and the per-cell relaxation rates (plus the adjoint's
-// checkpoints and records when asked for).  Every kernel runs on the context's
-// stream.
+// into the population buffer (one, streamed in place), the per-cell arrays of
+// the compact row layout (position code, link word, porosity, relaxation rate),
+// the per-row tables (neighbour-row deltas, inflow profile, box offset), plus
+// the adjoint's checkpoints and records when asked for.  Every kernel runs on
+// the context's stream.
 #include "lbm.h"
 
 #include <hip/hip_runtime.h>
@@ -40,7 +41,7 @@ size_t store_bytes(int storage) { return storage == LBM_STORE_FP32 ? 4 : 2; }
 double storage_unit(int storage) { return storage == LBM_STORE_FP16 ? 36.0 * 1024.0 : 36.0; }
 
 struct Layout {
-  size_t A, B, phi, cells, links, omega, shape, stage, part, diag, obj;
+  size_t A, code, links, phi, omega, delta, shape, rowbox, stage, part, diag, obj;
   // adjoint
   size_t ck, rec, rho, ah0, ah1, omh, phih;
   int nck, ckpt, T;
@@ -49,21 +50,57 @@ struct Layout {
 
 int blocks_for(int64_t n) { return (int)((n + BLOCK - 1) / BLOCK); }
 
-Layout make_layout(const lbm_grid& g, int64_t nf, int T, int ckpt) {
+// Rows of the compact layout: every (y, z) line holding fluid, ordered by z
+// then y, with the x range from its first to its last fluid cell.
+struct Rows {
+  std::vector<int> y, z, x0, x1;
+  std::vector<int64_t> cb;  // compact start of each row
+  int64_t nc = 0;           // compact cells (fluid + dead)
+  int64_t nf = 0;           // fluid cells
+};
+
+Rows find_rows(const lbm_grid& g, const uint8_t* solid) {
+  Rows r;
+  const int nx = g.nx;
+  for (int z = 0; z < g.nz; ++z)
+    for (int y = 0; y < g.ny; ++y) {
+      const uint8_t* line = solid + ((size_t)z * g.ny + y) * nx;
+      int lo = -1, hi = -1;
+      for (int x = 0; x < nx; ++x)
+        if (!line[x]) {
+          if (lo < 0) lo = x;
+          hi = x;
+          r.nf += 1;
+        }
+      if (lo < 0) continue;
+      r.y.push_back(y); r.z.push_back(z); r.x0.push_back(lo); r.x1.push_back(hi + 1);
+      r.cb.push_back(r.nc);
+      r.nc += hi + 1 - lo;
+    }
+  return r;
+}
+
+int xbits_for(int nx) {
+  int b = 1;
+  while ((1 << b) < nx) ++b;
+  return b;
+}
+
+Layout make_layout(const lbm_grid& g, int64_t nc, int64_t nrow, int T, int ckpt) {
   Layout L{};
-  const size_t nbox = (size_t)g.nx * g.ny * g.nz;
   const size_t ss = store_bytes(g.storage);
-  const int nblk = blocks_for(nf);
+  const int nblk = blocks_for(nc);
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
-  L.A = take(Q * nbox * ss);
-  L.B = take(Q * nbox * ss);
-  L.phi = take(nbox * 4);
-  L.cells = take((size_t)nf * 4);
-  L.links = take((size_t)nf * 4);
-  L.omega = take((size_t)nf * 4);
-  L.shape = take((size_t)g.ny * g.nz * 4);
-  L.stage = take((size_t)(Q + 1) * nf * 4);
+  L.A = take(Q * (size_t)nc * ss);
+  L.code = take((size_t)nc * 4);
+  L.links = take((size_t)nc * 4);
+  L.phi = take((size_t)nc * 4);
+  L.omega = take((size_t)nc * 4);
+  L.delta = take((size_t)nrow * 8 * 4);
+  L.shape = take((size_t)nrow * 4);
+  L.rowbox = take((size_t)nrow * 4);
+  L.stage = take((size_t)(Q + 1) * nc * 4);
   L.part = take((size_t)nblk * NDIAGP * 8);
   L.diag = take(64 * 8);
   L.obj = take((size_t)nblk * 8);
@@ -71,13 +108,13 @@ Layout make_layout(const lbm_grid& g, int64_t nf, int T, int ckpt) {
   L.ckpt = ckpt;
   if (T > 0) {
     L.nck = (T + ckpt - 1) / ckpt;
-    L.ck = take((size_t)L.nck * (Q + 1) * nf * 4);
-    L.rec = take((size_t)(ckpt + 1) * (Q + 1) * nf * 4);
-    L.rho = take((size_t)(ckpt + 1) * nbox * 4);
-    L.ah0 = take(Q * nbox * 4);
-    L.ah1 = take(Q * nbox * 4);
-    L.omh = take((size_t)nf * 4);
-    L.phih = take((size_t)nf * 8);
+    L.ck = take((size_t)L.nck * (Q + 1) * nc * 4);
+    L.rec = take((size_t)(ckpt + 1) * (Q + 1) * nc * 4);
+    L.rho = take((size_t)(ckpt + 1) * nc * 4);
+    L.ah0 = take(Q * (size_t)nc * 4);
+    L.ah1 = take(Q * (size_t)nc * 4);
+    L.omh = take((size_t)nc * 4);
+    L.phih = take((size_t)nc * 8);
   }
   L.total = o;
   return L;
@@ -119,16 +156,6 @@ void with_config(int storage, int shw, int mode, Fn&& fn) {
   });
 }
 
-// Granlund-Montgomery constants for unsigned division by d (d >= 1).
-void div_magic(uint32_t d, uint32_t& m, uint32_t& s1, uint32_t& s2) {
-  uint32_t l = 0;
-  while (((uint64_t)1 << l) < d) ++l;
-  const uint64_t mm = (((uint64_t)1 << 32) * (((uint64_t)1 << l) - d)) / d + 1;
-  m = (uint32_t)mm;
-  s1 = l < 1 ? l : 1;
-  s2 = l > 1 ? l - 1 : 0;
-}
-
 }  // namespace
 
 struct lbm_ctx {
@@ -137,11 +164,15 @@ struct lbm_ctx {
   lbm_porous po{};
   lbm_open op{};
   size_t nbox = 0;
-  int64_t nf = 0;
+  int64_t nf = 0;                 // fluid cells
+  int64_t nc = 0;                 // compact cells (fluid + dead)
+  int64_t nrow = 0;
   int nblk = 0;
   int64_t nreg = 0;
   double U = 36.0;
-  std::vector<int64_t> fluid_box;
+  Rows rows;
+  std::vector<int64_t> fluid_box; // box index per fluid cell (ascending)
+  std::vector<int64_t> fluid_c;   // compact index per fluid cell
   std::vector<double> phi_f;      // porosity per fluid cell (host, for state transfer)
   std::vector<uint8_t> solid;     // host copy of the mask
   std::vector<uint8_t> region_f;  // per fluid cell
@@ -150,9 +181,7 @@ struct lbm_ctx {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   Layout L{};
-  char* cur = nullptr;            // buffer holding the current state
-  char* nxt = nullptr;
-  int64_t t = 0;
+  int64_t t = 0;                  // time; its parity selects the slot layout
   bool poisoned = false;
   Params P{};
   float omega0 = 1.0f;
@@ -176,18 +205,19 @@ namespace {
     if ((ctx)->poisoned) return fail(LBM_E_STATE, "context poisoned by an earlier device error"); \
   } while (0)
 
-Bufs bufs(lbm_ctx* c, const void* A, void* B) {
+Bufs bufs(lbm_ctx* c) {
   Bufs b{};
-  b.A = A;
-  b.B = B;
-  b.cells = (const uint32_t*)(c->ws + c->L.cells);
+  b.A = c->ws + c->L.A;
+  b.code = (const uint32_t*)(c->ws + c->L.code);
   b.links = (const uint32_t*)(c->ws + c->L.links);
+  b.delta = (const int*)(c->ws + c->L.delta);
   b.phi = (const float*)(c->ws + c->L.phi);
   b.omega = (float*)(c->ws + c->L.omega);
   b.shape = (const float*)(c->ws + c->L.shape);
+  b.rowbox = (const uint32_t*)(c->ws + c->L.rowbox);
   b.part = (double*)(c->ws + c->L.part);
   b.rec = nullptr;
-  b.rho_box = nullptr;
+  b.rho_rec = nullptr;
   return b;
 }
 
@@ -201,10 +231,7 @@ lbm_status validate_grid(const lbm_grid* g) {
   if (!g) return fail(LBM_E_INVALID, "grid is NULL");
   if (g->nx < 1 || g->ny < 1 || g->nz < 1) return fail(LBM_E_INVALID, "grid dimensions must be positive");
   if (g->nx > 2048 || g->ny > 1024 || g->nz > 1024) return fail(LBM_E_INVALID, "grid exceeds 2048 x 1024 x 1024");
-  const double nbox = (double)g->nx * g->ny * g->nz;
   if (g->storage < 0 || g->storage > 2) return fail(LBM_E_INVALID, "unknown storage format");
-  if (nbox * Q * (double)store_bytes(g->storage) >= 4294967296.0)
-    return fail(LBM_E_INVALID, "population buffer would reach 4 GiB (kernels address it with 32-bit byte offsets)");
   if (g->shift_mode < 0 || g->shift_mode > 1) return fail(LBM_E_INVALID, "shift_mode must be 0 or 1");
   if (g->arith < 0 || g->arith > 2) return fail(LBM_E_INVALID, "unknown arithmetic mode");
   if (g->arith == LBM_ARITH_FP64 && g->storage != LBM_STORE_FP32)
@@ -212,11 +239,17 @@ lbm_status validate_grid(const lbm_grid* g) {
   return LBM_OK;
 }
 
-int64_t count_fluid(const lbm_grid* g, const uint8_t* solid) {
-  const size_t nbox = (size_t)g->nx * g->ny * g->nz;
-  int64_t n = 0;
-  for (size_t b = 0; b < nbox; ++b) n += solid[b] ? 0 : 1;
-  return n;
+// Limits of the compact layout for a given mask: 32-bit byte offsets into the
+// population planes (also the FP32 adjoint planes) and the position code.
+lbm_status check_rows(const lbm_grid* g, const Rows& r) {
+  if (r.nf == 0) return fail(LBM_E_INVALID, "no fluid cell");
+  if ((double)r.nc * Q * 4.0 >= 4294967296.0)
+    return fail(LBM_E_INVALID, "more than 56.5 M compact cells (kernels address the population planes with "
+                               "32-bit byte offsets)");
+  const int xb = xbits_for(g->nx);
+  if ((uint64_t)r.y.size() >= ((uint64_t)1 << (32 - xb)))
+    return fail(LBM_E_INVALID, "too many fluid rows for the 32-bit position code");
+  return LBM_OK;
 }
 
 lbm_status check_phi(const lbm_ctx* c, const float* phi) {
@@ -232,70 +265,77 @@ lbm_status check_phi(const lbm_ctx* c, const float* phi) {
   return LBM_OK;
 }
 
-// Link word of every fluid cell (see step.hpp): bounce-back mask of the pulls,
-// uniform-neighbour-porosity flag, open-face role, region, periodic faces.
+// Link word of every compact cell (see step.hpp): dead flag, bounce-back mask
+// of the pulls, uniform-neighbour-porosity flag, open-face role, region,
+// open-face unknowns.
 void build_links(const lbm_ctx* c, const std::vector<float>& phib, std::vector<uint32_t>& links) {
   const int nx = c->grid.nx, ny = c->grid.ny, nz = c->grid.nz;
   const int per[3] = {c->grid.periodic[0] != 0, c->grid.periodic[1] != 0, c->grid.periodic[2] != 0};
   const int dims[3] = {nx, ny, nz};
-  links.assign(c->nf, 0u);
+  links.assign(c->nc, LK_DEAD);
   for (int64_t k = 0; k < c->nf; ++k) {
     const int64_t b = c->fluid_box[k];
     const int X[3] = {(int)(b % nx), (int)((b / nx) % ny), (int)(b / ((int64_t)nx * ny))};
     uint32_t lk = 0;
     bool uni = true;
     const float ph = phib[b];
+    uint32_t unk = 0;
     for (int i = 1; i < Q; ++i) {
       const int cv[3] = {CX[i], CY[i], CZ[i]};
       for (int sgn = -1; sgn <= 1; sgn += 2) {  // -1: pull source x - c_i; +1: neighbour x + c_i
         int s[3];
-        bool out = false;
+        bool out = false, out_yz = false;
         for (int a = 0; a < 3; ++a) {
           s[a] = X[a] + sgn * cv[a];
           if (s[a] < 0 || s[a] >= dims[a]) {
             if (per[a]) s[a] = (s[a] + dims[a]) % dims[a];
-            else out = true;
+            else { out = true; if (a > 0) out_yz = true; }
           }
         }
         const int64_t sb = out ? -1 : (int64_t)s[0] + (int64_t)nx * ((int64_t)s[1] + (int64_t)ny * s[2]);
         const bool wall = out || c->solid[sb];
-        if (sgn < 0) { if (wall) lk |= 1u << i; }
-        else if (!wall && phib[sb] != ph) uni = false;
+        if (sgn < 0) {
+          if (wall) lk |= 1u << i;
+          // open-face unknown: the source lies beyond the inflow/outflow face only
+          if (out && !out_yz && c->openface[k]) {
+            const int* xs = c->openface[k] == 1 ? XIN : XOUT;
+            for (int j = 0; j < 5; ++j)
+              if (xs[j] == i) unk |= 1u << j;
+          }
+        } else if (!wall && phib[sb] != ph) {
+          uni = false;
+        }
       }
     }
     if (uni) lk |= LK_UNI;
     if (c->openface[k] == 1) lk |= LK_IN;
     if (c->openface[k] == 2) lk |= LK_OUT;
     if (c->region_f[k]) lk |= LK_REG;
-    uint32_t faces = 0;
-    for (int a = 0; a < 3; ++a) {
-      if (!per[a]) continue;
-      if (X[a] == 0) faces |= 1u << (2 * a);
-      if (X[a] == dims[a] - 1) faces |= 1u << (2 * a + 1);
-    }
-    if (faces) lk |= LK_WRAP | (faces << LK_FACE);
-    links[k] = lk;
+    lk |= unk << LK_UNK;
+    links[c->fluid_c[k]] = lk;
   }
 }
 
-// Upload the porosity box and the link words (which depend on it).
+// Upload the porosity and the link words (which depend on it).
 lbm_status upload_phi(lbm_ctx* c, const float* phi) {
-  std::vector<float> box(c->nbox, 0.0f);
+  std::vector<float> box(c->nbox, 0.0f), comp(c->nc, 0.0f);
   c->phi_f.resize(c->nf);
   for (int64_t k = 0; k < c->nf; ++k) {
-    box[c->fluid_box[k]] = phi[c->fluid_box[k]];
-    c->phi_f[k] = phi[c->fluid_box[k]];
+    const float v = phi[c->fluid_box[k]];
+    box[c->fluid_box[k]] = v;
+    comp[c->fluid_c[k]] = v;
+    c->phi_f[k] = v;
   }
   std::vector<uint32_t> links;
   build_links(c, box, links);
-  HIP_TRY(c, hipMemcpyAsync(c->ws + c->L.phi, box.data(), c->nbox * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->ws + c->L.phi, comp.data(), comp.size() * 4, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->ws + c->L.links, links.data(), links.size() * 4, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return LBM_OK;
 }
 
 lbm_status launch_init(lbm_ctx* c) {
-  Bufs b = bufs(c, nullptr, c->cur);
+  Bufs b = bufs(c);
   with_storage(c->grid.storage, c->grid.shift_mode, [&](auto tag, auto shw) {
     using S = typename decltype(tag)::T;
     hipLaunchKernelGGL((k_init<S, decltype(shw)::value>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b,
@@ -306,43 +346,46 @@ lbm_status launch_init(lbm_ctx* c) {
   return LBM_OK;
 }
 
-// One step from cur into nxt.  diag: 0 none, 1 diagnostics partials, 2 region
-// energy accumulation into the objective partials.  rec: record the step for
-// the adjoint (FP32, shift mode 0 only).
-lbm_status launch_step(lbm_ctx* c, int diag, float* rec, float* rho_box) {
-  Bufs b = bufs(c, c->cur, c->nxt);
+template <class Fn>
+void with_parity(int64_t t, Fn&& fn) {
+  if (t & 1) fn(std::true_type{}); else fn(std::false_type{});
+}
+
+// One step at time t (in place).  diag: 0 none, 1 diagnostics partials, 2
+// region energy accumulation into the objective partials.  rec: record the
+// step for the adjoint (FP32, shift mode 0 only).
+lbm_status launch_step(lbm_ctx* c, int diag, float* rec, float* rho_rec) {
+  Bufs b = bufs(c);
   const float amp = (float)amplitude(c, c->t);
   if (diag == 2) b.part = (double*)(c->ws + c->L.obj);
   if (rec) {
     b.rec = rec;
-    b.rho_box = rho_box;
+    b.rho_rec = rho_rec;
   }
   with_config(c->grid.storage, c->grid.shift_mode, c->amode, [&](auto tag, auto shw, auto rt) {
     using S = typename decltype(tag)::T;
     using R = typename decltype(rt)::T;
     constexpr bool PJ = decltype(rt)::proj;
     constexpr bool SH = decltype(shw)::value;
-    auto go = [&](auto per) {
-      constexpr bool PER = decltype(per)::value;
+    with_parity(c->t, [&](auto odd) {
+      constexpr bool OD = decltype(odd)::value;
       if (rec) {
         if constexpr (std::is_same<S, float>::value && !SH)
-          hipLaunchKernelGGL((k_step<S, false, PER, 0, true, R, PJ>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P,
+          hipLaunchKernelGGL((k_step<S, false, OD, 0, true, R, PJ>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P,
                              b, amp);
       } else if (diag == 0) {
-        hipLaunchKernelGGL((k_step<S, SH, PER, 0, false, R, PJ>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b,
+        hipLaunchKernelGGL((k_step<S, SH, OD, 0, false, R, PJ>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b,
                            amp);
       } else if (diag == 1) {
-        hipLaunchKernelGGL((k_step<S, SH, PER, 1, false, R, PJ>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b,
+        hipLaunchKernelGGL((k_step<S, SH, OD, 1, false, R, PJ>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b,
                            amp);
       } else {
-        hipLaunchKernelGGL((k_step<S, SH, PER, 2, false, R, PJ>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b,
+        hipLaunchKernelGGL((k_step<S, SH, OD, 2, false, R, PJ>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b,
                            amp);
       }
-    };
-    if (c->P.anyper) go(std::true_type{}); else go(std::false_type{});
+    });
   });
   HIP_TRY(c, hipGetLastError());
-  std::swap(c->cur, c->nxt);
   c->t += 1;
   return LBM_OK;
 }
@@ -373,40 +416,50 @@ lbm_status check_stable(lbm_ctx* c, const double* dg) {
 }
 
 lbm_status moments_launch(lbm_ctx* c, bool diag, float* rho, float* u, float* shear, float* omega, float* sigma) {
-  Bufs b = bufs(c, c->cur, nullptr);
+  Bufs b = bufs(c);
   const float amp = (float)amplitude(c, c->t);
   with_config(c->grid.storage, c->grid.shift_mode, c->amode == 2 ? 2 : 0, [&](auto tag, auto shw, auto rt) {
     using S = typename decltype(tag)::T;
     using R = typename decltype(rt)::T;
     constexpr bool SH = decltype(shw)::value;
-    if (diag)
-      hipLaunchKernelGGL((k_moments<S, SH, true, R>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, amp, rho, u,
-                         shear, omega, sigma);
-    else
-      hipLaunchKernelGGL((k_moments<S, SH, false, R>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, amp, rho, u,
-                         shear, omega, sigma);
+    with_parity(c->t, [&](auto odd) {
+      constexpr bool OD = decltype(odd)::value;
+      if (diag)
+        hipLaunchKernelGGL((k_moments<S, SH, OD, true, R>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, amp,
+                           c->nbox, rho, u, shear, omega, sigma);
+      else
+        hipLaunchKernelGGL((k_moments<S, SH, OD, false, R>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, amp,
+                           c->nbox, rho, u, shear, omega, sigma);
+    });
   });
   HIP_TRY(c, hipGetLastError());
   return LBM_OK;
 }
 
-// Compact pulled state (raw stored values as FP32, [19][nf]) of the current
-// buffer into dst (device).
+// Pulled state of time t (raw stored values as FP32, [19][nc], compact order)
+// into dst (device).
 lbm_status gather_state(lbm_ctx* c, float* dst) {
-  Bufs b = bufs(c, c->cur, nullptr);
+  Bufs b = bufs(c);
   with_storage(c->grid.storage, 0, [&](auto tag, auto) {
     using S = typename decltype(tag)::T;
-    hipLaunchKernelGGL((k_gather_state<S>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, dst);
+    with_parity(c->t, [&](auto odd) {
+      hipLaunchKernelGGL((k_gather_state<S, decltype(odd)::value>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P,
+                         b, dst);
+    });
   });
   HIP_TRY(c, hipGetLastError());
   return LBM_OK;
 }
 
+// Inverse of gather_state, into the slots of time t's parity.
 lbm_status scatter_state(lbm_ctx* c, const float* src) {
-  Bufs b = bufs(c, nullptr, c->cur);
+  Bufs b = bufs(c);
   with_storage(c->grid.storage, 0, [&](auto tag, auto) {
     using S = typename decltype(tag)::T;
-    hipLaunchKernelGGL((k_scatter_state<S>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, src);
+    with_parity(c->t, [&](auto odd) {
+      hipLaunchKernelGGL((k_scatter_state<S, decltype(odd)::value>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P,
+                         b, src);
+    });
   });
   HIP_TRY(c, hipGetLastError());
   return LBM_OK;
@@ -432,9 +485,10 @@ lbm_status lbm_workspace_size(const lbm_grid* grid, const uint8_t* solid, int ad
   if (s != LBM_OK) return s;
   if (!solid || !bytes) return fail(LBM_E_INVALID, "solid and bytes must not be NULL");
   if (adjoint_T < 0 || (adjoint_T > 0 && ckpt_every < 1)) return fail(LBM_E_INVALID, "bad adjoint_T / ckpt_every");
-  const int64_t nf = count_fluid(grid, solid);
-  if (nf == 0) return fail(LBM_E_INVALID, "no fluid cell");
-  *bytes = make_layout(*grid, nf, adjoint_T, adjoint_T > 0 ? ckpt_every : 0).total;
+  const Rows r = find_rows(*grid, solid);
+  s = check_rows(grid, r);
+  if (s != LBM_OK) return s;
+  *bytes = make_layout(*grid, r.nc, (int64_t)r.y.size(), adjoint_T, adjoint_T > 0 ? ckpt_every : 0).total;
   return LBM_OK;
 }
 
@@ -458,9 +512,11 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* solid, const float* p
   }
   if (!workspace) return fail(LBM_E_WORKSPACE, "workspace is NULL");
   if (((uintptr_t)workspace & 255) != 0) return fail(LBM_E_WORKSPACE, "workspace must be 256-byte aligned");
-  const int64_t nf0 = count_fluid(grid, solid);
-  if (nf0 == 0) return fail(LBM_E_INVALID, "no fluid cell");
-  const Layout L0 = make_layout(*grid, nf0, 0, 0);
+  Rows rows = find_rows(*grid, solid);
+  s = check_rows(grid, rows);
+  if (s != LBM_OK) return s;
+  const int64_t nrow = (int64_t)rows.y.size();
+  const Layout L0 = make_layout(*grid, rows.nc, nrow, 0, 0);
   if (ws_bytes < L0.total)
     return fail(LBM_E_WORKSPACE, "workspace too small: need " + std::to_string(L0.total) + " bytes");
 
@@ -474,41 +530,65 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* solid, const float* p
   c->solid.assign(solid, solid + c->nbox);
   c->stream = (hipStream_t)stream;
   c->U = storage_unit(grid->storage);
-  std::vector<uint32_t> cells;
-  cells.reserve(nf0);
-  c->fluid_box.reserve(nf0);
-  for (size_t b = 0; b < c->nbox; ++b) {
-    if (solid[b]) continue;
-    const int x = (int)(b % grid->nx);
-    cells.push_back((uint32_t)b);
-    c->fluid_box.push_back((int64_t)b);
-    c->region_f.push_back(region && region[b] ? 1 : 0);
-    uint8_t of = 0;
-    if (op && op->inlet && x == 0) of = 1;
-    else if (op && op->outlet && x == grid->nx - 1) of = 2;
-    c->openface.push_back(of);
-    c->nreg += (region && region[b]) ? 1 : 0;
+  c->nf = rows.nf;
+  c->nc = rows.nc;
+  c->nrow = nrow;
+  const int nx = grid->nx, xb = xbits_for(nx);
+  std::vector<uint32_t> code(c->nc, 0u), rowbox(nrow);
+  std::vector<int> delta((size_t)nrow * 8, 0);
+  std::vector<float> shape(nrow, 0.0f);
+  std::vector<int64_t> rowid((size_t)grid->ny * grid->nz, -1);
+  c->fluid_box.reserve(c->nf);
+  c->fluid_c.reserve(c->nf);
+  for (int64_t r = 0; r < nrow; ++r) {
+    const int y = rows.y[r], z = rows.z[r];
+    rowid[(size_t)z * grid->ny + y] = r;
+    const size_t base = ((size_t)z * grid->ny + y) * nx;
+    rowbox[r] = (uint32_t)base;
+    if (op && op->inlet) shape[r] = op->shape_yz[(size_t)z * grid->ny + y];
+    for (int x = rows.x0[r]; x < rows.x1[r]; ++x) {
+      const int64_t ci = rows.cb[r] + x - rows.x0[r];
+      code[ci] = ((uint32_t)r << xb) | (uint32_t)x;
+      const size_t b = base + x;
+      if (solid[b]) continue;
+      c->fluid_box.push_back((int64_t)b);
+      c->fluid_c.push_back(ci);
+      c->region_f.push_back(region && region[b] ? 1 : 0);
+      uint8_t of = 0;
+      if (op && op->inlet && x == 0) of = 1;
+      else if (op && op->outlet && x == nx - 1) of = 2;
+      c->openface.push_back(of);
+      c->nreg += (region && region[b]) ? 1 : 0;
+    }
   }
-  c->nf = (int64_t)cells.size();
+  // neighbour-row deltas: the row (y - cy, z - cz) of pair k, wrapped on periodic axes
+  for (int64_t r = 0; r < nrow; ++r) {
+    for (int k = 1; k < NPAIR; ++k) {
+      int sy = rows.y[r] - PCY[k], sz = rows.z[r] - PCZ[k];
+      if (grid->periodic[1]) sy = (sy + grid->ny) % grid->ny;
+      if (grid->periodic[2]) sz = (sz + grid->nz) % grid->nz;
+      if (sy < 0 || sy >= grid->ny || sz < 0 || sz >= grid->nz) continue;
+      const int64_t rr = rowid[(size_t)sz * grid->ny + sy];
+      if (rr < 0) continue;
+      delta[(size_t)r * 8 + (k - 1)] = (int)(rows.cb[rr] - rows.x0[rr]);
+    }
+  }
+  c->rows = std::move(rows);
   s = check_phi(c, phi);
   if (s != LBM_OK) { delete c; return s; }
-  c->nblk = blocks_for(c->nf);
+  c->nblk = blocks_for(c->nc);
   c->L = L0;
   c->ws = (char*)workspace;
   c->ws_bytes = ws_bytes;
-  c->cur = c->ws + c->L.A;
-  c->nxt = c->ws + c->L.B;
 
   Params& P = c->P;
-  P.nx = grid->nx; P.ny = grid->ny; P.nz = grid->nz; P.nf = (int)c->nf;
-  P.nxy = (uint32_t)grid->nx * grid->ny;
-  P.nbox = (uint32_t)c->nbox;
-  P.px = grid->periodic[0] ? 1 : 0; P.py = grid->periodic[1] ? 1 : 0; P.pz = grid->periodic[2] ? 1 : 0;
-  P.anyper = P.px | P.py | P.pz;
+  P.nx = nx;
+  P.nc = (int)c->nc;
+  P.px = grid->periodic[0] ? 1 : 0;
   P.inlet = (op && op->inlet) ? 1 : 0;
   P.outlet = (op && op->outlet) ? 1 : 0;
-  div_magic((uint32_t)grid->nx, P.dmag, P.dsh1, P.dsh2);
-  for (int i = 0; i < Q; ++i) P.plb[i] = (uint32_t)((size_t)i * c->nbox * store_bytes(grid->storage));
+  P.xbits = xb;
+  for (int i = 0; i < Q; ++i) P.plb[i] = (uint32_t)((size_t)i * c->nc * store_bytes(grid->storage));
   {
     Params::K<double> k{};
     k.U = c->U; k.iU = 1.0 / c->U; k.ks = c->U / 36.0;
@@ -534,12 +614,13 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* solid, const float* p
     hipError_t e_ = (expr);                                                                         \
     if (e_ != hipSuccess) return bail(fail(LBM_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_))); \
   } while (0)
-  HIP_TRY0(hipMemcpyAsync(c->ws + c->L.cells, cells.data(), cells.size() * 4, hipMemcpyHostToDevice, c->stream));
-  std::vector<float> shape((size_t)grid->ny * grid->nz, 0.0f);
-  if (op && op->inlet) std::memcpy(shape.data(), op->shape_yz, shape.size() * 4);
-  HIP_TRY0(hipMemcpyAsync(c->ws + c->L.shape, shape.data(), shape.size() * 4, hipMemcpyHostToDevice, c->stream));
   // slots that no consumer reads are never written by the kernels; clear them once
-  HIP_TRY0(hipMemsetAsync(c->ws + c->L.A, 0, c->L.phi - c->L.A, c->stream));
+  HIP_TRY0(hipMemsetAsync(c->ws + c->L.A, 0, c->L.code - c->L.A, c->stream));
+  HIP_TRY0(hipMemcpyAsync(c->ws + c->L.code, code.data(), code.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY0(hipMemcpyAsync(c->ws + c->L.delta, delta.data(), delta.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY0(hipMemcpyAsync(c->ws + c->L.shape, shape.data(), shape.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY0(hipMemcpyAsync(c->ws + c->L.rowbox, rowbox.data(), rowbox.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY0(hipMemsetAsync(c->ws + c->L.omega, 0, c->nc * 4, c->stream));
   HIP_TRY0(hipStreamSynchronize(c->stream));
 #undef HIP_TRY0
   s = upload_phi(c, phi);
@@ -594,23 +675,25 @@ lbm_status lbm_get_state(lbm_ctx* c, double* f, float* omega) {
   CTX_CHECK(c);
   if (!f && !omega) return fail(LBM_E_INVALID, "nothing to get");
   float* stage = (float*)(c->ws + c->L.stage);
-  const size_t nf = (size_t)c->nf;
+  const size_t nf = (size_t)c->nf, nc = (size_t)c->nc;
   if (f) {
     lbm_status s = gather_state(c, stage);
     if (s != LBM_OK) return s;
-    std::vector<float> h(Q * nf);
+    std::vector<float> h(Q * nc);
     HIP_TRY(c, hipMemcpyAsync(h.data(), stage, h.size() * 4, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     const double iU = 1.0 / c->U;
     for (int i = 0; i < Q; ++i)
       for (size_t k = 0; k < nf; ++k) {
-        const float v = h[i * nf + k];
+        const float v = h[i * nc + c->fluid_c[k]];
         f[i * nf + k] = std::isnan(v) ? 0.0 : (double)v * iU + rest_value(c, i, (int64_t)k);
       }
   }
   if (omega) {
-    HIP_TRY(c, hipMemcpyAsync(omega, c->ws + c->L.omega, nf * 4, hipMemcpyDeviceToHost, c->stream));
+    std::vector<float> h(nc);
+    HIP_TRY(c, hipMemcpyAsync(h.data(), c->ws + c->L.omega, nc * 4, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (size_t k = 0; k < nf; ++k) omega[k] = h[c->fluid_c[k]];
   }
   return LBM_OK;
 }
@@ -619,18 +702,21 @@ lbm_status lbm_set_state(lbm_ctx* c, const double* f, const float* omega) {
   CTX_CHECK(c);
   if (!f && !omega) return fail(LBM_E_INVALID, "nothing to set");
   float* stage = (float*)(c->ws + c->L.stage);
-  const size_t nf = (size_t)c->nf;
+  const size_t nf = (size_t)c->nf, nc = (size_t)c->nc;
   if (f) {
-    std::vector<float> h(Q * nf);
+    std::vector<float> h(Q * nc, 0.0f);
     for (int i = 0; i < Q; ++i)
-      for (size_t k = 0; k < nf; ++k) h[i * nf + k] = (float)((f[i * nf + k] - rest_value(c, i, (int64_t)k)) * c->U);
+      for (size_t k = 0; k < nf; ++k)
+        h[i * nc + c->fluid_c[k]] = (float)((f[i * nf + k] - rest_value(c, i, (int64_t)k)) * c->U);
     HIP_TRY(c, hipMemcpyAsync(stage, h.data(), h.size() * 4, hipMemcpyHostToDevice, c->stream));
     lbm_status s = scatter_state(c, stage);
     if (s != LBM_OK) return s;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
   }
   if (omega) {
-    HIP_TRY(c, hipMemcpyAsync(c->ws + c->L.omega, omega, nf * 4, hipMemcpyHostToDevice, c->stream));
+    std::vector<float> h(nc, 0.0f);
+    for (size_t k = 0; k < nf; ++k) h[c->fluid_c[k]] = omega[k];
+    HIP_TRY(c, hipMemcpyAsync(c->ws + c->L.omega, h.data(), nc * 4, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
   }
   return LBM_OK;

@@ -1,16 +1,31 @@
 // Fused D3Q19 VANSE Carreau-Yasuda stream-collide step and its companions
 // (rest-state init, moments/diagnostics, state gather/scatter).
 //
-// One work-item per fluid cell, 1-D grid over the compact fluid list.  The
-// populations live in two structure-of-arrays buffers over the dense box
-// (plane stride nbox); a step pulls from A at x - c_i and writes B at x.
+// Layout.  Fluid cells are stored row by row: a row is one (y, z) line of the
+// box that holds fluid, rows are ordered by z then y, and each row keeps the
+// contiguous x range from its first to its last fluid cell (solid cells inside
+// that range are "dead" slots that no kernel touches).  Every per-cell array
+// and each of the 19 population planes is indexed by this compact index, so
+// the touched memory is dense.  A cell's neighbour in the row (y - cy, z - cz)
+// sits at x' + delta[row][pair(cy, cz)], where delta = (compact start - first
+// x) of that row; periodic y and z wrap inside the delta table, periodic x by
+// wrapping x'.
 //
-// Stored values are scaled deviations from a rest value: with shift mode 0 the
-// producer at x stores U (q_i(x) - w_i phi~(x + c_i)), where phi~ is the
-// porosity of the consumer cell (its own porosity when the link bounces back),
-// so every consumer reads v_i = U (f_i - w_i phi(x)).  U = 36 (times 2^10 for
-// FP16) makes U w_i an exact integer (12, 2, 1 times 2^k) for every direction,
-// so the per-direction arithmetic carries no rounded weight: the collision
+// Streaming uses one population buffer in place (the AA pattern): at even
+// time t the populations f_i(t, x) sit at slot (i, x); the even step reads
+// them there and writes its post-collision q_i(x) to slot (opp i, x).  At odd
+// t, f_i(t, x) sits at slot (opp i, x - c_i) (slot (i, x) across a wall); the
+// odd step reads there and writes q_i(x) to slot (i, x + c_i) (slot (opp i, x)
+// across a wall), which is where the next even step finds it.  Within one
+// step every slot is read and written by the same work-item, so no two
+// work-items race.  The even step touches only the cell's own slots.
+//
+// Stored values are scaled deviations from a rest value: with shift mode 0 a
+// value consumed as f_i by cell y is stored as U (f_i - w_i phi(y)) (phi(y) is
+// the producer's phi~(x + c_i), its own porosity across a wall), so every
+// consumer reads v_i = U (f_i - w_i phi(x)).  U = 36 (times 2^10 for FP16)
+// makes U w_i an exact integer (12, 2, 1 times 2^k) for every direction, so
+// the per-direction arithmetic carries no rounded weight: the collision
 // conserves mass and momentum up to unbiased rounding only.  The whole
 // collision runs on these deviations:
 //   rho - 1 = sum(v) / (U phi),  m = sum(v c) / U,
@@ -21,11 +36,11 @@
 // keeps the O(u) signal far above FP32/FP16 rounding of the O(1) rest value.
 // Shift mode 1 stores U (f_i - w_i) instead and converts on load and store.
 //
-// Each fluid cell carries a link word: bit i (1..18) = the pull of direction i
+// Each cell carries a link word: bit i (1..18) = the pull of direction i
 // bounces back (x - c_i is solid or outside a non-periodic face), plus flags
-// (uniform neighbour porosity, open-face role, region, periodic-face bits).
-// Waves whose cells all have uniform neighbour porosity skip the neighbour
-// porosity loads and the porosity-jump arithmetic.
+// (dead slot, uniform neighbour porosity, open-face role, region, open-face
+// unknowns).  Waves whose cells all have uniform neighbour porosity skip the
+// neighbour porosity loads and the porosity-jump arithmetic.
 #pragma once
 #include <type_traits>
 
@@ -33,23 +48,25 @@
 
 namespace lbm {
 
+constexpr uint32_t LK_DEAD = 1u << 0;   // solid slot inside a row's range
 constexpr uint32_t LK_UNI = 1u << 19;   // every fluid neighbour has the cell's porosity
 constexpr uint32_t LK_IN = 1u << 20;    // inflow cell (x = 0)
 constexpr uint32_t LK_OUT = 1u << 21;   // outflow cell (x = nx - 1)
 constexpr uint32_t LK_REG = 1u << 22;   // objective region
-constexpr uint32_t LK_WRAP = 1u << 23;  // on a periodic face
-constexpr int LK_FACE = 24;             // 6 bits: x-, x+, y-, y+, z-, z+ periodic faces
+constexpr int LK_UNK = 23;              // 5 bits: which x-directed pulls are open-face unknowns
+// the x-directed pulls of an inflow (c_x = +1) and an outflow (c_x = -1) cell
+constexpr int XIN[5] = {1, 7, 9, 11, 13};
+constexpr int XOUT[5] = {2, 8, 10, 12, 14};
 
 // 36 w_i: 12 (rest), 2 (axis), 1 (edge).
 __host__ __device__ constexpr float kw(int i) { return i == 0 ? 12.0f : (i < 7 ? 2.0f : 1.0f); }
 
 struct Params {
-  int nx, ny, nz, nf;
-  uint32_t nxy, nbox;
-  int px, py, pz, anyper;
+  int nx, nc;                  // box x extent; compact cells (fluid + dead)
+  int px;                      // periodic x
   int inlet, outlet;
-  uint32_t dmag, dsh1, dsh2;  // division by nx (Granlund-Montgomery)
-  uint32_t plb[Q];            // byte offset of population plane i (i * nbox * sizeof(storage))
+  int xbits;                   // code = (row << xbits) | x
+  uint32_t plb[Q];             // byte offset of population plane i (i * nc * sizeof(storage))
   int cy_a2;                   // a == 2: (lambda g)^a is one multiply
   int forch;                   // Forchheimer drag on
   // physical constants in both precisions (the kernels read the one they
@@ -73,20 +90,17 @@ struct Params {
 };
 
 struct Bufs {
-  const void* A;
-  void* B;
-  const uint32_t* cells;  // box index per fluid cell
-  const uint32_t* links;  // link word per fluid cell
-  const float* phi;       // dense box porosity, 0 = solid
-  float* omega;           // per fluid cell, previous relaxation rate
-  const float* shape;     // inflow profile, ny*nz
+  void* A;                // populations, [19][nc], in place
+  const uint32_t* code;   // (row << xbits) | x per compact cell
+  const uint32_t* links;  // link word per compact cell
+  const int* delta;       // [nrow][8]: neighbour-row deltas for pairs 1..8
+  const float* phi;       // porosity per compact cell
+  float* omega;           // per compact cell, previous relaxation rate
+  const float* shape;     // inflow profile per row
+  const uint32_t* rowbox; // box index of (x = 0) of each row
   double* part;           // per-block partials
-  float* rec;             // recompute record: [20][nf] (pulled values, omega_prev)
-  float* rho_box;         // recompute record: dense rho of the step
-};
-
-template <int I> struct Dir {
-  static constexpr int cx = CX[I], cy = CY[I], cz = CZ[I], opp = OPP[I];
+  float* rec;             // recompute record: [20][nc] (pulled values, omega_prev)
+  float* rho_rec;         // recompute record: rho per compact cell
 };
 
 template <int A, int B, class F>
@@ -95,11 +109,6 @@ __device__ __forceinline__ void sfor(F&& f) {
     f(std::integral_constant<int, A>{});
     sfor<A + 1, B>(f);
   }
-}
-
-__device__ __forceinline__ uint32_t div_nx(const Params& p, uint32_t n) {
-  const uint32_t t = __umulhi(p.dmag, n);
-  return (t + ((n - t) >> p.dsh1)) >> p.dsh2;
 }
 
 // Hardware reciprocal refined by Newton steps (the raw v_rcp result is biased
@@ -118,20 +127,32 @@ __device__ __forceinline__ double rsqrt_(double x) { return __builtin_sqrt(x); }
 __device__ __forceinline__ float rfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double rfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-// Offset from x to x + s for the lattice vector s = (SX, SY, SZ), including the
-// periodic wrap corrections of cells on a periodic face (wc: x-, x+, y-, y+, z-, z+).
-template <int SX, int SY, int SZ, bool PER = true>
-__device__ __forceinline__ int nb_off(const Params& p, const int (&wc)[6]) {
-  int o = SX + SY * p.nx + SZ * (int)p.nxy;
-  if (PER) {
-    if (SX == -1) o += wc[0];
-    if (SX == 1) o += wc[1];
-    if (SY == -1) o += wc[2];
-    if (SY == 1) o += wc[3];
-    if (SZ == -1) o += wc[4];
-    if (SZ == 1) o += wc[5];
-  }
-  return o;
+// Position of a compact cell and the deltas of its neighbour rows.
+struct Pos {
+  uint32_t row;
+  int x;
+  int dl[NPAIR];
+};
+__device__ __forceinline__ Pos position(const Params& p, uint32_t c, uint32_t code) {
+  Pos q;
+  q.row = code >> p.xbits;
+  q.x = (int)(code & ((1u << p.xbits) - 1u));
+  q.dl[0] = (int)c - q.x;
+  return q;
+}
+__device__ __forceinline__ void load_deltas(const int* __restrict__ delta, Pos& q) {
+  const int4* d4 = (const int4*)(delta + (size_t)q.row * 8);
+  const int4 a = d4[0], b = d4[1];
+  q.dl[1] = a.x; q.dl[2] = a.y; q.dl[3] = a.z; q.dl[4] = a.w;
+  q.dl[5] = b.x; q.dl[6] = b.y; q.dl[7] = b.z; q.dl[8] = b.w;
+}
+// Compact index of x - c_I (valid when that cell is fluid).
+template <int I>
+__device__ __forceinline__ uint32_t src_of(const Params& p, const Pos& q) {
+  int xs = q.x - CX[I];
+  if (CX[I] == 1) xs += (p.px && xs < 0) ? p.nx : 0;
+  if (CX[I] == -1) xs -= (p.px && xs >= p.nx) ? p.nx : 0;
+  return (uint32_t)(xs + q.dl[PK[I]]);
 }
 
 // Load through a byte offset from a uniform base.
@@ -154,40 +175,39 @@ __device__ __forceinline__ void st_pop(S* base, uint32_t byte_off, float v) {
   else stb(base, byte_off, (S)v);
 }
 
-__device__ __forceinline__ void wrap_corr(const Params& p, uint32_t lk, int (&wc)[6]) {
-  const int nxy = (int)p.nxy;
-  wc[0] = (lk >> (LK_FACE + 0)) & 1 ? p.nx : 0;
-  wc[1] = (lk >> (LK_FACE + 1)) & 1 ? -p.nx : 0;
-  wc[2] = (lk >> (LK_FACE + 2)) & 1 ? p.ny * p.nx : 0;
-  wc[3] = (lk >> (LK_FACE + 3)) & 1 ? -p.ny * p.nx : 0;
-  wc[4] = (lk >> (LK_FACE + 4)) & 1 ? p.nz * nxy : 0;
-  wc[5] = (lk >> (LK_FACE + 5)) & 1 ? -p.nz * nxy : 0;
+// Byte offset of the slot holding f_I(t, x) at parity ODD.
+template <int I, bool ODD, class S>
+__device__ __forceinline__ uint32_t slot_in(const Params& p, uint32_t c, uint32_t lk, const Pos& q) {
+  constexpr uint32_t SB = sizeof(S);
+  if (!ODD || I == 0) return p.plb[I] + c * SB;
+  const bool bb = (lk >> I) & 1u;
+  return bb ? p.plb[I] + c * SB : p.plb[OPP[I]] + src_of<I>(p, q) * SB;
+}
+// Byte offset of the slot receiving q_I(x) at parity ODD.
+template <int I, bool ODD, class S>
+__device__ __forceinline__ uint32_t slot_out(const Params& p, uint32_t c, uint32_t lk, const Pos& q) {
+  constexpr uint32_t SB = sizeof(S);
+  constexpr int J = OPP[I];
+  if (!ODD || I == 0) return p.plb[J] + c * SB;
+  const bool wall = (lk >> J) & 1u;  // x + c_I = x - c_J is not a fluid cell
+  return wall ? p.plb[J] + c * SB : p.plb[I] + src_of<J>(p, q) * SB;
 }
 
-// Pull: v_i(x) = stored value at x - c_i, or the cell's own opposite value when
-// that link bounces back (solid or outside; the open-face unknowns are then
-// replaced by the Zou-He fill).  Unless UNI, also pt[j] = porosity of x + c_j
-// (phi(x) across walls) for the producer side.
-template <class S, bool SHW, bool UNI, bool PER>
-__device__ __forceinline__ void pull(const Params& p, const S* __restrict__ A, const float* __restrict__ phi,
-                                     uint32_t idx, uint32_t lk, const int (&wc)[6], float phx, float v[Q],
-                                     float pt[Q]) {
-  constexpr uint32_t SB = sizeof(S);
-  const uint32_t ib = idx * SB;
-  v[0] = ld_pop(A, ib);
+// Pull: v_i(x) = f_i(t, x) (the cell's own opposite output across a wall; the
+// open-face unknowns are then replaced by the Zou-He fill).  Unless UNI, also
+// pt[j] = porosity of x + c_j (phi(x) across walls) for the producer side.
+template <class S, bool SHW, bool UNI, bool ODD>
+__device__ __forceinline__ void pull(const Params& p, const S* A, const float* __restrict__ phi, uint32_t c,
+                                     uint32_t lk, const Pos& q, float phx, float v[Q], float pt[Q]) {
+  v[0] = ld_pop(A, slot_in<0, ODD, S>(p, c, lk, q));
   pt[0] = phx;
   sfor<1, Q>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
     constexpr int J = OPP[I];
-    const bool bb = (lk >> I) & 1u;
-    const int o = nb_off<-CX[I], -CY[I], -CZ[I], PER>(p, wc);
-    const uint32_t a_bb = p.plb[J] + ib;
-    const uint32_t a_nb = p.plb[I] + ib + (uint32_t)(o * (int)SB);
-    v[I] = ld_pop(A, bb ? a_bb : a_nb);
+    v[I] = ld_pop(A, slot_in<I, ODD, S>(p, c, lk, q));
     if (!UNI) {
-      // a bounced link reads the cell's own porosity, which is what phi~ is then
-      const uint32_t pidx = idx + (bb ? 0u : (uint32_t)o);
-      pt[J] = ldo(phi, pidx);
+      const bool bb = (lk >> I) & 1u;
+      pt[J] = ldo(phi, bb ? c : src_of<I>(p, q));
     } else {
       pt[J] = phx;
     }
@@ -201,7 +221,7 @@ __device__ __forceinline__ void pull(const Params& p, const S* __restrict__ A, c
 
 // Zou-He fill of the unknown populations on the open faces (phi = 1 there, so
 // the closures hold for the deviations as for the populations).
-__device__ __forceinline__ void open_fill(const Params& p, uint32_t idx, uint32_t lk, float amp,
+__device__ __forceinline__ void open_fill(const Params& p, uint32_t row, uint32_t lk, float amp,
                                           const float* __restrict__ shape, float d[Q]) {
   const bool in = (lk & LK_IN) != 0;
   const bool outl = (lk & LK_OUT) != 0;
@@ -211,7 +231,7 @@ __device__ __forceinline__ void open_fill(const Params& p, uint32_t idx, uint32_
   const float ny_ = 0.5f * (d[3] - d[4] + d[15] - d[16] + d[17] - d[18]);
   const float nz_ = 0.5f * (d[5] - d[6] + d[15] - d[16] - d[17] + d[18]);
   // inflow: prescribed u = (ux, 0, 0); density from mass and normal momentum
-  const float uin = in ? amp * shape[div_nx(p, idx)] : 0.0f;
+  const float uin = in ? amp * shape[row] : 0.0f;
   const float sm = d[2] + d[8] + d[10] + d[12] + d[14];
   const float rin = (1.0f + (s0 + 2.0f * sm) * iU) / (1.0f - uin);
   // outflow: prescribed density, normal velocity from mass and the known half
@@ -360,9 +380,9 @@ __device__ __forceinline__ void macro(const Params& p, float phx_f, const float 
 // difference to the intended momentum (input momentum + force + porosity-jump
 // momentum) onto the three axis pairs, leaving only the final rounding of
 // each stored value.
-template <class S, bool SHW, bool UNI, class R, bool PROJ>
-__device__ __forceinline__ void collide_store(const Params& p, S* __restrict__ B, uint32_t idx, float phx_f,
-                                              const float d[Q], const float pt[Q], const Macro<R>& M) {
+template <class S, bool SHW, bool UNI, bool ODD, class R, bool PROJ>
+__device__ __forceinline__ void collide_store(const Params& p, S* A, uint32_t c, uint32_t lk, const Pos& q,
+                                              float phx_f, const float d[Q], const float pt[Q], const Macro<R>& M) {
   const R phx = (R)phx_f;
   const R om = M.omega;
   const R pr = phx * M.rho;
@@ -422,16 +442,16 @@ __device__ __forceinline__ void collide_store(const Params& p, S* __restrict__ B
     o[3] = (float)((double)o[3] + ry); o[4] = (float)((double)o[4] - ry);
     o[5] = (float)((double)o[5] + rz); o[6] = (float)((double)o[6] - rz);
   }
-  const uint32_t ib = idx * (uint32_t)sizeof(S);
   if (SHW) {
     // stored relative to w_i instead of w_i phi~_i
     const float ksf = p.f.ks;
 #pragma unroll
     for (int i = 0; i < Q; ++i) o[i] += ksf * kw(i) * ((UNI ? phx_f : pt[i]) - 1.0f);
   }
-  st_pop(B, ib, o[0]);
-#pragma unroll
-  for (int i = 1; i < Q; ++i) st_pop(B, p.plb[i] + ib, o[i]);
+  sfor<0, Q>([&](auto ic) {
+    constexpr int I = decltype(ic)::value;
+    st_pop(A, slot_out<I, ODD, S>(p, c, lk, q), o[I]);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -491,52 +511,52 @@ __device__ __forceinline__ void diag_terms(const Params& p, float phx, const flo
 
 // Body of the step for one cell (UNI: the whole wave has uniform neighbour
 // porosity).
-template <class S, bool SHW, bool UNI, bool PER, int DIAG, bool REC, class R, bool PROJ>
-__device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32_t c, float amp,
+template <class S, bool SHW, bool UNI, bool ODD, int DIAG, bool REC, class R, bool PROJ>
+__device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32_t c, uint32_t lk, float amp,
                                           double (&dv)[NDIAGP], float& ke_reg) {
-  const uint32_t idx = b.cells[c];
-  const uint32_t lk = b.links[c];
-  const float phx = ldo(b.phi, idx);
-  int wc[6] = {0, 0, 0, 0, 0, 0};
-  if (PER) wrap_corr(p, lk, wc);
+  Pos q = position(p, c, b.code[c]);
+  if (ODD || !UNI) load_deltas(b.delta, q);
+  const float phx = ldo(b.phi, c);
   float d[Q], pt[Q];
-  pull<S, SHW, UNI, PER>(p, (const S*)b.A, b.phi, idx, lk, wc, phx, d, pt);
+  S* A = (S*)b.A;
+  pull<S, SHW, UNI, ODD>(p, A, b.phi, c, lk, q, phx, d, pt);
   if (REC) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) b.rec[(size_t)i * p.nf + c] = d[i];
+    for (int i = 0; i < Q; ++i) b.rec[(size_t)i * p.nc + c] = d[i];
   }
-  open_fill(p, idx, lk, amp, b.shape, d);
+  open_fill(p, q.row, lk, amp, b.shape, d);
   const float omp = b.omega[c];
   Macro<R> M;
   macro<R>(p, phx, d, omp, M);
   b.omega[c] = (float)M.omega;
   if (REC) {
-    b.rec[(size_t)Q * p.nf + c] = omp;
-    b.rho_box[idx] = (float)M.rho;
+    b.rec[(size_t)Q * p.nc + c] = omp;
+    b.rho_rec[c] = (float)M.rho;
   }
   const bool reg = (lk & LK_REG) != 0;
   if (DIAG == 1) diag_terms<R>(p, phx, d, M, reg, true, dv);
   if (DIAG == 2) ke_reg = reg ? (float)((R)0.5 * M.rho * M.uu) : 0.0f;
-  collide_store<S, SHW, UNI, R, PROJ>(p, (S*)b.B, idx, phx, d, pt, M);
+  collide_store<S, SHW, UNI, ODD, R, PROJ>(p, A, c, lk, q, phx, d, pt, M);
 }
 
 // ---------------------------------------------------------------------------
-// The step.  DIAG: 0 none, 1 diagnostics of the pre-collision state into
-// part[block][NDIAGP], 2 region kinetic energy accumulated into part[block].
-// REC: also record the pulled values and omega_prev ([20][nf]) and rho (box).
+// The step at parity ODD (t odd).  DIAG: 0 none, 1 diagnostics of the
+// pre-collision state into part[block][NDIAGP], 2 region kinetic energy
+// accumulated into part[block].  REC: also record the pulled values and
+// omega_prev ([20][nc]) and rho.
 // ---------------------------------------------------------------------------
-template <class S, bool SHW, bool PER, int DIAG, bool REC, class R, bool PROJ>
+template <class S, bool SHW, bool ODD, int DIAG, bool REC, class R, bool PROJ>
 __global__ __launch_bounds__(BLOCK) void k_step(Params p, Bufs b, float amp) {
-  const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-  const uint32_t c = blk * BLOCK + threadIdx.x;
-  const bool active = c < (uint32_t)p.nf;
+  const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
+  const uint32_t lk = c < (uint32_t)p.nc ? b.links[c] : LK_DEAD;
+  const bool active = !(lk & LK_DEAD);
   double dv[NDIAGP];
   float ke_reg = 0.0f;
-  const bool uni = !active || (b.links[active ? c : 0] & LK_UNI);
+  const bool uni = !active || (lk & LK_UNI);
   if (__all(uni)) {
-    if (active) step_cell<S, SHW, true, PER, DIAG, REC, R, PROJ>(p, b, c, amp, dv, ke_reg);
+    if (active) step_cell<S, SHW, true, ODD, DIAG, REC, R, PROJ>(p, b, c, lk, amp, dv, ke_reg);
   } else {
-    if (active) step_cell<S, SHW, false, PER, DIAG, REC, R, PROJ>(p, b, c, amp, dv, ke_reg);
+    if (active) step_cell<S, SHW, false, ODD, DIAG, REC, R, PROJ>(p, b, c, lk, amp, dv, ke_reg);
   }
   if (DIAG == 1) {
     if (!active) {
@@ -556,37 +576,37 @@ __global__ __launch_bounds__(BLOCK) void k_step(Params p, Bufs b, float amp) {
   }
 }
 
-// Moments of the current state (no collision): dense outputs (any may be null)
-// and optionally the diagnostics partials.
-template <class S, bool SHW, bool DIAG, class R>
-__global__ __launch_bounds__(BLOCK) void k_moments(Params p, Bufs b, float amp, float* rho_o, float* u_o,
-                                                    float* shear_o, float* omega_o, float* sigma_o) {
+// Moments of the current state (no collision): dense box outputs (any may be
+// null) and optionally the diagnostics partials.
+template <class S, bool SHW, bool ODD, bool DIAG, class R>
+__global__ __launch_bounds__(BLOCK) void k_moments(Params p, Bufs b, float amp, size_t nbox, float* rho_o,
+                                                    float* u_o, float* shear_o, float* omega_o, float* sigma_o) {
   const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
-  const bool active = c < (uint32_t)p.nf;
+  const uint32_t lk = c < (uint32_t)p.nc ? b.links[c] : LK_DEAD;
+  const bool active = !(lk & LK_DEAD);
   double dv[NDIAGP];
   if (active) {
-    const uint32_t idx = b.cells[c];
-    const uint32_t lk = b.links[c];
-    const float phx = ldo(b.phi, idx);
-    int wc[6] = {0, 0, 0, 0, 0, 0};
-    if (p.anyper) wrap_corr(p, lk, wc);
+    Pos q = position(p, c, b.code[c]);
+    if (ODD) load_deltas(b.delta, q);
+    const float phx = ldo(b.phi, c);
     float d[Q], pt[Q];
-    pull<S, SHW, true, true>(p, (const S*)b.A, b.phi, idx, lk, wc, phx, d, pt);
-    open_fill(p, idx, lk, amp, b.shape, d);
+    pull<S, SHW, true, ODD>(p, (const S*)b.A, b.phi, c, lk, q, phx, d, pt);
+    open_fill(p, q.row, lk, amp, b.shape, d);
     Macro<R> M;
     macro<R>(p, phx, d, b.omega[c], M);
+    const size_t idx = (size_t)b.rowbox[q.row] + (size_t)q.x;
     if (rho_o) rho_o[idx] = (float)M.rho;
     if (u_o) {
       u_o[idx] = (float)M.ux;
-      u_o[(size_t)p.nbox + idx] = (float)M.uy;
-      u_o[2 * (size_t)p.nbox + idx] = (float)M.uz;
+      u_o[nbox + idx] = (float)M.uy;
+      u_o[2 * nbox + idx] = (float)M.uz;
     }
     if (shear_o) shear_o[idx] = M.shear;
     if (omega_o) omega_o[idx] = (float)M.omega;
     if (sigma_o) {
       const R s = (R)0.5 * M.omega - (R)1;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) sigma_o[(size_t)k * p.nbox + idx] = (float)(s * M.P[k]);
+      for (int k = 0; k < 6; ++k) sigma_o[(size_t)k * nbox + idx] = (float)(s * M.P[k]);
     }
     if (DIAG) diag_terms<R>(p, phx, d, M, (lk & LK_REG) != 0, true, dv);
   } else if (DIAG) {
@@ -625,83 +645,67 @@ __global__ __launch_bounds__(BLOCK) void k_finalize(const double* part, int nblk
   }
 }
 
-// Rest state: every consumer reads f_i = w_i phi(x).
+// Rest state at even parity: slot (i, x) holds f_i(x) = w_i phi(x), which is
+// 0 in shift mode 0 and U w_i (phi(x) - 1) in shift mode 1.
 template <class S, bool SHW>
 __global__ __launch_bounds__(BLOCK) void k_init(Params p, Bufs b, float omega0) {
   const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
-  if (c >= (uint32_t)p.nf) return;
-  const uint32_t idx = b.cells[c];
-  const uint32_t lk = b.links[c];
-  const float phx = ldo(b.phi, idx);
-  int wc[6] = {0, 0, 0, 0, 0, 0};
-  if (p.anyper) wrap_corr(p, lk, wc);
-  S* B = (S*)b.B;
+  if (c >= (uint32_t)p.nc) return;
+  if (b.links[c] & LK_DEAD) return;
+  const float phx = ldo(b.phi, c);
+  S* A = (S*)b.A;
   const float ks = p.f.ks;
-  Store<S>::st(B, idx, SHW ? ks * kw(0) * (phx - 1.0f) : 0.0f, 0);
-  sfor<1, Q>([&](auto ic) {
-    constexpr int I = decltype(ic)::value;
-    // porosity of x + c_I (phi(x) when that link bounces, i.e. when the pull of
-    // the opposite direction bounces)
-    const bool bb = (lk >> OPP[I]) & 1u;
-    const float pn = bb ? phx : ldo(b.phi, idx + (uint32_t)nb_off<CX[I], CY[I], CZ[I]>(p, wc));
-    Store<S>::st(B, (uint32_t)I * p.nbox + idx, SHW ? ks * kw(I) * (pn - 1.0f) : 0.0f, I);
-  });
+#pragma unroll
+  for (int i = 0; i < Q; ++i) st_pop(A, p.plb[i] + c * (uint32_t)sizeof(S), SHW ? ks * kw(i) * (phx - 1.0f) : 0.0f);
   b.omega[c] = omega0;
 }
 
-// Whether the pull of direction I at this cell reads an open-face unknown
-// (source outside the inflow/outflow face and not outside a wall face).
+// Whether the pull of direction I reads an open-face unknown (flags set on
+// the host: source outside the inflow/outflow face, not outside a wall face).
 template <int I>
-__device__ __forceinline__ bool open_unknown(const Params& p, uint32_t idx, uint32_t lk) {
+__device__ __forceinline__ bool open_unknown(uint32_t lk) {
   if (CX[I] == 0) return false;
-  if (CX[I] == 1 && !(lk & LK_IN)) return false;
-  if (CX[I] == -1 && !(lk & LK_OUT)) return false;
-  const uint32_t q = div_nx(p, idx);  // y + ny z
-  const uint32_t z = q / (uint32_t)p.ny, y = q - z * (uint32_t)p.ny;
-  const int sy = (int)y - CY[I], sz = (int)z - CZ[I];
-  const bool wall = (!p.py && (sy < 0 || sy >= p.ny)) || (!p.pz && (sz < 0 || sz >= p.nz));
-  return !wall;
+  int k = -1;
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    if ((lk & LK_IN) && XIN[j] == I) k = j;
+    if ((lk & LK_OUT) && XOUT[j] == I) k = j;
+  }
+  return k >= 0 && ((lk >> (LK_UNK + k)) & 1u);
 }
 
-// State out: the pulled (pre-collision) stored values as FP32, [19][nf]; the
+// State out: the pulled (pre-collision) stored values as FP32, [19][nc]; the
 // host converts them back to populations in FP64.  Open-face unknowns are NaN.
-template <class S>
+template <class S, bool ODD>
 __global__ __launch_bounds__(BLOCK) void k_gather_state(Params p, Bufs b, float* out) {
   const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
-  if (c >= (uint32_t)p.nf) return;
-  const uint32_t idx = b.cells[c];
+  if (c >= (uint32_t)p.nc) return;
   const uint32_t lk = b.links[c];
-  int wc[6] = {0, 0, 0, 0, 0, 0};
-  if (p.anyper) wrap_corr(p, lk, wc);
+  if (lk & LK_DEAD) return;
+  Pos q = position(p, c, b.code[c]);
+  if (ODD) load_deltas(b.delta, q);
   const S* A = (const S*)b.A;
-  out[c] = Store<S>::ld(A, idx, 0);
-  sfor<1, Q>([&](auto ic) {
+  sfor<0, Q>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
-    const bool bb = (lk >> I) & 1u;
-    const uint32_t src = idx + (uint32_t)nb_off<-CX[I], -CY[I], -CZ[I]>(p, wc);
-    const uint32_t e = bb ? (uint32_t)OPP[I] * p.nbox + idx : (uint32_t)I * p.nbox + src;
-    out[(size_t)I * p.nf + c] = open_unknown<I>(p, idx, lk) ? __builtin_nanf("") : Store<S>::ld(A, e, I);
+    const float v = ld_pop(A, slot_in<I, ODD, S>(p, c, lk, q));
+    out[(size_t)I * p.nc + c] = open_unknown<I>(lk) ? __builtin_nanf("") : v;
   });
 }
 
-// State in: inverse of k_gather_state; each stored slot that some consumer
-// reads is written exactly once (by that consumer's link).
-template <class S>
+// State in: inverse of k_gather_state; each slot that some consumer reads is
+// written exactly once (by that consumer's link).
+template <class S, bool ODD>
 __global__ __launch_bounds__(BLOCK) void k_scatter_state(Params p, Bufs b, const float* in) {
   const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
-  if (c >= (uint32_t)p.nf) return;
-  const uint32_t idx = b.cells[c];
+  if (c >= (uint32_t)p.nc) return;
   const uint32_t lk = b.links[c];
-  int wc[6] = {0, 0, 0, 0, 0, 0};
-  if (p.anyper) wrap_corr(p, lk, wc);
-  S* A = (S*)b.B;
-  Store<S>::st(A, idx, in[c], 0);
-  sfor<1, Q>([&](auto ic) {
+  if (lk & LK_DEAD) return;
+  Pos q = position(p, c, b.code[c]);
+  if (ODD) load_deltas(b.delta, q);
+  S* A = (S*)b.A;
+  sfor<0, Q>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
-    const bool bb = (lk >> I) & 1u;
-    const uint32_t src = idx + (uint32_t)nb_off<-CX[I], -CY[I], -CZ[I]>(p, wc);
-    const uint32_t e = bb ? (uint32_t)OPP[I] * p.nbox + idx : (uint32_t)I * p.nbox + src;
-    if (!open_unknown<I>(p, idx, lk)) Store<S>::st(A, e, in[(size_t)I * p.nf + c], I);
+    if (!open_unknown<I>(lk)) st_pop(A, slot_in<I, ODD, S>(p, c, lk, q), in[(size_t)I * p.nc + c]);
   });
 }
 

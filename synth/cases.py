@@ -274,7 +274,8 @@ def tiny_case(kind: str = "open", seed: int = 0, nx: int = 9, ny: int = 7, nz: i
     on x = 0 and density outlet on x = nx - 1 (porosity 1 there), random porosity
     in [0.6, 1] elsewhere, fluid cells also touching the y/z faces (treated as
     walls).  ``periodic``: periodic x and z, solid layers at y = 0 and ny - 1 plus
-    random solid voxels, random porosity, body force.
+    random solid voxels, random porosity, body force.  ``periodic3``: periodic
+    in all three axes, random solid voxels, random porosity, body force.
     """
     rng = np.random.default_rng(1000 + seed)
     solid = (rng.random((nz, ny, nx)) < 0.15).astype(np.uint8)
@@ -299,6 +300,10 @@ def tiny_case(kind: str = "open", seed: int = 0, nx: int = 9, ny: int = 7, nz: i
         case = Case(name=f"tiny_periodic{seed}", nx=nx, ny=ny, nz=nz, periodic=(True, False, True),
                     solid=solid, phi=phi, sac=sac,
                     porous=dict(nu_d=0.1, kc=180.0, d=2.0, forchheimer=0, g=(2e-5, -1e-5, 5e-6)))
+    elif kind == "periodic3":
+        case = Case(name=f"tiny_periodic3_{seed}", nx=nx, ny=ny, nz=nz, periodic=(True, True, True),
+                    solid=solid, phi=phi, sac=sac,
+                    porous=dict(nu_d=0.1, kc=180.0, d=2.0, forchheimer=0, g=(1e-5, 2e-5, -1e-5)))
     else:
         raise ValueError(kind)
     case.phi = np.where(case.solid == 0, case.phi, 0.0).astype(np.float32)

@@ -55,9 +55,14 @@ def test_workspace_size_and_validation():
         lbm.lbm_workspace_size(_grid(nx=4096), np.zeros((5, 6, 4096), np.uint8))
     with pytest.raises(lbm.LBMError):
         lbm.lbm_workspace_size(g, np.ones((5, 6, 8), np.uint8))  # no fluid
-    # too large for 32-bit offsets
-    with pytest.raises(lbm.LBMError):
-        lbm.lbm_workspace_size(_grid(nx=2048, ny=1024, nz=1024), np.zeros(1, np.uint8))
+    # more compact cells than 32-bit byte offsets into 19 FP32 planes allow
+    # (58.7 M all-fluid cells); the same box with a sparse mask is accepted
+    big = np.zeros((224, 512, 512), np.uint8)
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.lbm_workspace_size(_grid(nx=512, ny=512, nz=224), big)
+    assert "offsets" in str(e.value)
+    big[:, :, 256:] = 1
+    assert lbm.lbm_workspace_size(_grid(nx=512, ny=512, nz=224), big) > 0
 
 
 def _create(g, solid, phi, rh=(0.1, 0.01, 50.0, 0.36, 2.0), po=(0.1, 2.0, 180.0), op=None, ws=4096,
