@@ -3,8 +3,9 @@
 Prints ONE JSON line.  The workload is the 512x320x320 tube-and-sac aneurysm
 (tube radius 32, sac radius 56, GRF sac porosity with correlation length 10,
 2 360 212 fluid cells): fluid-cell MLUPS with FP32 population storage is the
-headline ``value``; FP16 and BF16 storage (and the adjoint, when built) are
-reported on the same geometry under ``forms``.  A step is one time step of the
+headline ``value``; FP16 and BF16 storage and the adjoint (porosity gradient of
+the sac kinetic energy: forward pass, checkpointed recompute and reverse sweep,
+timed as one call) are reported on the same geometry under ``forms``.  A step is one time step of the
 whole hot path: pull-streaming with bounce-back and open-face fill, porosity-
 weighted moments, drag-corrected velocity, equilibrium and Pi, Carreau-Yasuda
 relaxation rate, collision and store (plus the FP64 stability reduction every
@@ -30,7 +31,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak
-B_ALG = {"fp32": 164, "fp16": 88, "bf16": 88}  # algorithmic bytes per fluid-cell update
+# algorithmic bytes per fluid-cell update: populations read + written, porosity,
+# relaxation rate read + written
+B_ALG = {"fp32": 164, "fp16": 88, "bf16": 88}
+# the adjoint call per fluid cell and time step: forward pass (164), recompute
+# with the record written (164 + 19*4 pulled values + omega_prev 4 + rho 4 = 248)
+# and the reverse step (record 80, adjoint populations gathered 76 and written
+# 76, porosity 4, neighbour rho 4, omega adjoint r/w 8, FP64 porosity adjoint
+# r/w 16 = 264)
+B_ALG_ADJ = 164 + 248 + 264
 
 
 def log(msg):
@@ -94,6 +103,26 @@ def copy_probe(torch, nbytes=4 << 30, reps=10):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def time_adjoint(torch, case, T: int, ckpt: int):
+    """Wall time of one lbm_adjoint call (forward pass with checkpoints,
+    segment recompute and reverse sweep) over T steps, window [T/2, T)."""
+    from paper_2402_10809_amd import Solver
+
+    s = Solver.from_case(case, adjoint_T=T, ckpt=ckpt)
+    tb, te = T // 2, T
+    s.adjoint(tb, te, T, ckpt)  # warm-up call
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, g = s.adjoint(tb, te, T, ckpt)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ok = bool(np.isfinite(J)) and bool(torch.isfinite(g).all().item())
+    s.close()
+    del s, g
+    torch.cuda.empty_cache()
+    return dt, ok
+
+
 def cpu_baseline(case, budget_s: float):
     """The FP64 oracle (as it stands) on a bounded number of steps of the same
     geometry, on this host's cores."""
@@ -104,7 +133,7 @@ def cpu_baseline(case, budget_s: float):
     t0 = time.perf_counter()
     o.run(f, om, 0, 1)
     one = time.perf_counter() - t0
-    n = max(1, min(50, int(budget_s / max(one, 1e-3))))
+    n = max(1, min(400, int(budget_s / max(one, 1e-3))))
     t0 = time.perf_counter()
     o.run(f, om, 1, n)
     dt = time.perf_counter() - t0
@@ -119,7 +148,9 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--config", default="c2")
-    ap.add_argument("--forms", default="fp16,bf16")
+    ap.add_argument("--forms", default="fp16,bf16,adjoint")
+    ap.add_argument("--adj-T", type=int, default=400)
+    ap.add_argument("--adj-ckpt", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--only", default=None, help="time one storage form only (profiling runs)")
@@ -146,6 +177,17 @@ def main():
     forms = ["fp32"] + [f for f in args.forms.split(",") if f]
     if args.only:
         forms = [args.only]
+    adjoint = None
+    if "adjoint" in forms:
+        forms.remove("adjoint")
+        T, ck = args.adj_T, args.adj_ckpt
+        log(f"[bench] adjoint: T={T}, checkpoint every {ck}, window [{T // 2}, {T})")
+        dt, ok = time_adjoint(torch, case, T, ck)
+        mlups = case.n_fluid * T / dt / 1e6
+        gbs = mlups * 1e6 * B_ALG_ADJ / 1e9
+        adjoint = dict(T=T, ckpt=ck, seconds=round(dt, 4), mlups=round(mlups, 1), bytes_per_update=B_ALG_ADJ,
+                       alg_GBps=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4), finite=ok)
+        log(f"[bench] adjoint: {dt * 1e3:.1f} ms, {mlups:.0f} M cell-steps/s, {gbs:.0f} GB/s algorithmic")
     for form in forms:
         s = Solver.from_case(case, storage=form)
         log(f"[bench] {form}: timing {args.steps} steps after {args.warmup} warmup")
@@ -198,6 +240,8 @@ def main():
                       "ms_per_step": round(v["ms_per_step"], 5)} for k, v in results.items()},
         "copy_probe_GBps": round(probe, 1),
     }
+    if adjoint is not None:
+        line["forms"]["adjoint"] = adjoint
     print(json.dumps(line), flush=True)
 
 
