@@ -201,7 +201,9 @@ lbm_status lbm_reset(lbm_ctx* ctx);
  * workspace sized for (T, ckpt_every) or larger; FP32 storage, shift mode 0,
  * no Forchheimer drag, a non-empty region, 0 <= t_begin < t_end <= T.
  *   J:       host, 1 double
- *   dJ_dphi: device, nx*ny*nz floats (box layout, 0 off the fluid), may be NULL
+ *   dJ_dphi: device, nx*ny*nz floats (box layout, 0 off the fluid), or NULL:
+ *            then only J is computed (the forward pass, no checkpoints; the
+ *            workspace of lbm_create suffices)
  * Leaves the context at the rest state (t = 0); syncs the stream. */
 lbm_status lbm_adjoint(lbm_ctx* ctx, const lbm_objective* obj, int T, int ckpt_every, double* J, float* dJ_dphi);
 

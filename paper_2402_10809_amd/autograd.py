@@ -1,0 +1,45 @@
+"""The sac kinetic-energy objective as a differentiable function of the porosity.
+
+``sac_kinetic_energy(phi, solver, t_begin, t_end, T)`` returns
+J(phi) = time average over steps [t_begin, t_end) of the region mean of
+rho |u|^2 / 2, for a run of T steps from rest with porosity phi.  When phi
+requires a gradient, the forward call runs ``lbm_adjoint``, which returns J and
+dJ/dphi together (hand-written reverse steps over checkpointed segments); the
+backward pass scales that gradient.  Otherwise only J is computed.
+
+phi is the dense box porosity (nz, ny, nx), FP32, on any device; it must keep
+the solver's solid mask (0 on solid voxels, in (0, 1] on fluid, 1 on open
+faces).  The solver is reset to the rest state by every evaluation.
+"""
+
+from __future__ import annotations
+
+from typing import Optional
+
+import numpy as np
+import torch
+
+
+class SacKineticEnergy(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, phi: torch.Tensor, solver, t_begin: int, t_end: int, T: int, ckpt: Optional[int]):
+        solver.set_porosity(phi.detach().to("cpu", torch.float32).numpy().astype(np.float32))
+        ctx.phi_device = phi.device
+        if ctx.needs_input_grad[0]:
+            J, g = solver.adjoint(t_begin, t_end, T, ckpt)
+            ctx.save_for_backward(g)
+        else:
+            J = solver.objective(t_begin, t_end, T)
+        return torch.tensor(J, dtype=torch.float64, device=phi.device)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (g,) = ctx.saved_tensors
+        gphi = (grad_out.to(g.device, torch.float64) * g.to(torch.float64)).to(torch.float32)
+        return gphi.to(ctx.phi_device), None, None, None, None, None
+
+
+def sac_kinetic_energy(phi: torch.Tensor, solver, t_begin: int, t_end: int, T: int,
+                       ckpt: Optional[int] = None) -> torch.Tensor:
+    """Differentiable J(phi); see the module docstring."""
+    return SacKineticEnergy.apply(phi, solver, int(t_begin), int(t_end), int(T), ckpt)

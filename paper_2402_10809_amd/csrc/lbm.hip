@@ -589,6 +589,7 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* solid, const float* p
   P.outlet = (op && op->outlet) ? 1 : 0;
   P.xbits = xb;
   for (int i = 0; i < Q; ++i) P.plb[i] = (uint32_t)((size_t)i * c->nc * store_bytes(grid->storage));
+  P.abytes = (uint32_t)((size_t)Q * c->nc * store_bytes(grid->storage));
   {
     Params::K<double> k{};
     k.U = c->U; k.iU = 1.0 / c->U; k.ks = c->U / 36.0;

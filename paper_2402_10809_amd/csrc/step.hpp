@@ -67,6 +67,7 @@ struct Params {
   int inlet, outlet;
   int xbits;                   // code = (row << xbits) | x
   uint32_t plb[Q];             // byte offset of population plane i (i * nc * sizeof(storage))
+  uint32_t abytes;             // byte size of the population buffer
   int cy_a2;                   // a == 2: (lambda g)^a is one multiply
   int forch;                   // Forchheimer drag on
   // physical constants in both precisions (the kernels read the one they
@@ -127,16 +128,19 @@ __device__ __forceinline__ double rsqrt_(double x) { return __builtin_sqrt(x); }
 __device__ __forceinline__ float rfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double rfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-// Position of a compact cell and the deltas of its neighbour rows.
+// Position of a compact cell and the deltas of its neighbour rows.  xm / xp
+// are x - 1 / x + 1, wrapped on a periodic x axis.
 struct Pos {
   uint32_t row;
-  int x;
+  int x, xm, xp;
   int dl[NPAIR];
 };
 __device__ __forceinline__ Pos position(const Params& p, uint32_t c, uint32_t code) {
   Pos q;
   q.row = code >> p.xbits;
   q.x = (int)(code & ((1u << p.xbits) - 1u));
+  q.xm = q.x - 1 + ((p.px && q.x == 0) ? p.nx : 0);
+  q.xp = q.x + 1 - ((p.px && q.x == p.nx - 1) ? p.nx : 0);
   q.dl[0] = (int)c - q.x;
   return q;
 }
@@ -148,10 +152,8 @@ __device__ __forceinline__ void load_deltas(const int* __restrict__ delta, Pos& 
 }
 // Compact index of x - c_I (valid when that cell is fluid).
 template <int I>
-__device__ __forceinline__ uint32_t src_of(const Params& p, const Pos& q) {
-  int xs = q.x - CX[I];
-  if (CX[I] == 1) xs += (p.px && xs < 0) ? p.nx : 0;
-  if (CX[I] == -1) xs -= (p.px && xs >= p.nx) ? p.nx : 0;
+__device__ __forceinline__ uint32_t src_of(const Params&, const Pos& q) {
+  const int xs = CX[I] == 1 ? q.xm : (CX[I] == -1 ? q.xp : q.x);
   return (uint32_t)(xs + q.dl[PK[I]]);
 }
 
@@ -160,51 +162,69 @@ template <class T>
 __device__ __forceinline__ T ldb(const T* base, uint32_t byte_off) {
   return *(const T*)((const char*)base + byte_off);
 }
-template <class T>
-__device__ __forceinline__ void stb(T* base, uint32_t byte_off, T v) {
-  *(T*)((char*)base + byte_off) = v;
-}
-template <class S>
-__device__ __forceinline__ float ld_pop(const S* base, uint32_t byte_off) {
-  if constexpr (std::is_same<S, float>::value) return ldb(base, byte_off);
-  else return (float)ldb(base, byte_off);
-}
-template <class S>
-__device__ __forceinline__ void st_pop(S* base, uint32_t byte_off, float v) {
-  if constexpr (std::is_same<S, float>::value) stb(base, byte_off, v);
-  else stb(base, byte_off, (S)v);
-}
 
-// Byte offset of the slot holding f_I(t, x) at parity ODD.
+// The population buffer as a raw buffer resource: every access is a 32-bit
+// byte offset split into a per-lane part (VGPR) and a wave-uniform part
+// (SGPR soffset), so the 19 plane offsets of a local access cost no vector
+// instructions.  The resource's size is the buffer's byte size.
+template <class S>
+struct Pop {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ Pop(const void* base, uint32_t bytes)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000)) {}
+  __device__ __forceinline__ float ld(uint32_t voff, uint32_t soff) const {
+    if constexpr (std::is_same<S, float>::value) {
+      return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    } else {
+      const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
+      return (float)__builtin_bit_cast(S, h);
+    }
+  }
+  __device__ __forceinline__ void st(uint32_t voff, uint32_t soff, float v) const {
+    if constexpr (std::is_same<S, float>::value) {
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+    } else {
+      __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (S)v), r, voff, soff, 0);
+    }
+  }
+};
+
+// A slot address: per-lane and wave-uniform byte offsets.
+struct Slot {
+  uint32_t v, s;
+};
+
+// Slot holding f_I(t, x) at parity ODD.
 template <int I, bool ODD, class S>
-__device__ __forceinline__ uint32_t slot_in(const Params& p, uint32_t c, uint32_t lk, const Pos& q) {
+__device__ __forceinline__ Slot slot_in(const Params& p, uint32_t c, uint32_t lk, const Pos& q) {
   constexpr uint32_t SB = sizeof(S);
-  if (!ODD || I == 0) return p.plb[I] + c * SB;
+  if (!ODD || I == 0) return {c * SB, p.plb[I]};
   const bool bb = (lk >> I) & 1u;
-  return bb ? p.plb[I] + c * SB : p.plb[OPP[I]] + src_of<I>(p, q) * SB;
+  return {bb ? p.plb[I] + c * SB : p.plb[OPP[I]] + src_of<I>(p, q) * SB, 0u};
 }
-// Byte offset of the slot receiving q_I(x) at parity ODD.
+// Slot receiving q_I(x) at parity ODD.
 template <int I, bool ODD, class S>
-__device__ __forceinline__ uint32_t slot_out(const Params& p, uint32_t c, uint32_t lk, const Pos& q) {
+__device__ __forceinline__ Slot slot_out(const Params& p, uint32_t c, uint32_t lk, const Pos& q) {
   constexpr uint32_t SB = sizeof(S);
   constexpr int J = OPP[I];
-  if (!ODD || I == 0) return p.plb[J] + c * SB;
+  if (!ODD || I == 0) return {c * SB, p.plb[J]};
   const bool wall = (lk >> J) & 1u;  // x + c_I = x - c_J is not a fluid cell
-  return wall ? p.plb[J] + c * SB : p.plb[I] + src_of<J>(p, q) * SB;
+  return {wall ? p.plb[J] + c * SB : p.plb[I] + src_of<J>(p, q) * SB, 0u};
 }
 
 // Pull: v_i(x) = f_i(t, x) (the cell's own opposite output across a wall; the
 // open-face unknowns are then replaced by the Zou-He fill).  Unless UNI, also
 // pt[j] = porosity of x + c_j (phi(x) across walls) for the producer side.
 template <class S, bool SHW, bool UNI, bool ODD>
-__device__ __forceinline__ void pull(const Params& p, const S* A, const float* __restrict__ phi, uint32_t c,
+__device__ __forceinline__ void pull(const Params& p, const Pop<S>& A, const float* __restrict__ phi, uint32_t c,
                                      uint32_t lk, const Pos& q, float phx, float v[Q], float pt[Q]) {
-  v[0] = ld_pop(A, slot_in<0, ODD, S>(p, c, lk, q));
+  auto ld = [&](Slot a) { return A.ld(a.v, a.s); };
+  v[0] = ld(slot_in<0, ODD, S>(p, c, lk, q));
   pt[0] = phx;
   sfor<1, Q>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
     constexpr int J = OPP[I];
-    v[I] = ld_pop(A, slot_in<I, ODD, S>(p, c, lk, q));
+    v[I] = ld(slot_in<I, ODD, S>(p, c, lk, q));
     if (!UNI) {
       const bool bb = (lk >> I) & 1u;
       pt[J] = ldo(phi, bb ? c : src_of<I>(p, q));
@@ -381,7 +401,7 @@ __device__ __forceinline__ void macro(const Params& p, float phx_f, const float 
 // momentum) onto the three axis pairs, leaving only the final rounding of
 // each stored value.
 template <class S, bool SHW, bool UNI, bool ODD, class R, bool PROJ>
-__device__ __forceinline__ void collide_store(const Params& p, S* A, uint32_t c, uint32_t lk, const Pos& q,
+__device__ __forceinline__ void collide_store(const Params& p, const Pop<S>& A, uint32_t c, uint32_t lk, const Pos& q,
                                               float phx_f, const float d[Q], const float pt[Q], const Macro<R>& M) {
   const R phx = (R)phx_f;
   const R om = M.omega;
@@ -450,7 +470,8 @@ __device__ __forceinline__ void collide_store(const Params& p, S* A, uint32_t c,
   }
   sfor<0, Q>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
-    st_pop(A, slot_out<I, ODD, S>(p, c, lk, q), o[I]);
+    const Slot a = slot_out<I, ODD, S>(p, c, lk, q);
+    A.st(a.v, a.s, o[I]);
   });
 }
 
@@ -518,11 +539,12 @@ __device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32
   if (ODD || !UNI) load_deltas(b.delta, q);
   const float phx = ldo(b.phi, c);
   float d[Q], pt[Q];
-  S* A = (S*)b.A;
+  const Pop<S> A(b.A, p.abytes);
   pull<S, SHW, UNI, ODD>(p, A, b.phi, c, lk, q, phx, d, pt);
   if (REC) {
+    // the segment record is read once, by the reverse step: stream it past the caches
 #pragma unroll
-    for (int i = 0; i < Q; ++i) b.rec[(size_t)i * p.nc + c] = d[i];
+    for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(d[i], &b.rec[(size_t)i * p.nc + c]);
   }
   open_fill(p, q.row, lk, amp, b.shape, d);
   const float omp = b.omega[c];
@@ -530,8 +552,8 @@ __device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32
   macro<R>(p, phx, d, omp, M);
   b.omega[c] = (float)M.omega;
   if (REC) {
-    b.rec[(size_t)Q * p.nc + c] = omp;
-    b.rho_rec[c] = (float)M.rho;
+    __builtin_nontemporal_store(omp, &b.rec[(size_t)Q * p.nc + c]);
+    __builtin_nontemporal_store((float)M.rho, &b.rho_rec[c]);
   }
   const bool reg = (lk & LK_REG) != 0;
   if (DIAG == 1) diag_terms<R>(p, phx, d, M, reg, true, dv);
@@ -590,7 +612,7 @@ __global__ __launch_bounds__(BLOCK) void k_moments(Params p, Bufs b, float amp, 
     if (ODD) load_deltas(b.delta, q);
     const float phx = ldo(b.phi, c);
     float d[Q], pt[Q];
-    pull<S, SHW, true, ODD>(p, (const S*)b.A, b.phi, c, lk, q, phx, d, pt);
+    pull<S, SHW, true, ODD>(p, Pop<S>(b.A, p.abytes), b.phi, c, lk, q, phx, d, pt);
     open_fill(p, q.row, lk, amp, b.shape, d);
     Macro<R> M;
     macro<R>(p, phx, d, b.omega[c], M);
@@ -653,10 +675,10 @@ __global__ __launch_bounds__(BLOCK) void k_init(Params p, Bufs b, float omega0) 
   if (c >= (uint32_t)p.nc) return;
   if (b.links[c] & LK_DEAD) return;
   const float phx = ldo(b.phi, c);
-  S* A = (S*)b.A;
+  const Pop<S> A(b.A, p.abytes);
   const float ks = p.f.ks;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) st_pop(A, p.plb[i] + c * (uint32_t)sizeof(S), SHW ? ks * kw(i) * (phx - 1.0f) : 0.0f);
+  for (int i = 0; i < Q; ++i) A.st(c * (uint32_t)sizeof(S), p.plb[i], SHW ? ks * kw(i) * (phx - 1.0f) : 0.0f);
   b.omega[c] = omega0;
 }
 
@@ -684,10 +706,11 @@ __global__ __launch_bounds__(BLOCK) void k_gather_state(Params p, Bufs b, float*
   if (lk & LK_DEAD) return;
   Pos q = position(p, c, b.code[c]);
   if (ODD) load_deltas(b.delta, q);
-  const S* A = (const S*)b.A;
+  const Pop<S> A(b.A, p.abytes);
   sfor<0, Q>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
-    const float v = ld_pop(A, slot_in<I, ODD, S>(p, c, lk, q));
+    const Slot a = slot_in<I, ODD, S>(p, c, lk, q);
+    const float v = A.ld(a.v, a.s);
     out[(size_t)I * p.nc + c] = open_unknown<I>(lk) ? __builtin_nanf("") : v;
   });
 }
@@ -702,10 +725,11 @@ __global__ __launch_bounds__(BLOCK) void k_scatter_state(Params p, Bufs b, const
   if (lk & LK_DEAD) return;
   Pos q = position(p, c, b.code[c]);
   if (ODD) load_deltas(b.delta, q);
-  S* A = (S*)b.A;
+  const Pop<S> A(b.A, p.abytes);
   sfor<0, Q>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
-    if (!open_unknown<I>(lk)) st_pop(A, slot_in<I, ODD, S>(p, c, lk, q), in[(size_t)I * p.nc + c]);
+    const Slot a = slot_in<I, ODD, S>(p, c, lk, q);
+    if (!open_unknown<I>(lk)) A.st(a.v, a.s, in[(size_t)I * p.nc + c]);
   });
 }
 

@@ -257,6 +257,13 @@ class Solver:
         ph = np.ascontiguousarray(phi, dtype=np.float32)
         check(lib().lbm_set_porosity(self.ctx, _p(ph)))
 
+    def objective(self, t_begin: int, t_end: int, T: int) -> float:
+        """J alone (forward pass from rest, no gradient); the context ends at rest."""
+        obj = lbm_objective(int(t_begin), int(t_end))
+        J = ct.c_double(0.0)
+        check(lib().lbm_adjoint(self.ctx, ct.byref(obj), int(T), 1, ct.byref(J), None))
+        return float(J.value)
+
     def adjoint(self, t_begin: int, t_end: int, T: int, ckpt: Optional[int] = None):
         """J and dJ/dphi (device tensor, box layout) of the region kinetic energy."""
         t = self.torch

@@ -1,0 +1,71 @@
+"""Writes the stored expected values of the full-size adjoint check (the
+128x96x96 aneurysm: tube radius 8, sac radius 14, GRF sac porosity with
+correlation length 4; 4000 steps; objective = sac kinetic energy averaged over
+steps [3000, 4000)).  Every number comes from the FP64 oracle only:
+
+* J, and its central finite differences at 16 seeded sac voxels (eps = 1e-4);
+* the exact discrete derivative at the same voxels (dual numbers);
+* the checkpointed reverse sweep (checkpoints every 64 steps) over every sac
+  voxel.
+
+Run from the repository root: python tests/golden/make_adjoint_c4.py
+(about 10 minutes on 8 cores).
+"""
+
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from synth import fd_voxels, make_config  # noqa: E402
+
+T, TB, TE, CKPT, EPS = 4000, 3000, 4000, 64, 1e-4
+OUT = os.path.dirname(os.path.abspath(__file__))
+
+
+def main():
+    t0 = time.time()
+    case = make_config("c4")
+    vox = fd_voxels(case, 16, seed=16)
+    o = oracle.Oracle(case)
+    J = o.objective(T, TB, TE)
+    print(f"J = {J:.15e} ({time.time() - t0:.0f} s)", flush=True)
+    phi0 = case.phi.reshape(-1).astype(np.float64)
+    fd = []
+    for k, v in enumerate(vox):
+        js = []
+        for sgn in (1.0, -1.0):
+            ph = phi0.copy()
+            ph[v] += sgn * EPS
+            o.set_phi(ph.reshape(case.phi.shape))
+            js.append(o.objective(T, TB, TE))
+        fd.append((js[0] - js[1]) / (2 * EPS))
+        print(f"fd voxel {k} ({v}): {fd[-1]:.10e} ({time.time() - t0:.0f} s)", flush=True)
+    o.set_phi(phi0.reshape(case.phi.shape))
+    Jd, gd = o.grad_dual(T, TB, TE, vox)
+    print(f"dual done ({time.time() - t0:.0f} s)", flush=True)
+    Jr, gbox = o.grad_reverse(T, TB, TE, CKPT)
+    print(f"reverse done ({time.time() - t0:.0f} s)", flush=True)
+    sac = np.flatnonzero(case.sac.reshape(-1))
+    np.save(os.path.join(OUT, "adjoint_c4_reverse_sac.npy"), np.asarray(gbox).reshape(-1)[sac].astype(np.float64))
+    rec = {
+        "case": "c4", "T": T, "t_begin": TB, "t_end": TE, "ckpt": CKPT, "eps": EPS,
+        "fd_seed": 16, "voxels": [int(v) for v in vox],
+        "J": J, "J_dual": float(Jd), "J_reverse": float(Jr),
+        "grad_fd": [float(x) for x in fd], "grad_dual": [float(x) for x in np.asarray(gd)],
+        "grad_reverse_at_voxels": [float(np.asarray(gbox).reshape(-1)[v]) for v in vox],
+        "sac_cells": int(sac.size),
+    }
+    with open(os.path.join(OUT, "adjoint_c4.json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(f"written ({time.time() - t0:.0f} s)", flush=True)
+
+
+if __name__ == "__main__":
+    main()
