@@ -51,7 +51,7 @@ __device__ __forceinline__ void sym_mv(const R s[6], R x, R y, R z, R& ox, R& oy
 // stored in FP32.
 __global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, float amp, float ew) {
   using R = double;
-  const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
+  const uint32_t c = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   if (c >= (uint32_t)p.nc) return;
   const uint32_t lk = a.links[c];
   if (lk & LK_DEAD) return;

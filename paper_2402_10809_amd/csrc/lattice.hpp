@@ -29,6 +29,16 @@ __device__ __forceinline__ void sto(T* base, uint32_t e, T v) {
   *(T*)((char*)base + (uint32_t)(e * (uint32_t)sizeof(T))) = v;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
+// Remap so that each XCD works on one contiguous eighth of the compact cells:
+// the cache lines that two neighbouring waves share (x-shifted slots, rows
+// y +- 1 and z +- 1) then meet in one L2 instead of being fetched twice.  The
+// map is a permutation of [0, nb).
+__device__ __forceinline__ uint32_t xcd_block(uint32_t bid, uint32_t nb) {
+  const uint32_t q = nb >> 3, r = nb & 7u, k = bid & 7u;
+  return k * q + (k < r ? k : r) + (bid >> 3);
+}
+
 // Neighbour-row pairs (cy, cz): the pull source x - c_i lies in the row
 // (y - cy, z - cz); PK[i] is the index of that pair, 0 for the cell's own row.
 constexpr int NPAIR = 9;

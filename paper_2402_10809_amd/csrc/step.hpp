@@ -569,7 +569,7 @@ __device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32
 // ---------------------------------------------------------------------------
 template <class S, bool SHW, bool ODD, int DIAG, bool REC, class R, bool PROJ>
 __global__ __launch_bounds__(BLOCK) void k_step(Params p, Bufs b, float amp) {
-  const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
+  const uint32_t c = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   const uint32_t lk = c < (uint32_t)p.nc ? b.links[c] : LK_DEAD;
   const bool active = !(lk & LK_DEAD);
   double dv[NDIAGP];
