@@ -326,10 +326,11 @@ __device__ __forceinline__ void macro(const Params& p, float phx_f, const float 
   const R phx = (R)phx_f;
   const R one = (R)1;
   const R iphi = fast_rcp(phx);
-  const R rm1 = s.s * fast_rcp(kc.U * phx);  // rho - 1
+  const R rm1 = s.s * (kc.iU * iphi);        // rho - 1
   const R rho = one + rm1;
   const R pr = phx * rho;                      // phi rho = sum f
-  const R iUS = fast_rcp(kc.U * pr);
+  const R irho = fast_rcp(rho);
+  const R iUS = kc.iU * iphi * irho;           // 1 / (U phi rho)
   const R hg = (R)0.5 * iphi;
   const R gx = kc.gx, gy = kc.gy, gz = kc.gz;
   const R vx = s.mx * iUS + gx * hg, vy = s.my * iUS + gy * hg, vz = s.mz * iUS + gz * hg;
@@ -368,8 +369,8 @@ __device__ __forceinline__ void macro(const Params& p, float phx_f, const float 
   M.P[5] = s.yz * iU - pr * uy * uz + h * (Fy * uz + uy * Fz);
   const float pn2 = (float)(M.P[0] * M.P[0] + M.P[1] * M.P[1] + M.P[2] * M.P[2] +
                             (R)2 * (M.P[3] * M.P[3] + M.P[4] * M.P[4] + M.P[5] * M.P[5]));
-  const float rhof = (float)rho;
-  const float shear = 3.0f * omega_prev * __builtin_sqrtf(pn2) * fast_rcp(rhof);
+  // |Pi|_F to one ulp (the hardware square root)
+  const float shear = 3.0f * omega_prev * __builtin_amdgcn_sqrtf(pn2) * (float)irho;
   // Carreau-Yasuda: nu = nu_inf + (nu0 - nu_inf) (1 + (lambda g)^a)^((n-1)/a)
   const float lg = p.f.lam * shear;
   float la;
@@ -414,7 +415,12 @@ __device__ __forceinline__ void collide_store(const Params& p, const Pop<S>& A, 
   const R keep = (R)1 - om;
   const R ev0 = om * A0 - K3 * uF;
   const R ks = p.k<R>().ks;
+  // U w_i = ks kw(i) takes two values on the moving directions (axis 2 ks,
+  // edge ks): fold it into the per-pair constants once
+  const R ka = ks * (R)kw(1), ke = ks * (R)kw(7);
   const R omC = om * Cc, omB = om * Bc;
+  const R ev0a = ka * ev0, omCa = ka * omC, K9a = ka * K9, omBa = ka * omB, K3a = ka * K3;
+  const R ev0e = ke * ev0, omCe = ke * omC, K9e = ke * K9, omBe = ke * omB, K3e = ke * K3;
   // porosity-jump term per unit weight: (rho - 1)(phi~_i - phi)
   auto jump = [&](int i) -> R { return UNI ? (R)0 : M.rm1 * ((R)pt[i] - phx); };
   float o[Q];
@@ -422,11 +428,17 @@ __device__ __forceinline__ void collide_store(const Params& p, const Pop<S>& A, 
   auto pair = [&](auto ic, R e, R h) {
     constexpr int I = decltype(ic)::value;
     constexpr int J = OPP[I];
-    const R ev = ev0 + omC * e * e + K9 * e * h;
-    const R od = omB * e + K3 * h;
-    const R kk = ks * (R)kw(I);
-    o[I] = (float)rfma(kk, ev + od + jump(I), keep * (R)d[I]);
-    o[J] = (float)rfma(kk, ev - od + jump(J), keep * (R)d[J]);
+    constexpr bool AX = I < 7;
+    const R kk = AX ? ka : ke;
+    const R ev = rfma(AX ? omCa : omCe, e * e, rfma(AX ? K9a : K9e, e * h, AX ? ev0a : ev0e));
+    const R od = rfma(AX ? omBa : omBe, e, (AX ? K3a : K3e) * h);
+    if (UNI) {
+      o[I] = (float)rfma(keep, (R)d[I], ev + od);
+      o[J] = (float)rfma(keep, (R)d[J], ev - od);
+    } else {
+      o[I] = (float)rfma(keep, (R)d[I], ev + od + kk * jump(I));
+      o[J] = (float)rfma(keep, (R)d[J], ev - od + kk * jump(J));
+    }
   };
   pair(std::integral_constant<int, 1>{}, M.ux, M.Fx);
   pair(std::integral_constant<int, 3>{}, M.uy, M.Fy);
