@@ -9,7 +9,8 @@ steps [3000, 4000)).  Every number comes from the FP64 oracle only:
   voxel.
 
 Run from the repository root: python tests/golden/make_adjoint_c4.py
-(about 10 minutes on 8 cores).
+(about an hour on 8 cores).  Finished stages are kept in
+adjoint_c4.partial.json (not tracked), so an interrupted run resumes.
 """
 
 import json
@@ -31,14 +32,28 @@ OUT = os.path.dirname(os.path.abspath(__file__))
 
 def main():
     t0 = time.time()
+    part_path = os.path.join(OUT, "adjoint_c4.partial.json")
+    part = {}
+    if os.path.exists(part_path):
+        with open(part_path) as fh:
+            part = json.load(fh)
+
+    def save():
+        with open(part_path, "w") as fh:
+            json.dump(part, fh)
+
     case = make_config("c4")
     vox = fd_voxels(case, 16, seed=16)
     o = oracle.Oracle(case)
-    J = o.objective(T, TB, TE)
+    if "J" not in part:
+        part["J"] = o.objective(T, TB, TE)
+        save()
+    J = part["J"]
     print(f"J = {J:.15e} ({time.time() - t0:.0f} s)", flush=True)
     phi0 = case.phi.reshape(-1).astype(np.float64)
-    fd = []
-    for k, v in enumerate(vox):
+    fd = part.setdefault("fd", [])
+    for k in range(len(fd), len(vox)):
+        v = vox[k]
         js = []
         for sgn in (1.0, -1.0):
             ph = phi0.copy()
@@ -46,24 +61,30 @@ def main():
             o.set_phi(ph.reshape(case.phi.shape))
             js.append(o.objective(T, TB, TE))
         fd.append((js[0] - js[1]) / (2 * EPS))
+        save()
         print(f"fd voxel {k} ({v}): {fd[-1]:.10e} ({time.time() - t0:.0f} s)", flush=True)
     o.set_phi(phi0.reshape(case.phi.shape))
-    Jd, gd = o.grad_dual(T, TB, TE, vox)
+    if "dual" not in part:
+        Jd, gd = o.grad_dual(T, TB, TE, vox)
+        part["J_dual"], part["dual"] = float(Jd), [float(x) for x in np.asarray(gd)]
+        save()
     print(f"dual done ({time.time() - t0:.0f} s)", flush=True)
     Jr, gbox = o.grad_reverse(T, TB, TE, CKPT)
     print(f"reverse done ({time.time() - t0:.0f} s)", flush=True)
     sac = np.flatnonzero(case.sac.reshape(-1))
-    np.save(os.path.join(OUT, "adjoint_c4_reverse_sac.npy"), np.asarray(gbox).reshape(-1)[sac].astype(np.float64))
+    gflat = np.asarray(gbox).reshape(-1)
+    np.save(os.path.join(OUT, "adjoint_c4_reverse_sac.npy"), gflat[sac].astype(np.float64))
     rec = {
         "case": "c4", "T": T, "t_begin": TB, "t_end": TE, "ckpt": CKPT, "eps": EPS,
         "fd_seed": 16, "voxels": [int(v) for v in vox],
-        "J": J, "J_dual": float(Jd), "J_reverse": float(Jr),
-        "grad_fd": [float(x) for x in fd], "grad_dual": [float(x) for x in np.asarray(gd)],
-        "grad_reverse_at_voxels": [float(np.asarray(gbox).reshape(-1)[v]) for v in vox],
+        "J": J, "J_dual": part["J_dual"], "J_reverse": float(Jr),
+        "grad_fd": fd, "grad_dual": part["dual"],
+        "grad_reverse_at_voxels": [float(gflat[v]) for v in vox],
         "sac_cells": int(sac.size),
     }
     with open(os.path.join(OUT, "adjoint_c4.json"), "w") as fh:
         json.dump(rec, fh, indent=1)
+    os.remove(part_path)
     print(f"written ({time.time() - t0:.0f} s)", flush=True)
 
 
