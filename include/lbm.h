@@ -167,7 +167,8 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* solid, const float* p
                       void* workspace, size_t ws_bytes, void* stream, lbm_ctx** out);
 
 /* Advance n time steps (collide and stream every fluid cell n times).  Every
- * 1000th step index the state is checked (see LBM_E_UNSTABLE). */
+ * 1000th step index the state is checked (see LBM_E_UNSTABLE); that check
+ * synchronises the stream. */
 lbm_status lbm_step(lbm_ctx* ctx, int n);
 
 /* Macroscopic fields of the current state (what the next step's collision

@@ -49,7 +49,7 @@ __device__ __forceinline__ void sym_mv(const R s[6], R x, R y, R z, R& ox, R& oy
 // recursion has the same slow modes as the forward map, so FP32 rounding of
 // per-cell scalars would accumulate the same way); the adjoint populations are
 // stored in FP32.
-__global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, float amp, float ew) {
+__global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, uint32_t t, float ew) {
   using R = double;
   const uint32_t c = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   if (c >= (uint32_t)p.nc) return;
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, float am
 #pragma unroll
   for (int i = 0; i < Q; ++i) d[i] = a.rec[(size_t)i * p.nc + c];
   const float omp = a.rec[(size_t)Q * p.nc + c];
-  open_fill(p, q.row, lk, amp, a.shape, d);
+  open_fill(p, q.row, lk, t, a.shape, d);
   Macro<R> M;
   macro<R>(p, phx_f, d, omp, M);
   const R phx = (R)phx_f;
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, float am
   const bool in = (lk & LK_IN) != 0;
   const bool outl = (lk & LK_OUT) != 0;
   if (in) {
-    const R uin = (R)amp * (R)a.shape[q.row];
+    const R uin = (R)inflow_amplitude(p, t) * (R)a.shape[q.row];
     fh[2] += fh[1]; fh[8] += fh[7]; fh[10] += fh[9]; fh[12] += fh[11]; fh[14] += fh[13];
     const R rinh = uin * (1.0 / 3.0) * fh[1] + uin * (1.0 / 6.0) * (fh[7] + fh[9] + fh[11] + fh[13]);
     const R nyh = 0.5 * (fh[9] - fh[7]), nzh = 0.5 * (fh[13] - fh[11]);

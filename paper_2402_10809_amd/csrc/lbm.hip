@@ -41,7 +41,7 @@ size_t store_bytes(int storage) { return storage == LBM_STORE_FP32 ? 4 : 2; }
 double storage_unit(int storage) { return storage == LBM_STORE_FP16 ? 36.0 * 1024.0 : 36.0; }
 
 struct Layout {
-  size_t A, code, links, phi, omega, delta, shape, rowbox, stage, part, diag, obj;
+  size_t A, code, links, phi, omega, delta, shape, rowbox, stage, part, diag, obj, tc;
   // adjoint
   size_t ck, rec, rho, ah0, ah1, omh, phih;
   int nck, ckpt, T;
@@ -49,6 +49,12 @@ struct Layout {
 };
 
 int blocks_for(int64_t n) { return (int)((n + BLOCK - 1) / BLOCK); }
+int blocks_for_nt(int64_t n, int nt) { return (int)((n + nt - 1) / nt); }
+
+// Workgroup size of the step kernel: 256 work-items with FP32 storage, 64 with
+// the 16-bit forms (measured fastest for each on the large aneurysm).
+constexpr int STEP_NT_MIN = 64;
+int step_nt(int storage) { return storage == LBM_STORE_FP32 ? 256 : 64; }
 
 // Rows of the compact layout: every (y, z) line holding fluid, ordered by z
 // then y, with the x range from its first to its last fluid cell.
@@ -89,7 +95,6 @@ int xbits_for(int nx) {
 Layout make_layout(const lbm_grid& g, int64_t nc, int64_t nrow, int T, int ckpt) {
   Layout L{};
   const size_t ss = store_bytes(g.storage);
-  const int nblk = blocks_for(nc);
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
   L.A = take(Q * (size_t)nc * ss);
@@ -101,9 +106,11 @@ Layout make_layout(const lbm_grid& g, int64_t nc, int64_t nrow, int T, int ckpt)
   L.shape = take((size_t)nrow * 4);
   L.rowbox = take((size_t)nrow * 4);
   L.stage = take((size_t)(Q + 1) * nc * 4);
-  L.part = take((size_t)nblk * NDIAGP * 8);
+  const size_t nbmax = (size_t)blocks_for_nt(nc, STEP_NT_MIN);  // most blocks any launch uses
+  L.part = take(nbmax * NDIAGP * 8);
   L.diag = take(64 * 8);
-  L.obj = take((size_t)nblk * 8);
+  L.obj = take(nbmax * 8);
+  L.tc = take(2 * sizeof(uint32_t));
   L.T = T;
   L.ckpt = ckpt;
   if (T > 0) {
@@ -167,7 +174,8 @@ struct lbm_ctx {
   int64_t nf = 0;                 // fluid cells
   int64_t nc = 0;                 // compact cells (fluid + dead)
   int64_t nrow = 0;
-  int nblk = 0;
+  int nblk = 0;                   // blocks of BLOCK work-items over the compact cells
+  int sblk = 0;                   // blocks of the step kernel
   int64_t nreg = 0;
   double U = 36.0;
   Rows rows;
@@ -218,14 +226,10 @@ Bufs bufs(lbm_ctx* c) {
   b.part = (double*)(c->ws + c->L.part);
   b.rec = nullptr;
   b.rho_rec = nullptr;
+  b.tc = (uint32_t*)(c->ws + c->L.tc);
   return b;
 }
 
-double amplitude(const lbm_ctx* c, int64_t t) {
-  if (!c->op.inlet) return 0.0;
-  const double pi = 3.14159265358979323846;
-  return c->op.a0 * (1.0 + c->op.a1 * std::sin(2.0 * pi * (double)t / c->op.period));
-}
 
 lbm_status validate_grid(const lbm_grid* g) {
   if (!g) return fail(LBM_E_INVALID, "grid is NULL");
@@ -356,7 +360,6 @@ void with_parity(int64_t t, Fn&& fn) {
 // step for the adjoint (FP32, shift mode 0 only).
 lbm_status launch_step(lbm_ctx* c, int diag, float* rec, float* rho_rec) {
   Bufs b = bufs(c);
-  const float amp = (float)amplitude(c, c->t);
   if (diag == 2) b.part = (double*)(c->ws + c->L.obj);
   if (rec) {
     b.rec = rec;
@@ -367,21 +370,19 @@ lbm_status launch_step(lbm_ctx* c, int diag, float* rec, float* rho_rec) {
     using R = typename decltype(rt)::T;
     constexpr bool PJ = decltype(rt)::proj;
     constexpr bool SH = decltype(shw)::value;
+    constexpr int NT = std::is_same<S, float>::value ? 256 : 64;
+    const dim3 grid(c->sblk), block(NT);
     with_parity(c->t, [&](auto odd) {
       constexpr bool OD = decltype(odd)::value;
       if (rec) {
         if constexpr (std::is_same<S, float>::value && !SH)
-          hipLaunchKernelGGL((k_step<S, false, OD, 0, true, R, PJ>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P,
-                             b, amp);
+          hipLaunchKernelGGL((k_step<S, false, OD, 0, true, R, PJ, NT>), grid, block, 0, c->stream, c->P, b);
       } else if (diag == 0) {
-        hipLaunchKernelGGL((k_step<S, SH, OD, 0, false, R, PJ>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b,
-                           amp);
+        hipLaunchKernelGGL((k_step<S, SH, OD, 0, false, R, PJ, NT>), grid, block, 0, c->stream, c->P, b);
       } else if (diag == 1) {
-        hipLaunchKernelGGL((k_step<S, SH, OD, 1, false, R, PJ>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b,
-                           amp);
+        hipLaunchKernelGGL((k_step<S, SH, OD, 1, false, R, PJ, NT>), grid, block, 0, c->stream, c->P, b);
       } else {
-        hipLaunchKernelGGL((k_step<S, SH, OD, 2, false, R, PJ>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b,
-                           amp);
+        hipLaunchKernelGGL((k_step<S, SH, OD, 2, false, R, PJ, NT>), grid, block, 0, c->stream, c->P, b);
       }
     });
   });
@@ -392,17 +393,18 @@ lbm_status launch_step(lbm_ctx* c, int diag, float* rec, float* rho_rec) {
 
 const uint32_t DIAG_OPS = (1u << 12) | (2u << 14) | (1u << 16);  // max |u|, min omega, max omega; rest sums
 
-lbm_status finalize(lbm_ctx* c, const double* part, int n, uint32_t ops, double* host_out) {
+lbm_status finalize(lbm_ctx* c, const double* part, int nparts, int n, uint32_t ops, double* host_out) {
   double* dout = (double*)(c->ws + c->L.diag);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(BLOCK), 0, c->stream, part, c->nblk, n, ops, dout);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(BLOCK), 0, c->stream, part, nparts, n, ops, dout);
   HIP_TRY(c, hipGetLastError());
   HIP_TRY(c, hipMemcpyAsync(host_out, dout, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return LBM_OK;
 }
 
-lbm_status read_diag(lbm_ctx* c, double* out) {
-  return finalize(c, (const double*)(c->ws + c->L.part), NDIAGP, DIAG_OPS, out);
+// nparts: the block count of the launch that wrote the partials
+lbm_status read_diag(lbm_ctx* c, int nparts, double* out) {
+  return finalize(c, (const double*)(c->ws + c->L.part), nparts, NDIAGP, DIAG_OPS, out);
 }
 
 lbm_status check_stable(lbm_ctx* c, const double* dg) {
@@ -417,7 +419,7 @@ lbm_status check_stable(lbm_ctx* c, const double* dg) {
 
 lbm_status moments_launch(lbm_ctx* c, bool diag, float* rho, float* u, float* shear, float* omega, float* sigma) {
   Bufs b = bufs(c);
-  const float amp = (float)amplitude(c, c->t);
+  const uint32_t t = (uint32_t)c->t;
   with_config(c->grid.storage, c->grid.shift_mode, c->amode == 2 ? 2 : 0, [&](auto tag, auto shw, auto rt) {
     using S = typename decltype(tag)::T;
     using R = typename decltype(rt)::T;
@@ -425,10 +427,10 @@ lbm_status moments_launch(lbm_ctx* c, bool diag, float* rho, float* u, float* sh
     with_parity(c->t, [&](auto odd) {
       constexpr bool OD = decltype(odd)::value;
       if (diag)
-        hipLaunchKernelGGL((k_moments<S, SH, OD, true, R>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, amp,
+        hipLaunchKernelGGL((k_moments<S, SH, OD, true, R>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, t,
                            c->nbox, rho, u, shear, omega, sigma);
       else
-        hipLaunchKernelGGL((k_moments<S, SH, OD, false, R>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, amp,
+        hipLaunchKernelGGL((k_moments<S, SH, OD, false, R>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, t,
                            c->nbox, rho, u, shear, omega, sigma);
     });
   });
@@ -577,6 +579,7 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* solid, const float* p
   s = check_phi(c, phi);
   if (s != LBM_OK) { delete c; return s; }
   c->nblk = blocks_for(c->nc);
+  c->sblk = blocks_for_nt(c->nc, step_nt(grid->storage));
   c->L = L0;
   c->ws = (char*)workspace;
   c->ws_bytes = ws_bytes;
@@ -603,6 +606,9 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* solid, const float* p
                            (float)k.lam, (float)k.cy_e, (float)k.cy_a, (float)k.nu_d, (float)k.kcd,
                            (float)k.gx, (float)k.gy, (float)k.gz, (float)k.rho_out};
   }
+  P.in_a0 = (op && op->inlet) ? op->a0 : 0.0;
+  P.in_a1 = (op && op->inlet) ? op->a1 : 0.0;
+  P.in_period = (op && op->inlet) ? op->period : 1.0;
   P.cy_a2 = rh->a == 2.0 ? 1 : 0;
   P.forch = po->forchheimer ? 1 : 0;
   c->amode = grid->arith == LBM_ARITH_FP64 ? 2
@@ -641,7 +647,7 @@ lbm_status lbm_step(lbm_ctx* c, int n) {
     if (st != LBM_OK) return st;
     if (check) {
       double dg[NDIAGP];
-      st = read_diag(c, dg);
+      st = read_diag(c, c->sblk, dg);
       if (st != LBM_OK) return st;
       st = check_stable(c, dg);
       if (st != LBM_OK) return st;
@@ -666,7 +672,7 @@ lbm_status lbm_diagnostics(lbm_ctx* c, double* out) {
   if (!out) return fail(LBM_E_INVALID, "out is NULL");
   lbm_status s = moments_launch(c, true, nullptr, nullptr, nullptr, nullptr, nullptr);
   if (s != LBM_OK) return s;
-  s = read_diag(c, out);
+  s = read_diag(c, c->nblk, out);
   if (s != LBM_OK) return s;
   out[NDIAGP] = (double)c->t;
   return LBM_OK;

@@ -70,6 +70,7 @@ struct Params {
   uint32_t abytes;             // byte size of the population buffer
   int cy_a2;                   // a == 2: (lambda g)^a is one multiply
   int forch;                   // Forchheimer drag on
+  double in_a0, in_a1, in_period;  // inflow waveform A(t) = a0 (1 + a1 sin(2 pi t / period))
   // physical constants in both precisions (the kernels read the one they
   // compute in, straight from the kernel arguments)
   template <class T>
@@ -102,6 +103,7 @@ struct Bufs {
   double* part;           // per-block partials
   float* rec;             // recompute record: [20][nc] (pulled values, omega_prev)
   float* rho_rec;         // recompute record: rho per compact cell
+  uint32_t* tc;           // time counter: the step at parity k reads tc[k] and writes t + 1 to tc[1 - k]
 };
 
 template <int A, int B, class F>
@@ -239,9 +241,16 @@ __device__ __forceinline__ void pull(const Params& p, const Pop<S>& A, const flo
   }
 }
 
+// Inflow amplitude at step t: a0 (1 + a1 sin(2 pi t / period)) in FP64,
+// rounded once to FP32 (the simulation section's pulsatile inflow, with the
+// waveform reading of the inflow profile).
+__device__ __forceinline__ float inflow_amplitude(const Params& p, uint32_t t) {
+  return (float)(p.in_a0 * (1.0 + p.in_a1 * sin(6.283185307179586 * (double)t / p.in_period)));
+}
+
 // Zou-He fill of the unknown populations on the open faces (phi = 1 there, so
 // the closures hold for the deviations as for the populations).
-__device__ __forceinline__ void open_fill(const Params& p, uint32_t row, uint32_t lk, float amp,
+__device__ __forceinline__ void open_fill(const Params& p, uint32_t row, uint32_t lk, uint32_t t,
                                           const float* __restrict__ shape, float d[Q]) {
   const bool in = (lk & LK_IN) != 0;
   const bool outl = (lk & LK_OUT) != 0;
@@ -251,7 +260,8 @@ __device__ __forceinline__ void open_fill(const Params& p, uint32_t row, uint32_
   const float ny_ = 0.5f * (d[3] - d[4] + d[15] - d[16] + d[17] - d[18]);
   const float nz_ = 0.5f * (d[5] - d[6] + d[15] - d[16] - d[17] + d[18]);
   // inflow: prescribed u = (ux, 0, 0); density from mass and normal momentum
-  const float uin = in ? amp * shape[row] : 0.0f;
+  float uin = 0.0f;
+  if (in) uin = inflow_amplitude(p, t) * shape[row];
   const float sm = d[2] + d[8] + d[10] + d[12] + d[14];
   const float rin = (1.0f + (s0 + 2.0f * sm) * iU) / (1.0f - uin);
   // outflow: prescribed density, normal velocity from mass and the known half
@@ -490,9 +500,9 @@ __device__ __forceinline__ void collide_store(const Params& p, const Pop<S>& A, 
 // ---------------------------------------------------------------------------
 // Block reduction of FP64 partials: wave64 shuffle, then LDS across the 4 waves.
 // ---------------------------------------------------------------------------
-template <int N>
+template <int N, int NT = BLOCK>
 __device__ __forceinline__ void block_reduce(double (&v)[N], const int (&op)[N], double* out) {
-  __shared__ double sh[BLOCK / 64][N];
+  __shared__ double sh[NT / 64][N];
 #pragma unroll
   for (int k = 0; k < N; ++k) {
 #pragma unroll
@@ -509,7 +519,7 @@ __device__ __forceinline__ void block_reduce(double (&v)[N], const int (&op)[N],
   if (threadIdx.x < N) {
     const int k = threadIdx.x;
     double r = sh[0][k];
-    for (int w = 1; w < BLOCK / 64; ++w)
+    for (int w = 1; w < NT / 64; ++w)
       r = op[k] == 0 ? r + sh[w][k] : (op[k] == 1 ? fmax(r, sh[w][k]) : fmin(r, sh[w][k]));
     out[k] = r;
   }
@@ -545,7 +555,7 @@ __device__ __forceinline__ void diag_terms(const Params& p, float phx, const flo
 // Body of the step for one cell (UNI: the whole wave has uniform neighbour
 // porosity).
 template <class S, bool SHW, bool UNI, bool ODD, int DIAG, bool REC, class R, bool PROJ>
-__device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32_t c, uint32_t lk, float amp,
+__device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32_t c, uint32_t lk, uint32_t t,
                                           double (&dv)[NDIAGP], float& ke_reg) {
   Pos q = position(p, c, b.code[c]);
   if (ODD || !UNI) load_deltas(b.delta, q);
@@ -558,7 +568,7 @@ __device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32
 #pragma unroll
     for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(d[i], &b.rec[(size_t)i * p.nc + c]);
   }
-  open_fill(p, q.row, lk, amp, b.shape, d);
+  open_fill(p, q.row, lk, t, b.shape, d);
   const float omp = b.omega[c];
   Macro<R> M;
   macro<R>(p, phx, d, omp, M);
@@ -574,23 +584,24 @@ __device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32
 }
 
 // ---------------------------------------------------------------------------
-// The step at parity ODD (t odd).  DIAG: 0 none, 1 diagnostics of the
-// pre-collision state into part[block][NDIAGP], 2 region kinetic energy
-// accumulated into part[block].  REC: also record the pulled values and
-// omega_prev ([20][nc]) and rho.
+// The step at parity ODD (t odd), NT work-items per workgroup.  DIAG: 0 none,
+// 1 diagnostics of the pre-collision state into part[block][NDIAGP], 2 region
+// kinetic energy accumulated into part[block].  REC: also record the pulled
+// values and omega_prev ([20][nc]) and rho.
 // ---------------------------------------------------------------------------
-template <class S, bool SHW, bool ODD, int DIAG, bool REC, class R, bool PROJ>
-__global__ __launch_bounds__(BLOCK) void k_step(Params p, Bufs b, float amp) {
-  const uint32_t c = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+template <class S, bool SHW, bool ODD, int DIAG, bool REC, class R, bool PROJ, int NT>
+__global__ __launch_bounds__(NT) void k_step(Params p, Bufs b) {
+  const uint32_t c = xcd_block(blockIdx.x, gridDim.x) * NT + threadIdx.x;
+  const uint32_t t = b.tc[ODD ? 1 : 0];
   const uint32_t lk = c < (uint32_t)p.nc ? b.links[c] : LK_DEAD;
   const bool active = !(lk & LK_DEAD);
   double dv[NDIAGP];
   float ke_reg = 0.0f;
   const bool uni = !active || (lk & LK_UNI);
   if (__all(uni)) {
-    if (active) step_cell<S, SHW, true, ODD, DIAG, REC, R, PROJ>(p, b, c, lk, amp, dv, ke_reg);
+    if (active) step_cell<S, SHW, true, ODD, DIAG, REC, R, PROJ>(p, b, c, lk, t, dv, ke_reg);
   } else {
-    if (active) step_cell<S, SHW, false, ODD, DIAG, REC, R, PROJ>(p, b, c, lk, amp, dv, ke_reg);
+    if (active) step_cell<S, SHW, false, ODD, DIAG, REC, R, PROJ>(p, b, c, lk, t, dv, ke_reg);
   }
   if (DIAG == 1) {
     if (!active) {
@@ -599,21 +610,23 @@ __global__ __launch_bounds__(BLOCK) void k_step(Params p, Bufs b, float amp) {
       diag_terms<R>(p, 0.f, d, M, false, false, dv);
     }
     const int ops[NDIAGP] = {0, 0, 0, 0, 0, 0, 1, 2, 1, 0};
-    block_reduce<NDIAGP>(dv, ops, b.part + (size_t)blockIdx.x * NDIAGP);
+    block_reduce<NDIAGP, NT>(dv, ops, b.part + (size_t)blockIdx.x * NDIAGP);
   }
   if (DIAG == 2) {
     double v[1] = {(double)ke_reg};
     const int ops[1] = {0};
     __shared__ double tmp[1];
-    block_reduce<1>(v, ops, tmp);
+    block_reduce<1, NT>(v, ops, tmp);
     if (threadIdx.x == 0) b.part[blockIdx.x] += tmp[0];
   }
+  // the next step (the other parity) reads t + 1 from the other slot
+  if (blockIdx.x == 0 && threadIdx.x == 0) b.tc[ODD ? 0 : 1] = t + 1u;
 }
 
 // Moments of the current state (no collision): dense box outputs (any may be
 // null) and optionally the diagnostics partials.
 template <class S, bool SHW, bool ODD, bool DIAG, class R>
-__global__ __launch_bounds__(BLOCK) void k_moments(Params p, Bufs b, float amp, size_t nbox, float* rho_o,
+__global__ __launch_bounds__(BLOCK) void k_moments(Params p, Bufs b, uint32_t t, size_t nbox, float* rho_o,
                                                     float* u_o, float* shear_o, float* omega_o, float* sigma_o) {
   const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
   const uint32_t lk = c < (uint32_t)p.nc ? b.links[c] : LK_DEAD;
@@ -625,7 +638,7 @@ __global__ __launch_bounds__(BLOCK) void k_moments(Params p, Bufs b, float amp, 
     const float phx = ldo(b.phi, c);
     float d[Q], pt[Q];
     pull<S, SHW, true, ODD>(p, Pop<S>(b.A, p.abytes), b.phi, c, lk, q, phx, d, pt);
-    open_fill(p, q.row, lk, amp, b.shape, d);
+    open_fill(p, q.row, lk, t, b.shape, d);
     Macro<R> M;
     macro<R>(p, phx, d, b.omega[c], M);
     const size_t idx = (size_t)b.rowbox[q.row] + (size_t)q.x;
@@ -692,6 +705,12 @@ __global__ __launch_bounds__(BLOCK) void k_init(Params p, Bufs b, float omega0) 
 #pragma unroll
   for (int i = 0; i < Q; ++i) A.st(c * (uint32_t)sizeof(S), p.plb[i], SHW ? ks * kw(i) * (phx - 1.0f) : 0.0f);
   b.omega[c] = omega0;
+  if (c == 0) b.tc[0] = 0u;
+}
+
+// Set the time counter slot of parity t & 1 to t (one work-item).
+__global__ void k_set_time(uint32_t* tc, uint32_t t) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) tc[t & 1u] = t;
 }
 
 // Whether the pull of direction I reads an open-face unknown (flags set on

@@ -233,6 +233,33 @@ def test_restored_state_continues_trajectory(kind, t_split):
     assert np.array_equal(fa, fb) and np.array_equal(oa, ob)
 
 
+def test_long_calls_match_single_steps():
+    """Long lbm_step calls give exactly what one-step calls give (the step
+    kernels take the time from a device counter), with other work (moments,
+    diagnostics) between the calls, from odd and even start times and across
+    a stability check (step 999)."""
+    case = tiny_case("open", seed=6)
+    a = Solver.from_case(case)   # one step per call
+    b = Solver.from_case(case)   # long calls
+
+    def single(n):
+        for _ in range(n):
+            a.step(1)
+
+    plan = [1, 300, 129, 64, 570, 180]   # odd and even starts, a call across step 999
+    for n in plan:
+        single(n)
+        b.step(n)
+        assert a.t == b.t
+        fa, oa = a.get_state()
+        fb, ob = b.get_state()
+        assert np.array_equal(fa, fb) and np.array_equal(oa, ob), f"state differs after t={b.t}"
+        # other work between the calls
+        a.moments(sigma=True)
+        db = b.diagnostics()
+        assert db["nonfinite"] == 0
+
+
 def test_diagnostics_match_oracle():
     case = tiny_case("periodic", seed=2)
     s = Solver.from_case(case)
