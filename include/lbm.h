@@ -16,12 +16,14 @@
  *     corrected second moment Pi, deviatoric stress (section "Lattice
  *     Boltzmann Method for Volume-Averaged Navier-Stokes");
  *   - the boundaries: halfway bounce-back walls, Zou-He velocity inflow with a
- *     Hagen-Poiseuille profile (section "Numerical Simulations in a Realistic
- *     Aneurysm", boundary-condition paragraph).
- * The library uses the D3Q19 velocity set, a Kozeny-Carman constant that is a
- * parameter, a constant-density (Zou-He pressure) outflow and a sinusoidal
- * inflow amplitude; all quantities are in lattice units (dx = dt = 1,
- * c_s^2 = 1/3, reference density 1).
+ *     Hagen-Poiseuille profile, extrapolation outflow, pre-run ramp (section
+ *     "Numerical Simulations in a Realistic Aneurysm", boundary-condition
+ *     paragraph and the paragraph after the parameter table).
+ * The library uses the D3Q19 velocity set and a Kozeny-Carman constant that is
+ * a parameter; the outflow is the paper's extrapolation or a constant-density
+ * (Zou-He pressure) outflow, the inflow amplitude a sine or a sampled waveform
+ * with an optional linear pre-run ramp; all quantities are in lattice units
+ * (dx = dt = 1, c_s^2 = 1/3, reference density 1).
  *
  * Conventions
  *   - Box of nx*ny*nz voxels; box index b = x + nx*(y + ny*z) (x fastest).
@@ -119,18 +121,36 @@ typedef struct {
 } lbm_porous;
 
 /* Open faces.  inlet: the x = 0 face is a Zou-He velocity inflow with
- * u = (A(t) * shape_yz[y + ny*z], 0, 0) and A(t) = a0 (1 + a1 sin(2 pi t/period)),
- * t the step index; shape_yz is host memory (ny*nz floats), e.g. the
- * normalised Hagen-Poiseuille profile 1 - r^2/R^2.  outlet: the x = nx-1 face
- * is a Zou-He constant-density outflow with density rho_out and zero
- * tangential velocity.  Fluid cells on an open face must have phi = 1.
- * Fluid cells on other non-periodic faces see the outside as wall. */
+ * u = (A(t) * shape_yz[y + ny*z], 0, 0), t the step index; shape_yz is host
+ * memory (ny*nz floats), e.g. the normalised Hagen-Poiseuille profile
+ * 1 - r^2/R^2 of the paper's inflow (simulation section).  The waveform W(s)
+ * is a0 (1 + a1 sin(2 pi s / period)), or, when wave_table is set, the
+ * table_len samples (host, FP64, 1 <= table_len <= 1024) of one period of
+ * `period` steps, sample k at s = k period / table_len, interpolated linearly
+ * and repeated periodically (a sampled waveform such as a 1D-0D network
+ * model's mean inflow velocity).  ramp_steps = R > 0 adds the paper's pre-run:
+ * A(t) = (t / R) W(0) for t < R, then A(t) = W(t - R); R = 0: A(t) = W(t).
+ * outlet (x = nx-1 face): 0 none (wall); LBM_OUTLET_DENSITY, a Zou-He
+ * constant-density outflow with density rho_out and zero tangential velocity;
+ * LBM_OUTLET_EXTRAPOLATION, the non-reflecting extrapolation outflow the
+ * paper's boundary-condition paragraph uses (after Geier et al.): each unknown
+ * population i (c_x = -1) is carried out at the speed of sound, upwind in x,
+ *   f_i(t+1, x) = (1 - c_s) f_i(t, x) + c_s f_i(t, x - e_x),
+ * with pre-collision values (f_i(t, x) alone where x - e_x is solid); these
+ * unknowns are then part of the state (see lbm_get_state), and rho_out is
+ * unused.  Fluid cells on an open face must have phi = 1.  Fluid cells on
+ * other non-periodic faces see the outside as wall.  Fields after rho_out may
+ * be left zero. */
+enum { LBM_OUTLET_NONE = 0, LBM_OUTLET_DENSITY = 1, LBM_OUTLET_EXTRAPOLATION = 2 };
 typedef struct {
   int inlet;
   const float* shape_yz;
   double a0, a1, period;
   int outlet;
   double rho_out;
+  int ramp_steps;
+  const double* wave_table;
+  int table_len;
 } lbm_open;
 
 /* Objective for lbm_adjoint: J = (1/(t_end - t_begin)) sum_{t=t_begin}^{t_end-1} e(t),
@@ -184,7 +204,9 @@ lbm_status lbm_diagnostics(lbm_ctx* ctx, double* out);
 /* State transfer (host memory, per fluid cell): f[19][n_fluid] pre-collision
  * populations (unshifted, FP64), omega[n_fluid] the relaxation rate of the
  * previous step.  Populations that would arrive through an open face are
- * unknown: get writes 0 there, set ignores them.  Both sync the stream. */
+ * unknown: get writes 0 there, set ignores them; the extrapolation outflow's
+ * are part of the state instead (get returns them, set uses them).  Both sync
+ * the stream. */
 lbm_status lbm_get_state(lbm_ctx* ctx, double* f, float* omega);
 lbm_status lbm_set_state(lbm_ctx* ctx, const double* f, const float* omega);
 
@@ -200,7 +222,8 @@ lbm_status lbm_reset(lbm_ctx* ctx);
  * accumulating J and storing a checkpoint every ckpt_every steps, then sweeps
  * back through the segments (recompute forward, then reverse steps).  Needs a
  * workspace sized for (T, ckpt_every) or larger; FP32 storage, shift mode 0,
- * no Forchheimer drag, a non-empty region, 0 <= t_begin < t_end <= T.
+ * no Forchheimer drag, no extrapolation outflow (for the gradient), a non-empty region,
+ * 0 <= t_begin < t_end <= T.
  *   J:       host, 1 double
  *   dJ_dphi: device, nx*ny*nz floats (box layout, 0 off the fluid), or NULL:
  *            then only J is computed (the forward pass, no checkpoints; the

@@ -44,6 +44,7 @@ class _Case(ct.Structure):
         ("nu_d", ct.c_double), ("kc", ct.c_double), ("d", ct.c_double),
         ("forchheimer", ct.c_int),
         ("g", ct.c_double * 3),
+        ("ramp", ct.c_int), ("wave_table", ct.c_void_p), ("table_len", ct.c_int),
     ]
 
 
@@ -113,6 +114,12 @@ def make_struct(case, keep: list, **override) -> _Case:
     s.forchheimer = int(po.get("forchheimer", 0))
     for a in range(3):
         s.g[a] = float(po["g"][a])
+    s.ramp = int(getattr(case, "ramp_steps", 0) or 0)
+    table = getattr(case, "wave_table", None)
+    if table is not None:
+        table = np.ascontiguousarray(table, dtype=np.float64)
+        keep.append(table)
+        s.wave_table, s.table_len = _ptr(table), int(table.size)
     return s
 
 
@@ -192,6 +199,8 @@ class Oracle:
         J = np.zeros(1)
         g = np.zeros(self.case.n_box)
         lib().oracle_grad_reverse(self.h, int(T), int(tb), int(te), int(ckpt), _ptr(J), _ptr(g))
+        if np.isnan(J[0]):
+            raise ValueError("the reverse sweep supports the density outflow only")
         return float(J[0]), g.reshape(self.case.nz, self.case.ny, self.case.nx)
 
 

@@ -6,7 +6,8 @@ the C++ oracle's compact cell list and neighbour table, so that indexing, wall
 and open-face mistakes in either show up as a mismatch on tiny lattices.
 
 State layout here: ``f`` of shape (19, nz, ny, nx), pre-collision populations,
-0 on solid voxels and on the unknown links of open-face cells.
+0 on solid voxels and on the unknown links of open-face cells (an extrapolation
+outflow keeps its extrapolated values there).
 """
 
 from __future__ import annotations
@@ -61,7 +62,7 @@ def _link_kinds(case):
                 t = t % n
             else:
                 if a == 0:
-                    opn = ((t < 0) & case.inlet) | ((t >= n) & case.outlet)
+                    opn = ((t < 0) & bool(case.inlet)) | ((t >= n) & bool(case.outlet))
                     out_open |= opn
                     out_wall |= outside & ~opn
                 else:
@@ -74,6 +75,27 @@ def _link_kinds(case):
     return kinds
 
 
+def inflow_amplitude(case, t):
+    """Pre-run ramp to the waveform's starting value over ``case.ramp_steps``
+    steps, then the waveform: the sine of ``case.wave`` or the sampled period
+    ``case.wave_table`` (linear interpolation, periodic)."""
+    a0, a1, period = case.wave
+    ramp = int(getattr(case, "ramp_steps", 0) or 0)
+    table = getattr(case, "wave_table", None)
+
+    def w(s):
+        if table is None:
+            return a0 * (1.0 + a1 * np.sin(2.0 * np.pi * s / period))
+        tab = np.asarray(table, dtype=np.float64)
+        pos = (s / period - np.floor(s / period)) * tab.size
+        k = min(int(pos), tab.size - 1)
+        return tab[k] + (pos - k) * (tab[(k + 1) % tab.size] - tab[k])
+
+    if t < ramp:
+        return (t / ramp) * w(0.0)
+    return w(float(t - ramp))
+
+
 def step(case, f, omega_prev, t):
     """One step on dense arrays; returns (f_next, omega_new, fields)."""
     fluid = case.solid == 0
@@ -81,10 +103,10 @@ def step(case, f, omega_prev, t):
     nz, ny, nx = fluid.shape
     kinds = _link_kinds(case)
     f = f.copy()
-    # open-face fill: Zou-He inflow on x = 0, constant-density outflow on x = nx-1
+    # open-face fill: Zou-He inflow on x = 0; constant-density or extrapolation
+    # outflow on x = nx-1
     if case.inlet:
-        a0, a1, period = case.wave
-        amp = a0 * (1.0 + a1 * np.sin(2.0 * np.pi * t / period))
+        amp = inflow_amplitude(case, t)
         fx = f[:, :, :, 0]
         ux = amp * case.inlet_shape.astype(np.float64)
         zero = C[:, 0] == 0
@@ -99,7 +121,7 @@ def step(case, f, omega_prev, t):
         fx[13] = fx[14] + rho * ux / 6 + nz_
         m = fluid[:, :, 0]
         f[:, :, :, 0] = np.where(m[None], fx, f[:, :, :, 0])
-    if case.outlet:
+    if int(case.outlet) == 1:
         fx = f[:, :, :, nx - 1]
         ro = case.rho_out
         zero = C[:, 0] == 0
@@ -164,6 +186,17 @@ def step(case, f, omega_prev, t):
         moved = _shift(np.where(kinds[i] == 0, q[i], 0.0), C[i], case.periodic, 0.0)
         fn[i] += moved
         fn[OPP[i]] += np.where(kinds[i] == 1, q[i], 0.0)
+    if int(case.outlet) == 2:
+        # extrapolation outflow: each unknown population (c_x = -1) of an
+        # outflow cell is advected out at the speed of sound, upwind in x:
+        # next = (1 - c_s) * (its value now) + c_s * (value now one cell
+        # upstream, or its own value if that cell is solid)
+        cs = np.sqrt(CS2)
+        for i in np.flatnonzero(C[:, 0] == -1):
+            own = f[i, :, :, nx - 1]
+            up = np.where(fluid[:, :, nx - 2], f[i, :, :, nx - 2], own)
+            unk = fluid[:, :, nx - 1] & (kinds[OPP[i]][:, :, nx - 1] == 2)
+            fn[i, :, :, nx - 1] = np.where(unk, (1 - cs) * own + cs * up, fn[i, :, :, nx - 1])
     fn = np.where(fluid[None], fn, 0.0)
     fields = dict(rho=rho, u=u, shear=shear, omega=omega, Pi=Pi)
     return fn, np.where(fluid, omega, 0.0), fields

@@ -14,7 +14,8 @@
 //                                 law (model section, eq. carreau); semi-explicit
 //                                 shear rate from the corrected second moment Pi
 //   boundaries .................. simulation section: halfway bounce-back walls,
-//                                 Zou-He velocity inflow, Poiseuille profile.
+//                                 Zou-He velocity inflow, Poiseuille profile,
+//                                 extrapolation outflow.
 // Where the paper is silent the reading is stated at the point of use.
 //
 // Lattice units throughout: dx = dt = 1, c_s^2 = 1/3.  State = pre-collision,
@@ -22,7 +23,8 @@
 // index order, box index = x + nx*(y + ny*z)), plus the relaxation rate of the
 // previous step at every fluid cell.  Populations that arrive from outside an
 // open (inflow/outflow) face are unknown; the state holds 0 there and the
-// Zou-He fill of the next step replaces them.
+// Zou-He fill of the next step replaces them.  An extrapolation outflow instead
+// keeps its unknowns in the state (see extrapolate_outlet).
 //
 // The scalar type is a template parameter so that forward-mode dual numbers give
 // exact derivatives of the discrete map (used by the gradient checks).
@@ -117,7 +119,7 @@ typedef struct {
   const uint8_t* solid;        // nx*ny*nz, 1 = solid
   const double* phi;           // nx*ny*nz, porosity in (0, 1] on fluid
   const uint8_t* sac;          // nx*ny*nz or NULL: objective region
-  int inlet, outlet;           // velocity inflow at x = 0, density outflow at x = nx-1
+  int inlet, outlet;           // velocity inflow at x = 0; outflow at x = nx-1: 1 density, 2 extrapolation
   const double* inlet_shape;   // ny*nz (index y + ny*z): u_x/amplitude on the x = 0 face
   double a0, a1, period;       // amplitude(t) = a0 (1 + a1 sin(2 pi t / period))
   double rho_out;
@@ -125,6 +127,9 @@ typedef struct {
   double nu_d, kc, d;                // Darcy viscosity, Kozeny-Carman constant, grain size
   int forchheimer;                   // 0: C_F = 0; 1: Ergun C_F = 1.75/sqrt(150 phi^3)
   double g[3];                       // body force per unit mass
+  int ramp;                          // pre-run length R (0: none)
+  const double* wave_table;          // NULL: sine waveform; else samples of one period
+  int table_len;
 } oracle_case;
 }
 
@@ -136,7 +141,7 @@ const int NB_OPEN = -2;  // leaves through an open face: dropped
 struct Ctx {
   oracle_case c;
   std::vector<uint8_t> solid, sac;
-  std::vector<double> phi_box, shape;
+  std::vector<double> phi_box, shape, wave;
   std::vector<int64_t> cells;          // fluid -> box index
   std::vector<int64_t> box2f;          // box -> fluid (or -1)
   std::vector<int> nbr;                // [Q][nf]: fluid index of x + c_i, or NB_WALL/NB_OPEN
@@ -146,9 +151,32 @@ struct Ctx {
   long nsac = 0;
 };
 
-double amplitude(const oracle_case& c, int t) {
-  const double pi = 3.14159265358979323846;
-  return c.a0 * (1.0 + c.a1 * std::sin(2.0 * pi * (double)t / c.period));
+// Inflow waveform at time s of its period: the sine a0 (1 + a1 sin(2 pi s / T)),
+// or the sampled period (sample k at s = k T / n), read by linear
+// interpolation between neighbouring samples and repeated every T steps.
+double waveform(const Ctx& C, double s) {
+  const oracle_case& c = C.c;
+  if (C.wave.empty()) {
+    const double pi = 3.14159265358979323846;
+    return c.a0 * (1.0 + c.a1 * std::sin(2.0 * pi * s / c.period));
+  }
+  const int n = (int)C.wave.size();
+  double phase = s / c.period;
+  phase -= std::floor(phase);
+  const double pos = phase * n;
+  int k = (int)pos;
+  if (k >= n) k = n - 1;
+  const int k1 = (k + 1) % n;
+  return C.wave[k] + (pos - k) * (C.wave[k1] - C.wave[k]);
+}
+
+// Inflow amplitude at step t.  The simulation section starts from rest with a
+// pre-run in which the inflow grows linearly to the waveform's starting value;
+// the waveform runs from the end of the pre-run.
+double amplitude(const Ctx& C, int t) {
+  const int R = C.c.ramp;
+  if (t < R) return ((double)t / (double)R) * waveform(C, 0.0);
+  return waveform(C, (double)(t - R));
 }
 
 // Which fluid cell (or wall / open face) lies at x + c_i.
@@ -294,6 +322,31 @@ void cell_update(const oracle_case& c, const T f[Q], T omega_prev, T phi, const 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Extrapolation outflow (the simulation section's non-reflecting outflow after
+// Geier et al.).  Reading: every population is treated as a field carried out
+// through the outflow face at the speed of sound c_s, and the advection is
+// discretised upwind in space and forward in time, so an unknown population i
+// (c_x = -1) of an outflow cell x_b at the next step is
+//   f_i(t+1, x_b) = (1 - c_s) f_i(t, x_b) + c_s f_i(t, x_b - e_x),
+// both pre-collision values of step t (f_i(t, x_b) being the previous
+// extrapolated value).  The state therefore keeps these unknowns: the rest
+// state holds their rest value, and each step writes them while streaming.
+// If x_b - e_x is not a fluid cell the upstream term is the cell's own.
+// ---------------------------------------------------------------------------
+template <class T>
+void extrapolate_outlet(const Ctx& C, const T* f, int64_t x, T* fn) {
+  const int64_t nf = C.nf;
+  const double cs = std::sqrt(CS2);
+  const int up = C.nbr[2 * nf + x];  // direction 2 is -x
+  for (int i = 0; i < Q; ++i) {
+    if (CV[i][0] != -1 || C.nbr[opposite(i) * nf + x] != NB_OPEN) continue;
+    const T own = f[i * nf + x];
+    const T ups = up >= 0 ? f[i * nf + up] : own;
+    fn[i * nf + x] = (1.0 - cs) * own + cs * ups;
+  }
+}
+
 // Gather a cell's inputs: its populations (after the open-face fill at step t)
 // and the porosity of its neighbours.
 template <class T>
@@ -301,9 +354,9 @@ void cell_inputs(const Ctx& C, const T* f, int64_t x, int t, const T* phi_f, T f
   const int64_t nf = C.nf;
   for (int i = 0; i < Q; ++i) fl[i] = f[i * nf + x];
   if (C.kind[x] == 1) {
-    double ux = amplitude(C.c, t) * C.shape[C.yc[x] + (int64_t)C.c.ny * C.zc[x]];
+    double ux = amplitude(C, t) * C.shape[C.yc[x] + (int64_t)C.c.ny * C.zc[x]];
     zouhe_inlet(fl, ux, 0.0, 0.0);
-  } else if (C.kind[x] == 2) {
+  } else if (C.kind[x] == 2 && C.c.outlet == 1) {
     zouhe_outlet(fl, C.c.rho_out);
   }
   for (int i = 0; i < Q; ++i) {
@@ -340,6 +393,7 @@ void step(const Ctx& C, std::vector<T>& f, std::vector<T>& omega, const std::vec
     omega[x] = r.omega;
     if (ke && C.sac[x]) keloc[x] = 0.5 * r.rho * (r.u[0] * r.u[0] + r.u[1] * r.u[1] + r.u[2] * r.u[2]);
     stream_out(C, x, r.q, fn.data());
+    if (C.kind[x] == 2 && C.c.outlet == 2) extrapolate_outlet(C, f.data(), x, fn.data());
   }
   f.swap(fn);
   if (ke) {
@@ -360,8 +414,9 @@ void rest_state(const Ctx& C, const std::vector<T>& phi_f, std::vector<T>& f, st
     for (int i = 0; i < Q; ++i) {
       bool unknown = false;
       int o = opposite(i);
-      // population i arrives from x - c_i = x + c_o; unknown if that is an open face
-      if (C.nbr[o * nf + x] == NB_OPEN) unknown = true;
+      // population i arrives from x - c_i = x + c_o; unknown if that is an open
+      // face, except on an extrapolation outflow, whose state keeps them
+      if (C.nbr[o * nf + x] == NB_OPEN && !(C.kind[x] == 2 && C.c.outlet == 2)) unknown = true;
       f[i * nf + x] = unknown ? T(0.0) : WT[i] * phi_f[x];
     }
 }
@@ -382,7 +437,9 @@ void* oracle_new(const oracle_case* c) {
   C->sac.clear();
   if (c->inlet_shape) C->shape.assign(c->inlet_shape, c->inlet_shape + (int64_t)c->ny * c->nz);
   else C->shape.assign((int64_t)c->ny * c->nz, 0.0);
+  if (c->wave_table && c->table_len > 0) C->wave.assign(c->wave_table, c->wave_table + c->table_len);
   C->c.solid = nullptr; C->c.phi = nullptr; C->c.sac = nullptr; C->c.inlet_shape = nullptr;
+  C->c.wave_table = nullptr;
   C->box2f.assign(nb, -1);
   for (int64_t b = 0; b < nb; ++b)
     if (!c->solid[b]) { C->box2f[b] = (int64_t)C->cells.size(); C->cells.push_back(b); }
@@ -408,7 +465,7 @@ void oracle_free(void* h) { delete (Ctx*)h; }
 int64_t oracle_nfluid(void* h) { return ((Ctx*)h)->nf; }
 void oracle_cells(void* h, int64_t* out) { Ctx* C = (Ctx*)h; std::copy(C->cells.begin(), C->cells.end(), out); }
 void oracle_neighbours(void* h, int32_t* out) { Ctx* C = (Ctx*)h; std::copy(C->nbr.begin(), C->nbr.end(), out); }
-double oracle_amplitude(void* h, int t) { return amplitude(((Ctx*)h)->c, t); }
+double oracle_amplitude(void* h, int t) { return amplitude(*(Ctx*)h, t); }
 
 static std::vector<double> fluid_phi(const Ctx& C) {
   std::vector<double> p(C.nf);
@@ -547,6 +604,10 @@ void oracle_grad_reverse(void* h, int T, int tb, int te, int ckpt, double* J, do
   typedef Dual<NI> D;
   Ctx* C = (Ctx*)h;
   const int64_t nf = C->nf;
+  if (C->c.outlet == 2) {  // the local maps below assume a cell-local open-face fill
+    *J = std::nan("");
+    return;
+  }
   std::vector<double> ph = fluid_phi(*C), f, om;
   rest_state(*C, ph, f, om);
   // forward with checkpoints
@@ -594,7 +655,7 @@ void oracle_grad_reverse(void* h, int T, int tb, int te, int ckpt, double* J, do
         }
         // open-face fill (inside the local map)
         if (C->kind[x] == 1) {
-          double ux = amplitude(C->c, t) * C->shape[C->yc[x] + (int64_t)C->c.ny * C->zc[x]];
+          double ux = amplitude(*C, t) * C->shape[C->yc[x] + (int64_t)C->c.ny * C->zc[x]];
           zouhe_inlet(fl, ux, 0.0, 0.0);
         } else if (C->kind[x] == 2) {
           zouhe_outlet(fl, C->c.rho_out);

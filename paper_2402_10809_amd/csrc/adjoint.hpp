@@ -29,6 +29,7 @@ struct AdjBufs {
   const int* delta;       // neighbour-row deltas
   const float* phi;       // porosity per compact cell
   const float* shape;     // inflow profile per row
+  const double* wave;     // sampled inflow waveform
   const float* rec;       // record of step n: [19][nc] pulled values (before the fill), [nc] omega_prev
   const float* rho_prev;  // density of step n-1 per compact cell (null for n = 0)
   const float* ph_next;   // adjoint of the pulled populations of step n+1, [19][nc]
@@ -65,7 +66,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, uint32_t
 #pragma unroll
   for (int i = 0; i < Q; ++i) d[i] = a.rec[(size_t)i * p.nc + c];
   const float omp = a.rec[(size_t)Q * p.nc + c];
-  open_fill(p, q.row, lk, t, a.shape, d);
+  open_fill(p, q.row, lk, t, a.shape, a.wave, nullptr, d);
   Macro<R> M;
   macro<R>(p, phx_f, d, omp, M);
   const R phx = (R)phx_f;
@@ -226,7 +227,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, uint32_t
   const bool in = (lk & LK_IN) != 0;
   const bool outl = (lk & LK_OUT) != 0;
   if (in) {
-    const R uin = (R)inflow_amplitude(p, t) * (R)a.shape[q.row];
+    const R uin = (R)inflow_amplitude(p, a.wave, t) * (R)a.shape[q.row];
     fh[2] += fh[1]; fh[8] += fh[7]; fh[10] += fh[9]; fh[12] += fh[11]; fh[14] += fh[13];
     const R rinh = uin * (1.0 / 3.0) * fh[1] + uin * (1.0 / 6.0) * (fh[7] + fh[9] + fh[11] + fh[13]);
     const R nyh = 0.5 * (fh[9] - fh[7]), nzh = 0.5 * (fh[13] - fh[11]);

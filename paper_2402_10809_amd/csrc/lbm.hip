@@ -41,7 +41,7 @@ size_t store_bytes(int storage) { return storage == LBM_STORE_FP32 ? 4 : 2; }
 double storage_unit(int storage) { return storage == LBM_STORE_FP16 ? 36.0 * 1024.0 : 36.0; }
 
 struct Layout {
-  size_t A, code, links, phi, omega, delta, shape, rowbox, stage, part, diag, obj, tc;
+  size_t A, code, links, phi, omega, delta, shape, rowbox, stage, part, diag, obj, tc, wave, side;
   // adjoint
   size_t ck, rec, rho, ah0, ah1, omh, phih;
   int nck, ckpt, T;
@@ -54,6 +54,7 @@ int blocks_for_nt(int64_t n, int nt) { return (int)((n + nt - 1) / nt); }
 // Workgroup size of the step kernel: 256 work-items with FP32 storage, 64 with
 // the 16-bit forms (measured fastest for each on the large aneurysm).
 constexpr int STEP_NT_MIN = 64;
+constexpr int MAX_WAVE_TABLE = 1024;  // samples of a sampled inflow waveform
 int step_nt(int storage) { return storage == LBM_STORE_FP32 ? 256 : 64; }
 
 // Rows of the compact layout: every (y, z) line holding fluid, ordered by z
@@ -111,6 +112,8 @@ Layout make_layout(const lbm_grid& g, int64_t nc, int64_t nrow, int T, int ckpt)
   L.diag = take(64 * 8);
   L.obj = take(nbmax * 8);
   L.tc = take(2 * sizeof(uint32_t));
+  L.wave = take(MAX_WAVE_TABLE * sizeof(double));
+  L.side = take((size_t)2 * nrow * 10 * sizeof(float));
   L.T = T;
   L.ckpt = ckpt;
   if (T > 0) {
@@ -227,6 +230,8 @@ Bufs bufs(lbm_ctx* c) {
   b.rec = nullptr;
   b.rho_rec = nullptr;
   b.tc = (uint32_t*)(c->ws + c->L.tc);
+  b.wave = (const double*)(c->ws + c->L.wave);
+  b.side = (float*)(c->ws + c->L.side);
   return b;
 }
 
@@ -314,6 +319,8 @@ void build_links(const lbm_ctx* c, const std::vector<float>& phib, std::vector<u
     if (uni) lk |= LK_UNI;
     if (c->openface[k] == 1) lk |= LK_IN;
     if (c->openface[k] == 2) lk |= LK_OUT;
+    // -x neighbour of an extrapolation-outflow cell
+    if (c->P.outlet == 2 && X[0] == nx - 2 && !c->solid[b + 1]) lk |= LK_UPS;
     if (c->region_f[k]) lk |= LK_REG;
     lk |= unk << LK_UNK;
     links[c->fluid_c[k]] = lk;
@@ -346,6 +353,10 @@ lbm_status launch_init(lbm_ctx* c) {
                        c->omega0);
   });
   HIP_TRY(c, hipGetLastError());
+  // extrapolation outflow: the kept values of the rest state (phi = 1 on the
+  // outflow cells, so w_i, i.e. deviation 0; the -x neighbour's values are
+  // those the rest state's outflow populations extrapolate from)
+  HIP_TRY(c, hipMemsetAsync(b.side, 0, (size_t)2 * c->nrow * 10 * sizeof(float), c->stream));
   c->t = 0;
   return LBM_OK;
 }
@@ -510,7 +521,11 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* solid, const float* p
     if (grid->periodic[0]) return fail(LBM_E_INVALID, "open faces need a non-periodic x axis");
     if (op->inlet && (!op->shape_yz || !(op->period > 0)))
       return fail(LBM_E_INVALID, "inlet needs shape_yz and period > 0");
-    if (op->outlet && !(op->rho_out > 0)) return fail(LBM_E_INVALID, "outlet density must be positive");
+    if (op->inlet && op->ramp_steps < 0) return fail(LBM_E_INVALID, "ramp_steps must be >= 0");
+    if (op->inlet && op->wave_table && (op->table_len < 1 || op->table_len > MAX_WAVE_TABLE))
+      return fail(LBM_E_INVALID, "table_len must lie in [1, " + std::to_string(MAX_WAVE_TABLE) + "]");
+    if (op->outlet < 0 || op->outlet > 2) return fail(LBM_E_INVALID, "outlet must be 0, 1 or 2");
+    if (op->outlet == 1 && !(op->rho_out > 0)) return fail(LBM_E_INVALID, "outlet density must be positive");
   }
   if (!workspace) return fail(LBM_E_WORKSPACE, "workspace is NULL");
   if (((uintptr_t)workspace & 255) != 0) return fail(LBM_E_WORKSPACE, "workspace must be 256-byte aligned");
@@ -528,6 +543,7 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* solid, const float* p
   c->po = *po;
   if (op) c->op = *op;
   c->op.shape_yz = nullptr;
+  c->op.wave_table = nullptr;
   c->nbox = (size_t)grid->nx * grid->ny * grid->nz;
   c->solid.assign(solid, solid + c->nbox);
   c->stream = (hipStream_t)stream;
@@ -589,7 +605,8 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* solid, const float* p
   P.nc = (int)c->nc;
   P.px = grid->periodic[0] ? 1 : 0;
   P.inlet = (op && op->inlet) ? 1 : 0;
-  P.outlet = (op && op->outlet) ? 1 : 0;
+  P.outlet = op ? op->outlet : 0;
+  P.nrow = (int)nrow;
   P.xbits = xb;
   for (int i = 0; i < Q; ++i) P.plb[i] = (uint32_t)((size_t)i * c->nc * store_bytes(grid->storage));
   P.abytes = (uint32_t)((size_t)Q * c->nc * store_bytes(grid->storage));
@@ -600,7 +617,7 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* solid, const float* p
     k.lam = rh->lambda; k.cy_e = (rh->n - 1.0) / rh->a; k.cy_a = rh->a;
     k.nu_d = po->nu_darcy; k.kcd = po->kc / (po->d * po->d);
     k.gx = po->g[0]; k.gy = po->g[1]; k.gz = po->g[2];
-    k.rho_out = (op && op->outlet) ? op->rho_out : 1.0;
+    k.rho_out = (op && op->outlet == 1) ? op->rho_out : 1.0;
     P.d = k;
     P.f = Params::K<float>{(float)k.U, (float)k.iU, (float)k.ks, (float)k.nu0, (float)k.nu_inf, (float)k.dnu,
                            (float)k.lam, (float)k.cy_e, (float)k.cy_a, (float)k.nu_d, (float)k.kcd,
@@ -609,6 +626,8 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* solid, const float* p
   P.in_a0 = (op && op->inlet) ? op->a0 : 0.0;
   P.in_a1 = (op && op->inlet) ? op->a1 : 0.0;
   P.in_period = (op && op->inlet) ? op->period : 1.0;
+  P.in_table = (op && op->inlet && op->wave_table) ? op->table_len : 0;
+  P.in_ramp = (op && op->inlet) ? (uint32_t)op->ramp_steps : 0u;
   P.cy_a2 = rh->a == 2.0 ? 1 : 0;
   P.forch = po->forchheimer ? 1 : 0;
   c->amode = grid->arith == LBM_ARITH_FP64 ? 2
@@ -627,6 +646,9 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* solid, const float* p
   HIP_TRY0(hipMemcpyAsync(c->ws + c->L.delta, delta.data(), delta.size() * 4, hipMemcpyHostToDevice, c->stream));
   HIP_TRY0(hipMemcpyAsync(c->ws + c->L.shape, shape.data(), shape.size() * 4, hipMemcpyHostToDevice, c->stream));
   HIP_TRY0(hipMemcpyAsync(c->ws + c->L.rowbox, rowbox.data(), rowbox.size() * 4, hipMemcpyHostToDevice, c->stream));
+  if (P.in_table > 0)
+    HIP_TRY0(hipMemcpyAsync(c->ws + c->L.wave, op->wave_table, (size_t)P.in_table * sizeof(double),
+                            hipMemcpyHostToDevice, c->stream));
   HIP_TRY0(hipMemsetAsync(c->ws + c->L.omega, 0, c->nc * 4, c->stream));
   HIP_TRY0(hipStreamSynchronize(c->stream));
 #undef HIP_TRY0

@@ -54,6 +54,7 @@ constexpr uint32_t LK_IN = 1u << 20;    // inflow cell (x = 0)
 constexpr uint32_t LK_OUT = 1u << 21;   // outflow cell (x = nx - 1)
 constexpr uint32_t LK_REG = 1u << 22;   // objective region
 constexpr int LK_UNK = 23;              // 5 bits: which x-directed pulls are open-face unknowns
+constexpr uint32_t LK_UPS = 1u << 28;   // -x neighbour of an extrapolation-outflow cell
 // the x-directed pulls of an inflow (c_x = +1) and an outflow (c_x = -1) cell
 constexpr int XIN[5] = {1, 7, 9, 11, 13};
 constexpr int XOUT[5] = {2, 8, 10, 12, 14};
@@ -63,14 +64,17 @@ __host__ __device__ constexpr float kw(int i) { return i == 0 ? 12.0f : (i < 7 ?
 
 struct Params {
   int nx, nc;                  // box x extent; compact cells (fluid + dead)
+  int nrow;                    // rows of the compact layout
   int px;                      // periodic x
-  int inlet, outlet;
+  int inlet, outlet;           // outlet: 1 constant density, 2 extrapolation
   int xbits;                   // code = (row << xbits) | x
   uint32_t plb[Q];             // byte offset of population plane i (i * nc * sizeof(storage))
   uint32_t abytes;             // byte size of the population buffer
   int cy_a2;                   // a == 2: (lambda g)^a is one multiply
   int forch;                   // Forchheimer drag on
-  double in_a0, in_a1, in_period;  // inflow waveform A(t) = a0 (1 + a1 sin(2 pi t / period))
+  double in_a0, in_a1, in_period;  // inflow waveform W(s) = a0 (1 + a1 sin(2 pi s / period))
+  int in_table;                    // > 0: W is the sampled table of that length over one period
+  uint32_t in_ramp;                // pre-run ramp length R (0: none)
   // physical constants in both precisions (the kernels read the one they
   // compute in, straight from the kernel arguments)
   template <class T>
@@ -104,6 +108,8 @@ struct Bufs {
   float* rec;             // recompute record: [20][nc] (pulled values, omega_prev)
   float* rho_rec;         // recompute record: rho per compact cell
   uint32_t* tc;           // time counter: the step at parity k reads tc[k] and writes t + 1 to tc[1 - k]
+  const double* wave;     // sampled inflow waveform (in_table entries)
+  float* side;            // extrapolation outflow: [2][nrow][10] kept values by parity
 };
 
 template <int A, int B, class F>
@@ -241,27 +247,81 @@ __device__ __forceinline__ void pull(const Params& p, const Pop<S>& A, const flo
   }
 }
 
-// Inflow amplitude at step t: a0 (1 + a1 sin(2 pi t / period)) in FP64,
-// rounded once to FP32 (the simulation section's pulsatile inflow, with the
-// waveform reading of the inflow profile).
-__device__ __forceinline__ float inflow_amplitude(const Params& p, uint32_t t) {
-  return (float)(p.in_a0 * (1.0 + p.in_a1 * sin(6.283185307179586 * (double)t / p.in_period)));
+// Inflow amplitude at step t, in FP64, rounded once to FP32 (the simulation
+// section's pulsatile inflow and its pre-run ramp): A(t) = (t/R) W(0) during
+// the ramp, W(t - R) after it; W is the sine waveform or the periodic, linearly
+// interpolated sample table.
+__device__ __forceinline__ float inflow_amplitude(const Params& p, const double* wave, uint32_t t) {
+  double ramp = 1.0, s = 0.0;
+  if (t < p.in_ramp) ramp = (double)t / (double)p.in_ramp;
+  else s = (double)(t - p.in_ramp);
+  double w;
+  if (p.in_table > 0) {
+    double ph = s / p.in_period;
+    ph -= floor(ph);
+    const double x = ph * (double)p.in_table;
+    int i = (int)x;
+    if (i >= p.in_table) i = p.in_table - 1;
+    const int j = i + 1 == p.in_table ? 0 : i + 1;
+    w = wave[i] + (x - (double)i) * (wave[j] - wave[i]);
+  } else {
+    w = p.in_a0 * (1.0 + p.in_a1 * sin(6.283185307179586 * s / p.in_period));
+  }
+  return (float)(ramp * w);
+}
+
+// c_s in lattice units
+constexpr float CS = 0.57735026918962576f;
+
+// Extrapolation outflow (the simulation section's non-reflecting outflow):
+// each unknown population i (c_x = -1) of an outflow cell is carried out at
+// the speed of sound, upwind in x and forward in time:
+//   f_i(t, x) = (1 - c_s) f_i(t-1, x) + c_s f_i(t-1, x - e_x).
+// Both terms are pre-collision values of the previous step, kept per row in
+// side[parity of t][row][10] (FP32, relative to w_i): [0, 5) the outflow
+// cell's own c_x = -1 populations, [5, 10) those of its -x neighbour (whose
+// slots are rewritten during the step, hence the copy).  Without a fluid -x
+// neighbour the population keeps its value.  phi = 1 on the outflow cell, so
+// its deviations are relative to w_i as well.
+__device__ __forceinline__ void extrapolate_out(uint32_t row, uint32_t lk, const float* __restrict__ side_in,
+                                                float d[Q]) {
+  const float* e = side_in + (size_t)row * 10;
+  const bool up = !((lk >> 1) & 1u);  // x - e_x is fluid
+#pragma unroll
+  for (int k = 0; k < 5; ++k)
+    if ((lk >> (LK_UNK + k)) & 1u) d[XOUT[k]] = up ? rfma(CS, e[5 + k] - e[k], e[k]) : e[k];
+}
+
+// Keep this step's c_x = -1 pre-collision populations of an outflow cell
+// (after the fill) or of its -x neighbour for the next step.
+__device__ __forceinline__ void outflow_keep(const Params& p, uint32_t row, uint32_t lk, float phx, const float d[Q],
+                                             float* __restrict__ side_out) {
+  const float s = p.f.ks * (phx - 1.0f);
+  float* e = side_out + (size_t)row * 10 + ((lk & LK_OUT) ? 0 : 5);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) e[k] = rfma(kw(XOUT[k]), s, d[XOUT[k]]);
 }
 
 // Zou-He fill of the unknown populations on the open faces (phi = 1 there, so
-// the closures hold for the deviations as for the populations).
+// the closures hold for the deviations as for the populations), or the
+// extrapolation outflow.
 __device__ __forceinline__ void open_fill(const Params& p, uint32_t row, uint32_t lk, uint32_t t,
-                                          const float* __restrict__ shape, float d[Q]) {
+                                          const float* __restrict__ shape, const double* wave,
+                                          const float* __restrict__ side_in, float d[Q]) {
   const bool in = (lk & LK_IN) != 0;
-  const bool outl = (lk & LK_OUT) != 0;
+  bool outl = (lk & LK_OUT) != 0;
   if (!(in || outl)) return;
+  if (outl && p.outlet == 2) {
+    extrapolate_out(row, lk, side_in, d);
+    return;
+  }
   const float U = p.f.U, iU = p.f.iU;
   const float s0 = d[0] + d[3] + d[4] + d[5] + d[6] + d[15] + d[16] + d[17] + d[18];
   const float ny_ = 0.5f * (d[3] - d[4] + d[15] - d[16] + d[17] - d[18]);
   const float nz_ = 0.5f * (d[5] - d[6] + d[15] - d[16] - d[17] + d[18]);
   // inflow: prescribed u = (ux, 0, 0); density from mass and normal momentum
   float uin = 0.0f;
-  if (in) uin = inflow_amplitude(p, t) * shape[row];
+  if (in) uin = inflow_amplitude(p, wave, t) * shape[row];
   const float sm = d[2] + d[8] + d[10] + d[12] + d[14];
   const float rin = (1.0f + (s0 + 2.0f * sm) * iU) / (1.0f - uin);
   // outflow: prescribed density, normal velocity from mass and the known half
@@ -568,7 +628,9 @@ __device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32
 #pragma unroll
     for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(d[i], &b.rec[(size_t)i * p.nc + c]);
   }
-  open_fill(p, q.row, lk, t, b.shape, d);
+  const size_t half = (size_t)p.nrow * 10;
+  open_fill(p, q.row, lk, t, b.shape, b.wave, b.side + (ODD ? half : 0), d);
+  if (p.outlet == 2 && (lk & (LK_OUT | LK_UPS))) outflow_keep(p, q.row, lk, phx, d, b.side + (ODD ? 0 : half));
   const float omp = b.omega[c];
   Macro<R> M;
   macro<R>(p, phx, d, omp, M);
@@ -638,7 +700,7 @@ __global__ __launch_bounds__(BLOCK) void k_moments(Params p, Bufs b, uint32_t t,
     const float phx = ldo(b.phi, c);
     float d[Q], pt[Q];
     pull<S, SHW, true, ODD>(p, Pop<S>(b.A, p.abytes), b.phi, c, lk, q, phx, d, pt);
-    open_fill(p, q.row, lk, t, b.shape, d);
+    open_fill(p, q.row, lk, t, b.shape, b.wave, b.side + (ODD ? (size_t)p.nrow * 10 : 0), d);
     Macro<R> M;
     macro<R>(p, phx, d, b.omega[c], M);
     const size_t idx = (size_t)b.rowbox[q.row] + (size_t)q.x;
@@ -727,8 +789,16 @@ __device__ __forceinline__ bool open_unknown(uint32_t lk) {
   return k >= 0 && ((lk >> (LK_UNK + k)) & 1u);
 }
 
+// Whether the state keeps the open-face unknown I: the extrapolation outflow's.
+template <int I>
+__device__ __forceinline__ bool kept_unknown(const Params& p, uint32_t lk) {
+  return CX[I] == -1 && (lk & LK_OUT) && p.outlet == 2;
+}
+
 // State out: the pulled (pre-collision) stored values as FP32, [19][nc]; the
-// host converts them back to populations in FP64.  Open-face unknowns are NaN.
+// host converts them back to populations in FP64.  Open-face unknowns are NaN,
+// except the extrapolation outflow's, which are part of the state: their
+// value at time t is extrapolated as the next step would.
 template <class S, bool ODD>
 __global__ __launch_bounds__(BLOCK) void k_gather_state(Params p, Bufs b, float* out) {
   const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
@@ -738,16 +808,24 @@ __global__ __launch_bounds__(BLOCK) void k_gather_state(Params p, Bufs b, float*
   Pos q = position(p, c, b.code[c]);
   if (ODD) load_deltas(b.delta, q);
   const Pop<S> A(b.A, p.abytes);
+  float d[Q];
   sfor<0, Q>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
     const Slot a = slot_in<I, ODD, S>(p, c, lk, q);
-    const float v = A.ld(a.v, a.s);
-    out[(size_t)I * p.nc + c] = open_unknown<I>(lk) ? __builtin_nanf("") : v;
+    d[I] = A.ld(a.v, a.s);
+  });
+  if ((lk & LK_OUT) && p.outlet == 2) extrapolate_out(q.row, lk, b.side + (ODD ? (size_t)p.nrow * 10 : 0), d);
+  sfor<0, Q>([&](auto ic) {
+    constexpr int I = decltype(ic)::value;
+    const bool unk = open_unknown<I>(lk) && !kept_unknown<I>(p, lk);
+    out[(size_t)I * p.nc + c] = unk ? __builtin_nanf("") : d[I];
   });
 }
 
 // State in: inverse of k_gather_state; each slot that some consumer reads is
-// written exactly once (by that consumer's link).
+// written exactly once (by that consumer's link).  A kept unknown of the
+// extrapolation outflow goes to both side values, so that the next step's
+// extrapolation returns it.
 template <class S, bool ODD>
 __global__ __launch_bounds__(BLOCK) void k_scatter_state(Params p, Bufs b, const float* in) {
   const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
@@ -760,7 +838,17 @@ __global__ __launch_bounds__(BLOCK) void k_scatter_state(Params p, Bufs b, const
   sfor<0, Q>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
     const Slot a = slot_in<I, ODD, S>(p, c, lk, q);
-    if (!open_unknown<I>(lk)) A.st(a.v, a.s, in[(size_t)I * p.nc + c]);
+    const float v = in[(size_t)I * p.nc + c];
+    if (kept_unknown<I>(p, lk) && open_unknown<I>(lk)) {
+      int k = 0;
+#pragma unroll
+      for (int j = 0; j < 5; ++j) k = XOUT[j] == I ? j : k;
+      float* e = b.side + (ODD ? (size_t)p.nrow * 10 : 0) + (size_t)q.row * 10;
+      e[k] = v;
+      e[5 + k] = v;
+    } else if (!open_unknown<I>(lk)) {
+      A.st(a.v, a.s, v);
+    }
   });
 }
 

@@ -43,7 +43,8 @@ class lbm_porous(ct.Structure):
 
 class lbm_open(ct.Structure):
     _fields_ = [("inlet", ct.c_int), ("shape_yz", ct.c_void_p), ("a0", ct.c_double), ("a1", ct.c_double),
-                ("period", ct.c_double), ("outlet", ct.c_int), ("rho_out", ct.c_double)]
+                ("period", ct.c_double), ("outlet", ct.c_int), ("rho_out", ct.c_double),
+                ("ramp_steps", ct.c_int), ("wave_table", ct.c_void_p), ("table_len", ct.c_int)]
 
 
 class lbm_objective(ct.Structure):
@@ -126,7 +127,8 @@ class Solver:
 
     solid, phi, region: arrays of shape (nz, ny, nx) (box index x + nx*(y + ny*z)).
     rheology: dict(nu0, nu_inf, lam, n, a); porous: dict(nu_d, d, kc, forchheimer, g).
-    inlet: None or dict(shape=(nz, ny) array, a0, a1, period); outlet: None or rho_out.
+    inlet: None or dict(shape=(nz, ny) array, a0, a1, period[, ramp=steps][, table=FP64 samples of one period]);
+    outlet: None, rho_out (constant-density outflow) or "extrapolation" (the non-reflecting outflow).
     adjoint_T/ckpt: reserve workspace for lbm_adjoint runs of up to adjoint_T steps.
     """
 
@@ -164,7 +166,15 @@ class Solver:
             self._shape_yz = np.ascontiguousarray(inlet["shape"], dtype=np.float32)
             o.inlet, o.shape_yz = 1, _p(self._shape_yz)
             o.a0, o.a1, o.period = float(inlet["a0"]), float(inlet["a1"]), float(inlet["period"])
-        if outlet is not None:
+            o.ramp_steps = int(inlet.get("ramp", 0) or 0)
+            if inlet.get("table") is not None:
+                self._wave = np.ascontiguousarray(inlet["table"], dtype=np.float64)
+                o.wave_table, o.table_len = _p(self._wave), int(self._wave.size)
+        if isinstance(outlet, str):
+            if outlet != "extrapolation":
+                raise ValueError(f"unknown outlet {outlet!r}")
+            o.outlet = 2
+        elif outlet is not None:
             o.outlet, o.rho_out = 1, float(outlet)
         self.adjoint_T, self.ckpt = int(adjoint_T), int(ckpt)
         nbytes = lbm_workspace_size(g, solid, self.adjoint_T, self.ckpt)
@@ -188,8 +198,10 @@ class Solver:
         inlet = None
         if getattr(case, "inlet", False):
             a0, a1, period = case.wave
-            inlet = dict(shape=case.inlet_shape, a0=a0, a1=a1, period=period)
-        outlet = case.rho_out if getattr(case, "outlet", False) else None
+            inlet = dict(shape=case.inlet_shape, a0=a0, a1=a1, period=period,
+                         ramp=getattr(case, "ramp_steps", 0), table=getattr(case, "wave_table", None))
+        kind = int(getattr(case, "outlet", 0) or 0)
+        outlet = "extrapolation" if kind == 2 else (case.rho_out if kind == 1 else None)
         return cls(case.solid, case.phi, periodic=case.periodic, region=case.sac, rheology=case.rheology,
                    porous=case.porous, inlet=inlet, outlet=outlet, **kw)
 

@@ -15,6 +15,7 @@ from .cases import (  # noqa: F401
     periodic_box_case,
     tiny_case,
     fd_voxels,
+    sampled_waveform,
     CONFIGS,
     make_config,
 )

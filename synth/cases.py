@@ -48,9 +48,13 @@ class Case:
     phi: np.ndarray
     sac: np.ndarray
     inlet: bool = False
-    outlet: bool = False
+    outlet: int = 0  # outflow on x = nx - 1: 0 none, 1 constant density, 2 extrapolation
     inlet_shape: Optional[np.ndarray] = None
     wave: Tuple[float, float, float] = (0.0, 0.0, 1.0)
+    # optional: pre-run ramp length and a sampled waveform (one period, FP64)
+    # that replaces the sine of ``wave`` (whose period still applies)
+    ramp_steps: int = 0
+    wave_table: Optional[np.ndarray] = None
     rho_out: float = 1.0
     rheology: Dict[str, float] = dataclasses.field(default_factory=lambda: dict(CY_DEFAULT))
     # Darcy/Forchheimer drag parameters: nu_d (kinematic viscosity in the
@@ -285,6 +289,9 @@ def tiny_case(kind: str = "open", seed: int = 0, nx: int = 9, ny: int = 7, nz: i
     walls).  ``periodic``: periodic x and z, solid layers at y = 0 and ny - 1 plus
     random solid voxels, random porosity, body force.  ``periodic3``: periodic
     in all three axes, random solid voxels, random porosity, body force.
+    ``open_wave``: ``open`` with a 6-step pre-run ramp and a sampled 9-point
+    inflow waveform of period 13 steps.  ``open_extrap``: ``open`` with the
+    extrapolation outflow and one outflow cell whose -x neighbour is solid.
     """
     rng = np.random.default_rng(1000 + seed)
     solid = (rng.random((nz, ny, nx)) < 0.15).astype(np.uint8)
@@ -303,6 +310,23 @@ def tiny_case(kind: str = "open", seed: int = 0, nx: int = 9, ny: int = 7, nz: i
                     solid=solid, phi=phi, sac=sac, inlet=True, outlet=True, inlet_shape=shape,
                     wave=(0.03, 0.5, 40.0), rho_out=1.0,
                     porous=dict(nu_d=0.1, kc=180.0, d=2.0, forchheimer=0, g=(0.0, 0.0, 0.0)))
+    elif kind == "open_wave":
+        case = tiny_case("open", seed=seed, nx=nx, ny=ny, nz=nz)
+        case.name = f"tiny_open_wave{seed}"
+        case.ramp_steps = 6
+        case.wave = (0.0, 0.0, 13.0)
+        case.wave_table = sampled_waveform(9, peak=0.05, base=0.015)
+        return case
+    elif kind == "open_extrap":
+        case = tiny_case("open", seed=seed, nx=nx, ny=ny, nz=nz)
+        case.name = f"tiny_open_extrap{seed}"
+        case.outlet = 2
+        case.solid[nz // 2, ny // 2, nx - 2] = 1
+        case.solid[nz // 2, ny // 2, nx - 1] = 0
+        case.phi = np.where(case.solid == 0, case.phi, 0.0).astype(np.float32)
+        case.phi[nz // 2, ny // 2, nx - 1] = 1.0
+        case.sac = case.sac & (case.solid == 0)
+        return case
     elif kind == "periodic":
         solid[:, 0, :] = 1
         solid[:, ny - 1, :] = 1
@@ -318,6 +342,17 @@ def tiny_case(kind: str = "open", seed: int = 0, nx: int = 9, ny: int = 7, nz: i
     case.phi = np.where(case.solid == 0, case.phi, 0.0).astype(np.float32)
     case.sac = case.sac & (case.solid == 0)
     return case
+
+
+def sampled_waveform(n: int = 128, peak: float = 0.05, base: float = 0.015) -> np.ndarray:
+    """One period of a systole-like inflow waveform, n samples: a base level
+    plus a raised-cosine systolic pulse in the first third of the period and a
+    small secondary (dicrotic) bump.  Stands in for the paper's 1D-0D network
+    waveform, which is not available."""
+    s = np.arange(n, dtype=np.float64) / n
+    pulse = np.where(s < 1.0 / 3.0, 0.5 * (1.0 - np.cos(6.0 * np.pi * s)), 0.0)
+    bump = 0.15 * np.exp(-((s - 0.45) / 0.05) ** 2)
+    return base + (peak - base) * (pulse + bump) / (1.0 + 0.15)
 
 
 def fd_voxels(case: Case, count: int = 16, seed: int = 16) -> np.ndarray:

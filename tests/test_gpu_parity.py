@@ -49,7 +49,7 @@ def rel_l2(a, ref):
     return float(np.sqrt(((a - ref) ** 2).sum()) / np.sqrt((ref ** 2).sum()))
 
 
-@pytest.mark.parametrize("kind", ["open", "periodic", "periodic3"])
+@pytest.mark.parametrize("kind", ["open", "open_wave", "open_extrap", "periodic", "periodic3"])
 @pytest.mark.parametrize("seed", [0, 1])
 def test_one_step_from_random_state(kind, seed):
     """Every cell type (walls, open faces, periodic wrap, porosity jumps): one
@@ -128,6 +128,60 @@ def test_aneurysm_fp32_parity(aneurysm_ref):
     # stress and relaxation rate of the same state
     assert max_rel(g["omega"], ref["omega"]) < 1e-5
     assert max_rel(g["sigma"], ref["sigma"]) < 1e-4
+
+
+def test_aneurysm_ramp_and_sampled_waveform():
+    """The simulation section's inflow: a pre-run ramp (400 steps here) to the
+    start of a sampled periodic waveform (128 samples per 4000-step period),
+    on the 192x128x128 aneurysm, 1000 steps, FP32 storage."""
+    from synth import sampled_waveform
+
+    case = make_config("c1")
+    case.ramp_steps = 400
+    case.wave_table = sampled_waveform(128)
+    steps = 1000
+    say(f"ramp + sampled waveform: aneurysm {case.nx}x{case.ny}x{case.nz}, {steps} steps")
+    o, f, om, ref = _oracle_run(case, steps)
+    s = Solver.from_case(case)
+    s.step(steps)
+    g = _gpu_fields(s)
+    eu, es = max_rel(g["u"], ref["u"]), max_rel(g["shear"], ref["shear"])
+    say(f"  u max-rel {eu:.3e}  shear max-rel {es:.3e}")
+    assert eu < 1e-5 and es < 1e-4
+
+
+@pytest.mark.parametrize("storage,bound_u", [("fp32", 1e-5), ("fp16", 1e-3)])
+def test_aneurysm_extrapolation_outflow(storage, bound_u):
+    """The paper's outflow: the 192x128x128 aneurysm with the extrapolation
+    outflow, 1000 steps; FP32 by max-relative, FP16 storage by relative L2 of
+    the velocity."""
+    case = make_config("c1")
+    case.outlet = 2
+    steps = 1000
+    say(f"extrapolation outflow: aneurysm {case.nx}x{case.ny}x{case.nz}, {storage}, {steps} steps")
+    o, f, om, ref = _oracle_run(case, steps)
+    s = Solver.from_case(case, storage=storage)
+    s.step(steps)
+    g = _gpu_fields(s)
+    eu, el = max_rel(g["u"], ref["u"]), rel_l2(g["u"], ref["u"])
+    say(f"  u max-rel {eu:.3e}  u rel-L2 {el:.3e}  shear max-rel {max_rel(g['shear'], ref['shear']):.3e}")
+    assert (eu if storage == "fp32" else el) < bound_u
+
+
+def test_extrapolation_outflow_multi_step_tiny():
+    """200 steps on the tiny open case with the extrapolation outflow (one
+    outflow cell without a fluid -x neighbour), state compared in full,
+    including the outflow's kept unknowns."""
+    case = tiny_case("open_extrap", seed=2)
+    o = oracle.Oracle(case)
+    f, om = o.init()
+    o.run(f, om, 0, 200)
+    s = Solver.from_case(case)
+    s.step(200)
+    g, gom = s.get_state()
+    err = np.abs(g - f).max() / np.abs(f).max()
+    say(f"  tiny extrapolation outflow, 200 steps: max |f_gpu - f_oracle| / max |f| = {err:.3e}")
+    assert err < 1e-6
 
 
 @pytest.mark.parametrize("shift_mode,arith", [(0, "fp64"), (0, "fp32"), (1, "auto"), (1, "fp64")])
@@ -212,7 +266,7 @@ def test_state_roundtrip_and_reset():
     assert np.abs(gom0 - om0).max() < 1e-7
 
 
-@pytest.mark.parametrize("kind", ["open", "periodic3"])
+@pytest.mark.parametrize("kind", ["open", "open_extrap", "periodic3"])
 @pytest.mark.parametrize("t_split", [7, 8])
 def test_restored_state_continues_trajectory(kind, t_split):
     """get_state / set_state at an odd and an even time (the two slot layouts of

@@ -26,7 +26,7 @@ def _dense(case, cells, f, om):
     return fd.reshape(19, case.nz, case.ny, case.nx), od.reshape(case.nz, case.ny, case.nx)
 
 
-@pytest.mark.parametrize("kind", ["open", "periodic", "periodic3"])
+@pytest.mark.parametrize("kind", ["open", "open_wave", "open_extrap", "periodic", "periodic3"])
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_matches_dense_bruteforce(kind, seed):
     """Compact-list C++ oracle vs dense-array NumPy transcription: 1 and 10 steps
@@ -54,7 +54,7 @@ def test_matches_dense_bruteforce(kind, seed):
     assert np.abs(fields["shear"].reshape(-1)[cells] - m["shear"]).max() < 1e-12
 
 
-@pytest.mark.parametrize("kind", ["open", "periodic"])
+@pytest.mark.parametrize("kind", ["open", "open_extrap", "periodic"])
 def test_rest_state_is_stationary(kind):
     """Fluid at rest with heterogeneous porosity, walls and (zero-velocity)
     open faces stays at rest: the porosity-jump term, the porosity-shifted
@@ -62,6 +62,10 @@ def test_rest_state_is_stationary(kind):
     case = tiny_case(kind, seed=3)
     case.porous = dict(case.porous, g=(0.0, 0.0, 0.0))
     case.wave = (0.0, 0.0, 1.0)
+    if kind == "open_extrap":
+        # the extrapolation mixes populations of the last three layers, which
+        # carry their cells' porosity at rest: uniform porosity there
+        case.phi[:, :, -3:] = np.where(case.solid[:, :, -3:] == 0, 1.0, 0.0)
     o = oracle.Oracle(case)
     f, om = o.init()
     f1, o1 = f.copy(), om.copy()
@@ -145,3 +149,31 @@ def test_deterministic():
     o.run(*a, 0, 15)
     o.run(*b, 0, 15)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_inflow_waveform_definition():
+    """The pre-run grows linearly from 0 to the waveform's starting value over
+    R steps (the simulation section's ramp); afterwards the sampled period is
+    reproduced at its sample times, interpolated linearly in between and
+    repeated every period."""
+    case = tiny_case("open_wave", seed=0)
+    o = oracle.Oracle(case)
+    R = case.ramp_steps
+    tab = case.wave_table
+    T = case.wave[2]
+    n = tab.size
+    amp = [o.amplitude(t) for t in range(R + 4 * int(T) + 1)]
+    assert amp[0] == 0.0
+    for t in range(R + 1):
+        assert abs(amp[t] - tab[0] * t / R) < 1e-15
+    # sample times s = k T / n that fall on integer steps (T = 13, n = 9: k = 0 and 9 -> s = 0, 13)
+    for m in range(4):
+        assert abs(o.amplitude(R + int(T) * m) - tab[0]) < 1e-15
+    # every value lies on the piecewise-linear interpolant of the samples
+    for t in range(R, R + 3 * int(T)):
+        sp = (t - R) % T
+        pos = sp / T * n
+        k = int(pos)
+        lo, hi = tab[k], tab[(k + 1) % n]
+        assert min(lo, hi) - 1e-15 <= o.amplitude(t) <= max(lo, hi) + 1e-15
+        assert abs(o.amplitude(t) - o.amplitude(t + int(T))) < 1e-15
