@@ -220,7 +220,10 @@ lbm_status lbm_reset(lbm_ctx* ctx);
 /* Gradient of the region kinetic-energy objective with respect to the
  * porosity of every fluid cell.  Resets to rest, runs T steps forward while
  * accumulating J and storing a checkpoint every ckpt_every steps, then sweeps
- * back through the segments (recompute forward, then reverse steps).  Needs a
+ * back through the segments (recompute forward, then reverse steps).  The
+ * forward passes compute the collision in FP64 (LBM_ARITH_FP64) whatever the
+ * context's arithmetic mode; the reverse steps are FP64 arithmetic with FP32
+ * adjoint populations.  Needs a
  * workspace sized for (T, ckpt_every) or larger; FP32 storage, shift mode 0,
  * no Forchheimer drag, no extrapolation outflow (for the gradient), a non-empty region,
  * 0 <= t_begin < t_end <= T.
