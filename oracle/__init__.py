@@ -70,15 +70,15 @@ def lib():
         L.oracle_set_phi.argtypes = [vp, vp]
         L.oracle_init.argtypes = [vp, vp, vp]
         L.oracle_run.argtypes = [vp, vp, vp, i32, i32, vp]
-        L.oracle_moments.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp]
+        L.oracle_moments.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]
         L.oracle_cell.argtypes = [ct.POINTER(_Case), vp, dbl, dbl, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.oracle_zouhe_inlet.argtypes = [vp, dbl, dbl, dbl]
         L.oracle_zouhe_outlet.argtypes = [vp, dbl]
         L.oracle_lattice.argtypes = [vp, vp]
         L.oracle_objective.restype = dbl
-        L.oracle_objective.argtypes = [vp, i32, i32, i32]
-        L.oracle_grad_dual.argtypes = [vp, i32, i32, i32, vp, i32, vp, vp]
-        L.oracle_grad_reverse.argtypes = [vp, i32, i32, i32, i32, vp, vp]
+        L.oracle_objective.argtypes = [vp, i32, i32, i32, i32]
+        L.oracle_grad_dual.argtypes = [vp, i32, i32, i32, vp, i32, vp, vp, i32]
+        L.oracle_grad_reverse.argtypes = [vp, i32, i32, i32, i32, vp, vp, i32]
         L.oracle_threads.restype = i32
         _lib = L
     return _lib
@@ -121,6 +121,9 @@ def make_struct(case, keep: list, **override) -> _Case:
         keep.append(table)
         s.wave_table, s.table_len = _ptr(table), int(table.size)
     return s
+
+
+OBJECTIVE = {"ke": 0, "wss": 1}
 
 
 class Oracle:
@@ -180,25 +183,29 @@ class Oracle:
         shear = np.empty(nf)
         om = np.empty(nf)
         sigma = np.empty((6, nf))
+        tau = np.empty((3, nf))
         lib().oracle_moments(self.h, _ptr(np.ascontiguousarray(f)), _ptr(np.ascontiguousarray(omega)), int(t),
-                             _ptr(rho), _ptr(u), _ptr(shear), _ptr(om), _ptr(sigma))
-        return dict(rho=rho, u=u, shear=shear, omega=om, sigma=sigma)
+                             _ptr(rho), _ptr(u), _ptr(shear), _ptr(om), _ptr(sigma), _ptr(tau))
+        return dict(rho=rho, u=u, shear=shear, omega=om, sigma=sigma, tau=tau)
 
-    def objective(self, T: int, tb: int, te: int) -> float:
-        return float(lib().oracle_objective(self.h, int(T), int(tb), int(te)))
+    def objective(self, T: int, tb: int, te: int, kind: str = "ke") -> float:
+        """J over steps [tb, te) of a T-step run from rest; kind "ke" (region
+        kinetic energy) or "wss" (WSS magnitude over the region's wall cells)."""
+        return float(lib().oracle_objective(self.h, int(T), int(tb), int(te), OBJECTIVE[kind]))
 
-    def grad_dual(self, T: int, tb: int, te: int, box_cells):
+    def grad_dual(self, T: int, tb: int, te: int, box_cells, kind: str = "ke"):
         cells = np.ascontiguousarray(np.asarray(box_cells, dtype=np.int64))
         assert cells.size <= 16
         J = np.zeros(1)
         g = np.zeros(cells.size)
-        lib().oracle_grad_dual(self.h, int(T), int(tb), int(te), _ptr(cells), int(cells.size), _ptr(J), _ptr(g))
+        lib().oracle_grad_dual(self.h, int(T), int(tb), int(te), _ptr(cells), int(cells.size), _ptr(J), _ptr(g),
+                               OBJECTIVE[kind])
         return float(J[0]), g
 
-    def grad_reverse(self, T: int, tb: int, te: int, ckpt: int):
+    def grad_reverse(self, T: int, tb: int, te: int, ckpt: int, kind: str = "ke"):
         J = np.zeros(1)
         g = np.zeros(self.case.n_box)
-        lib().oracle_grad_reverse(self.h, int(T), int(tb), int(te), int(ckpt), _ptr(J), _ptr(g))
+        lib().oracle_grad_reverse(self.h, int(T), int(tb), int(te), int(ckpt), _ptr(J), _ptr(g), OBJECTIVE[kind])
         if np.isnan(J[0]):
             raise ValueError("the reverse sweep supports the density outflow only")
         return float(J[0]), g.reshape(self.case.nz, self.case.ny, self.case.nx)

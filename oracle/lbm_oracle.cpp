@@ -147,8 +147,11 @@ struct Ctx {
   std::vector<int> nbr;                // [Q][nf]: fluid index of x + c_i, or NB_WALL/NB_OPEN
   std::vector<int> xc, yc, zc;         // coordinates of fluid cells
   std::vector<uint8_t> kind;           // 0 interior, 1 inlet, 2 outlet
+  std::vector<double> nrm;             // [nf][3]: outer wall normal (0 off the wall)
+  std::vector<uint8_t> wall;           // 1: the cell has a wall normal
   int64_t nf = 0;
   long nsac = 0;
+  long nwss = 0;                       // objective-region cells on the wall
 };
 
 // Inflow waveform at time s of its period: the sine a0 (1 + a1 sin(2 pi s / T)),
@@ -347,6 +350,54 @@ void extrapolate_outlet(const Ctx& C, const T* f, int64_t x, T* fn) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Wall shear stress (the simulation section's WSS, here on the voxel wall).
+// Reading: the paper extrapolates the deviatoric stress to a wall mesh and
+// projects it on the tangential plane; with no mesh, the wall is the set of
+// fluid cells that have a bounce-back link, the outer normal of such a cell is
+// the lattice-weighted mean direction of its wall links,
+//   n = m / |m|,  m = sum over {i : x + c_i is wall} of w_i c_i,
+// and tau = sigma n - (n . sigma n) n with the cell's deviatoric stress
+// sigma = (omega/2 - 1) Pi (omega the relaxation rate the cell computes in
+// this step).  A cell whose wall links cancel (m = 0) has no normal and no WSS.
+// Open-face links are not wall.
+// ---------------------------------------------------------------------------
+bool wall_normal(const Ctx& C, int64_t x, double n[3]) {
+  double m[3] = {0.0, 0.0, 0.0};
+  for (int i = 1; i < Q; ++i)
+    if (C.nbr[i * C.nf + x] == NB_WALL)
+      for (int a = 0; a < 3; ++a) m[a] += WT[i] * CV[i][a];
+  const double len = std::sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+  for (int a = 0; a < 3; ++a) n[a] = len > 0.0 ? m[a] / len : 0.0;
+  return len > 0.0;
+}
+
+template <class T>
+void wall_shear(const CellResult<T>& r, const double n[3], T tau[3]) {
+  const T s = r.omega / 2.0 - 1.0;
+  // full symmetric tensor from the stored xx yy zz xy xz yz
+  const T P[3][3] = {{r.Pi[0], r.Pi[3], r.Pi[4]}, {r.Pi[3], r.Pi[1], r.Pi[5]}, {r.Pi[4], r.Pi[5], r.Pi[2]}};
+  T sn[3];
+  for (int a = 0; a < 3; ++a) sn[a] = s * (P[a][0] * n[0] + P[a][1] * n[1] + P[a][2] * n[2]);
+  const T nsn = sn[0] * n[0] + sn[1] * n[1] + sn[2] * n[2];
+  for (int a = 0; a < 3; ++a) tau[a] = sn[a] - nsn * n[a];
+}
+
+// Per-cell term of the objective e(t): kind 0 the kinetic energy rho |u|^2 / 2
+// on region cells, kind 1 the WSS magnitude |tau| on region cells of the wall.
+template <class T>
+T objective_term(const Ctx& C, int64_t x, const CellResult<T>& r, int kind) {
+  if (!C.sac[x]) return T(0.0);
+  if (kind == 0) return 0.5 * r.rho * (r.u[0] * r.u[0] + r.u[1] * r.u[1] + r.u[2] * r.u[2]);
+  if (!C.wall[x]) return T(0.0);
+  T tau[3];
+  wall_shear(r, &C.nrm[3 * x], tau);
+  return Sqrt(tau[0] * tau[0] + tau[1] * tau[1] + tau[2] * tau[2]);
+}
+
+// Number of cells e(t) averages over.
+long objective_count(const Ctx& C, int kind) { return std::max(1L, kind == 0 ? C.nsac : C.nwss); }
+
 // Gather a cell's inputs: its populations (after the open-face fill at step t)
 // and the porosity of its neighbours.
 template <class T>
@@ -380,7 +431,8 @@ void stream_out(const Ctx& C, int64_t x, const T q[Q], T* fn) {
 // One full step in place: f (pre-collision, [Q][nf]) and omega (previous rate).
 // If ke is non-null, also returns the sac-averaged kinetic energy of step t.
 template <class T>
-void step(const Ctx& C, std::vector<T>& f, std::vector<T>& omega, const std::vector<T>& phi_f, int t, T* ke) {
+void step(const Ctx& C, std::vector<T>& f, std::vector<T>& omega, const std::vector<T>& phi_f, int t, T* ke,
+          int kind = 0) {
   const int64_t nf = C.nf;
   std::vector<T> fn((size_t)Q * nf, T(0.0));
   std::vector<T> keloc(ke ? nf : 0, T(0.0));
@@ -391,7 +443,7 @@ void step(const Ctx& C, std::vector<T>& f, std::vector<T>& omega, const std::vec
     CellResult<T> r;
     cell_update(C.c, fl, omega[x], phi_f[x], phit, r);
     omega[x] = r.omega;
-    if (ke && C.sac[x]) keloc[x] = 0.5 * r.rho * (r.u[0] * r.u[0] + r.u[1] * r.u[1] + r.u[2] * r.u[2]);
+    if (ke) keloc[x] = objective_term(C, x, r, kind);
     stream_out(C, x, r.q, fn.data());
     if (C.kind[x] == 2 && C.c.outlet == 2) extrapolate_outlet(C, f.data(), x, fn.data());
   }
@@ -399,7 +451,7 @@ void step(const Ctx& C, std::vector<T>& f, std::vector<T>& omega, const std::vec
   if (ke) {
     T s = 0;
     for (int64_t x = 0; x < nf; ++x) if (C.sac[x]) s += keloc[x];
-    *ke = s / (double)std::max(1L, C.nsac);
+    *ke = s / (double)objective_count(C, kind);
   }
 }
 
@@ -458,6 +510,12 @@ void* oracle_new(const oracle_case* c) {
   C->nbr.assign((size_t)Q * nf, 0);
   for (int64_t x = 0; x < nf; ++x)
     for (int i = 0; i < Q; ++i) C->nbr[i * nf + x] = classify(*C, C->xc[x], C->yc[x], C->zc[x], i);
+  C->nrm.assign((size_t)3 * nf, 0.0);
+  C->wall.assign(nf, 0);
+  for (int64_t x = 0; x < nf; ++x) {
+    C->wall[x] = wall_normal(*C, x, &C->nrm[3 * x]) ? 1 : 0;
+    if (C->wall[x] && C->sac[x]) C->nwss++;
+  }
   return C;
 }
 
@@ -501,10 +559,11 @@ void oracle_run(void* h, double* f, double* omega, int t0, int nsteps, double* k
 }
 
 // Macroscopic fields of the state at step t (fill, moments, velocity, Pi,
-// shear rate, new relaxation rate, deviatoric stress sigma = (omega/2 - 1) Pi),
-// per fluid cell.  Any output may be NULL.
+// shear rate, new relaxation rate, deviatoric stress sigma = (omega/2 - 1) Pi,
+// wall shear stress tau [3][nf], 0 off the wall), per fluid cell.  Any output
+// may be NULL.
 void oracle_moments(void* h, const double* f, const double* omega, int t, double* rho, double* u,
-                    double* shear, double* omega_new, double* sigma) {
+                    double* shear, double* omega_new, double* sigma, double* tau) {
   Ctx* C = (Ctx*)h;
   const int64_t nf = C->nf;
   std::vector<double> ph = fluid_phi(*C);
@@ -519,6 +578,11 @@ void oracle_moments(void* h, const double* f, const double* omega, int t, double
     if (shear) shear[x] = r.shear;
     if (omega_new) omega_new[x] = r.omega;
     if (sigma) for (int k = 0; k < 6; ++k) sigma[k * nf + x] = (r.omega / 2.0 - 1.0) * r.Pi[k];
+    if (tau) {
+      double tw[3] = {0.0, 0.0, 0.0};
+      if (C->wall[x]) wall_shear(r, &C->nrm[3 * x], tw);
+      for (int a = 0; a < 3; ++a) tau[a * nf + x] = tw[a];
+    }
   }
 }
 
@@ -549,8 +613,9 @@ void oracle_lattice(int* c, double* w) {
 }
 
 // Objective: J = (1/(te-tb)) sum_{t=tb}^{te-1} e(t), e(t) = sac mean of
-// (1/2) rho |u|^2 from step t's moments, starting at rest and running T steps.
-double oracle_objective(void* h, int T, int tb, int te) {
+// (1/2) rho |u|^2 (kind 0) or of the WSS magnitude over the sac's wall cells
+// (kind 1) from step t's moments, starting at rest and running T steps.
+double oracle_objective(void* h, int T, int tb, int te, int kind) {
   Ctx* C = (Ctx*)h;
   std::vector<double> ph = fluid_phi(*C), f, om;
   rest_state(*C, ph, f, om);
@@ -558,7 +623,7 @@ double oracle_objective(void* h, int T, int tb, int te) {
   for (int t = 0; t < T; ++t) {
     double ke = 0;
     bool in = (t >= tb && t < te);
-    step(*C, f, om, ph, t, in ? &ke : nullptr);
+    step(*C, f, om, ph, t, in ? &ke : nullptr, kind);
     if (in) J += ke;
   }
   return J / (double)(te - tb);
@@ -567,7 +632,7 @@ double oracle_objective(void* h, int T, int tb, int te) {
 // Exact discrete derivative dJ/dphi at up to 16 cells (box indices) by
 // forward-mode dual numbers (one derivative component per cell).
 void oracle_grad_dual(void* h, int T, int tb, int te, const int64_t* boxcells, int ncells, double* J,
-                      double* grads) {
+                      double* grads, int kind) {
   const int N = 16;
   typedef Dual<N> D;
   Ctx* C = (Ctx*)h;
@@ -584,7 +649,7 @@ void oracle_grad_dual(void* h, int T, int tb, int te, const int64_t* boxcells, i
   for (int t = 0; t < T; ++t) {
     D ke;
     bool in = (t >= tb && t < te);
-    step(*C, f, om, ph, t, in ? &ke : nullptr);
+    step(*C, f, om, ph, t, in ? &ke : nullptr, kind);
     if (in) acc += ke;
   }
   acc = acc / (double)(te - tb);
@@ -599,7 +664,7 @@ void oracle_grad_dual(void* h, int T, int tb, int te, const int64_t* boxcells, i
 //   -> (19 post-collision populations, new omega, kinetic-energy term)
 // is taken with 39-component dual numbers and its transpose applied to the
 // output adjoints; the streaming transpose gathers along +c_i.
-void oracle_grad_reverse(void* h, int T, int tb, int te, int ckpt, double* J, double* grad_box) {
+void oracle_grad_reverse(void* h, int T, int tb, int te, int ckpt, double* J, double* grad_box, int kind) {
   const int NI = 39;
   typedef Dual<NI> D;
   Ctx* C = (Ctx*)h;
@@ -618,11 +683,11 @@ void oracle_grad_reverse(void* h, int T, int tb, int te, int ckpt, double* J, do
     if (t % ckpt == 0) { cf[t / ckpt] = f; co[t / ckpt] = om; }
     double ke = 0;
     bool in = (t >= tb && t < te);
-    step(*C, f, om, ph, t, in ? &ke : nullptr);
+    step(*C, f, om, ph, t, in ? &ke : nullptr, kind);
     if (in) acc += ke;
   }
   *J = acc / (double)(te - tb);
-  const double ew = 1.0 / ((double)(te - tb) * (double)std::max(1L, C->nsac));
+  const double ew = 1.0 / ((double)(te - tb) * (double)objective_count(*C, kind));
 
   std::vector<double> fh((size_t)Q * nf, 0.0), fh_new((size_t)Q * nf, 0.0);  // adjoint of f_{n+1}, f_n
   std::vector<double> oh(nf, 0.0), oh_new(nf, 0.0);                           // adjoint of omega_n, omega_{n-1}
@@ -662,7 +727,7 @@ void oracle_grad_reverse(void* h, int T, int tb, int te, int ckpt, double* J, do
         }
         CellResult<D> r;
         cell_update(C->c, fl, omp, phx, phit, r);
-        D e = 0.5 * r.rho * (r.u[0] * r.u[0] + r.u[1] * r.u[1] + r.u[2] * r.u[2]);
+        D e = objective_term(*C, x, r, kind);
         // output adjoints
         double qh[Q];
         for (int i = 0; i < Q; ++i) {
