@@ -154,16 +154,22 @@ typedef struct {
 } lbm_open;
 
 /* Objective for lbm_adjoint: J = (1/(t_end - t_begin)) sum_{t=t_begin}^{t_end-1} e(t),
- * e(t) = mean over the region cells of (1/2) rho |u|^2 evaluated from the
- * pre-collision state of step t (the region is given to lbm_create). */
-typedef struct { int t_begin, t_end; } lbm_objective;
+ * evaluated from the pre-collision state of step t (the region is given to
+ * lbm_create):
+ *   kind LBM_OBJ_KINETIC: e(t) = mean over the region cells of (1/2) rho |u|^2;
+ *   kind LBM_OBJ_WSS:     e(t) = mean over the region's wall cells of |tau|,
+ *                         the wall shear stress of lbm_moments (the quantity
+ *                         the paper averages over the aneurysm wall). */
+enum { LBM_OBJ_KINETIC = 0, LBM_OBJ_WSS = 1 };
+typedef struct { int t_begin, t_end; int kind; } lbm_objective;
 
 /* Diagnostics vector (lbm_diagnostics), all FP64, of the current state:
  *   [0] mass  sum_x phi rho            [1..3] momentum sum_x sum_i f_i c_i
  *   [4] kinetic energy sum_x rho|u|^2/2 [5] same over the region cells
  *   [6] max |u|   [7] min omega   [8] max omega
- *   [9] number of cells with a non-finite value   [10] step index t */
-#define LBM_NDIAG 11
+ *   [9] number of cells with a non-finite value   [10] step index t
+ *   [11] mean wall shear stress |tau| over the region's wall cells (0 if none) */
+#define LBM_NDIAG 12
 
 /* Bytes of device workspace a context needs.  adjoint_T > 0 adds room for an
  * lbm_adjoint run of adjoint_T steps with checkpoints every ckpt_every steps.
@@ -193,10 +199,14 @@ lbm_status lbm_step(lbm_ctx* ctx, int n);
 
 /* Macroscopic fields of the current state (what the next step's collision
  * uses): density rho, velocity u [3][nx*ny*nz], shear rate, the relaxation
- * rate omega the next collision will use, and the deviatoric stress
- * sigma = (omega/2 - 1) Pi [6][nx*ny*nz] in the order xx yy zz xy xz yz.
+ * rate omega the next collision will use, the deviatoric stress
+ * sigma = (omega/2 - 1) Pi [6][nx*ny*nz] in the order xx yy zz xy xz yz, and
+ * the wall shear stress tau = sigma n - (n . sigma n) n [3][nx*ny*nz]
+ * (simulation section) on the voxel wall: the fluid cells with a bounce-back
+ * link, whose outer normal n is the normalised sum over their wall links
+ * x + c_i of w_i c_i (0 where that sum vanishes and off the wall).
  * Device outputs in box layout, 0 on solid voxels; any may be NULL. */
-lbm_status lbm_moments(lbm_ctx* ctx, float* rho, float* u, float* shear, float* omega, float* sigma);
+lbm_status lbm_moments(lbm_ctx* ctx, float* rho, float* u, float* shear, float* omega, float* sigma, float* tau);
 
 /* FP64 diagnostics of the current state into out[LBM_NDIAG] (host); syncs. */
 lbm_status lbm_diagnostics(lbm_ctx* ctx, double* out);
@@ -217,16 +227,17 @@ lbm_status lbm_set_porosity(lbm_ctx* ctx, const float* phi);
 /* Reset to the rest state at t = 0. */
 lbm_status lbm_reset(lbm_ctx* ctx);
 
-/* Gradient of the region kinetic-energy objective with respect to the
- * porosity of every fluid cell.  Resets to rest, runs T steps forward while
+/* Gradient of the region objective (kinetic energy or wall shear stress) with
+ * respect to the porosity of every fluid cell.  Resets to rest, runs T steps forward while
  * accumulating J and storing a checkpoint every ckpt_every steps, then sweeps
  * back through the segments (recompute forward, then reverse steps).  The
  * forward passes compute the collision in FP64 (LBM_ARITH_FP64) whatever the
  * context's arithmetic mode; the reverse steps are FP64 arithmetic with FP32
- * adjoint populations.  Needs a
- * workspace sized for (T, ckpt_every) or larger; FP32 storage, shift mode 0,
- * no Forchheimer drag, no extrapolation outflow (for the gradient), a non-empty region,
- * 0 <= t_begin < t_end <= T.
+ * adjoint populations.  Needs a workspace sized for (T, ckpt_every) or
+ * larger; FP32 storage, shift mode 0, no Forchheimer drag, no extrapolation
+ * outflow (for the gradient), a region with a fluid cell (with a wall cell for
+ * LBM_OBJ_WSS), 0 <= t_begin < t_end <= T.  At a wall cell where tau = 0 the
+ * WSS term contributes no gradient (|tau| is not differentiable there).
  *   J:       host, 1 double
  *   dJ_dphi: device, nx*ny*nz floats (box layout, 0 off the fluid), or NULL:
  *            then only J is computed (the forward pass, no checkpoints; the

@@ -1,11 +1,18 @@
-"""The sac kinetic-energy objective as a differentiable function of the porosity.
+"""The sac objectives as differentiable functions of the porosity.
 
-``sac_kinetic_energy(phi, solver, t_begin, t_end, T)`` returns
-J(phi) = time average over steps [t_begin, t_end) of the region mean of
-rho |u|^2 / 2, for a run of T steps from rest with porosity phi.  When phi
-requires a gradient, the forward call runs ``lbm_adjoint``, which returns J and
-dJ/dphi together (hand-written reverse steps over checkpointed segments); the
-backward pass scales that gradient.  Otherwise only J is computed.
+``region_objective(phi, solver, t_begin, t_end, T, kind=...)`` returns
+J(phi) = time average over steps [t_begin, t_end) of a region mean, for a run
+of T steps from rest with porosity phi:
+
+* kind "ke": the region mean of rho |u|^2 / 2 (``sac_kinetic_energy``);
+* kind "wss": the mean wall shear stress magnitude |tau| over the region's
+  wall cells, the quantity the paper averages over the aneurysm wall
+  (``sac_wall_shear_stress``).
+
+When phi requires a gradient, the forward call runs ``lbm_adjoint``, which
+returns J and dJ/dphi together (hand-written reverse steps over checkpointed
+segments); the backward pass scales that gradient.  Otherwise only J is
+computed.
 
 phi is the dense box porosity (nz, ny, nx), FP32, on any device; it must keep
 the solver's solid mask (0 on solid voxels, in (0, 1] on fluid, 1 on open
@@ -20,26 +27,38 @@ import numpy as np
 import torch
 
 
-class SacKineticEnergy(torch.autograd.Function):
+class RegionObjective(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, phi: torch.Tensor, solver, t_begin: int, t_end: int, T: int, ckpt: Optional[int]):
+    def forward(ctx, phi: torch.Tensor, solver, t_begin: int, t_end: int, T: int, ckpt: Optional[int], kind: str):
         solver.set_porosity(phi.detach().to("cpu", torch.float32).numpy().astype(np.float32))
         ctx.phi_device = phi.device
         if ctx.needs_input_grad[0]:
-            J, g = solver.adjoint(t_begin, t_end, T, ckpt)
+            J, g = solver.adjoint(t_begin, t_end, T, ckpt, kind=kind)
             ctx.save_for_backward(g)
         else:
-            J = solver.objective(t_begin, t_end, T)
+            J = solver.objective(t_begin, t_end, T, kind=kind)
         return torch.tensor(J, dtype=torch.float64, device=phi.device)
 
     @staticmethod
     def backward(ctx, grad_out):
         (g,) = ctx.saved_tensors
         gphi = (grad_out.to(g.device, torch.float64) * g.to(torch.float64)).to(torch.float32)
-        return gphi.to(ctx.phi_device), None, None, None, None, None
+        return gphi.to(ctx.phi_device), None, None, None, None, None, None
+
+
+def region_objective(phi: torch.Tensor, solver, t_begin: int, t_end: int, T: int,
+                     ckpt: Optional[int] = None, kind: str = "ke") -> torch.Tensor:
+    """Differentiable J(phi); see the module docstring."""
+    return RegionObjective.apply(phi, solver, int(t_begin), int(t_end), int(T), ckpt, kind)
 
 
 def sac_kinetic_energy(phi: torch.Tensor, solver, t_begin: int, t_end: int, T: int,
                        ckpt: Optional[int] = None) -> torch.Tensor:
-    """Differentiable J(phi); see the module docstring."""
-    return SacKineticEnergy.apply(phi, solver, int(t_begin), int(t_end), int(T), ckpt)
+    """Differentiable time-averaged region kinetic energy."""
+    return region_objective(phi, solver, t_begin, t_end, T, ckpt, "ke")
+
+
+def sac_wall_shear_stress(phi: torch.Tensor, solver, t_begin: int, t_end: int, T: int,
+                          ckpt: Optional[int] = None) -> torch.Tensor:
+    """Differentiable time-averaged WSS magnitude over the region's wall cells."""
+    return region_objective(phi, solver, t_begin, t_end, T, ckpt, "wss")

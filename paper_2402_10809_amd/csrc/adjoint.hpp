@@ -38,19 +38,11 @@ struct AdjBufs {
   double* phih;           // per cell: porosity adjoint accumulator
 };
 
-// Symmetric 3x3 stored as xx yy zz xy xz yz.
-template <class R>
-__device__ __forceinline__ void sym_mv(const R s[6], R x, R y, R z, R& ox, R& oy, R& oz) {
-  ox = s[0] * x + s[3] * y + s[4] * z;
-  oy = s[3] * x + s[1] * y + s[5] * z;
-  oz = s[4] * x + s[5] * y + s[2] * z;
-}
-
 // One reverse step at every fluid cell.  Arithmetic in FP64 (the adjoint
 // recursion has the same slow modes as the forward map, so FP32 rounding of
 // per-cell scalars would accumulate the same way); the adjoint populations are
 // stored in FP32.
-__global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, uint32_t t, float ew) {
+__global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, uint32_t t, float ew, int kind) {
   using R = double;
   const uint32_t c = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   if (c >= (uint32_t)p.nc) return;
@@ -148,8 +140,34 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, uint32_t
   const R us2F = ux * s2Fx + uy * s2Fy + uz * s2Fz;
   const R Aeq = phx * M.rm1 - 1.5 * pr * uu;
 
+  // WSS objective term of a region wall cell: e = |tau|, tau = sigma n -
+  // (n . sigma n) n, sigma = (omega/2 - 1) Pi.  d|tau| = t . d sigma n with
+  // the unit t = tau/|tau|, i.e. the symmetric tensor sym(t n) against d sigma;
+  // it reaches Pi scaled by (omega/2 - 1) and omega through Pi/2.
+  R wG[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  R wom = 0.0;
+  if (kind == 1 && reg && ew != 0.0f) {
+    float nw[3];
+    if (wall_normal(lk, nw)) {
+      R tau[3];
+      const R tm = wall_tau(M, nw, tau);
+      if (tm > 0.0) {
+        const R e = (R)ew / tm;
+        const R tx = e * tau[0], ty = e * tau[1], tz = e * tau[2];
+        const R nx = nw[0], ny = nw[1], nz = nw[2];
+        const R sh[6] = {tx * nx, ty * ny, tz * nz, 0.5 * (tx * ny + ty * nx), 0.5 * (tx * nz + tz * nx),
+                         0.5 * (ty * nz + tz * ny)};
+        const R sg = 0.5 * M.omega - 1.0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) wG[k] = sg * sh[k];
+        wom = 0.5 * (sh[0] * M.P[0] + sh[1] * M.P[1] + sh[2] * M.P[2] +
+                     2.0 * (sh[3] * M.P[3] + sh[4] * M.P[4] + sh[5] * M.P[5]));
+      }
+    }
+  }
+
   // collision: q = (1-omega) f + omega feq + K g + w rho (phi~ - phi)
-  R omh = (R)a.omh[c] + (Aeq * s0 + 3.0 * pr * s1u + 4.5 * pr * us2u - qd) -
+  R omh = (R)a.omh[c] + wom + (Aeq * s0 + 3.0 * pr * s1u + 4.5 * pr * us2u - qd) -
           0.5 * (3.0 * s1F - 3.0 * s0 * uF + 9.0 * us2F);
   R uhx = K * (9.0 * s2Fx - 3.0 * s0 * Fx), uhy = K * (9.0 * s2Fy - 3.0 * s0 * Fy),
     uhz = K * (9.0 * s2Fz - 3.0 * s0 * Fz);
@@ -178,7 +196,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, uint32_t
   const R gsc = Nn > 0.0 ? Nh * fast_rcp(Nn) : 0.0;
   R G[6];
 #pragma unroll
-  for (int k = 0; k < 6; ++k) G[k] = gsc * M.P[k];
+  for (int k = 0; k < 6; ++k) G[k] = gsc * M.P[k] + wG[k];
   R Gux, Guy, Guz, GFx, GFy, GFz;
   sym_mv(G, ux, uy, uz, Gux, Guy, Guz);
   sym_mv(G, Fx, Fy, Fz, GFx, GFy, GFz);
@@ -189,8 +207,8 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, uint32_t
   uhy += GFy - 2.0 * pr * Guy;
   uhz += GFz - 2.0 * pr * Guz;
   Fhx += Gux; Fhy += Guy; Fhz += Guz;
-  // objective e = rho |u|^2 / 2 on region cells
-  const R eh = reg ? (R)ew : 0.0;
+  // kinetic-energy objective e = rho |u|^2 / 2 on region cells
+  const R eh = (reg && kind == 0) ? (R)ew : 0.0;
   rhoh += eh * 0.5 * uu;
   uhx += eh * rho * ux; uhy += eh * rho * uy; uhz += eh * rho * uz;
   // force F = rho (g - D u), D = phi^2 nu / k

@@ -7,7 +7,7 @@ namespace lbm {
 
 constexpr int Q = 19;
 constexpr int BLOCK = 256;   // 4 wave64 per workgroup
-constexpr int NDIAGP = 10;   // per-block diagnostic partials
+constexpr int NDIAGP = 11;   // per-block diagnostic partials
 
 // Direction order: rest; +x -x +y -y +z -z; xy edges; xz edges; yz edges,
 // each odd-numbered direction followed by its opposite.

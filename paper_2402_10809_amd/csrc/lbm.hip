@@ -180,6 +180,7 @@ struct lbm_ctx {
   int nblk = 0;                   // blocks of BLOCK work-items over the compact cells
   int sblk = 0;                   // blocks of the step kernel
   int64_t nreg = 0;
+  int64_t nwss = 0;               // region cells on the wall (with a wall normal)
   double U = 36.0;
   Rows rows;
   std::vector<int64_t> fluid_box; // box index per fluid cell (ascending)
@@ -276,8 +277,10 @@ lbm_status check_phi(const lbm_ctx* c, const float* phi) {
 
 // Link word of every compact cell (see step.hpp): dead flag, bounce-back mask
 // of the pulls, uniform-neighbour-porosity flag, open-face role, region,
-// open-face unknowns.
-void build_links(const lbm_ctx* c, const std::vector<float>& phib, std::vector<uint32_t>& links) {
+// open-face unknowns.  Returns the number of region cells on the wall (a wall
+// link that is not an open-face unknown, and a nonzero weighted link sum).
+int64_t build_links(const lbm_ctx* c, const std::vector<float>& phib, std::vector<uint32_t>& links) {
+  int64_t nwss = 0;
   const int nx = c->grid.nx, ny = c->grid.ny, nz = c->grid.nz;
   const int per[3] = {c->grid.periodic[0] != 0, c->grid.periodic[1] != 0, c->grid.periodic[2] != 0};
   const int dims[3] = {nx, ny, nz};
@@ -289,6 +292,7 @@ void build_links(const lbm_ctx* c, const std::vector<float>& phib, std::vector<u
     bool uni = true;
     const float ph = phib[b];
     uint32_t unk = 0;
+    int m[3] = {0, 0, 0};  // sum over wall links x + c_j of 36 w_j c_j
     for (int i = 1; i < Q; ++i) {
       const int cv[3] = {CX[i], CY[i], CZ[i]};
       for (int sgn = -1; sgn <= 1; sgn += 2) {  // -1: pull source x - c_i; +1: neighbour x + c_i
@@ -306,11 +310,14 @@ void build_links(const lbm_ctx* c, const std::vector<float>& phib, std::vector<u
         if (sgn < 0) {
           if (wall) lk |= 1u << i;
           // open-face unknown: the source lies beyond the inflow/outflow face only
-          if (out && !out_yz && c->openface[k]) {
+          const bool open = out && !out_yz && c->openface[k];
+          if (open) {
             const int* xs = c->openface[k] == 1 ? XIN : XOUT;
             for (int j = 0; j < 5; ++j)
               if (xs[j] == i) unk |= 1u << j;
           }
+          if (wall && !open)
+            for (int a = 0; a < 3; ++a) m[a] -= (int)kw(i) * cv[a];
         } else if (!wall && phib[sb] != ph) {
           uni = false;
         }
@@ -324,7 +331,9 @@ void build_links(const lbm_ctx* c, const std::vector<float>& phib, std::vector<u
     if (c->region_f[k]) lk |= LK_REG;
     lk |= unk << LK_UNK;
     links[c->fluid_c[k]] = lk;
+    if (c->region_f[k] && (m[0] | m[1] | m[2]) != 0) ++nwss;
   }
+  return nwss;
 }
 
 // Upload the porosity and the link words (which depend on it).
@@ -338,7 +347,7 @@ lbm_status upload_phi(lbm_ctx* c, const float* phi) {
     c->phi_f[k] = v;
   }
   std::vector<uint32_t> links;
-  build_links(c, box, links);
+  c->nwss = build_links(c, box, links);
   HIP_TRY(c, hipMemcpyAsync(c->ws + c->L.phi, comp.data(), comp.size() * 4, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->ws + c->L.links, links.data(), links.size() * 4, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -367,11 +376,12 @@ void with_parity(int64_t t, Fn&& fn) {
 }
 
 // One step at time t (in place).  diag: 0 none, 1 diagnostics partials, 2
-// region energy accumulation into the objective partials.  rec: record the
+// region kinetic energy, 3 region wall shear stress, accumulated into the
+// objective partials.  rec: record the
 // step for the adjoint (FP32, shift mode 0 only).
 lbm_status launch_step(lbm_ctx* c, int diag, float* rec, float* rho_rec) {
   Bufs b = bufs(c);
-  if (diag == 2) b.part = (double*)(c->ws + c->L.obj);
+  if (diag >= 2) b.part = (double*)(c->ws + c->L.obj);
   if (rec) {
     b.rec = rec;
     b.rho_rec = rho_rec;
@@ -392,8 +402,10 @@ lbm_status launch_step(lbm_ctx* c, int diag, float* rec, float* rho_rec) {
         hipLaunchKernelGGL((k_step<S, SH, OD, 0, false, R, PJ, NT>), grid, block, 0, c->stream, c->P, b);
       } else if (diag == 1) {
         hipLaunchKernelGGL((k_step<S, SH, OD, 1, false, R, PJ, NT>), grid, block, 0, c->stream, c->P, b);
-      } else {
+      } else if (diag == 2) {
         hipLaunchKernelGGL((k_step<S, SH, OD, 2, false, R, PJ, NT>), grid, block, 0, c->stream, c->P, b);
+      } else {
+        hipLaunchKernelGGL((k_step<S, SH, OD, 3, false, R, PJ, NT>), grid, block, 0, c->stream, c->P, b);
       }
     });
   });
@@ -428,7 +440,8 @@ lbm_status check_stable(lbm_ctx* c, const double* dg) {
   return LBM_OK;
 }
 
-lbm_status moments_launch(lbm_ctx* c, bool diag, float* rho, float* u, float* shear, float* omega, float* sigma) {
+lbm_status moments_launch(lbm_ctx* c, bool diag, float* rho, float* u, float* shear, float* omega, float* sigma,
+                          float* tau) {
   Bufs b = bufs(c);
   const uint32_t t = (uint32_t)c->t;
   with_config(c->grid.storage, c->grid.shift_mode, c->amode == 2 ? 2 : 0, [&](auto tag, auto shw, auto rt) {
@@ -439,10 +452,10 @@ lbm_status moments_launch(lbm_ctx* c, bool diag, float* rho, float* u, float* sh
       constexpr bool OD = decltype(odd)::value;
       if (diag)
         hipLaunchKernelGGL((k_moments<S, SH, OD, true, R>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, t,
-                           c->nbox, rho, u, shear, omega, sigma);
+                           c->nbox, rho, u, shear, omega, sigma, tau);
       else
         hipLaunchKernelGGL((k_moments<S, SH, OD, false, R>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, t,
-                           c->nbox, rho, u, shear, omega, sigma);
+                           c->nbox, rho, u, shear, omega, sigma, tau);
     });
   });
   HIP_TRY(c, hipGetLastError());
@@ -678,7 +691,7 @@ lbm_status lbm_step(lbm_ctx* c, int n) {
   return LBM_OK;
 }
 
-lbm_status lbm_moments(lbm_ctx* c, float* rho, float* u, float* shear, float* omega, float* sigma) {
+lbm_status lbm_moments(lbm_ctx* c, float* rho, float* u, float* shear, float* omega, float* sigma, float* tau) {
   CTX_CHECK(c);
   const size_t nb = c->nbox * 4;
   if (rho) HIP_TRY(c, hipMemsetAsync(rho, 0, nb, c->stream));
@@ -686,17 +699,21 @@ lbm_status lbm_moments(lbm_ctx* c, float* rho, float* u, float* shear, float* om
   if (shear) HIP_TRY(c, hipMemsetAsync(shear, 0, nb, c->stream));
   if (omega) HIP_TRY(c, hipMemsetAsync(omega, 0, nb, c->stream));
   if (sigma) HIP_TRY(c, hipMemsetAsync(sigma, 0, 6 * nb, c->stream));
-  return moments_launch(c, false, rho, u, shear, omega, sigma);
+  if (tau) HIP_TRY(c, hipMemsetAsync(tau, 0, 3 * nb, c->stream));
+  return moments_launch(c, false, rho, u, shear, omega, sigma, tau);
 }
 
 lbm_status lbm_diagnostics(lbm_ctx* c, double* out) {
   CTX_CHECK(c);
   if (!out) return fail(LBM_E_INVALID, "out is NULL");
-  lbm_status s = moments_launch(c, true, nullptr, nullptr, nullptr, nullptr, nullptr);
+  lbm_status s = moments_launch(c, true, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
   if (s != LBM_OK) return s;
-  s = read_diag(c, c->nblk, out);
+  double dg[NDIAGP];
+  s = read_diag(c, c->nblk, dg);
   if (s != LBM_OK) return s;
-  out[NDIAGP] = (double)c->t;
+  for (int k = 0; k < 10; ++k) out[k] = dg[k];
+  out[10] = (double)c->t;
+  out[11] = c->nwss > 0 ? dg[10] / (double)c->nwss : 0.0;
   return LBM_OK;
 }
 

@@ -346,6 +346,53 @@ __device__ __forceinline__ void open_fill(const Params& p, uint32_t row, uint32_
   d[14] = outl ? o14 : d[14];
 }
 
+// Whether the pull of direction I reads an open-face unknown (flags set on
+// the host: source outside the inflow/outflow face, not outside a wall face).
+template <int I>
+__device__ __forceinline__ bool open_unknown(uint32_t lk) {
+  if (CX[I] == 0) return false;
+  int k = -1;
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    if ((lk & LK_IN) && XIN[j] == I) k = j;
+    if ((lk & LK_OUT) && XOUT[j] == I) k = j;
+  }
+  return k >= 0 && ((lk >> (LK_UNK + k)) & 1u);
+}
+
+// Outer wall normal of a cell (the simulation section's WSS on the voxel
+// wall): n = m / |m| with m = sum over the wall links x + c_i of 36 w_i c_i,
+// a wall link being a bounce-back pull (of the opposite direction) that is not
+// an open-face unknown.  False where the cell has no wall link or its links
+// cancel.
+__device__ __forceinline__ bool wall_normal(uint32_t lk, float n[3]) {
+  int mx = 0, my = 0, mz = 0;
+  sfor<1, Q>([&](auto ic) {
+    constexpr int I = decltype(ic)::value;  // link x + c_I, pulled by direction J from x - c_J
+    constexpr int J = OPP[I];
+    constexpr int k = (int)kw(I);
+    if (((lk >> J) & 1u) && !open_unknown<J>(lk)) {
+      mx += k * CX[I];
+      my += k * CY[I];
+      mz += k * CZ[I];
+    }
+  });
+  if ((mx | my | mz) == 0) return false;
+  const float il = 1.0f / __builtin_sqrtf((float)(mx * mx + my * my + mz * mz));
+  n[0] = (float)mx * il;
+  n[1] = (float)my * il;
+  n[2] = (float)mz * il;
+  return true;
+}
+
+// Symmetric 3x3 stored as xx yy zz xy xz yz, times a vector.
+template <class R>
+__device__ __forceinline__ void sym_mv(const R s[6], R x, R y, R z, R& ox, R& oy, R& oz) {
+  ox = s[0] * x + s[3] * y + s[4] * z;
+  oy = s[3] * x + s[1] * y + s[5] * z;
+  oz = s[4] * x + s[5] * y + s[2] * z;
+}
+
 // Moment sums of the 19 values from opposite-pair sums and differences, in
 // the arithmetic type R.
 template <class R>
@@ -455,6 +502,31 @@ __device__ __forceinline__ void macro(const Params& p, float phx_f, const float 
   M.ux = ux; M.uy = uy; M.uz = uz; M.uu = uu;
   M.Fx = Fx; M.Fy = Fy; M.Fz = Fz;
   M.shear = shear;
+}
+
+// Wall shear stress tau = sigma n - (n . sigma n) n of a wall cell, with the
+// deviatoric stress sigma = (omega/2 - 1) Pi of this step; returns |tau|.
+template <class R>
+__device__ __forceinline__ R wall_tau(const Macro<R>& M, const float n[3], R tau[3]) {
+  const R s = (R)0.5 * M.omega - (R)1;
+  const R nx = (R)n[0], ny = (R)n[1], nz = (R)n[2];
+  R sx, sy, sz;
+  sym_mv(M.P, nx, ny, nz, sx, sy, sz);
+  sx *= s; sy *= s; sz *= s;
+  const R nsn = sx * nx + sy * ny + sz * nz;
+  tau[0] = sx - nsn * nx;
+  tau[1] = sy - nsn * ny;
+  tau[2] = sz - nsn * nz;
+  return rsqrt_(tau[0] * tau[0] + tau[1] * tau[1] + tau[2] * tau[2]);
+}
+
+// |tau| of a region wall cell, 0 elsewhere (the WSS objective's cell term).
+template <class R>
+__device__ __forceinline__ R region_wss(uint32_t lk, const Macro<R>& M) {
+  float n[3];
+  if (!(lk & LK_REG) || !wall_normal(lk, n)) return (R)0;
+  R tau[3];
+  return wall_tau(M, n, tau);
 }
 
 // BGK + Guo + porosity-jump collision, stored as deviations for the consumer.
@@ -586,12 +658,13 @@ __device__ __forceinline__ void block_reduce(double (&v)[N], const int (&op)[N],
 }
 
 // Per-cell diagnostic contributions: mass, momentum, energy, region energy,
-// max |u|, min/max omega, non-finite count.
+// max |u|, min/max omega, non-finite count, region wall shear stress |tau|.
 template <class R>
-__device__ __forceinline__ void diag_terms(const Params& p, float phx, const float d[Q], const Macro<R>& M, bool reg,
+__device__ __forceinline__ void diag_terms(const Params& p, float phx, const float d[Q], const Macro<R>& M, uint32_t lk,
                                            bool active, double (&v)[NDIAGP]) {
+  const bool reg = (lk & LK_REG) != 0;
   if (!active) {
-    v[0] = v[1] = v[2] = v[3] = v[4] = v[5] = v[9] = 0.0;
+    v[0] = v[1] = v[2] = v[3] = v[4] = v[5] = v[9] = v[10] = 0.0;
     v[6] = 0.0; v[7] = 1e300; v[8] = -1e300;
     return;
   }
@@ -610,6 +683,7 @@ __device__ __forceinline__ void diag_terms(const Params& p, float phx, const flo
                      __builtin_isfinite((double)M.omega) && __builtin_isfinite(M.shear));
   v[9] = bad ? 1.0 : 0.0;
   if (bad) { v[6] = 1e300; }
+  v[10] = (double)region_wss<R>(lk, M);
 }
 
 // Body of the step for one cell (UNI: the whole wave has uniform neighbour
@@ -640,15 +714,17 @@ __device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32
     __builtin_nontemporal_store((float)M.rho, &b.rho_rec[c]);
   }
   const bool reg = (lk & LK_REG) != 0;
-  if (DIAG == 1) diag_terms<R>(p, phx, d, M, reg, true, dv);
+  if (DIAG == 1) diag_terms<R>(p, phx, d, M, lk, true, dv);
   if (DIAG == 2) ke_reg = reg ? (float)((R)0.5 * M.rho * M.uu) : 0.0f;
+  if (DIAG == 3) ke_reg = (float)region_wss<R>(lk, M);
   collide_store<S, SHW, UNI, ODD, R, PROJ>(p, A, c, lk, q, phx, d, pt, M);
 }
 
 // ---------------------------------------------------------------------------
 // The step at parity ODD (t odd), NT work-items per workgroup.  DIAG: 0 none,
 // 1 diagnostics of the pre-collision state into part[block][NDIAGP], 2 region
-// kinetic energy accumulated into part[block].  REC: also record the pulled
+// kinetic energy, 3 region wall shear stress |tau|, accumulated into
+// part[block].  REC: also record the pulled
 // values and omega_prev ([20][nc]) and rho.
 // ---------------------------------------------------------------------------
 template <class S, bool SHW, bool ODD, int DIAG, bool REC, class R, bool PROJ, int NT>
@@ -669,12 +745,12 @@ __global__ __launch_bounds__(NT) void k_step(Params p, Bufs b) {
     if (!active) {
       float d[Q] = {};
       Macro<R> M{};
-      diag_terms<R>(p, 0.f, d, M, false, false, dv);
+      diag_terms<R>(p, 0.f, d, M, 0u, false, dv);
     }
-    const int ops[NDIAGP] = {0, 0, 0, 0, 0, 0, 1, 2, 1, 0};
+    const int ops[NDIAGP] = {0, 0, 0, 0, 0, 0, 1, 2, 1, 0, 0};
     block_reduce<NDIAGP, NT>(dv, ops, b.part + (size_t)blockIdx.x * NDIAGP);
   }
-  if (DIAG == 2) {
+  if (DIAG >= 2) {
     double v[1] = {(double)ke_reg};
     const int ops[1] = {0};
     __shared__ double tmp[1];
@@ -689,7 +765,8 @@ __global__ __launch_bounds__(NT) void k_step(Params p, Bufs b) {
 // null) and optionally the diagnostics partials.
 template <class S, bool SHW, bool ODD, bool DIAG, class R>
 __global__ __launch_bounds__(BLOCK) void k_moments(Params p, Bufs b, uint32_t t, size_t nbox, float* rho_o,
-                                                    float* u_o, float* shear_o, float* omega_o, float* sigma_o) {
+                                                    float* u_o, float* shear_o, float* omega_o, float* sigma_o,
+                                                    float* tau_o) {
   const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
   const uint32_t lk = c < (uint32_t)p.nc ? b.links[c] : LK_DEAD;
   const bool active = !(lk & LK_DEAD);
@@ -717,14 +794,21 @@ __global__ __launch_bounds__(BLOCK) void k_moments(Params p, Bufs b, uint32_t t,
 #pragma unroll
       for (int k = 0; k < 6; ++k) sigma_o[(size_t)k * nbox + idx] = (float)(s * M.P[k]);
     }
-    if (DIAG) diag_terms<R>(p, phx, d, M, (lk & LK_REG) != 0, true, dv);
+    if (tau_o) {
+      float n[3];
+      R tw[3] = {(R)0, (R)0, (R)0};
+      if (wall_normal(lk, n)) wall_tau(M, n, tw);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) tau_o[(size_t)a * nbox + idx] = (float)tw[a];
+    }
+    if (DIAG) diag_terms<R>(p, phx, d, M, lk, true, dv);
   } else if (DIAG) {
     float d[Q] = {};
     Macro<R> M{};
-    diag_terms<R>(p, 0.f, d, M, false, false, dv);
+    diag_terms<R>(p, 0.f, d, M, 0u, false, dv);
   }
   if (DIAG) {
-    const int ops[NDIAGP] = {0, 0, 0, 0, 0, 0, 1, 2, 1, 0};
+    const int ops[NDIAGP] = {0, 0, 0, 0, 0, 0, 1, 2, 1, 0, 0};
     block_reduce<NDIAGP>(dv, ops, b.part + (size_t)blockIdx.x * NDIAGP);
   }
 }
@@ -773,20 +857,6 @@ __global__ __launch_bounds__(BLOCK) void k_init(Params p, Bufs b, float omega0) 
 // Set the time counter slot of parity t & 1 to t (one work-item).
 __global__ void k_set_time(uint32_t* tc, uint32_t t) {
   if (blockIdx.x == 0 && threadIdx.x == 0) tc[t & 1u] = t;
-}
-
-// Whether the pull of direction I reads an open-face unknown (flags set on
-// the host: source outside the inflow/outflow face, not outside a wall face).
-template <int I>
-__device__ __forceinline__ bool open_unknown(uint32_t lk) {
-  if (CX[I] == 0) return false;
-  int k = -1;
-#pragma unroll
-  for (int j = 0; j < 5; ++j) {
-    if ((lk & LK_IN) && XIN[j] == I) k = j;
-    if ((lk & LK_OUT) && XOUT[j] == I) k = j;
-  }
-  return k >= 0 && ((lk >> (LK_UNK + k)) & 1u);
 }
 
 // Whether the state keeps the open-face unknown I: the extrapolation outflow's.

@@ -21,9 +21,10 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 LBM_OK, LBM_E_INVALID, LBM_E_DEVICE, LBM_E_UNSTABLE, LBM_E_STATE, LBM_E_WORKSPACE = range(6)
 STORAGE = {"fp32": 0, "fp16": 1, "bf16": 2}
 ARITH = {"auto": 0, "fp32": 1, "fp64": 2}
-NDIAG = 11
+NDIAG = 12
 DIAG_NAMES = ["mass", "mom_x", "mom_y", "mom_z", "ke", "ke_region", "max_u", "min_omega", "max_omega",
-              "nonfinite", "t"]
+              "nonfinite", "t", "wss_region"]
+OBJECTIVE = {"ke": 0, "wss": 1}
 
 
 class lbm_grid(ct.Structure):
@@ -48,7 +49,7 @@ class lbm_open(ct.Structure):
 
 
 class lbm_objective(ct.Structure):
-    _fields_ = [("t_begin", ct.c_int), ("t_end", ct.c_int)]
+    _fields_ = [("t_begin", ct.c_int), ("t_end", ct.c_int), ("kind", ct.c_int)]
 
 
 class LBMError(RuntimeError):
@@ -73,7 +74,7 @@ def lib():
         L.lbm_create.argtypes = [P(lbm_grid), vp, vp, vp, P(lbm_rheology), P(lbm_porous), P(lbm_open), vp, sz, vp,
                                  P(vp)]
         L.lbm_step.argtypes = [vp, i32]
-        L.lbm_moments.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.lbm_moments.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.lbm_diagnostics.argtypes = [vp, vp]
         L.lbm_get_state.argtypes = [vp, vp, vp]
         L.lbm_set_state.argtypes = [vp, vp, vp]
@@ -235,8 +236,9 @@ class Solver:
         return out
 
     # -- outputs --------------------------------------------------------------
-    def moments(self, sigma: bool = False):
-        """Dense device tensors rho, u (3, nz, ny, nx), shear, omega [, sigma (6, ...)]."""
+    def moments(self, sigma: bool = False, tau: bool = False):
+        """Dense device tensors rho, u (3, nz, ny, nx), shear, omega [, sigma (6, ...)]
+        [, tau (3, ...): the wall shear stress on the voxel wall]."""
         t = self.torch
         nz, ny, nx = self.shape
         kw = dict(dtype=t.float32, device=self.device)
@@ -244,9 +246,12 @@ class Solver:
                    shear=t.empty((nz, ny, nx), **kw), omega=t.empty((nz, ny, nx), **kw))
         if sigma:
             out["sigma"] = t.empty((6, nz, ny, nx), **kw)
+        if tau:
+            out["tau"] = t.empty((3, nz, ny, nx), **kw)
         check(lib().lbm_moments(self.ctx, ct.c_void_p(out["rho"].data_ptr()), ct.c_void_p(out["u"].data_ptr()),
                                 ct.c_void_p(out["shear"].data_ptr()), ct.c_void_p(out["omega"].data_ptr()),
-                                ct.c_void_p(out["sigma"].data_ptr()) if sigma else None))
+                                ct.c_void_p(out["sigma"].data_ptr()) if sigma else None,
+                                ct.c_void_p(out["tau"].data_ptr()) if tau else None))
         return out
 
     def diagnostics(self) -> dict:
@@ -269,18 +274,20 @@ class Solver:
         ph = np.ascontiguousarray(phi, dtype=np.float32)
         check(lib().lbm_set_porosity(self.ctx, _p(ph)))
 
-    def objective(self, t_begin: int, t_end: int, T: int) -> float:
-        """J alone (forward pass from rest, no gradient); the context ends at rest."""
-        obj = lbm_objective(int(t_begin), int(t_end))
+    def objective(self, t_begin: int, t_end: int, T: int, kind: str = "ke") -> float:
+        """J alone (forward pass from rest, no gradient); the context ends at rest.
+        kind: "ke" (region kinetic energy) or "wss" (WSS over the region's wall)."""
+        obj = lbm_objective(int(t_begin), int(t_end), OBJECTIVE[kind])
         J = ct.c_double(0.0)
         check(lib().lbm_adjoint(self.ctx, ct.byref(obj), int(T), 1, ct.byref(J), None))
         return float(J.value)
 
-    def adjoint(self, t_begin: int, t_end: int, T: int, ckpt: Optional[int] = None):
-        """J and dJ/dphi (device tensor, box layout) of the region kinetic energy."""
+    def adjoint(self, t_begin: int, t_end: int, T: int, ckpt: Optional[int] = None, kind: str = "ke"):
+        """J and dJ/dphi (device tensor, box layout) of the region objective:
+        kind "ke" (kinetic energy) or "wss" (wall shear stress magnitude)."""
         t = self.torch
         ck = self.ckpt if ckpt is None else int(ckpt)
-        obj = lbm_objective(int(t_begin), int(t_end))
+        obj = lbm_objective(int(t_begin), int(t_end), OBJECTIVE[kind])
         J = ct.c_double(0.0)
         grad = t.empty(self.shape, dtype=t.float32, device=self.device)
         check(lib().lbm_adjoint(self.ctx, ct.byref(obj), int(T), ck, ct.byref(J), ct.c_void_p(grad.data_ptr())))

@@ -1,6 +1,7 @@
-"""GPU adjoint (porosity gradient of the region kinetic energy) against the
-FP64 oracle: its checkpointed reverse sweep over every fluid cell, and its
-exact dual-number derivative at seeded region voxels.
+"""GPU adjoint (porosity gradient of the region kinetic energy or of the
+region's wall shear stress) against the FP64 oracle: its checkpointed reverse
+sweep over every fluid cell, and its exact dual-number derivative at seeded
+region voxels.
 
 Metric: max over cells of |g_gpu - g_ref| / max over cells of |g_ref|; the
 bound 1e-4 is the gradient tolerance of the method's FP32 adjoint.
@@ -28,15 +29,16 @@ def _tiny(kind, seed):
     return c
 
 
-@pytest.mark.parametrize("kind,seed", [("open", 0), ("open", 1), ("periodic", 0)])
-def test_adjoint_matches_oracle_reverse_sweep(kind, seed):
+@pytest.mark.parametrize("kind,seed,objective", [("open", 0, "ke"), ("open", 1, "ke"), ("periodic", 0, "ke"),
+                                                 ("open", 0, "wss"), ("open", 1, "wss"), ("periodic", 0, "wss")])
+def test_adjoint_matches_oracle_reverse_sweep(kind, seed, objective):
     case = _tiny(kind, seed)
     T, tb, te, ck = 30, 15, 30, 7
-    say(f"adjoint: {case.name} T={T} window=[{tb},{te}) ckpt={ck}")
+    say(f"adjoint ({objective}): {case.name} T={T} window=[{tb},{te}) ckpt={ck}")
     o = oracle.Oracle(case)
-    J_ref, g_ref = o.grad_reverse(T, tb, te, ck)
+    J_ref, g_ref = o.grad_reverse(T, tb, te, ck, objective)
     s = Solver.from_case(case, adjoint_T=T, ckpt=ck)
-    J, g = s.adjoint(tb, te, T, ck)
+    J, g = s.adjoint(tb, te, T, ck, kind=objective)
     g = g.cpu().numpy()
     fluid = case.solid == 0
     err = np.abs(g - g_ref)[fluid].max() / np.abs(g_ref)[fluid].max()
@@ -73,18 +75,19 @@ def test_adjoint_rejects_unsupported():
         s2.adjoint(2, 10, 40, 5)   # workspace sized for T = 10
 
 
-def test_adjoint_small_aneurysm_dual():
+@pytest.mark.parametrize("objective", ["ke", "wss"])
+def test_adjoint_small_aneurysm_dual(objective):
     """48x40x40 tube-and-sac aneurysm from the same generator (pulsatile Zou-He
     inflow, density outflow, GRF sac porosity): GPU gradient at 16 seeded sac
     voxels against the oracle's exact dual-number derivative."""
     case = aneurysm_case(48, 40, 40, R=5, Rs=8, ell=3, seed=4, wave=(0.05, 0.5, 200.0), name="mini")
     T, tb, te, ck = 300, 200, 300, 16
     vox = fd_voxels(case, 16, seed=16)
-    say(f"adjoint mini aneurysm ({case.n_fluid} cells): T={T} window=[{tb},{te}), {len(vox)} voxels")
+    say(f"adjoint ({objective}) mini aneurysm ({case.n_fluid} cells): T={T} window=[{tb},{te}), {len(vox)} voxels")
     o = oracle.Oracle(case)
-    J_ref, gd = o.grad_dual(T, tb, te, vox)
+    J_ref, gd = o.grad_dual(T, tb, te, vox, objective)
     s = Solver.from_case(case, adjoint_T=T, ckpt=ck)
-    J, g = s.adjoint(tb, te, T, ck)
+    J, g = s.adjoint(tb, te, T, ck, kind=objective)
     g = g.cpu().numpy().reshape(-1)
     gv = g[vox]
     scale = np.abs(gd).max()

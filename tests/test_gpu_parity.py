@@ -29,7 +29,7 @@ def _oracle_run(case, steps):
 
 
 def _gpu_fields(s):
-    m = s.moments(sigma=True)
+    m = s.moments(sigma=True, tau=True)
     idx = s.fluid_index()
     out = {}
     for k, v in m.items():
@@ -125,9 +125,14 @@ def test_aneurysm_fp32_parity(aneurysm_ref):
     say(f"  u max-rel {eu:.3e}  shear max-rel {es:.3e}  rho max-abs {np.abs(g['rho'] - ref['rho']).max():.3e}")
     assert eu < 1e-5
     assert es < 1e-4
-    # stress and relaxation rate of the same state
+    # stress, wall shear stress and relaxation rate of the same state
+    et = max_rel(g["tau"], ref["tau"])
+    say(f"  sigma max-rel {max_rel(g['sigma'], ref['sigma']):.3e}  tau max-rel {et:.3e}")
     assert max_rel(g["omega"], ref["omega"]) < 1e-5
     assert max_rel(g["sigma"], ref["sigma"]) < 1e-4
+    assert et < 1e-4
+    # the voxel wall is the same set of cells
+    assert np.array_equal(np.abs(g["tau"]).sum(0) > 0, np.abs(ref["tau"]).sum(0) > 0)
 
 
 def test_aneurysm_ramp_and_sampled_waveform():
@@ -333,6 +338,14 @@ def test_diagnostics_match_oracle():
     assert abs(d["max_u"] - np.sqrt((m["u"] ** 2).sum(0)).max()) < 1e-6
     assert abs(d["min_omega"] - m["omega"].min()) < 1e-6 and abs(d["max_omega"] - m["omega"].max()) < 1e-6
     assert d["nonfinite"] == 0 and d["t"] == 30
+    # region-mean WSS magnitude over the region's wall cells (wall link, m != 0)
+    nb = o.neighbours()
+    w = np.array([12.0] + [2.0] * 6 + [1.0] * 12)
+    mvec = np.einsum("ix,ia->ax", (nb == -1) * w[:, None], c.astype(np.float64))
+    on = sac & (np.abs(mvec).sum(0) > 0)
+    wss = np.sqrt((m["tau"] ** 2).sum(0))[on].mean()
+    say(f"  wss_region gpu {d['wss_region']:.6e} oracle {wss:.6e}")
+    assert abs(d["wss_region"] - wss) < 1e-5 * wss
 
 
 def test_porosity_update_resets():
