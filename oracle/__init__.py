@@ -45,6 +45,7 @@ class _Case(ct.Structure):
         ("forchheimer", ct.c_int),
         ("g", ct.c_double * 3),
         ("ramp", ct.c_int), ("wave_table", ct.c_void_p), ("table_len", ct.c_int),
+        ("aniso", ct.c_double * 6), ("aniso_iters", ct.c_int),
     ]
 
 
@@ -115,6 +116,11 @@ def make_struct(case, keep: list, **override) -> _Case:
     for a in range(3):
         s.g[a] = float(po["g"][a])
     s.ramp = int(getattr(case, "ramp_steps", 0) or 0)
+    an = po.get("aniso")
+    if an is not None:
+        for k in range(6):
+            s.aniso[k] = float(an[k])
+        s.aniso_iters = int(po.get("aniso_iters", 8))
     table = getattr(case, "wave_table", None)
     if table is not None:
         table = np.ascontiguousarray(table, dtype=np.float64)

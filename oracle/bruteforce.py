@@ -150,10 +150,31 @@ def step(case, f, omega_prev, t):
     c0 = 0.5 + phi * po["nu_d"] * invk / 4
     c1 = phi ** 2 * cf * np.sqrt(invk) / 2
     vn = np.sqrt((v ** 2).sum(0))
-    u = v / (c0 + np.sqrt(c0 ** 2 + c1 * vn))[None]
-    un = np.sqrt((u ** 2).sum(0))
-    F = rho[None] * (g[:, None, None, None] - (phi ** 2 * po["nu_d"] * invk)[None] * u
-                     - (phi ** 3 * cf * np.sqrt(invk) * un)[None] * u)
+    an = po.get("aniso")
+    if an is None:
+        u = v / (c0 + np.sqrt(c0 ** 2 + c1 * vn))[None]
+        un = np.sqrt((u ** 2).sum(0))
+        F = rho[None] * (g[:, None, None, None] - (phi ** 2 * po["nu_d"] * invk)[None] * u
+                         - (phi ** 3 * cf * np.sqrt(invk) * un)[None] * u)
+    else:
+        # anisotropic permeability K = k M: the Remark's fixed point, batched
+        M = np.array([[an[0], an[3], an[4]], [an[3], an[1], an[5]], [an[4], an[5], an[2]]], dtype=np.float64)
+        lam, V = np.linalg.eigh(M)
+        Kinv = invk[..., None, None] * np.linalg.inv(M)
+        Khalf = np.sqrt(invk)[..., None, None] * (V @ np.diag(lam ** -0.5) @ V.T)
+        A = np.eye(3) + (0.5 * phi * po["nu_d"])[..., None, None] * Kinv
+        B = (0.5 * phi ** 2 * cf)[..., None, None] * Khalf
+        vl = np.moveaxis(v, 0, -1)
+        ul = vl.copy()
+        for _ in range(int(po.get("aniso_iters", 8))):
+            X = A + np.linalg.norm(ul, axis=-1)[..., None, None] * B
+            ul = np.linalg.solve(X, vl[..., None])[..., 0]
+        u = np.moveaxis(ul, -1, 0)
+        un = np.sqrt((u ** 2).sum(0))
+        kd = np.moveaxis(np.einsum("...ab,...b->...a", Kinv, ul), -1, 0)
+        kf = np.moveaxis(np.einsum("...ab,...b->...a", Khalf, ul), -1, 0)
+        F = rho[None] * (g[:, None, None, None] - (phi ** 2 * po["nu_d"])[None] * kd
+                         - (phi ** 3 * cf * un)[None] * kf)
     cu = np.einsum("ia,az...->iz...", C.astype(np.float64), u)
     uu = (u ** 2).sum(0)
     feq = W[:, None, None, None] * (phi * rho)[None] * (1 + cu / CS2 + cu ** 2 / (2 * CS2 ** 2) - uu[None] / (2 * CS2))

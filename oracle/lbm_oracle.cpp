@@ -130,10 +130,89 @@ typedef struct {
   int ramp;                          // pre-run length R (0: none)
   const double* wave_table;          // NULL: sine waveform; else samples of one period
   int table_len;
+  double aniso[6];                   // permeability shape M (xx yy zz xy xz yz); all 0: isotropic
+  int aniso_iters;                   // fixed-point iterations of the anisotropic velocity
 } oracle_case;
 }
 
 namespace {
+
+// ---------------------------------------------------------------------------
+// Anisotropic permeability (the Remark of the method section).  Reading: the
+// paper leaves open how K varies; here K(x) = k(phi(x)) M with k the
+// Kozeny-Carman permeability and M a fixed symmetric positive definite shape,
+// so K^-1 = (1/k) M^-1 and K^-1/2 = (1/k)^1/2 M^-1/2.  M = 0 means isotropic.
+// M^-1 and M^-1/2 come from the eigen-decomposition M = V diag(l) V^T by
+// cyclic Jacobi rotations.
+// ---------------------------------------------------------------------------
+struct Shape {
+  bool on = false;
+  double Minv[3][3], Mhi[3][3];
+};
+
+Shape shape_of(const oracle_case& c) {
+  Shape S;
+  const double* a = c.aniso;
+  S.on = false;
+  for (int k = 0; k < 6; ++k) S.on = S.on || a[k] != 0.0;
+  if (!S.on) return S;
+  double A[3][3] = {{a[0], a[3], a[4]}, {a[3], a[1], a[5]}, {a[4], a[5], a[2]}};
+  double V[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  for (int sweep = 0; sweep < 50; ++sweep) {
+    double off = std::fabs(A[0][1]) + std::fabs(A[0][2]) + std::fabs(A[1][2]);
+    if (off < 1e-300) break;
+    for (int p = 0; p < 2; ++p)
+      for (int q = p + 1; q < 3; ++q) {
+        if (A[p][q] == 0.0) continue;
+        // rotation angle that annihilates A[p][q]
+        const double th = 0.5 * std::atan2(2.0 * A[p][q], A[q][q] - A[p][p]);
+        const double cs = std::cos(th), sn = std::sin(th);
+        for (int k = 0; k < 3; ++k) {  // A <- A J
+          const double akp = A[k][p], akq = A[k][q];
+          A[k][p] = cs * akp - sn * akq;
+          A[k][q] = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < 3; ++k) {  // A <- J^T A
+          const double apk = A[p][k], aqk = A[q][k];
+          A[p][k] = cs * apk - sn * aqk;
+          A[q][k] = sn * apk + cs * aqk;
+        }
+        for (int k = 0; k < 3; ++k) {  // V <- V J
+          const double vkp = V[k][p], vkq = V[k][q];
+          V[k][p] = cs * vkp - sn * vkq;
+          V[k][q] = sn * vkp + cs * vkq;
+        }
+      }
+  }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s1 = 0.0, s2 = 0.0;
+      for (int k = 0; k < 3; ++k) {
+        s1 += V[i][k] * V[j][k] / A[k][k];
+        s2 += V[i][k] * V[j][k] / std::sqrt(A[k][k]);
+      }
+      S.Minv[i][j] = s1;
+      S.Mhi[i][j] = s2;
+    }
+  return S;
+}
+
+// Solve X u = v for a 3x3 matrix X (Cramer's rule).
+template <class T>
+void solve3(const T X[3][3], const T v[3], T u[3]) {
+  const T c00 = X[1][1] * X[2][2] - X[1][2] * X[2][1];
+  const T c01 = X[1][2] * X[2][0] - X[1][0] * X[2][2];
+  const T c02 = X[1][0] * X[2][1] - X[1][1] * X[2][0];
+  const T det = X[0][0] * c00 + X[0][1] * c01 + X[0][2] * c02;
+  T Y[3][3];  // X with column j replaced by v, determinant by cofactors
+  for (int j = 0; j < 3; ++j) {
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 3; ++k) Y[i][k] = k == j ? v[i] : X[i][k];
+    const T d = Y[0][0] * (Y[1][1] * Y[2][2] - Y[1][2] * Y[2][1]) - Y[0][1] * (Y[1][0] * Y[2][2] - Y[1][2] * Y[2][0]) +
+                Y[0][2] * (Y[1][0] * Y[2][1] - Y[1][1] * Y[2][0]);
+    u[j] = d / det;
+  }
+}
 
 const int NB_WALL = -1;  // halfway bounce-back
 const int NB_OPEN = -2;  // leaves through an open face: dropped
@@ -147,6 +226,7 @@ struct Ctx {
   std::vector<int> nbr;                // [Q][nf]: fluid index of x + c_i, or NB_WALL/NB_OPEN
   std::vector<int> xc, yc, zc;         // coordinates of fluid cells
   std::vector<uint8_t> kind;           // 0 interior, 1 inlet, 2 outlet
+  Shape shape_m;                       // anisotropic permeability shape
   std::vector<double> nrm;             // [nf][3]: outer wall normal (0 off the wall)
   std::vector<uint8_t> wall;           // 1: the cell has a wall normal
   int64_t nf = 0;
@@ -259,7 +339,8 @@ struct CellResult {
 // fill; phit[i] is the porosity at x + c_i (the cell's own porosity where that
 // neighbour is solid or outside: no porosity jump across walls).
 template <class T>
-void cell_update(const oracle_case& c, const T f[Q], T omega_prev, T phi, const T phit[Q], CellResult<T>& r) {
+void cell_update(const oracle_case& c, const Shape& S, const T f[Q], T omega_prev, T phi, const T phit[Q],
+                 CellResult<T>& r) {
   // moments: rho = phi^-1 sum f, momentum sum f c
   T sumf = 0, m[3] = {0, 0, 0};
   for (int i = 0; i < Q; ++i) {
@@ -278,16 +359,52 @@ void cell_update(const oracle_case& c, const T f[Q], T omega_prev, T phi, const 
   T invk = c.kc * om * om / (c.d * c.d * phi * phi * phi);
   T CF = 0;
   if (c.forchheimer) CF = 1.75 / Sqrt(150.0 * phi * phi * phi);
-  // explicit velocity: u = v / (C0 + sqrt(C0^2 + C1 |v|))
-  T C0 = 0.5 + phi * c.nu_d * invk / 4.0;
-  T C1 = phi * phi * CF * Sqrt(invk) / 2.0;
-  T vn = Sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-  T den = C0 + Sqrt(C0 * C0 + C1 * vn);
-  for (int a = 0; a < 3; ++a) r.u[a] = v[a] / den;
-  // force density rho f(u): body force, Darcy and Forchheimer drag
-  T un = Sqrt(r.u[0] * r.u[0] + r.u[1] * r.u[1] + r.u[2] * r.u[2]);
-  for (int a = 0; a < 3; ++a)
-    r.F[a] = rho * (c.g[a] - phi * phi * c.nu_d * invk * r.u[a] - phi * phi * phi * CF * Sqrt(invk) * un * r.u[a]);
+  if (!S.on) {
+    // explicit velocity: u = v / (C0 + sqrt(C0^2 + C1 |v|))
+    T C0 = 0.5 + phi * c.nu_d * invk / 4.0;
+    T C1 = phi * phi * CF * Sqrt(invk) / 2.0;
+    T vn = Sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    T den = C0 + Sqrt(C0 * C0 + C1 * vn);
+    for (int a = 0; a < 3; ++a) r.u[a] = v[a] / den;
+    // force density rho f(u): body force, Darcy and Forchheimer drag
+    T un = Sqrt(r.u[0] * r.u[0] + r.u[1] * r.u[1] + r.u[2] * r.u[2]);
+    for (int a = 0; a < 3; ++a)
+      r.F[a] = rho * (c.g[a] - phi * phi * c.nu_d * invk * r.u[a] - phi * phi * phi * CF * Sqrt(invk) * un * r.u[a]);
+  } else {
+    // anisotropic: A = Id + (phi nu / 2) K^-1, B = (phi^2 C_F / 2) K^-1/2,
+    // u_{m+1} = (A + |u_m| B)^-1 v from u_0 = v (the Remark's fixed point)
+    T Ki[3][3], Kh[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        Ki[i][j] = invk * S.Minv[i][j];
+        Kh[i][j] = Sqrt(invk) * S.Mhi[i][j];
+      }
+    T A[3][3], B[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        A[i][j] = (i == j ? 1.0 : 0.0) + 0.5 * phi * c.nu_d * Ki[i][j];
+        B[i][j] = 0.5 * phi * phi * CF * Kh[i][j];
+      }
+    T u[3] = {v[0], v[1], v[2]};
+    for (int m = 0; m < c.aniso_iters; ++m) {
+      T un = Sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+      T X[3][3];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) X[i][j] = A[i][j] + un * B[i][j];
+      solve3(X, v, u);
+    }
+    for (int a = 0; a < 3; ++a) r.u[a] = u[a];
+    // force density: body force and the tensor drag -phi^2 nu K^-1 u - phi^3 C_F |u| K^-1/2 u
+    T un = Sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    for (int a = 0; a < 3; ++a) {
+      T kd = 0, kf = 0;
+      for (int b = 0; b < 3; ++b) {
+        kd += Ki[a][b] * u[b];
+        kf += Kh[a][b] * u[b];
+      }
+      r.F[a] = rho * (c.g[a] - phi * phi * c.nu_d * kd - phi * phi * phi * CF * un * kf);
+    }
+  }
   r.rho = rho;
   // equilibrium with porosity
   T uu = r.u[0] * r.u[0] + r.u[1] * r.u[1] + r.u[2] * r.u[2];
@@ -441,7 +558,7 @@ void step(const Ctx& C, std::vector<T>& f, std::vector<T>& omega, const std::vec
     T fl[Q], phit[Q];
     cell_inputs(C, f.data(), x, t, phi_f.data(), fl, phit);
     CellResult<T> r;
-    cell_update(C.c, fl, omega[x], phi_f[x], phit, r);
+    cell_update(C.c, C.shape_m, fl, omega[x], phi_f[x], phit, r);
     omega[x] = r.omega;
     if (ke) keloc[x] = objective_term(C, x, r, kind);
     stream_out(C, x, r.q, fn.data());
@@ -510,6 +627,7 @@ void* oracle_new(const oracle_case* c) {
   C->nbr.assign((size_t)Q * nf, 0);
   for (int64_t x = 0; x < nf; ++x)
     for (int i = 0; i < Q; ++i) C->nbr[i * nf + x] = classify(*C, C->xc[x], C->yc[x], C->zc[x], i);
+  C->shape_m = shape_of(C->c);
   C->nrm.assign((size_t)3 * nf, 0.0);
   C->wall.assign(nf, 0);
   for (int64_t x = 0; x < nf; ++x) {
@@ -572,7 +690,7 @@ void oracle_moments(void* h, const double* f, const double* omega, int t, double
     double fl[Q], phit[Q];
     cell_inputs(*C, f, x, t, ph.data(), fl, phit);
     CellResult<double> r;
-    cell_update(C->c, fl, omega[x], ph[x], phit, r);
+    cell_update(C->c, C->shape_m, fl, omega[x], ph[x], phit, r);
     if (rho) rho[x] = r.rho;
     if (u) for (int a = 0; a < 3; ++a) u[a * nf + x] = r.u[a];
     if (shear) shear[x] = r.shear;
@@ -595,7 +713,7 @@ void oracle_cell(const oracle_case* c, const double* f, double omega_prev, doubl
   CellResult<double> r;
   double pt[Q];
   for (int i = 0; i < Q; ++i) pt[i] = phit[i];
-  cell_update(*c, f, omega_prev, phi, pt, r);
+  cell_update(*c, shape_of(*c), f, omega_prev, phi, pt, r);
   if (rho) *rho = r.rho;
   for (int a = 0; a < 3; ++a) { if (u) u[a] = r.u[a]; if (F) F[a] = r.F[a]; }
   for (int i = 0; i < Q; ++i) { if (feq) feq[i] = r.feq[i]; if (q) q[i] = r.q[i]; }
@@ -726,7 +844,7 @@ void oracle_grad_reverse(void* h, int T, int tb, int te, int ckpt, double* J, do
           zouhe_outlet(fl, C->c.rho_out);
         }
         CellResult<D> r;
-        cell_update(C->c, fl, omp, phx, phit, r);
+        cell_update(C->c, C->shape_m, fl, omp, phx, phit, r);
         D e = objective_term(*C, x, r, kind);
         // output adjoints
         double qh[Q];

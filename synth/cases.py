@@ -289,6 +289,8 @@ def tiny_case(kind: str = "open", seed: int = 0, nx: int = 9, ny: int = 7, nz: i
     walls).  ``periodic``: periodic x and z, solid layers at y = 0 and ny - 1 plus
     random solid voxels, random porosity, body force.  ``periodic3``: periodic
     in all three axes, random solid voxels, random porosity, body force.
+    ``periodic_aniso``: ``periodic`` with Forchheimer drag and an anisotropic
+    permeability shape (seeded SPD matrix, 6 fixed-point iterations).
     ``open_wave``: ``open`` with a 6-step pre-run ramp and a sampled 9-point
     inflow waveform of period 13 steps.  ``open_extrap``: ``open`` with the
     extrapolation outflow and one outflow cell whose -x neighbour is solid.
@@ -333,6 +335,14 @@ def tiny_case(kind: str = "open", seed: int = 0, nx: int = 9, ny: int = 7, nz: i
         case = Case(name=f"tiny_periodic{seed}", nx=nx, ny=ny, nz=nz, periodic=(True, False, True),
                     solid=solid, phi=phi, sac=sac,
                     porous=dict(nu_d=0.1, kc=180.0, d=2.0, forchheimer=0, g=(2e-5, -1e-5, 5e-6)))
+    elif kind == "periodic_aniso":
+        case = tiny_case("periodic", seed=seed, nx=nx, ny=ny, nz=nz)
+        case.name = f"tiny_periodic_aniso{seed}"
+        a = rng.standard_normal((3, 3))
+        m = a @ a.T + 0.5 * np.eye(3)
+        case.porous = dict(case.porous, forchheimer=1, aniso_iters=6,
+                           aniso=(m[0, 0], m[1, 1], m[2, 2], m[0, 1], m[0, 2], m[1, 2]))
+        return case
     elif kind == "periodic3":
         case = Case(name=f"tiny_periodic3_{seed}", nx=nx, ny=ny, nz=nz, periodic=(True, True, True),
                     solid=solid, phi=phi, sac=sac,

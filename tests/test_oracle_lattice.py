@@ -26,7 +26,7 @@ def _dense(case, cells, f, om):
     return fd.reshape(19, case.nz, case.ny, case.nx), od.reshape(case.nz, case.ny, case.nx)
 
 
-@pytest.mark.parametrize("kind", ["open", "open_wave", "open_extrap", "periodic", "periodic3"])
+@pytest.mark.parametrize("kind", ["open", "open_wave", "open_extrap", "periodic", "periodic_aniso", "periodic3"])
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_matches_dense_bruteforce(kind, seed):
     """Compact-list C++ oracle vs dense-array NumPy transcription: 1 and 10 steps
