@@ -113,11 +113,20 @@ typedef struct { double nu0, nu_inf, lambda, n, a; } lbm_rheology;
 /* Porous medium (model section):  1/k = kc (1-phi)^2 / (d^2 phi^3)  (finite,
  * and 0 at phi = 1);  Darcy drag -phi^2 nu_darcy u / k;  Forchheimer drag
  * -phi^3 C_F |u| u / sqrt(k) with C_F = 1.75/sqrt(150 phi^3) when
- * forchheimer = 1, else 0;  g: body force per unit mass, added to the drag. */
+ * forchheimer = 1, else 0;  g: body force per unit mass, added to the drag.
+ * Anisotropic permeability (the method section's Remark): if aniso (the
+ * symmetric shape M, order xx yy zz xy xz yz) is not all zero, K = k(phi) M,
+ * the drag is -phi^2 nu_darcy K^-1 u - phi^3 C_F |u| K^-1/2 u, and the
+ * velocity is the Remark's fixed-point iteration u_{m+1} = (A + |u_m| B)^-1 v,
+ * A = Id + (phi nu_darcy / 2) K^-1, B = (phi^2 C_F / 2) K^-1/2, from u_0 = v,
+ * exactly aniso_iters times (1..64; one suffices without Forchheimer drag).
+ * M must be positive definite.  Fields after g may be left zero. */
 typedef struct {
   double nu_darcy, d, kc;
   int forchheimer;
   double g[3];
+  double aniso[6];
+  int aniso_iters;
 } lbm_porous;
 
 /* Open faces.  inlet: the x = 0 face is a Zou-He velocity inflow with
@@ -235,7 +244,7 @@ lbm_status lbm_reset(lbm_ctx* ctx);
  * context's arithmetic mode; the reverse steps are FP64 arithmetic with FP32
  * adjoint populations.  Needs a workspace sized for (T, ckpt_every) or
  * larger; FP32 storage, shift mode 0, no Forchheimer drag, no extrapolation
- * outflow (for the gradient), a region with a fluid cell (with a wall cell for
+ * outflow (for the gradient), isotropic permeability, a region with a fluid cell (with a wall cell for
  * LBM_OBJ_WSS), 0 <= t_begin < t_end <= T.  At a wall cell where tau = 0 the
  * WSS term contributes no gradient (|tau| is not differentiable there).
  *   J:       host, 1 double

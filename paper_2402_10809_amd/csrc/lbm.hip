@@ -10,6 +10,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -164,6 +166,57 @@ void with_config(int storage, int shw, int mode, Fn&& fn) {
       fn(tag, sh, RF32{});
     }
   });
+}
+
+// Symmetric 3x3 matrices as full arrays: inverse by the adjugate.
+using M3 = std::array<std::array<double, 3>, 3>;
+bool inv3(const M3& a, M3& r) {
+  const double c00 = a[1][1] * a[2][2] - a[1][2] * a[2][1], c01 = a[1][2] * a[2][0] - a[1][0] * a[2][2],
+               c02 = a[1][0] * a[2][1] - a[1][1] * a[2][0];
+  const double det = a[0][0] * c00 + a[0][1] * c01 + a[0][2] * c02;
+  if (!(std::fabs(det) > 0.0) || !std::isfinite(det)) return false;
+  const double id = 1.0 / det;
+  r[0][0] = c00 * id; r[1][0] = c01 * id; r[2][0] = c02 * id;
+  r[0][1] = (a[0][2] * a[2][1] - a[0][1] * a[2][2]) * id;
+  r[1][1] = (a[0][0] * a[2][2] - a[0][2] * a[2][0]) * id;
+  r[2][1] = (a[0][1] * a[2][0] - a[0][0] * a[2][1]) * id;
+  r[0][2] = (a[0][1] * a[1][2] - a[0][2] * a[1][1]) * id;
+  r[1][2] = (a[0][2] * a[1][0] - a[0][0] * a[1][2]) * id;
+  r[2][2] = (a[0][0] * a[1][1] - a[0][1] * a[1][0]) * id;
+  return true;
+}
+
+// Anisotropic permeability shape M (xx yy zz xy xz yz): checks positive
+// definiteness (leading minors) and returns M^-1 and M^-1/2, the latter by the
+// Denman-Beavers iteration Y <- (Y + Z^-1)/2, Z <- (Z + Y^-1)/2 from Y = M,
+// Z = Id, whose Z converges quadratically to M^-1/2.
+bool aniso_shape(const double m6[6], double inv6[6], double ihalf6[6]) {
+  const M3 M = {{{m6[0], m6[3], m6[4]}, {m6[3], m6[1], m6[5]}, {m6[4], m6[5], m6[2]}}};
+  const double d1 = M[0][0], d2 = M[0][0] * M[1][1] - M[0][1] * M[0][1];
+  const double d3 = M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[1][2]) -
+                    M[0][1] * (M[0][1] * M[2][2] - M[1][2] * M[0][2]) + M[0][2] * (M[0][1] * M[1][2] - M[1][1] * M[0][2]);
+  if (!(d1 > 0.0 && d2 > 0.0 && d3 > 0.0)) return false;
+  M3 Mi, Y = M, Z = {{{1, 0, 0}, {0, 1, 0}, {0, 0, 1}}};
+  if (!inv3(M, Mi)) return false;
+  for (int it = 0; it < 100; ++it) {
+    M3 Yi, Zi;
+    if (!inv3(Y, Yi) || !inv3(Z, Zi)) return false;
+    double ch = 0.0;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        const double yn = 0.5 * (Y[i][j] + Zi[i][j]), zn = 0.5 * (Z[i][j] + Yi[i][j]);
+        ch = std::max(ch, std::fabs(zn - Z[i][j]));
+        Y[i][j] = yn;
+        Z[i][j] = zn;
+      }
+    if (ch < 1e-15 * (1.0 + std::fabs(Z[0][0]) + std::fabs(Z[1][1]) + std::fabs(Z[2][2]))) break;
+  }
+  const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+  for (int k = 0; k < 6; ++k) {
+    inv6[k] = 0.5 * (Mi[ia[k]][ib[k]] + Mi[ib[k]][ia[k]]);
+    ihalf6[k] = 0.5 * (Z[ia[k]][ib[k]] + Z[ib[k]][ia[k]]);
+  }
+  return true;
 }
 
 }  // namespace
@@ -395,7 +448,13 @@ lbm_status launch_step(lbm_ctx* c, int diag, float* rec, float* rho_rec) {
     const dim3 grid(c->sblk), block(NT);
     with_parity(c->t, [&](auto odd) {
       constexpr bool OD = decltype(odd)::value;
-      if (rec) {
+      if (c->P.an_iters > 0) {
+        // anisotropic permeability: plain steps and diagnostics checks only
+        if (diag == 0)
+          hipLaunchKernelGGL((k_step<S, SH, OD, 0, false, R, PJ, NT, true>), grid, block, 0, c->stream, c->P, b);
+        else
+          hipLaunchKernelGGL((k_step<S, SH, OD, 1, false, R, PJ, NT, true>), grid, block, 0, c->stream, c->P, b);
+      } else if (rec) {
         if constexpr (std::is_same<S, float>::value && !SH)
           hipLaunchKernelGGL((k_step<S, false, OD, 0, true, R, PJ, NT>), grid, block, 0, c->stream, c->P, b);
       } else if (diag == 0) {
@@ -450,9 +509,16 @@ lbm_status moments_launch(lbm_ctx* c, bool diag, float* rho, float* u, float* sh
     constexpr bool SH = decltype(shw)::value;
     with_parity(c->t, [&](auto odd) {
       constexpr bool OD = decltype(odd)::value;
-      if (diag)
+      const bool an = c->P.an_iters > 0;
+      if (diag && an)
+        hipLaunchKernelGGL((k_moments<S, SH, OD, true, R, true>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b,
+                           t, c->nbox, rho, u, shear, omega, sigma, tau);
+      else if (diag)
         hipLaunchKernelGGL((k_moments<S, SH, OD, true, R>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, t,
                            c->nbox, rho, u, shear, omega, sigma, tau);
+      else if (an)
+        hipLaunchKernelGGL((k_moments<S, SH, OD, false, R, true>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b,
+                           t, c->nbox, rho, u, shear, omega, sigma, tau);
       else
         hipLaunchKernelGGL((k_moments<S, SH, OD, false, R>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, t,
                            c->nbox, rho, u, shear, omega, sigma, tau);
@@ -530,6 +596,14 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* solid, const float* p
   if (!(rh->a > 0) || !(rh->lambda >= 0) || !std::isfinite(rh->n))
     return fail(LBM_E_INVALID, "bad Carreau-Yasuda a, lambda or n");
   if (!(po->kc >= 0) || !(po->d > 0) || !(po->nu_darcy >= 0)) return fail(LBM_E_INVALID, "bad porous parameters");
+  bool aniso = false;
+  double an_inv[6] = {0}, an_ih[6] = {0};
+  for (int k = 0; k < 6; ++k) aniso = aniso || po->aniso[k] != 0.0;
+  if (aniso) {
+    if (po->aniso_iters < 1 || po->aniso_iters > 64) return fail(LBM_E_INVALID, "aniso_iters must lie in [1, 64]");
+    if (!aniso_shape(po->aniso, an_inv, an_ih))
+      return fail(LBM_E_INVALID, "the anisotropic permeability shape must be symmetric positive definite");
+  }
   if (op && (op->inlet || op->outlet)) {
     if (grid->periodic[0]) return fail(LBM_E_INVALID, "open faces need a non-periodic x axis");
     if (op->inlet && (!op->shape_yz || !(op->period > 0)))
@@ -643,6 +717,13 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* solid, const float* p
   P.in_ramp = (op && op->inlet) ? (uint32_t)op->ramp_steps : 0u;
   P.cy_a2 = rh->a == 2.0 ? 1 : 0;
   P.forch = po->forchheimer ? 1 : 0;
+  P.an_iters = aniso ? po->aniso_iters : 0;
+  for (int k = 0; k < 6; ++k) {
+    P.d.Mi[k] = an_inv[k];
+    P.d.Mh[k] = an_ih[k];
+    P.f.Mi[k] = (float)an_inv[k];
+    P.f.Mh[k] = (float)an_ih[k];
+  }
   c->amode = grid->arith == LBM_ARITH_FP64 ? 2
              : (grid->arith == LBM_ARITH_AUTO && grid->storage == LBM_STORE_FP32) ? 1 : 0;
   c->omega0 = (float)(2.0 / (6.0 * rh->nu0 + 1.0));

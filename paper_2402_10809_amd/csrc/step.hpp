@@ -72,6 +72,7 @@ struct Params {
   uint32_t abytes;             // byte size of the population buffer
   int cy_a2;                   // a == 2: (lambda g)^a is one multiply
   int forch;                   // Forchheimer drag on
+  int an_iters;                // anisotropic permeability: fixed-point iterations
   double in_a0, in_a1, in_period;  // inflow waveform W(s) = a0 (1 + a1 sin(2 pi s / period))
   int in_table;                    // > 0: W is the sampled table of that length over one period
   uint32_t in_ramp;                // pre-run ramp length R (0: none)
@@ -85,6 +86,7 @@ struct Params {
     T nu_d, kcd;                 // Darcy viscosity, kc/d^2
     T gx, gy, gz;                // body force
     T rho_out;
+    T Mi[6], Mh[6];              // anisotropic permeability shape: M^-1, M^-1/2 (xx yy zz xy xz yz)
   };
   K<float> f;
   K<double> d;
@@ -436,7 +438,13 @@ struct Macro {
 // type of everything that feeds the collision's mass and momentum: with FP32
 // storage it is FP64, because FP32 rounding of these per-cell scalars is
 // common to all 19 directions and acts as a persistent momentum source.
-template <class R>
+//
+// AN: anisotropic permeability K = k M (the method section's Remark): the
+// velocity is the fixed point of (A + |u| B) u = v with A = Id + (phi nu/2)
+// K^-1 and B = (phi^2 C_F / 2) K^-1/2, iterated an_iters times from u_0 = v
+// (each iterate one symmetric 3x3 solve by the adjugate), and the drag is
+// the tensor drag -phi^2 nu K^-1 u - phi^3 C_F |u| K^-1/2 u.
+template <class R, bool AN = false>
 __device__ __forceinline__ void macro(const Params& p, float phx_f, const float d[Q], float omega_prev, Macro<R>& M) {
   const Sums<R> s = moment_sums<R>(d);
   const auto& kc = p.k<R>();
@@ -455,24 +463,60 @@ __device__ __forceinline__ void macro(const Params& p, float phx_f, const float 
   const R om = one - phx;
   const R invk = kc.kcd * om * om * iphi * iphi * iphi;
   const R dark = phx * kc.nu_d * invk;      // phi nu / k
-  const R C0 = (R)0.5 + (R)0.25 * dark;
-  R den, fcoef;
-  if (p.forch) {
+  R ux, uy, uz, Fx, Fy, Fz;
+  if constexpr (AN) {
     const R sik = rsqrt_(invk);
-    const R cf = (R)1.75 * rsqrt_(iphi * iphi * iphi * (R)(1.0 / 150.0));
-    const R C1 = (R)0.5 * phx * phx * cf * sik;
-    const R vn = rsqrt_(vx * vx + vy * vy + vz * vz);
-    den = C0 + rsqrt_(C0 * C0 + C1 * vn);
-    fcoef = phx * phx * phx * cf * sik;        // times |u| below
+    const R cf = p.forch ? (R)1.75 * rsqrt_(iphi * iphi * iphi * (R)(1.0 / 150.0)) : (R)0;
+    const R ha = (R)0.5 * dark, hb = (R)0.5 * phx * phx * cf * sik;
+    R Am[6], Bm[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      Am[k] = ha * kc.Mi[k] + (k < 3 ? one : (R)0);
+      Bm[k] = hb * kc.Mh[k];
+    }
+    ux = vx; uy = vy; uz = vz;
+    for (int m = 0; m < p.an_iters; ++m) {
+      const R un = rsqrt_(ux * ux + uy * uy + uz * uz);
+      R X[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) X[k] = rfma(un, Bm[k], Am[k]);
+      // adjugate of [[X0 X3 X4] [X3 X1 X5] [X4 X5 X2]]
+      const R a00 = X[1] * X[2] - X[5] * X[5], a11 = X[0] * X[2] - X[4] * X[4], a22 = X[0] * X[1] - X[3] * X[3];
+      const R a01 = X[4] * X[5] - X[3] * X[2], a02 = X[3] * X[5] - X[4] * X[1], a12 = X[3] * X[4] - X[0] * X[5];
+      const R idet = fast_rcp(X[0] * a00 + X[3] * a01 + X[4] * a02);
+      ux = (a00 * vx + a01 * vy + a02 * vz) * idet;
+      uy = (a01 * vx + a11 * vy + a12 * vz) * idet;
+      uz = (a02 * vx + a12 * vy + a22 * vz) * idet;
+    }
+    R kdx, kdy, kdz, khx, khy, khz;
+    sym_mv(kc.Mi, ux, uy, uz, kdx, kdy, kdz);
+    sym_mv(kc.Mh, ux, uy, uz, khx, khy, khz);
+    const R dd = phx * dark;                                          // phi^2 nu / k
+    const R df = phx * phx * phx * cf * sik * rsqrt_(ux * ux + uy * uy + uz * uz);  // phi^3 C_F |u| / sqrt(k)
+    Fx = rho * (gx - dd * kdx - df * khx);
+    Fy = rho * (gy - dd * kdy - df * khy);
+    Fz = rho * (gz - dd * kdz - df * khz);
   } else {
-    den = (R)2 * C0;
-    fcoef = (R)0;
+    const R C0 = (R)0.5 + (R)0.25 * dark;
+    R den, fcoef;
+    if (p.forch) {
+      const R sik = rsqrt_(invk);
+      const R cf = (R)1.75 * rsqrt_(iphi * iphi * iphi * (R)(1.0 / 150.0));
+      const R C1 = (R)0.5 * phx * phx * cf * sik;
+      const R vn = rsqrt_(vx * vx + vy * vy + vz * vz);
+      den = C0 + rsqrt_(C0 * C0 + C1 * vn);
+      fcoef = phx * phx * phx * cf * sik;        // times |u| below
+    } else {
+      den = (R)2 * C0;
+      fcoef = (R)0;
+    }
+    const R iden = fast_rcp(den);
+    ux = vx * iden; uy = vy * iden; uz = vz * iden;
+    const R uu0 = ux * ux + uy * uy + uz * uz;
+    const R drag = phx * dark + (p.forch ? fcoef * rsqrt_(uu0) : (R)0);  // phi^2 nu/k + phi^3 C_F |u|/sqrt(k)
+    Fx = rho * (gx - drag * ux); Fy = rho * (gy - drag * uy); Fz = rho * (gz - drag * uz);
   }
-  const R iden = fast_rcp(den);
-  const R ux = vx * iden, uy = vy * iden, uz = vz * iden;
   const R uu = ux * ux + uy * uy + uz * uz;
-  const R drag = phx * dark + (p.forch ? fcoef * rsqrt_(uu) : (R)0);  // phi^2 nu/k + phi^3 C_F |u|/sqrt(k)
-  const R Fx = rho * (gx - drag * ux), Fy = rho * (gy - drag * uy), Fz = rho * (gz - drag * uz);
   // Pi = sum (f - f_eq) c c + (F u + u F)/2
   //    = sum(v c c)/U - [phi (rho-1)/3 I + phi rho u u] + (F u + u F)/2
   const R iso = phx * rm1 * (R)(1.0 / 3.0);
@@ -688,7 +732,7 @@ __device__ __forceinline__ void diag_terms(const Params& p, float phx, const flo
 
 // Body of the step for one cell (UNI: the whole wave has uniform neighbour
 // porosity).
-template <class S, bool SHW, bool UNI, bool ODD, int DIAG, bool REC, class R, bool PROJ>
+template <class S, bool SHW, bool UNI, bool ODD, int DIAG, bool REC, class R, bool PROJ, bool AN>
 __device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32_t c, uint32_t lk, uint32_t t,
                                           double (&dv)[NDIAGP], float& ke_reg) {
   Pos q = position(p, c, b.code[c]);
@@ -707,7 +751,7 @@ __device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32
   if (p.outlet == 2 && (lk & (LK_OUT | LK_UPS))) outflow_keep(p, q.row, lk, phx, d, b.side + (ODD ? 0 : half));
   const float omp = b.omega[c];
   Macro<R> M;
-  macro<R>(p, phx, d, omp, M);
+  macro<R, AN>(p, phx, d, omp, M);
   b.omega[c] = (float)M.omega;
   if (REC) {
     __builtin_nontemporal_store(omp, &b.rec[(size_t)Q * p.nc + c]);
@@ -727,7 +771,7 @@ __device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32
 // part[block].  REC: also record the pulled
 // values and omega_prev ([20][nc]) and rho.
 // ---------------------------------------------------------------------------
-template <class S, bool SHW, bool ODD, int DIAG, bool REC, class R, bool PROJ, int NT>
+template <class S, bool SHW, bool ODD, int DIAG, bool REC, class R, bool PROJ, int NT, bool AN = false>
 __global__ __launch_bounds__(NT) void k_step(Params p, Bufs b) {
   const uint32_t c = xcd_block(blockIdx.x, gridDim.x) * NT + threadIdx.x;
   const uint32_t t = b.tc[ODD ? 1 : 0];
@@ -737,9 +781,9 @@ __global__ __launch_bounds__(NT) void k_step(Params p, Bufs b) {
   float ke_reg = 0.0f;
   const bool uni = !active || (lk & LK_UNI);
   if (__all(uni)) {
-    if (active) step_cell<S, SHW, true, ODD, DIAG, REC, R, PROJ>(p, b, c, lk, t, dv, ke_reg);
+    if (active) step_cell<S, SHW, true, ODD, DIAG, REC, R, PROJ, AN>(p, b, c, lk, t, dv, ke_reg);
   } else {
-    if (active) step_cell<S, SHW, false, ODD, DIAG, REC, R, PROJ>(p, b, c, lk, t, dv, ke_reg);
+    if (active) step_cell<S, SHW, false, ODD, DIAG, REC, R, PROJ, AN>(p, b, c, lk, t, dv, ke_reg);
   }
   if (DIAG == 1) {
     if (!active) {
@@ -763,7 +807,7 @@ __global__ __launch_bounds__(NT) void k_step(Params p, Bufs b) {
 
 // Moments of the current state (no collision): dense box outputs (any may be
 // null) and optionally the diagnostics partials.
-template <class S, bool SHW, bool ODD, bool DIAG, class R>
+template <class S, bool SHW, bool ODD, bool DIAG, class R, bool AN = false>
 __global__ __launch_bounds__(BLOCK) void k_moments(Params p, Bufs b, uint32_t t, size_t nbox, float* rho_o,
                                                     float* u_o, float* shear_o, float* omega_o, float* sigma_o,
                                                     float* tau_o) {
@@ -779,7 +823,7 @@ __global__ __launch_bounds__(BLOCK) void k_moments(Params p, Bufs b, uint32_t t,
     pull<S, SHW, true, ODD>(p, Pop<S>(b.A, p.abytes), b.phi, c, lk, q, phx, d, pt);
     open_fill(p, q.row, lk, t, b.shape, b.wave, b.side + (ODD ? (size_t)p.nrow * 10 : 0), d);
     Macro<R> M;
-    macro<R>(p, phx, d, b.omega[c], M);
+    macro<R, AN>(p, phx, d, b.omega[c], M);
     const size_t idx = (size_t)b.rowbox[q.row] + (size_t)q.x;
     if (rho_o) rho_o[idx] = (float)M.rho;
     if (u_o) {

@@ -39,7 +39,7 @@ class lbm_rheology(ct.Structure):
 
 class lbm_porous(ct.Structure):
     _fields_ = [("nu_darcy", ct.c_double), ("d", ct.c_double), ("kc", ct.c_double), ("forchheimer", ct.c_int),
-                ("g", ct.c_double * 3)]
+                ("g", ct.c_double * 3), ("aniso", ct.c_double * 6), ("aniso_iters", ct.c_int)]
 
 
 class lbm_open(ct.Structure):
@@ -127,7 +127,8 @@ class Solver:
     """One simulation context on the current HIP device.
 
     solid, phi, region: arrays of shape (nz, ny, nx) (box index x + nx*(y + ny*z)).
-    rheology: dict(nu0, nu_inf, lam, n, a); porous: dict(nu_d, d, kc, forchheimer, g).
+    rheology: dict(nu0, nu_inf, lam, n, a); porous: dict(nu_d, d, kc, forchheimer, g[, aniso=(M xx yy zz xy xz yz),
+    aniso_iters]).
     inlet: None or dict(shape=(nz, ny) array, a0, a1, period[, ramp=steps][, table=FP64 samples of one period]);
     outlet: None, rho_out (constant-density outflow) or "extrapolation" (the non-reflecting outflow).
     adjoint_T/ckpt: reserve workspace for lbm_adjoint runs of up to adjoint_T steps.
@@ -161,6 +162,10 @@ class Solver:
         p.nu_darcy, p.d, p.kc, p.forchheimer = po["nu_d"], po["d"], po["kc"], int(po.get("forchheimer", 0))
         for a in range(3):
             p.g[a] = float(po["g"][a])
+        if po.get("aniso") is not None:
+            for k in range(6):
+                p.aniso[k] = float(po["aniso"][k])
+            p.aniso_iters = int(po.get("aniso_iters", 8))
         o = lbm_open()
         self._shape_yz = None
         if inlet is not None:

@@ -16,6 +16,8 @@ from .cases import (  # noqa: F401
     tiny_case,
     fd_voxels,
     sampled_waveform,
+    aniso_shape,
+    with_anisotropic_drag,
     CONFIGS,
     make_config,
 )

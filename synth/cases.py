@@ -354,6 +354,24 @@ def tiny_case(kind: str = "open", seed: int = 0, nx: int = 9, ny: int = 7, nz: i
     return case
 
 
+def aniso_shape(seed: int = 9, ratio: float = 3.0) -> tuple:
+    """A seeded permeability shape M (xx yy zz xy xz yz): a random rotation of
+    diag(sqrt(ratio), 1, 1/sqrt(ratio)), i.e. permeability 'ratio' times larger
+    along one direction than along another, as a coil's wire direction might
+    impose.  An input, not part of the method."""
+    rng = np.random.default_rng(1000 + seed)
+    q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    m = q @ np.diag([np.sqrt(ratio), 1.0, 1.0 / np.sqrt(ratio)]) @ q.T
+    return (m[0, 0], m[1, 1], m[2, 2], m[0, 1], m[0, 2], m[1, 2])
+
+
+def with_anisotropic_drag(case: Case, iters: int = 6, seed: int = 9) -> Case:
+    """The case with Forchheimer drag and the anisotropic shape of aniso_shape."""
+    case.porous = dict(case.porous, forchheimer=1, aniso=aniso_shape(seed), aniso_iters=iters)
+    case.name = case.name + "_aniso"
+    return case
+
+
 def sampled_waveform(n: int = 128, peak: float = 0.05, base: float = 0.015) -> np.ndarray:
     """One period of a systole-like inflow waveform, n samples: a base level
     plus a raised-cosine systolic pulse in the first third of the period and a

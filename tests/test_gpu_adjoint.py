@@ -73,6 +73,11 @@ def test_adjoint_rejects_unsupported():
         s2.adjoint(2, 12, 10, 5)   # window beyond T
     with pytest.raises(lbm.LBMError):
         s2.adjoint(2, 10, 40, 5)   # workspace sized for T = 10
+    an = _tiny("open", 3)
+    an.porous = dict(an.porous, aniso=(1.0, 2.0, 1.0, 0.1, 0.0, 0.0), aniso_iters=4)
+    s3 = Solver.from_case(an, adjoint_T=10, ckpt=5)
+    with pytest.raises(lbm.LBMError):
+        s3.adjoint(2, 10, 10, 5)   # anisotropic permeability
 
 
 @pytest.mark.parametrize("objective", ["ke", "wss"])

@@ -49,7 +49,7 @@ def rel_l2(a, ref):
     return float(np.sqrt(((a - ref) ** 2).sum()) / np.sqrt((ref ** 2).sum()))
 
 
-@pytest.mark.parametrize("kind", ["open", "open_wave", "open_extrap", "periodic", "periodic3"])
+@pytest.mark.parametrize("kind", ["open", "open_wave", "open_extrap", "periodic", "periodic_aniso", "periodic3"])
 @pytest.mark.parametrize("seed", [0, 1])
 def test_one_step_from_random_state(kind, seed):
     """Every cell type (walls, open faces, periodic wrap, porosity jumps): one
@@ -164,6 +164,25 @@ def test_aneurysm_extrapolation_outflow(storage, bound_u):
     case.outlet = 2
     steps = 1000
     say(f"extrapolation outflow: aneurysm {case.nx}x{case.ny}x{case.nz}, {storage}, {steps} steps")
+    o, f, om, ref = _oracle_run(case, steps)
+    s = Solver.from_case(case, storage=storage)
+    s.step(steps)
+    g = _gpu_fields(s)
+    eu, el = max_rel(g["u"], ref["u"]), rel_l2(g["u"], ref["u"])
+    say(f"  u max-rel {eu:.3e}  u rel-L2 {el:.3e}  shear max-rel {max_rel(g['shear'], ref['shear']):.3e}")
+    assert (eu if storage == "fp32" else el) < bound_u
+
+
+@pytest.mark.parametrize("storage,bound_u", [("fp32", 1e-5), ("fp16", 1e-3)])
+def test_aneurysm_anisotropic_permeability(storage, bound_u):
+    """The Remark's anisotropic permeability on the 192x128x128 aneurysm: a
+    seeded shape with a 3:1 permeability ratio, Forchheimer drag on, six
+    fixed-point iterations per cell and step; 1000 steps."""
+    from synth import with_anisotropic_drag
+
+    case = with_anisotropic_drag(make_config("c1"))
+    steps = 1000
+    say(f"anisotropic permeability: aneurysm {case.nx}x{case.ny}x{case.nz}, {storage}, {steps} steps")
     o, f, om, ref = _oracle_run(case, steps)
     s = Solver.from_case(case, storage=storage)
     s.step(steps)
