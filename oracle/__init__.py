@@ -18,16 +18,21 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.cpp")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# one library per velocity set (the source is compiled with ORACLE_Q = 19 / 27)
+_LIBS = {19: os.path.join(_HERE, "liboracle.so"), 27: os.path.join(_HERE, "liboracle27.so")}
+_LIB = _LIBS[19]
 Q = 19
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle into ``oracle/liboracle.so`` (g++, OpenMP)."""
-    if force or not os.path.exists(_LIB):
-        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-o", _LIB + ".tmp", _SRC]
-        subprocess.check_call(cmd)
-        os.replace(_LIB + ".tmp", _LIB)
+    """Compile the oracle into ``oracle/liboracle.so`` (D3Q19) and
+    ``oracle/liboracle27.so`` (D3Q27) (g++, OpenMP)."""
+    for q, path in _LIBS.items():
+        if force or not os.path.exists(path):
+            cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", f"-DORACLE_Q={q}", "-o",
+                   path + ".tmp", _SRC]
+            subprocess.check_call(cmd)
+            os.replace(path + ".tmp", path)
     return _LIB
 
 
@@ -49,15 +54,19 @@ class _Case(ct.Structure):
     ]
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB):
+def lattice_of(case) -> int:
+    """Velocity-set size of a case (attribute ``lattice``, default 19)."""
+    return int(getattr(case, "lattice", 19) or 19)
+
+
+def lib(q: int = 19):
+    if q not in _libs:
+        if not os.path.exists(_LIBS[q]):
             build(force=False)
-        L = ct.CDLL(_LIB)
+        L = ct.CDLL(_LIBS[q])
         vp, i32, i64, dbl = ct.c_void_p, ct.c_int, ct.c_int64, ct.c_double
         L.oracle_new.restype = vp
         L.oracle_new.argtypes = [ct.POINTER(_Case)]
@@ -81,8 +90,10 @@ def lib():
         L.oracle_grad_dual.argtypes = [vp, i32, i32, i32, vp, i32, vp, vp, i32]
         L.oracle_grad_reverse.argtypes = [vp, i32, i32, i32, i32, vp, vp, i32]
         L.oracle_threads.restype = i32
-        _lib = L
-    return _lib
+        L.oracle_q.restype = i32
+        assert L.oracle_q() == q
+        _libs[q] = L
+    return _libs[q]
 
 
 def _ptr(a: np.ndarray):
@@ -143,43 +154,45 @@ class Oracle:
         self._keep = []
         kw = {} if phi is None else dict(phi=phi)
         self._struct = make_struct(case, self._keep, **kw)
-        self.h = lib().oracle_new(ct.byref(self._struct))
-        self.nf = int(lib().oracle_nfluid(self.h))
+        self.q = lattice_of(case)
+        self._L = lib(self.q)
+        self.h = self._L.oracle_new(ct.byref(self._struct))
+        self.nf = int(self._L.oracle_nfluid(self.h))
 
     def __del__(self):
         if getattr(self, "h", None):
-            lib().oracle_free(self.h)
+            self._L.oracle_free(self.h)
             self.h = None
 
     def cells(self) -> np.ndarray:
         out = np.empty(self.nf, np.int64)
-        lib().oracle_cells(self.h, _ptr(out))
+        self._L.oracle_cells(self.h, _ptr(out))
         return out
 
     def neighbours(self) -> np.ndarray:
-        out = np.empty((Q, self.nf), np.int32)
-        lib().oracle_neighbours(self.h, _ptr(out))
+        out = np.empty((self.q, self.nf), np.int32)
+        self._L.oracle_neighbours(self.h, _ptr(out))
         return out
 
     def amplitude(self, t: int) -> float:
-        return float(lib().oracle_amplitude(self.h, int(t)))
+        return float(self._L.oracle_amplitude(self.h, int(t)))
 
     def set_phi(self, phi_box: np.ndarray):
         p = np.ascontiguousarray(phi_box.reshape(-1), dtype=np.float64)
-        lib().oracle_set_phi(self.h, _ptr(p))
+        self._L.oracle_set_phi(self.h, _ptr(p))
 
     def init(self):
-        f = np.empty((Q, self.nf), np.float64)
+        f = np.empty((self.q, self.nf), np.float64)
         om = np.empty(self.nf, np.float64)
-        lib().oracle_init(self.h, _ptr(f), _ptr(om))
+        self._L.oracle_init(self.h, _ptr(f), _ptr(om))
         return f, om
 
     def run(self, f, omega, t0: int, nsteps: int, want_ke: bool = False):
         """Advance ``nsteps`` steps from step index ``t0`` (in place)."""
-        assert f.dtype == np.float64 and f.flags.c_contiguous and f.shape == (Q, self.nf)
+        assert f.dtype == np.float64 and f.flags.c_contiguous and f.shape == (self.q, self.nf)
         assert omega.dtype == np.float64 and omega.flags.c_contiguous
         ke = np.empty(nsteps, np.float64) if want_ke else None
-        lib().oracle_run(self.h, _ptr(f), _ptr(omega), int(t0), int(nsteps), _ptr(ke))
+        self._L.oracle_run(self.h, _ptr(f), _ptr(omega), int(t0), int(nsteps), _ptr(ke))
         return ke
 
     def moments(self, f, omega, t: int):
@@ -190,28 +203,28 @@ class Oracle:
         om = np.empty(nf)
         sigma = np.empty((6, nf))
         tau = np.empty((3, nf))
-        lib().oracle_moments(self.h, _ptr(np.ascontiguousarray(f)), _ptr(np.ascontiguousarray(omega)), int(t),
+        self._L.oracle_moments(self.h, _ptr(np.ascontiguousarray(f)), _ptr(np.ascontiguousarray(omega)), int(t),
                              _ptr(rho), _ptr(u), _ptr(shear), _ptr(om), _ptr(sigma), _ptr(tau))
         return dict(rho=rho, u=u, shear=shear, omega=om, sigma=sigma, tau=tau)
 
     def objective(self, T: int, tb: int, te: int, kind: str = "ke") -> float:
         """J over steps [tb, te) of a T-step run from rest; kind "ke" (region
         kinetic energy) or "wss" (WSS magnitude over the region's wall cells)."""
-        return float(lib().oracle_objective(self.h, int(T), int(tb), int(te), OBJECTIVE[kind]))
+        return float(self._L.oracle_objective(self.h, int(T), int(tb), int(te), OBJECTIVE[kind]))
 
     def grad_dual(self, T: int, tb: int, te: int, box_cells, kind: str = "ke"):
         cells = np.ascontiguousarray(np.asarray(box_cells, dtype=np.int64))
         assert cells.size <= 16
         J = np.zeros(1)
         g = np.zeros(cells.size)
-        lib().oracle_grad_dual(self.h, int(T), int(tb), int(te), _ptr(cells), int(cells.size), _ptr(J), _ptr(g),
+        self._L.oracle_grad_dual(self.h, int(T), int(tb), int(te), _ptr(cells), int(cells.size), _ptr(J), _ptr(g),
                                OBJECTIVE[kind])
         return float(J[0]), g
 
     def grad_reverse(self, T: int, tb: int, te: int, ckpt: int, kind: str = "ke"):
         J = np.zeros(1)
         g = np.zeros(self.case.n_box)
-        lib().oracle_grad_reverse(self.h, int(T), int(tb), int(te), int(ckpt), _ptr(J), _ptr(g), OBJECTIVE[kind])
+        self._L.oracle_grad_reverse(self.h, int(T), int(tb), int(te), int(ckpt), _ptr(J), _ptr(g), OBJECTIVE[kind])
         if np.isnan(J[0]):
             raise ValueError("the reverse sweep supports the density outflow only")
         return float(J[0]), g.reshape(self.case.nz, self.case.ny, self.case.nx)
@@ -222,32 +235,35 @@ def cell(case, f, omega_prev, phi, phit):
     u, F, feq, Pi (xx yy zz xy xz yz), shear, nu, omega and q."""
     keep = []
     s = make_struct(case, keep)
+    q = lattice_of(case)
     f = np.ascontiguousarray(f, dtype=np.float64)
     phit = np.ascontiguousarray(phit, dtype=np.float64)
-    out = {k: np.zeros(n) for k, n in dict(rho=1, u=3, F=3, feq=Q, Pi=6, shear=1, nu=1, omega=1, q=Q).items()}
-    lib().oracle_cell(ct.byref(s), _ptr(f), float(omega_prev), float(phi), _ptr(phit),
-                      *[_ptr(out[k]) for k in ("rho", "u", "F", "feq", "Pi", "shear", "nu", "omega", "q")])
+    out = {k: np.zeros(n) for k, n in dict(rho=1, u=3, F=3, feq=q, Pi=6, shear=1, nu=1, omega=1, q=q).items()}
+    lib(q).oracle_cell(ct.byref(s), _ptr(f), float(omega_prev), float(phi), _ptr(phit),
+                       *[_ptr(out[k]) for k in ("rho", "u", "F", "feq", "Pi", "shear", "nu", "omega", "q")])
     for k in ("rho", "shear", "nu", "omega"):
         out[k] = float(out[k][0])
     return out
 
 
 def zouhe_inlet(f, ux, uy=0.0, uz=0.0):
+    """Zou-He inflow fill of one cell's populations (the set of len(f))."""
     f = np.array(f, dtype=np.float64)
-    lib().oracle_zouhe_inlet(_ptr(f), float(ux), float(uy), float(uz))
+    lib(f.size).oracle_zouhe_inlet(_ptr(f), float(ux), float(uy), float(uz))
     return f
 
 
 def zouhe_outlet(f, rho_out):
+    """Zou-He constant-density outflow fill (the set of len(f))."""
     f = np.array(f, dtype=np.float64)
-    lib().oracle_zouhe_outlet(_ptr(f), float(rho_out))
+    lib(f.size).oracle_zouhe_outlet(_ptr(f), float(rho_out))
     return f
 
 
-def lattice():
-    c = np.zeros((Q, 3), np.int32)
-    w = np.zeros(Q, np.float64)
-    lib().oracle_lattice(_ptr(c), _ptr(w))
+def lattice(q: int = 19):
+    c = np.zeros((q, 3), np.int32)
+    w = np.zeros(q, np.float64)
+    lib(q).oracle_lattice(_ptr(c), _ptr(w))
     return c, w
 
 

@@ -5,7 +5,8 @@ section, written over whole (nz, ny, nx) arrays with explicit shifts instead of
 the C++ oracle's compact cell list and neighbour table, so that indexing, wall
 and open-face mistakes in either show up as a mismatch on tiny lattices.
 
-State layout here: ``f`` of shape (19, nz, ny, nx), pre-collision populations,
+State layout here: ``f`` of shape (Q, nz, ny, nx) (Q = 19 or 27, the case's
+``lattice``), pre-collision populations,
 0 on solid voxels and on the unknown links of open-face cells (an extrapolation
 outflow keeps its extrapolated values there).
 """
@@ -23,6 +24,20 @@ C = np.array([(0, 0, 0),
 W = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
 OPP = np.array([int(np.flatnonzero((C == -C[i]).all(axis=1))[0]) for i in range(19)])
 CS2 = 1.0 / 3.0
+
+# D3Q27: the 19 above, then the 8 corners in opposite pairs; the weight of a
+# velocity with n nonzero components is (2/3)^(3-n) (1/6)^n
+C27 = np.concatenate([C, np.array([(1, 1, 1), (-1, -1, -1), (1, 1, -1), (-1, -1, 1),
+                                   (1, -1, 1), (-1, 1, -1), (-1, 1, 1), (1, -1, -1)], dtype=np.int64)])
+W27 = np.array([(2 / 3) ** (3 - n) * (1 / 6) ** n for n in np.abs(C27).sum(1)])
+OPP27 = np.array([int(np.flatnonzero((C27 == -C27[i]).all(axis=1))[0]) for i in range(27)])
+
+
+def lattice(case):
+    """(C, W, OPP) of the case's velocity set."""
+    if int(getattr(case, "lattice", 19) or 19) == 27:
+        return C27, W27, OPP27
+    return C, W, OPP
 
 
 def _shift(a, c, periodic, fill):
@@ -46,11 +61,12 @@ def _shift(a, c, periodic, fill):
 def _link_kinds(case):
     """For each direction i and cell x: 0 if x + c_i is a fluid cell, 1 if it is
     a wall (solid voxel or outside a wall face), 2 if it is outside an open face."""
+    C, _, _ = lattice(case)
     fluid = case.solid == 0
     nz, ny, nx = fluid.shape
-    kinds = np.zeros((19,) + fluid.shape, np.int8)
+    kinds = np.zeros((len(C),) + fluid.shape, np.int8)
     zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
-    for i in range(19):
+    for i in range(len(C)):
         cx, cy, cz = C[i]
         tx, ty, tz = xx + cx, yy + cy, zz + cz
         out_wall = np.zeros_like(fluid)
@@ -96,8 +112,34 @@ def inflow_amplitude(case, t):
     return w(float(t - ramp))
 
 
+def _zouhe_solve(case, fx, side, rho, ux, uy, uz):
+    """D3Q27 Zou-He fill of one face (side +1: the c_x = +1 unknowns of an
+    inflow, -1: the c_x = -1 unknowns of an outflow): f_i = f_opp(i) +
+    2 w_i rho c_i.u / c_s^2 - 18 w_i (c_iy N_y + c_iz N_z), with (N_y, N_z)
+    solved from the transverse momentum balance as a 2x2 linear system."""
+    C, W, OPP = lattice(case)
+    unk = np.flatnonzero(C[:, 0] == side)
+    u = np.stack([np.broadcast_to(ux, rho.shape), np.broadcast_to(uy, rho.shape), np.broadcast_to(uz, rho.shape)])
+    base = {}
+    for i in unk:
+        cu = C[i, 0] * u[0] + C[i, 1] * u[1] + C[i, 2] * u[2]
+        base[i] = fx[OPP[i]] + 2 * W[i] * rho * cu / CS2
+    known = np.flatnonzero(C[:, 0] != side)
+    # transverse momentum with N = 0, and its derivative in N (a constant matrix)
+    m0 = [sum(fx[j] * C[j, a] for j in known) + sum(base[i] * C[i, a] for i in unk) for a in (1, 2)]
+    D = np.array([[-18 * sum(W[i] * C[i, a] * C[i, b] for i in unk) for b in (1, 2)] for a in (1, 2)])
+    rhs = np.stack([rho * u[1] - m0[0], rho * u[2] - m0[1]], axis=-1)
+    N = np.linalg.solve(D, rhs[..., None])[..., 0]
+    out = fx.copy()
+    for i in unk:
+        out[i] = base[i] - 18 * W[i] * (C[i, 1] * N[..., 0] + C[i, 2] * N[..., 1])
+    return out
+
+
 def step(case, f, omega_prev, t):
     """One step on dense arrays; returns (f_next, omega_new, fields)."""
+    C, W, OPP = lattice(case)
+    Q = len(W)
     fluid = case.solid == 0
     phi = np.where(fluid, case.phi.astype(np.float64), 1.0)
     nz, ny, nx = fluid.shape
@@ -105,7 +147,14 @@ def step(case, f, omega_prev, t):
     f = f.copy()
     # open-face fill: Zou-He inflow on x = 0; constant-density or extrapolation
     # outflow on x = nx-1
-    if case.inlet:
+    if case.inlet and Q == 27:
+        amp = inflow_amplitude(case, t)
+        fx = f[:, :, :, 0]
+        ux = amp * case.inlet_shape.astype(np.float64)
+        rho = (fx[C[:, 0] == 0].sum(0) + 2 * fx[C[:, 0] == -1].sum(0)) / (1 - ux)
+        fx = _zouhe_solve(case, fx, 1, rho, ux, 0.0, 0.0)
+        f[:, :, :, 0] = np.where(fluid[:, :, 0][None], fx, f[:, :, :, 0])
+    elif case.inlet:
         amp = inflow_amplitude(case, t)
         fx = f[:, :, :, 0]
         ux = amp * case.inlet_shape.astype(np.float64)
@@ -121,7 +170,13 @@ def step(case, f, omega_prev, t):
         fx[13] = fx[14] + rho * ux / 6 + nz_
         m = fluid[:, :, 0]
         f[:, :, :, 0] = np.where(m[None], fx, f[:, :, :, 0])
-    if int(case.outlet) == 1:
+    if int(case.outlet) == 1 and Q == 27:
+        fx = f[:, :, :, nx - 1]
+        ro = case.rho_out
+        ux = (fx[C[:, 0] == 0].sum(0) + 2 * fx[C[:, 0] == 1].sum(0)) / ro - 1
+        fx = _zouhe_solve(case, fx, -1, np.full(ux.shape, ro), ux, 0.0, 0.0)
+        f[:, :, :, nx - 1] = np.where(fluid[:, :, nx - 1][None], fx, f[:, :, :, nx - 1])
+    elif int(case.outlet) == 1:
         fx = f[:, :, :, nx - 1]
         ro = case.rho_out
         zero = C[:, 0] == 0
@@ -188,13 +243,13 @@ def step(case, f, omega_prev, t):
     lam_s = rp["lam"] * shear
     nu = rp["nu_inf"] + (rp["nu0"] - rp["nu_inf"]) * (1 + np.where(lam_s > 0, lam_s, 0.0) ** rp["a"]) ** ((rp["n"] - 1) / rp["a"])
     omega = 2 * rho * CS2 / (2 * nu + rho * CS2)
-    phi_t = np.empty((19,) + fluid.shape)
-    for i in range(19):
+    phi_t = np.empty((Q,) + fluid.shape)
+    for i in range(Q):
         # porosity at x + c_i, or phi(x) across walls and open faces
         nb = _shift(phi, -C[i], case.periodic, 0.0)
         phi_t[i] = np.where(kinds[i] == 0, nb, phi)
     guo = np.zeros_like(f)
-    for i in range(19):
+    for i in range(Q):
         s = np.zeros(fluid.shape)
         for a in range(3):
             s += ((C[i, a] - u[a]) / CS2 + cu[i] * C[i, a] / CS2 ** 2) * F[a]
@@ -203,7 +258,7 @@ def step(case, f, omega_prev, t):
     q = np.where(fluid[None], q, 0.0)
     # push streaming with halfway bounce-back; open-face links are dropped
     fn = np.zeros_like(f)
-    for i in range(19):
+    for i in range(Q):
         moved = _shift(np.where(kinds[i] == 0, q[i], 0.0), C[i], case.periodic, 0.0)
         fn[i] += moved
         fn[OPP[i]] += np.where(kinds[i] == 1, q[i], 0.0)

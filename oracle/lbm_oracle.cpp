@@ -39,21 +39,39 @@
 namespace {
 
 // ---------------------------------------------------------------------------
-// D3Q19 velocity set.  Rest, 6 axis neighbours (weight 1/18), 12 edge
-// neighbours (weight 1/36); each odd-numbered moving direction is followed by
-// its opposite.
+// Velocity set, chosen at compile time (ORACLE_Q = 19 or 27; the paper's
+// method section uses D3Q27).  D3Q19: rest (1/3), 6 axis neighbours (1/18),
+// 12 edge neighbours (1/36).  D3Q27: rest (8/27), axis (2/27), edges (1/54),
+// 8 corners (1/216).  Each odd-numbered moving direction is followed by its
+// opposite; the first 19 directions are the same in both sets.
 // ---------------------------------------------------------------------------
-const int Q = 19;
-const int CV[Q][3] = {
+#ifndef ORACLE_Q
+#define ORACLE_Q 19
+#endif
+const int Q = ORACLE_Q;
+const int CV[27][3] = {
     {0, 0, 0},
     {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
     {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
     {1, 0, 1},  {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
-    {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+    {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1},
+    {1, 1, 1},  {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1},
+    {1, -1, 1}, {-1, 1, -1}, {-1, 1, 1}, {1, -1, -1}};
+#if ORACLE_Q == 19
 const double WT[Q] = {1.0 / 3.0,
                       1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
                       1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
                       1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+#elif ORACLE_Q == 27
+const double WT[Q] = {8.0 / 27.0,
+                      2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0,
+                      1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0,
+                      1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0,
+                      1.0 / 216.0, 1.0 / 216.0, 1.0 / 216.0, 1.0 / 216.0,
+                      1.0 / 216.0, 1.0 / 216.0, 1.0 / 216.0, 1.0 / 216.0};
+#else
+#error "ORACLE_Q must be 19 or 27"
+#endif
 const double CS2 = 1.0 / 3.0;
 
 int opposite(int i) {
@@ -288,6 +306,45 @@ int classify(const Ctx& C, int x, int y, int z, int i) {
 // Outflow on x = nx-1 with prescribed density and zero tangential velocity: the
 // unknowns are the five populations with c_x = -1.
 // ---------------------------------------------------------------------------
+#if ORACLE_Q == 27
+// D3Q27 (nine unknowns per face).  Reading: the closure of the D3Q19 version
+// generalised with weight-proportional transverse corrections,
+//   f_i = f_opp(i) + 2 w_i rho (c_i . u) / c_s^2 - 18 w_i (c_iy N_y + c_iz N_z),
+// N_a = sum_{c_x = 0} f c_a - (2/3) rho u_a, which imposes rho and the whole
+// velocity and reduces to the D3Q19 closure above on the D3Q19 set.
+template <class T>
+void zouhe_face(T f[Q], int side, T rho, T ux, T uy, T uz) {
+  T sy = 0, sz = 0;
+  for (int i = 0; i < Q; ++i)
+    if (CV[i][0] == 0) { sy += f[i] * (double)CV[i][1]; sz += f[i] * (double)CV[i][2]; }
+  const T Ny = sy - (2.0 / 3.0) * rho * uy, Nz = sz - (2.0 / 3.0) * rho * uz;
+  for (int i = 0; i < Q; ++i) {
+    if (CV[i][0] != side) continue;
+    const int o = opposite(i);
+    const T cu = (double)CV[i][0] * ux + (double)CV[i][1] * uy + (double)CV[i][2] * uz;
+    f[i] = f[o] + 2.0 * WT[i] * rho * cu / CS2 - 18.0 * WT[i] * ((double)CV[i][1] * Ny + (double)CV[i][2] * Nz);
+  }
+}
+template <class T>
+void zouhe_inlet(T f[Q], double ux, double uy, double uz) {
+  T s0 = 0, sm = 0;
+  for (int i = 0; i < Q; ++i) {
+    if (CV[i][0] == 0) s0 += f[i];
+    if (CV[i][0] == -1) sm += f[i];
+  }
+  zouhe_face(f, 1, (s0 + 2.0 * sm) / (1.0 - ux), T(ux), T(uy), T(uz));
+}
+template <class T>
+void zouhe_outlet(T f[Q], double rho_out) {
+  T s0 = 0, sp = 0;
+  for (int i = 0; i < Q; ++i) {
+    if (CV[i][0] == 0) s0 += f[i];
+    if (CV[i][0] == 1) sp += f[i];
+  }
+  T ux = (s0 + 2.0 * sp) / rho_out - 1.0;
+  zouhe_face(f, -1, T(rho_out), ux, T(0.0), T(0.0));
+}
+#else
 template <class T>
 void zouhe_inlet(T f[Q], double ux, double uy, double uz) {
   T s0 = 0, sm = 0, sy = 0, sz = 0;
@@ -327,6 +384,7 @@ void zouhe_outlet(T f[Q], double rho_out) {
     else f[i] = f[o] - rho_out * ux / 6.0 - (double)cz * Nz;
   }
 }
+#endif
 
 // Everything one cell computes in one step.
 template <class T>
@@ -783,7 +841,7 @@ void oracle_grad_dual(void* h, int T, int tb, int te, const int64_t* boxcells, i
 // is taken with 39-component dual numbers and its transpose applied to the
 // output adjoints; the streaming transpose gathers along +c_i.
 void oracle_grad_reverse(void* h, int T, int tb, int te, int ckpt, double* J, double* grad_box, int kind) {
-  const int NI = 39;
+  const int NI = 2 * Q + 1;
   typedef Dual<NI> D;
   Ctx* C = (Ctx*)h;
   const int64_t nf = C->nf;
@@ -829,11 +887,11 @@ void oracle_grad_reverse(void* h, int T, int tb, int te, int ckpt, double* J, do
         // seed inputs
         D fl[Q], phit[Q], phx, omp;
         for (int i = 0; i < Q; ++i) { fl[i] = D(fs[i * nf + x]); fl[i].d[i] = 1.0; }
-        omp = D(os[x]); omp.d[19] = 1.0;
-        phx = D(ph[x]); phx.d[20] = 1.0;
+        omp = D(os[x]); omp.d[Q] = 1.0;
+        phx = D(ph[x]); phx.d[Q + 1] = 1.0;
         for (int i = 0; i < Q; ++i) {
           int nb = C->nbr[i * nf + x];
-          if (i > 0 && nb >= 0) { phit[i] = D(ph[nb]); phit[i].d[20 + i] = 1.0; }
+          if (i > 0 && nb >= 0) { phit[i] = D(ph[nb]); phit[i].d[Q + 1 + i] = 1.0; }
           else phit[i] = phx;
         }
         // open-face fill (inside the local map)
@@ -863,9 +921,9 @@ void oracle_grad_reverse(void* h, int T, int tb, int te, int ckpt, double* J, do
           g[k] = s2;
         }
         for (int i = 0; i < Q; ++i) fh_new[i * nf + x] = g[i];
-        oh_new[x] = g[19];
-        phh[x] += g[20];
-        for (int i = 1; i < Q; ++i) nbcontrib[i * nf + x] = g[20 + i];
+        oh_new[x] = g[Q];
+        phh[x] += g[Q + 1];
+        for (int i = 1; i < Q; ++i) nbcontrib[i * nf + x] = g[Q + 1 + i];
       }
       // scatter neighbour-porosity adjoints (serial: plain and race-free)
       for (int64_t x = 0; x < nf; ++x)
@@ -890,5 +948,6 @@ void oracle_grad_reverse(void* h, int T, int tb, int te, int ckpt, double* J, do
 }
 
 int oracle_threads(void) { return omp_get_max_threads(); }
+int oracle_q(void) { return Q; }
 
 }  // extern "C"

@@ -17,6 +17,7 @@ from .cases import (  # noqa: F401
     fd_voxels,
     sampled_waveform,
     aniso_shape,
+    as_d3q27,
     with_anisotropic_drag,
     CONFIGS,
     make_config,

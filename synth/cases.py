@@ -64,6 +64,7 @@ class Case:
         default_factory=lambda: dict(nu_d=0.1, kc=180.0, d=2.0, forchheimer=0, g=(0.0, 0.0, 0.0)))
     steps: int = 0
     extra: Dict[str, object] = dataclasses.field(default_factory=dict)
+    lattice: int = 19  # velocity set: 19 (D3Q19) or 27 (D3Q27, the paper's)
 
     @property
     def n_box(self) -> int:
@@ -351,6 +352,13 @@ def tiny_case(kind: str = "open", seed: int = 0, nx: int = 9, ny: int = 7, nz: i
         raise ValueError(kind)
     case.phi = np.where(case.solid == 0, case.phi, 0.0).astype(np.float32)
     case.sac = case.sac & (case.solid == 0)
+    return case
+
+
+def as_d3q27(case: Case) -> Case:
+    """The same case on the D3Q27 velocity set."""
+    case.lattice = 27
+    case.name = case.name + "_q27"
     return case
 
 

@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 from oracle import bruteforce as bf
-from synth import channel_case, tiny_case
+from synth import as_d3q27, channel_case, tiny_case
 
 
 def _random_state(o, seed, amp=0.1):
@@ -19,20 +19,25 @@ def _random_state(o, seed, amp=0.1):
 
 
 def _dense(case, cells, f, om):
-    fd = np.zeros((19, case.n_box))
+    q = f.shape[0]
+    fd = np.zeros((q, case.n_box))
     fd[:, cells] = f
     od = np.zeros(case.n_box)
     od[cells] = om
-    return fd.reshape(19, case.nz, case.ny, case.nx), od.reshape(case.nz, case.ny, case.nx)
+    return fd.reshape(q, case.nz, case.ny, case.nx), od.reshape(case.nz, case.ny, case.nx)
 
 
-@pytest.mark.parametrize("kind", ["open", "open_wave", "open_extrap", "periodic", "periodic_aniso", "periodic3"])
+@pytest.mark.parametrize("kind", ["open", "open_wave", "open_extrap", "periodic", "periodic_aniso", "periodic3",
+                                  "open_q27", "open_extrap_q27", "periodic_q27", "periodic3_q27"])
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_matches_dense_bruteforce(kind, seed):
     """Compact-list C++ oracle vs dense-array NumPy transcription: 1 and 10 steps
     from a random non-equilibrium state with walls, open faces, periodic wrap and
-    heterogeneous porosity."""
-    case = tiny_case(kind, seed=seed)
+    heterogeneous porosity, on D3Q19 and D3Q27."""
+    q27 = kind.endswith("_q27")
+    case = tiny_case(kind[:-4] if q27 else kind, seed=seed)
+    if q27:
+        case = as_d3q27(case)
     o = oracle.Oracle(case)
     cells = o.cells()
     f, om = _random_state(o, seed)
@@ -41,12 +46,12 @@ def test_matches_dense_bruteforce(kind, seed):
     f1, o1 = f.copy(), om.copy()
     o.run(f1, o1, t0, 1)
     fd1, od1, _ = bf.step(case, fd, od, t0)
-    assert np.abs(fd1.reshape(19, -1)[:, cells] - f1).max() < 1e-14
+    assert np.abs(fd1.reshape(fd1.shape[0], -1)[:, cells] - f1).max() < 1e-14
     assert np.abs(od1.reshape(-1)[cells] - o1).max() < 1e-13
     o.run(f1, o1, t0 + 1, 9)
     for s in range(1, 10):
         fd1, od1, _ = bf.step(case, fd1, od1, t0 + s)
-    assert np.abs(fd1.reshape(19, -1)[:, cells] - f1).max() < 1e-13
+    assert np.abs(fd1.reshape(fd1.shape[0], -1)[:, cells] - f1).max() < 1e-13
     # moments of the state agree too
     m = o.moments(f1, o1, t0 + 10)
     _, _, fields = bf.step(case, fd1, od1, t0 + 10)
@@ -54,12 +59,16 @@ def test_matches_dense_bruteforce(kind, seed):
     assert np.abs(fields["shear"].reshape(-1)[cells] - m["shear"]).max() < 1e-12
 
 
-@pytest.mark.parametrize("kind", ["open", "open_extrap", "periodic"])
+@pytest.mark.parametrize("kind", ["open", "open_extrap", "periodic", "open_q27", "periodic_q27"])
 def test_rest_state_is_stationary(kind):
     """Fluid at rest with heterogeneous porosity, walls and (zero-velocity)
     open faces stays at rest: the porosity-jump term, the porosity-shifted
     equilibrium and bounce-back are mutually consistent."""
+    q27 = kind.endswith("_q27")
+    kind = kind[:-4] if q27 else kind
     case = tiny_case(kind, seed=3)
+    if q27:
+        case = as_d3q27(case)
     case.porous = dict(case.porous, g=(0.0, 0.0, 0.0))
     case.wave = (0.0, 0.0, 1.0)
     if kind == "open_extrap":
@@ -76,8 +85,10 @@ def test_rest_state_is_stationary(kind):
     assert np.abs(m["rho"] - 1).max() < 1e-14
 
 
-def test_mass_exact_for_uniform_porosity():
+@pytest.mark.parametrize("q", [19, 27])
+def test_mass_exact_for_uniform_porosity(q):
     case = tiny_case("periodic", seed=4)
+    case.lattice = q
     case.phi = np.where(case.solid == 0, 0.8, 0.0).astype(np.float32)
     o = oracle.Oracle(case)
     f, om = _random_state(o, 4)
@@ -107,17 +118,19 @@ def test_mass_budget_heterogeneous_porosity():
         assert abs(f.sum() - before - (rho * jump).sum()) < 1e-15 * before
 
 
-def test_momentum_gain_equals_body_force():
+@pytest.mark.parametrize("q", [19, 27])
+def test_momentum_gain_equals_body_force(q):
     """Periodic box without walls, porosity 1: total momentum grows by
     g * sum_x rho(x) per step."""
     case = channel_case(6, g=3e-5)
+    case.lattice = q
     case.solid[:] = 0
     case.periodic = (True, True, True)
     case.phi = np.ones(case.phi.shape, np.float32)
     case.porous = dict(case.porous, g=(3e-5, -1e-5, 2e-5))
     o = oracle.Oracle(case)
     f, om = _random_state(o, 6, amp=0.05)
-    c, _ = oracle.lattice()
+    c, _ = oracle.lattice(q)
     g = np.array(case.porous["g"])
     for t in range(10):
         rho = o.moments(f, om, t)["rho"]
