@@ -33,7 +33,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak
 # algorithmic bytes per fluid-cell update: populations read + written, porosity,
 # relaxation rate read + written
-B_ALG = {"fp32": 164, "fp16": 88, "bf16": 88, "fp32_aniso": 164, "fp16_aniso": 88}
+B_ALG = {"fp32": 164, "fp16": 88, "bf16": 88, "fp32_aniso": 164, "fp16_aniso": 88,
+         # D3Q27: 27 populations read + written
+         "fp32_q27": 27 * 8 + 12, "fp16_q27": 27 * 4 + 12, "bf16_q27": 27 * 4 + 12}
 # the adjoint call per fluid cell and time step: forward pass (164), recompute
 # with the record written (164 + 19*4 pulled values + omega_prev 4 + rho 4 = 248)
 # and the reverse step (record 80, adjoint populations gathered 76 and written
@@ -148,7 +150,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--config", default="c2")
-    ap.add_argument("--forms", default="fp16,bf16,fp32_aniso,adjoint")
+    ap.add_argument("--forms", default="fp16,bf16,fp32_aniso,fp32_q27,fp16_q27,adjoint")
     ap.add_argument("--adj-T", type=int, default=400)
     ap.add_argument("--adj-ckpt", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
@@ -190,7 +192,12 @@ def main():
         log(f"[bench] adjoint: {dt * 1e3:.1f} ms, {mlups:.0f} M cell-steps/s, {gbs:.0f} GB/s algorithmic")
     for form in forms:
         storage = form.split("_")[0]
-        if form.endswith("_aniso"):
+        if form.endswith("_q27"):
+            import copy
+
+            from synth import as_d3q27
+            s = Solver.from_case(as_d3q27(copy.copy(case)), storage=storage)
+        elif form.endswith("_aniso"):
             # the Remark's anisotropic drag: Forchheimer on, 6 fixed-point iterations
             import copy
 

@@ -32,6 +32,11 @@
  *   - D3Q19 directions in the order: rest; +x, -x, +y, -y, +z, -z;
  *     (+1,+1,0), (-1,-1,0), (+1,-1,0), (-1,+1,0); (+1,0,+1), (-1,0,-1),
  *     (+1,0,-1), (-1,0,+1); (0,+1,+1), (0,-1,-1), (0,+1,-1), (0,-1,+1).
+ *     D3Q27 continues with the corners (+1,+1,+1), (-1,-1,-1), (+1,+1,-1),
+ *     (-1,-1,+1), (+1,-1,+1), (-1,+1,-1), (-1,+1,+1), (+1,-1,-1).  Arrays
+ *     "[19]" below hold 27 entries on D3Q27.  On D3Q27 the storage unit U is
+ *     216 (216 * 2^9 for FP16) and the Zou-He faces use a weight-proportional
+ *     transverse correction that reduces to the D3Q19 closure.
  *   - "Host" pointers are ordinary CPU memory; "device" pointers are HIP
  *     device memory (e.g. a torch tensor's data_ptr()).
  *
@@ -101,6 +106,8 @@ typedef struct {
                           1: stored value f_i - w_i */
   int arith;           /* lbm_arith: AUTO = projected FP32 with FP32 storage, FP32 with
                           FP16/BF16 storage; FP64 is only available with FP32 storage */
+  int velocity_set;    /* 19 (or 0): D3Q19; 27: D3Q27, the method section's lattice (weights
+                          8/27, 2/27, 1/54, 1/216; no adjoint, no anisotropic permeability) */
 } lbm_grid;
 
 /* Carreau-Yasuda law (eq. carreau) in kinematic lattice units:

@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "step.hpp"
+#include "step27.hpp"
 #include "adjoint.hpp"
 
 using namespace lbm;
@@ -40,7 +41,12 @@ size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 size_t store_bytes(int storage) { return storage == LBM_STORE_FP32 ? 4 : 2; }
 // Storage unit U: stored value = U (f - rest).  36 w_i is an integer; FP16 adds
 // 2^10 so that typical deviations sit in the normal range.
-double storage_unit(int storage) { return storage == LBM_STORE_FP16 ? 36.0 * 1024.0 : 36.0; }
+// (2^9 on D3Q27, whose rest weight is larger relative to U.)
+double storage_unit(int storage, int q) {
+  if (q == 27) return storage == LBM_STORE_FP16 ? 216.0 * 512.0 : 216.0;
+  return storage == LBM_STORE_FP16 ? 36.0 * 1024.0 : 36.0;
+}
+int qof(const lbm_grid& g) { return g.velocity_set == 27 ? 27 : 19; }
 
 struct Layout {
   size_t A, code, links, phi, omega, delta, shape, rowbox, stage, part, diag, obj, tc, wave, side;
@@ -100,22 +106,23 @@ Layout make_layout(const lbm_grid& g, int64_t nc, int64_t nrow, int T, int ckpt)
   const size_t ss = store_bytes(g.storage);
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
-  L.A = take(Q * (size_t)nc * ss);
+  const int q = qof(g);
+  L.A = take((size_t)q * (size_t)nc * ss);
   L.code = take((size_t)nc * 4);
-  L.links = take((size_t)nc * 4);
+  L.links = take((size_t)nc * (q == 27 ? 8 : 4));
   L.phi = take((size_t)nc * 4);
   L.omega = take((size_t)nc * 4);
   L.delta = take((size_t)nrow * 8 * 4);
   L.shape = take((size_t)nrow * 4);
   L.rowbox = take((size_t)nrow * 4);
-  L.stage = take((size_t)(Q + 1) * nc * 4);
+  L.stage = take((size_t)(q + 1) * nc * 4);
   const size_t nbmax = (size_t)blocks_for_nt(nc, STEP_NT_MIN);  // most blocks any launch uses
   L.part = take(nbmax * NDIAGP * 8);
   L.diag = take(64 * 8);
   L.obj = take(nbmax * 8);
   L.tc = take(2 * sizeof(uint32_t));
   L.wave = take(MAX_WAVE_TABLE * sizeof(double));
-  L.side = take((size_t)2 * nrow * 10 * sizeof(float));
+  L.side = take((size_t)2 * nrow * (q == 27 ? 18 : 10) * sizeof(float));
   L.T = T;
   L.ckpt = ckpt;
   if (T > 0) {
@@ -234,6 +241,7 @@ struct lbm_ctx {
   int sblk = 0;                   // blocks of the step kernel
   int64_t nreg = 0;
   int64_t nwss = 0;               // region cells on the wall (with a wall normal)
+  int q = 19;                     // velocity set
   double U = 36.0;
   Rows rows;
   std::vector<int64_t> fluid_box; // box index per fluid cell (ascending)
@@ -299,6 +307,8 @@ lbm_status validate_grid(const lbm_grid* g) {
   if (g->arith < 0 || g->arith > 2) return fail(LBM_E_INVALID, "unknown arithmetic mode");
   if (g->arith == LBM_ARITH_FP64 && g->storage != LBM_STORE_FP32)
     return fail(LBM_E_INVALID, "FP64 arithmetic is only available with FP32 storage");
+  if (g->velocity_set != 0 && g->velocity_set != 19 && g->velocity_set != 27)
+    return fail(LBM_E_INVALID, "velocity_set must be 19 or 27");
   return LBM_OK;
 }
 
@@ -306,9 +316,10 @@ lbm_status validate_grid(const lbm_grid* g) {
 // population planes (also the FP32 adjoint planes) and the position code.
 lbm_status check_rows(const lbm_grid* g, const Rows& r) {
   if (r.nf == 0) return fail(LBM_E_INVALID, "no fluid cell");
-  if ((double)r.nc * Q * 4.0 >= 4294967296.0)
-    return fail(LBM_E_INVALID, "more than 56.5 M compact cells (kernels address the population planes with "
-                               "32-bit byte offsets)");
+  if ((double)r.nc * qof(*g) * 4.0 >= 4294967296.0)
+    return fail(LBM_E_INVALID, std::string("more than ") + (qof(*g) == 27 ? "39.7" : "56.5") +
+                                   " M compact cells (kernels address the population planes with 32-bit byte "
+                                   "offsets)");
   const int xb = xbits_for(g->nx);
   if ((uint64_t)r.y.size() >= ((uint64_t)1 << (32 - xb)))
     return fail(LBM_E_INVALID, "too many fluid rows for the 32-bit position code");
@@ -389,6 +400,81 @@ int64_t build_links(const lbm_ctx* c, const std::vector<float>& phib, std::vecto
   return nwss;
 }
 
+// The 64-bit link words of the D3Q27 kernels (layout in step27.hpp); returns
+// the number of region cells on the wall.
+int64_t build_links27(const lbm_ctx* c, const std::vector<float>& phib, std::vector<uint64_t>& links) {
+  namespace L = q27;
+  const int nx = c->grid.nx, ny = c->grid.ny, nz = c->grid.nz;
+  const int per[3] = {c->grid.periodic[0] != 0, c->grid.periodic[1] != 0, c->grid.periodic[2] != 0};
+  const int dims[3] = {nx, ny, nz};
+  int64_t nwss = 0;
+  links.assign(c->nc, L::L_DEAD);
+  for (int64_t k = 0; k < c->nf; ++k) {
+    const int64_t b = c->fluid_box[k];
+    const int X[3] = {(int)(b % nx), (int)((b / nx) % ny), (int)(b / ((int64_t)nx * ny))};
+    uint64_t lk = 0;
+    bool uni = true;
+    const float ph = phib[b];
+    uint64_t unk = 0;
+    int m[3] = {0, 0, 0};
+    for (int i = 1; i < L::Q; ++i) {
+      const int cv[3] = {L::CX[i], L::CY[i], L::CZ[i]};
+      for (int sgn = -1; sgn <= 1; sgn += 2) {  // -1: pull source x - c_i; +1: neighbour x + c_i
+        int sidx[3];
+        bool out = false, out_yz = false;
+        for (int a = 0; a < 3; ++a) {
+          sidx[a] = X[a] + sgn * cv[a];
+          if (sidx[a] < 0 || sidx[a] >= dims[a]) {
+            if (per[a]) sidx[a] = (sidx[a] + dims[a]) % dims[a];
+            else { out = true; if (a > 0) out_yz = true; }
+          }
+        }
+        const int64_t sb = out ? -1 : (int64_t)sidx[0] + (int64_t)nx * ((int64_t)sidx[1] + (int64_t)ny * sidx[2]);
+        const bool wall = out || c->solid[sb];
+        if (sgn < 0) {
+          if (wall) lk |= 1ull << i;
+          const bool open = out && !out_yz && c->openface[k];
+          if (open) {
+            const int* xs = c->openface[k] == 1 ? L::XIN : L::XOUT;
+            for (int j = 0; j < L::NX; ++j)
+              if (xs[j] == i) unk |= 1ull << j;
+          }
+          if (wall && !open)
+            for (int a = 0; a < 3; ++a) m[a] -= L::kw(i) * cv[a];
+        } else if (!wall && phib[sb] != ph) {
+          uni = false;
+        }
+      }
+    }
+    if (uni) lk |= L::L_UNI;
+    if (c->openface[k] == 1) lk |= L::L_IN;
+    if (c->openface[k] == 2) lk |= L::L_OUT;
+    if (c->P.outlet == 2 && X[0] == nx - 2 && !c->solid[b + 1]) lk |= L::L_UPS;
+    if (c->region_f[k]) lk |= L::L_REG;
+    lk |= unk << L::L_UNK;
+    links[c->fluid_c[k]] = lk;
+    if (c->region_f[k] && (m[0] | m[1] | m[2]) != 0) ++nwss;
+  }
+  return nwss;
+}
+
+q27::Bufs27 bufs27(lbm_ctx* c) {
+  q27::Bufs27 b{};
+  b.A = c->ws + c->L.A;
+  b.code = (const uint32_t*)(c->ws + c->L.code);
+  b.links = (const uint64_t*)(c->ws + c->L.links);
+  b.delta = (const int*)(c->ws + c->L.delta);
+  b.phi = (const float*)(c->ws + c->L.phi);
+  b.omega = (float*)(c->ws + c->L.omega);
+  b.shape = (const float*)(c->ws + c->L.shape);
+  b.rowbox = (const uint32_t*)(c->ws + c->L.rowbox);
+  b.part = (double*)(c->ws + c->L.part);
+  b.tc = (uint32_t*)(c->ws + c->L.tc);
+  b.wave = (const double*)(c->ws + c->L.wave);
+  b.side = (float*)(c->ws + c->L.side);
+  return b;
+}
+
 // Upload the porosity and the link words (which depend on it).
 lbm_status upload_phi(lbm_ctx* c, const float* phi) {
   std::vector<float> box(c->nbox, 0.0f), comp(c->nc, 0.0f);
@@ -400,9 +486,15 @@ lbm_status upload_phi(lbm_ctx* c, const float* phi) {
     c->phi_f[k] = v;
   }
   std::vector<uint32_t> links;
-  c->nwss = build_links(c, box, links);
+  std::vector<uint64_t> links64;
+  if (c->q == 27) c->nwss = build_links27(c, box, links64);
+  else c->nwss = build_links(c, box, links);
   HIP_TRY(c, hipMemcpyAsync(c->ws + c->L.phi, comp.data(), comp.size() * 4, hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(c->ws + c->L.links, links.data(), links.size() * 4, hipMemcpyHostToDevice, c->stream));
+  if (c->q == 27)
+    HIP_TRY(c, hipMemcpyAsync(c->ws + c->L.links, links64.data(), links64.size() * 8, hipMemcpyHostToDevice,
+                              c->stream));
+  else
+    HIP_TRY(c, hipMemcpyAsync(c->ws + c->L.links, links.data(), links.size() * 4, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return LBM_OK;
 }
@@ -411,14 +503,18 @@ lbm_status launch_init(lbm_ctx* c) {
   Bufs b = bufs(c);
   with_storage(c->grid.storage, c->grid.shift_mode, [&](auto tag, auto shw) {
     using S = typename decltype(tag)::T;
-    hipLaunchKernelGGL((k_init<S, decltype(shw)::value>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b,
-                       c->omega0);
+    if (c->q == 27)
+      hipLaunchKernelGGL((q27::k_init<S, decltype(shw)::value>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P,
+                         bufs27(c), c->omega0);
+    else
+      hipLaunchKernelGGL((k_init<S, decltype(shw)::value>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b,
+                         c->omega0);
   });
   HIP_TRY(c, hipGetLastError());
   // extrapolation outflow: the kept values of the rest state (phi = 1 on the
   // outflow cells, so w_i, i.e. deviation 0; the -x neighbour's values are
   // those the rest state's outflow populations extrapolate from)
-  HIP_TRY(c, hipMemsetAsync(b.side, 0, (size_t)2 * c->nrow * 10 * sizeof(float), c->stream));
+  HIP_TRY(c, hipMemsetAsync(b.side, 0, (size_t)2 * c->nrow * (c->q == 27 ? 18 : 10) * sizeof(float), c->stream));
   c->t = 0;
   return LBM_OK;
 }
@@ -432,7 +528,30 @@ void with_parity(int64_t t, Fn&& fn) {
 // region kinetic energy, 3 region wall shear stress, accumulated into the
 // objective partials.  rec: record the
 // step for the adjoint (FP32, shift mode 0 only).
+lbm_status launch_step27(lbm_ctx* c, int diag) {
+  const q27::Bufs27 b = bufs27(c);
+  with_config(c->grid.storage, c->grid.shift_mode, c->amode, [&](auto tag, auto shw, auto rt) {
+    using S = typename decltype(tag)::T;
+    using R = typename decltype(rt)::T;
+    constexpr bool PJ = decltype(rt)::proj;
+    constexpr bool SH = decltype(shw)::value;
+    constexpr int NT = std::is_same<S, float>::value ? 256 : 64;
+    const dim3 grid(c->sblk), block(NT);
+    with_parity(c->t, [&](auto odd) {
+      constexpr bool OD = decltype(odd)::value;
+      if (diag == 0)
+        hipLaunchKernelGGL((q27::k_step<S, SH, OD, 0, R, PJ, NT>), grid, block, 0, c->stream, c->P, b);
+      else
+        hipLaunchKernelGGL((q27::k_step<S, SH, OD, 1, R, PJ, NT>), grid, block, 0, c->stream, c->P, b);
+    });
+  });
+  HIP_TRY(c, hipGetLastError());
+  c->t += 1;
+  return LBM_OK;
+}
+
 lbm_status launch_step(lbm_ctx* c, int diag, float* rec, float* rho_rec) {
+  if (c->q == 27) return launch_step27(c, diag);
   Bufs b = bufs(c);
   if (diag >= 2) b.part = (double*)(c->ws + c->L.obj);
   if (rec) {
@@ -509,6 +628,16 @@ lbm_status moments_launch(lbm_ctx* c, bool diag, float* rho, float* u, float* sh
     constexpr bool SH = decltype(shw)::value;
     with_parity(c->t, [&](auto odd) {
       constexpr bool OD = decltype(odd)::value;
+      if (c->q == 27) {
+        const q27::Bufs27 b27 = bufs27(c);
+        if (diag)
+          hipLaunchKernelGGL((q27::k_moments<S, SH, OD, true, R>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P,
+                             b27, t, c->nbox, rho, u, shear, omega, sigma, tau);
+        else
+          hipLaunchKernelGGL((q27::k_moments<S, SH, OD, false, R>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P,
+                             b27, t, c->nbox, rho, u, shear, omega, sigma, tau);
+        return;
+      }
       const bool an = c->P.an_iters > 0;
       if (diag && an)
         hipLaunchKernelGGL((k_moments<S, SH, OD, true, R, true>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b,
@@ -535,8 +664,12 @@ lbm_status gather_state(lbm_ctx* c, float* dst) {
   with_storage(c->grid.storage, 0, [&](auto tag, auto) {
     using S = typename decltype(tag)::T;
     with_parity(c->t, [&](auto odd) {
-      hipLaunchKernelGGL((k_gather_state<S, decltype(odd)::value>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P,
-                         b, dst);
+      if (c->q == 27)
+        hipLaunchKernelGGL((q27::k_gather_state<S, decltype(odd)::value>), dim3(c->nblk), dim3(BLOCK), 0, c->stream,
+                           c->P, bufs27(c), dst);
+      else
+        hipLaunchKernelGGL((k_gather_state<S, decltype(odd)::value>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P,
+                           b, dst);
     });
   });
   HIP_TRY(c, hipGetLastError());
@@ -549,8 +682,12 @@ lbm_status scatter_state(lbm_ctx* c, const float* src) {
   with_storage(c->grid.storage, 0, [&](auto tag, auto) {
     using S = typename decltype(tag)::T;
     with_parity(c->t, [&](auto odd) {
-      hipLaunchKernelGGL((k_scatter_state<S, decltype(odd)::value>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P,
-                         b, src);
+      if (c->q == 27)
+        hipLaunchKernelGGL((q27::k_scatter_state<S, decltype(odd)::value>), dim3(c->nblk), dim3(BLOCK), 0, c->stream,
+                           c->P, bufs27(c), src);
+      else
+        hipLaunchKernelGGL((k_scatter_state<S, decltype(odd)::value>), dim3(c->nblk), dim3(BLOCK), 0, c->stream,
+                           c->P, b, src);
     });
   });
   HIP_TRY(c, hipGetLastError());
@@ -558,7 +695,7 @@ lbm_status scatter_state(lbm_ctx* c, const float* src) {
 }
 
 double rest_value(const lbm_ctx* c, int i, int64_t k) {
-  const double w = i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+  const double w = c->q == 27 ? q27::kw(i) / 216.0 : (i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0));
   return w * (c->grid.shift_mode ? 1.0 : c->phi_f[k]);
 }
 
@@ -599,6 +736,8 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* solid, const float* p
   bool aniso = false;
   double an_inv[6] = {0}, an_ih[6] = {0};
   for (int k = 0; k < 6; ++k) aniso = aniso || po->aniso[k] != 0.0;
+  if (aniso && grid->velocity_set == 27)
+    return fail(LBM_E_INVALID, "anisotropic permeability is built for D3Q19 only");
   if (aniso) {
     if (po->aniso_iters < 1 || po->aniso_iters > 64) return fail(LBM_E_INVALID, "aniso_iters must lie in [1, 64]");
     if (!aniso_shape(po->aniso, an_inv, an_ih))
@@ -634,7 +773,8 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* solid, const float* p
   c->nbox = (size_t)grid->nx * grid->ny * grid->nz;
   c->solid.assign(solid, solid + c->nbox);
   c->stream = (hipStream_t)stream;
-  c->U = storage_unit(grid->storage);
+  c->q = qof(*grid);
+  c->U = storage_unit(grid->storage, c->q);
   c->nf = rows.nf;
   c->nc = rows.nc;
   c->nrow = nrow;
@@ -695,11 +835,11 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* solid, const float* p
   P.outlet = op ? op->outlet : 0;
   P.nrow = (int)nrow;
   P.xbits = xb;
-  for (int i = 0; i < Q; ++i) P.plb[i] = (uint32_t)((size_t)i * c->nc * store_bytes(grid->storage));
-  P.abytes = (uint32_t)((size_t)Q * c->nc * store_bytes(grid->storage));
+  for (int i = 0; i < c->q; ++i) P.plb[i] = (uint32_t)((size_t)i * c->nc * store_bytes(grid->storage));
+  P.abytes = (uint32_t)((size_t)c->q * c->nc * store_bytes(grid->storage));
   {
     Params::K<double> k{};
-    k.U = c->U; k.iU = 1.0 / c->U; k.ks = c->U / 36.0;
+    k.U = c->U; k.iU = 1.0 / c->U; k.ks = c->U / (c->q == 27 ? 216.0 : 36.0);  // U w_i = ks * (integer weight)
     k.nu0 = rh->nu0; k.nu_inf = rh->nu_inf; k.dnu = rh->nu0 - rh->nu_inf;
     k.lam = rh->lambda; k.cy_e = (rh->n - 1.0) / rh->a; k.cy_a = rh->a;
     k.nu_d = po->nu_darcy; k.kcd = po->kc / (po->d * po->d);
@@ -806,11 +946,12 @@ lbm_status lbm_get_state(lbm_ctx* c, double* f, float* omega) {
   if (f) {
     lbm_status s = gather_state(c, stage);
     if (s != LBM_OK) return s;
-    std::vector<float> h(Q * nc);
+    const int q = c->q;
+    std::vector<float> h(q * nc);
     HIP_TRY(c, hipMemcpyAsync(h.data(), stage, h.size() * 4, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     const double iU = 1.0 / c->U;
-    for (int i = 0; i < Q; ++i)
+    for (int i = 0; i < q; ++i)
       for (size_t k = 0; k < nf; ++k) {
         const float v = h[i * nc + c->fluid_c[k]];
         f[i * nf + k] = std::isnan(v) ? 0.0 : (double)v * iU + rest_value(c, i, (int64_t)k);
@@ -831,8 +972,9 @@ lbm_status lbm_set_state(lbm_ctx* c, const double* f, const float* omega) {
   float* stage = (float*)(c->ws + c->L.stage);
   const size_t nf = (size_t)c->nf, nc = (size_t)c->nc;
   if (f) {
-    std::vector<float> h(Q * nc, 0.0f);
-    for (int i = 0; i < Q; ++i)
+    const int q = c->q;
+    std::vector<float> h(q * nc, 0.0f);
+    for (int i = 0; i < q; ++i)
       for (size_t k = 0; k < nf; ++k)
         h[i * nc + c->fluid_c[k]] = (float)((f[i * nf + k] - rest_value(c, i, (int64_t)k)) * c->U);
     HIP_TRY(c, hipMemcpyAsync(stage, h.data(), h.size() * 4, hipMemcpyHostToDevice, c->stream));

@@ -68,7 +68,7 @@ struct Params {
   int px;                      // periodic x
   int inlet, outlet;           // outlet: 1 constant density, 2 extrapolation
   int xbits;                   // code = (row << xbits) | x
-  uint32_t plb[Q];             // byte offset of population plane i (i * nc * sizeof(storage))
+  uint32_t plb[27];            // byte offset of population plane i (i * nc * sizeof(storage)), i < Q of the set
   uint32_t abytes;             // byte size of the population buffer
   int cy_a2;                   // a == 2: (lambda g)^a is one multiply
   int forch;                   // Forchheimer drag on
@@ -444,9 +444,11 @@ struct Macro {
 // K^-1 and B = (phi^2 C_F / 2) K^-1/2, iterated an_iters times from u_0 = v
 // (each iterate one symmetric 3x3 solve by the adjugate), and the drag is
 // the tensor drag -phi^2 nu K^-1 u - phi^3 C_F |u| K^-1/2 u.
+// macro_sums takes the moment sums of the cell's values (any velocity set);
+// macro forms them from the D3Q19 values.
 template <class R, bool AN = false>
-__device__ __forceinline__ void macro(const Params& p, float phx_f, const float d[Q], float omega_prev, Macro<R>& M) {
-  const Sums<R> s = moment_sums<R>(d);
+__device__ __forceinline__ void macro_sums(const Params& p, float phx_f, const Sums<R>& s, float omega_prev,
+                                           Macro<R>& M) {
   const auto& kc = p.k<R>();
   const R phx = (R)phx_f;
   const R one = (R)1;
@@ -546,6 +548,10 @@ __device__ __forceinline__ void macro(const Params& p, float phx_f, const float 
   M.ux = ux; M.uy = uy; M.uz = uz; M.uu = uu;
   M.Fx = Fx; M.Fy = Fy; M.Fz = Fz;
   M.shear = shear;
+}
+template <class R, bool AN = false>
+__device__ __forceinline__ void macro(const Params& p, float phx_f, const float d[Q], float omega_prev, Macro<R>& M) {
+  macro_sums<R, AN>(p, phx_f, moment_sums<R>(d), omega_prev, M);
 }
 
 // Wall shear stress tau = sigma n - (n . sigma n) n of a wall cell, with the

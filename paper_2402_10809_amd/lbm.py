@@ -29,7 +29,7 @@ OBJECTIVE = {"ke": 0, "wss": 1}
 
 class lbm_grid(ct.Structure):
     _fields_ = [("nx", ct.c_int), ("ny", ct.c_int), ("nz", ct.c_int), ("periodic", ct.c_int * 3),
-                ("storage", ct.c_int), ("shift_mode", ct.c_int), ("arith", ct.c_int)]
+                ("storage", ct.c_int), ("shift_mode", ct.c_int), ("arith", ct.c_int), ("velocity_set", ct.c_int)]
 
 
 class lbm_rheology(ct.Structure):
@@ -132,11 +132,12 @@ class Solver:
     inlet: None or dict(shape=(nz, ny) array, a0, a1, period[, ramp=steps][, table=FP64 samples of one period]);
     outlet: None, rho_out (constant-density outflow) or "extrapolation" (the non-reflecting outflow).
     adjoint_T/ckpt: reserve workspace for lbm_adjoint runs of up to adjoint_T steps.
+    lattice: 19 (D3Q19) or 27 (D3Q27).
     """
 
     def __init__(self, solid, phi, *, periodic=(False, False, False), storage="fp32", shift_mode=0, arith="auto",
                  region=None, rheology=None, porous=None, inlet=None, outlet=None, adjoint_T=0, ckpt=64,
-                 device=None, stream=None):
+                 lattice=19, device=None, stream=None):
         import torch
 
         self.torch = torch
@@ -153,6 +154,8 @@ class Solver:
         g.storage = STORAGE[storage]
         g.shift_mode = int(shift_mode)
         g.arith = ARITH[arith]
+        g.velocity_set = int(lattice)
+        self.q = 27 if int(lattice) == 27 else 19
         self.grid = g
         self.storage = storage
         rh = dict(nu0=0.1, nu_inf=0.01, lam=50.0, n=0.36, a=2.0) if rheology is None else rheology
@@ -208,6 +211,7 @@ class Solver:
                          ramp=getattr(case, "ramp_steps", 0), table=getattr(case, "wave_table", None))
         kind = int(getattr(case, "outlet", 0) or 0)
         outlet = "extrapolation" if kind == 2 else (case.rho_out if kind == 1 else None)
+        kw.setdefault("lattice", int(getattr(case, "lattice", 19) or 19))
         return cls(case.solid, case.phi, periodic=case.periodic, region=case.sac, rheology=case.rheology,
                    porous=case.porous, inlet=inlet, outlet=outlet, **kw)
 
@@ -265,7 +269,7 @@ class Solver:
         return dict(zip(DIAG_NAMES, out.tolist()))
 
     def get_state(self):
-        f = np.empty((19, self.n_fluid), np.float64)
+        f = np.empty((self.q, self.n_fluid), np.float64)
         om = np.empty(self.n_fluid, np.float32)
         check(lib().lbm_get_state(self.ctx, _p(f), _p(om)))
         return f, om

@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 from paper_2402_10809_amd import Solver, lbm
-from synth import channel_case, make_config, tiny_case
+from synth import as_d3q27, channel_case, make_config, tiny_case
 
 pytestmark = pytest.mark.gpu
 
@@ -49,12 +49,20 @@ def rel_l2(a, ref):
     return float(np.sqrt(((a - ref) ** 2).sum()) / np.sqrt((ref ** 2).sum()))
 
 
-@pytest.mark.parametrize("kind", ["open", "open_wave", "open_extrap", "periodic", "periodic_aniso", "periodic3"])
+def _tiny_any(kind, seed):
+    """tiny_case, with a "_q27" suffix for the D3Q27 velocity set."""
+    if kind.endswith("_q27"):
+        return as_d3q27(tiny_case(kind[:-4], seed=seed))
+    return tiny_case(kind, seed=seed)
+
+
+@pytest.mark.parametrize("kind", ["open", "open_wave", "open_extrap", "periodic", "periodic_aniso", "periodic3",
+                                  "open_q27", "open_extrap_q27", "periodic_q27", "periodic3_q27"])
 @pytest.mark.parametrize("seed", [0, 1])
 def test_one_step_from_random_state(kind, seed):
     """Every cell type (walls, open faces, periodic wrap, porosity jumps): one
-    step from a random non-equilibrium state."""
-    case = tiny_case(kind, seed=seed)
+    step from a random non-equilibrium state, on D3Q19 and D3Q27."""
+    case = _tiny_any(kind, seed)
     say(f"one step: {case.name} seed={seed} box={case.nx}x{case.ny}x{case.nz}")
     o = oracle.Oracle(case)
     f0, om0 = o.init()
@@ -192,6 +200,42 @@ def test_aneurysm_anisotropic_permeability(storage, bound_u):
     assert (eu if storage == "fp32" else el) < bound_u
 
 
+@pytest.mark.parametrize("storage,shift_mode,bound_u", [("fp32", 0, 1e-5), ("fp16", 0, 1e-3), ("bf16", 0, 2e-2)])
+def test_aneurysm_d3q27(storage, shift_mode, bound_u):
+    """The method section's D3Q27 velocity set on the 192x128x128 aneurysm,
+    1000 steps: FP32 by max-relative velocity error, the 16-bit forms by
+    relative L2, against the D3Q27 oracle."""
+    case = as_d3q27(make_config("c1"))
+    steps = 1000
+    say(f"D3Q27: aneurysm {case.nx}x{case.ny}x{case.nz}, {storage}, {steps} steps")
+    o, f, om, ref = _oracle_run(case, steps)
+    s = Solver.from_case(case, storage=storage, shift_mode=shift_mode)
+    s.step(steps)
+    g = _gpu_fields(s)
+    eu, el = max_rel(g["u"], ref["u"]), rel_l2(g["u"], ref["u"])
+    say(f"  u max-rel {eu:.3e}  u rel-L2 {el:.3e}  shear max-rel {max_rel(g['shear'], ref['shear']):.3e}  "
+        f"tau max-rel {max_rel(g['tau'], ref['tau']):.3e}")
+    assert (eu if storage == "fp32" else el) < bound_u
+    if storage == "fp32":
+        assert max_rel(g["shear"], ref["shear"]) < 1e-4 and max_rel(g["tau"], ref["tau"]) < 1e-4
+
+
+def test_d3q27_diagnostics_and_rejections():
+    case = as_d3q27(tiny_case("periodic", seed=2))
+    s = Solver.from_case(case)
+    s.step(30)
+    d = s.diagnostics()
+    o = oracle.Oracle(case)
+    f, om = o.init()
+    o.run(f, om, 0, 30)
+    c, _ = oracle.lattice(27)
+    assert abs(d["mass"] - f.sum()) < 1e-5
+    assert np.abs(np.array([d["mom_x"], d["mom_y"], d["mom_z"]]) - (f.T @ c).sum(0)).max() < 1e-6
+    assert d["nonfinite"] == 0 and d["t"] == 30
+    with pytest.raises(lbm.LBMError):
+        s.adjoint(5, 10, 10, 5)
+
+
 def test_extrapolation_outflow_multi_step_tiny():
     """200 steps on the tiny open case with the extrapolation outflow (one
     outflow cell without a fluid -x neighbour), state compared in full,
@@ -290,12 +334,12 @@ def test_state_roundtrip_and_reset():
     assert np.abs(gom0 - om0).max() < 1e-7
 
 
-@pytest.mark.parametrize("kind", ["open", "open_extrap", "periodic3"])
+@pytest.mark.parametrize("kind", ["open", "open_extrap", "periodic3", "open_q27", "open_extrap_q27"])
 @pytest.mark.parametrize("t_split", [7, 8])
 def test_restored_state_continues_trajectory(kind, t_split):
     """get_state / set_state at an odd and an even time (the two slot layouts of
     the in-place streaming) continue the uninterrupted run bit for bit."""
-    case = tiny_case(kind, seed=5)
+    case = _tiny_any(kind, 5)
     a = Solver.from_case(case)
     a.step(t_split + 5)
     fa, oa = a.get_state()
