@@ -595,7 +595,7 @@ __device__ __forceinline__ R region_wss(uint32_t lk, const Macro<R>& M) {
 // each stored value.
 template <class S, bool SHW, bool UNI, bool ODD, class R, bool PROJ>
 __device__ __forceinline__ void collide_store(const Params& p, const Pop<S>& A, uint32_t c, uint32_t lk, const Pos& q,
-                                              float phx_f, const float d[Q], const float pt[Q], const Macro<R>& M) {
+                                              float phx_f, float d[Q], const float pt[Q], const Macro<R>& M) {
   const R phx = (R)phx_f;
   const R om = M.omega;
   const R pr = phx * M.rho;
@@ -615,7 +615,13 @@ __device__ __forceinline__ void collide_store(const Params& p, const Pop<S>& A, 
   const R ev0e = ke * ev0, omCe = ke * omC, K9e = ke * K9, omBe = ke * omB, K3e = ke * K3;
   // porosity-jump term per unit weight: (rho - 1)(phi~_i - phi)
   auto jump = [&](int i) -> R { return UNI ? (R)0 : M.rm1 * ((R)pt[i] - phx); };
-  float o[Q];
+  // the projection's input momentum, taken before the outputs overwrite d[]
+  double tmx = 0.0, tmy = 0.0, tmz = 0.0;
+  if constexpr (PROJ) {
+    const Sums<double> si = moment_sums<double>(d);
+    tmx = si.mx; tmy = si.my; tmz = si.mz;
+  }
+  float* o = d;
   o[0] = (float)rfma(ks * (R)kw(0), ev0 + jump(0), keep * (R)d[0]);
   auto pair = [&](auto ic, R e, R h) {
     constexpr int I = decltype(ic)::value;
@@ -643,10 +649,9 @@ __device__ __forceinline__ void collide_store(const Params& p, const Pop<S>& A, 
   pair(std::integral_constant<int, 17>{}, M.uy - M.uz, M.Fy - M.Fz);
   if constexpr (PROJ) {
     // momentum in and out (pair differences are exact in FP64)
-    const Sums<double> si = moment_sums<double>(d);
     const Sums<double> so = moment_sums<double>(o);
     const double U = p.d.U;
-    double tx = si.mx + U * (double)M.Fx, ty = si.my + U * (double)M.Fy, tz = si.mz + U * (double)M.Fz;
+    double tx = tmx + U * (double)M.Fx, ty = tmy + U * (double)M.Fy, tz = tmz + U * (double)M.Fz;
     if (!UNI) {
       const double rm1 = (double)M.rm1, ph = (double)phx_f;
       double jx = 0.0, jy = 0.0, jz = 0.0;

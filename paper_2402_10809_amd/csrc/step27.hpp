@@ -243,7 +243,7 @@ __device__ __forceinline__ bool wall_normal(uint64_t lk, float n[3]) {
 // projection onto the axis pairs, shift mode 1 conversion).
 template <class S, bool SHW, bool UNI, bool ODD, class R, bool PROJ>
 __device__ __forceinline__ void collide_store(const Params& p, const Pop<S>& A, uint32_t c, uint64_t lk, const Pos& q,
-                                              float phx_f, const float d[Q], const float pt[Q], const Macro<R>& M) {
+                                              float phx_f, float d[Q], const float pt[Q], const Macro<R>& M) {
   const R phx = (R)phx_f;
   const R om = M.omega;
   const R pr = phx * M.rho;
@@ -255,7 +255,14 @@ __device__ __forceinline__ void collide_store(const Params& p, const Pop<S>& A, 
   const R ev0 = om * A0 - K3 * uF;
   const R omB = om * (R)3 * pr, omC = om * (R)4.5 * pr;
   const R ks = p.k<R>().ks;
-  float o[Q];
+  // the input momentum for the projection, before d[] is overwritten by the
+  // outputs (27 values kept once, not twice)
+  double tx = 0.0, ty = 0.0, tz = 0.0;
+  if constexpr (PROJ) {
+    const Sums<double> si = moment_sums<double>(d);
+    tx = si.mx; ty = si.my; tz = si.mz;
+  }
+  float* o = d;
   sfor<0, Q>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
     const R e = (R)CX[I] * M.ux + (R)CY[I] * M.uy + (R)CZ[I] * M.uz;
@@ -265,10 +272,9 @@ __device__ __forceinline__ void collide_store(const Params& p, const Pop<S>& A, 
     o[I] = (float)rfma(ks * (R)kw(I), g, keep * (R)d[I]);
   });
   if constexpr (PROJ) {
-    const Sums<double> si = moment_sums<double>(d);
     const Sums<double> so = moment_sums<double>(o);
     const double U = p.d.U;
-    double tx = si.mx + U * (double)M.Fx, ty = si.my + U * (double)M.Fy, tz = si.mz + U * (double)M.Fz;
+    tx += U * (double)M.Fx; ty += U * (double)M.Fy; tz += U * (double)M.Fz;
     if (!UNI) {
       const double rm1 = (double)M.rm1, ph = (double)phx_f;
       double jx = 0.0, jy = 0.0, jz = 0.0;
