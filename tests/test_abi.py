@@ -63,14 +63,33 @@ def test_workspace_size_and_validation():
     assert "offsets" in str(e.value)
     big[:, :, 256:] = 1
     assert lbm.lbm_workspace_size(_grid(nx=512, ny=512, nz=224), big) > 0
+    # D3Q27: 27 planes and 64-bit link words, a lower compact-cell limit (39.7 M)
+    g27 = _grid()
+    g27.velocity_set = 27
+    assert lbm.lbm_workspace_size(g27, solid) > n0
+    big27 = np.zeros((224, 512, 512), np.uint8)
+    big27[:, :, 384:] = 1  # 44 M cells: within the D3Q19 limit, beyond the D3Q27 one
+    assert lbm.lbm_workspace_size(_grid(nx=512, ny=512, nz=224), big27) > 0
+    g27b = _grid(nx=512, ny=512, nz=224)
+    g27b.velocity_set = 27
+    with pytest.raises(lbm.LBMError):
+        lbm.lbm_workspace_size(g27b, big27)
+    g23 = _grid()
+    g23.velocity_set = 23
+    with pytest.raises(lbm.LBMError):
+        lbm.lbm_workspace_size(g23, solid)
 
 
 def _create(g, solid, phi, rh=(0.1, 0.01, 50.0, 0.36, 2.0), po=(0.1, 2.0, 180.0), op=None, ws=4096,
-            ws_bytes=1 << 30):
+            ws_bytes=1 << 30, aniso=None, aniso_iters=6):
     L = lbm.lib()
     r = lbm.lbm_rheology(*rh)
     p = lbm.lbm_porous()
     p.nu_darcy, p.d, p.kc = po
+    if aniso is not None:
+        for k in range(6):
+            p.aniso[k] = aniso[k]
+        p.aniso_iters = aniso_iters
     ctx = ct.c_void_p()
     s = np.ascontiguousarray(solid, np.uint8)
     f = np.ascontiguousarray(phi, np.float32)
@@ -105,3 +124,21 @@ def test_create_rejects_bad_inputs_before_device_work():
     assert _create(g, solid, p2, op=op) == lbm.LBM_E_INVALID
     msg = lbm.lib().lbm_last_error().decode()
     assert "open-face" in msg
+    # outflow kind, ramp and waveform table
+    op2 = lbm.lbm_open()
+    op2.outlet = 3
+    assert _create(g, solid, phi, op=op2) == lbm.LBM_E_INVALID
+    op.ramp_steps = -1
+    assert _create(g, solid, phi, op=op) == lbm.LBM_E_INVALID
+    op.ramp_steps = 0
+    table = np.ones(2000, np.float64)
+    op.wave_table, op.table_len = table.ctypes.data_as(ct.c_void_p), 2000
+    assert _create(g, solid, phi, op=op) == lbm.LBM_E_INVALID
+    # anisotropic permeability: positive definite shape, 1..64 iterations, D3Q19 only
+    assert _create(g, solid, phi, aniso=(1.0, 1.0, -0.5, 0.0, 0.0, 0.0)) == lbm.LBM_E_INVALID
+    assert _create(g, solid, phi, aniso=(1.0, 1.0, 1.0, 2.0, 0.0, 0.0)) == lbm.LBM_E_INVALID
+    assert _create(g, solid, phi, aniso=(2.0, 1.0, 1.0, 0.3, 0.0, 0.0), aniso_iters=0) == lbm.LBM_E_INVALID
+    assert "aniso_iters" in lbm.lib().lbm_last_error().decode()
+    g27 = _grid()
+    g27.velocity_set = 27
+    assert _create(g27, solid, phi, aniso=(2.0, 1.0, 1.0, 0.3, 0.0, 0.0)) == lbm.LBM_E_INVALID
