@@ -127,26 +127,29 @@ def test_autograd_function_and_objective_only():
     assert s.t == 0
 
 
-def test_adjoint_full_size_against_stored_references():
+@pytest.mark.parametrize("objective", ["ke", "wss"])
+def test_adjoint_full_size_against_stored_references(objective):
     """The 128x96x96 aneurysm (37 736 fluid cells), 4000 steps, objective over
-    the last 1000, checkpoints every 64: GPU gradient vs the oracle's central
-    finite differences and dual-number derivative at 16 seeded sac voxels, and
-    vs its FP64 reverse sweep over every sac voxel (stored values written by
-    tests/golden/make_adjoint_c4.py)."""
+    the last 1000 (sac kinetic energy, or WSS over the sac's wall), checkpoints
+    every 64: GPU gradient vs the oracle's central finite differences and
+    dual-number derivative at 16 seeded sac voxels, and vs its FP64 reverse
+    sweep over every sac voxel (stored values written by
+    tests/golden/make_adjoint_c4.py [--kind wss])."""
     import json
     import os
 
     from synth import make_config
 
     gdir = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
-    with open(os.path.join(gdir, "adjoint_c4.json")) as fh:
+    stem = "adjoint_c4" if objective == "ke" else "adjoint_c4_wss"
+    with open(os.path.join(gdir, stem + ".json")) as fh:
         ref = json.load(fh)
-    g_sac_ref = np.load(os.path.join(gdir, "adjoint_c4_reverse_sac.npy"))
+    g_sac_ref = np.load(os.path.join(gdir, stem + "_reverse_sac.npy"))
     case = make_config("c4")
     T, tb, te, ck = ref["T"], ref["t_begin"], ref["t_end"], ref["ckpt"]
-    say(f"adjoint c4 ({case.n_fluid} cells): T={T} window=[{tb},{te}) ckpt={ck}")
+    say(f"adjoint ({objective}) c4 ({case.n_fluid} cells): T={T} window=[{tb},{te}) ckpt={ck}")
     s = Solver.from_case(case, adjoint_T=T, ckpt=ck)
-    J, g = s.adjoint(tb, te, T, ck)
+    J, g = s.adjoint(tb, te, T, ck, kind=objective)
     g = g.cpu().numpy().reshape(-1).astype(np.float64)
     vox = np.asarray(ref["voxels"])
     fd = np.asarray(ref["grad_fd"])
