@@ -388,6 +388,8 @@ int64_t build_links(const lbm_ctx* c, const std::vector<float>& phib, std::vecto
       }
     }
     if (uni) lk |= LK_UNI;
+    // interior: every pull source is fluid and none wraps around x
+    if ((lk & 0x7fffeu) == 0 && !(per[0] && (X[0] == 0 || X[0] == nx - 1))) lk |= LK_INR;
     if (c->openface[k] == 1) lk |= LK_IN;
     if (c->openface[k] == 2) lk |= LK_OUT;
     // -x neighbour of an extrapolation-outflow cell

@@ -38,9 +38,10 @@
 //
 // Each cell carries a link word: bit i (1..18) = the pull of direction i
 // bounces back (x - c_i is solid or outside a non-periodic face), plus flags
-// (dead slot, uniform neighbour porosity, open-face role, region, open-face
-// unknowns).  Waves whose cells all have uniform neighbour porosity skip the
-// neighbour porosity loads and the porosity-jump arithmetic.
+// (dead slot, uniform neighbour porosity, interior, open-face role, region,
+// open-face unknowns).  Waves whose cells all have uniform neighbour porosity
+// skip the neighbour porosity loads and the porosity-jump arithmetic; on odd
+// steps, waves of interior cells also skip the bounce-back address selects.
 #pragma once
 #include <type_traits>
 
@@ -55,6 +56,7 @@ constexpr uint32_t LK_OUT = 1u << 21;   // outflow cell (x = nx - 1)
 constexpr uint32_t LK_REG = 1u << 22;   // objective region
 constexpr int LK_UNK = 23;              // 5 bits: which x-directed pulls are open-face unknowns
 constexpr uint32_t LK_UPS = 1u << 28;   // -x neighbour of an extrapolation-outflow cell
+constexpr uint32_t LK_INR = 1u << 29;   // interior: no bounce-back pull, no x wrap
 // the x-directed pulls of an inflow (c_x = +1) and an outflow (c_x = -1) cell
 constexpr int XIN[5] = {1, 7, 9, 11, 13};
 constexpr int XOUT[5] = {2, 8, 10, 12, 14};
@@ -144,6 +146,7 @@ struct Pos {
   uint32_t row;
   int x, xm, xp;
   int dl[NPAIR];
+  uint32_t bo[NPAIR];  // interior cells: byte offset of (x, neighbour row k) in a plane
 };
 __device__ __forceinline__ Pos position(const Params& p, uint32_t c, uint32_t code) {
   Pos q;
@@ -159,6 +162,16 @@ __device__ __forceinline__ void load_deltas(const int* __restrict__ delta, Pos& 
   const int4 a = d4[0], b = d4[1];
   q.dl[1] = a.x; q.dl[2] = a.y; q.dl[3] = a.z; q.dl[4] = a.w;
   q.dl[5] = b.x; q.dl[6] = b.y; q.dl[7] = b.z; q.dl[8] = b.w;
+}
+// Interior cells (every pull source fluid, no x wrap): the sources of a
+// neighbour-row pair k are x - c_x in that row, so one byte offset per row,
+// (x + delta_k) * SB, serves all of them; the +-1 x shift and the plane go
+// into the wave-uniform part.  x + delta_k is itself a fluid cell of that row
+// (the pair's c_x = 0 direction pulls from it), hence non-negative.
+template <class S>
+__device__ __forceinline__ void interior_offsets(Pos& q) {
+#pragma unroll
+  for (int k = 0; k < NPAIR; ++k) q.bo[k] = (uint32_t)(q.x + q.dl[k]) * (uint32_t)sizeof(S);
 }
 // Compact index of x - c_I (valid when that cell is fluid).
 template <int I>
@@ -182,14 +195,17 @@ struct Pop {
   __amdgpu_buffer_rsrc_t r;
   __device__ __forceinline__ Pop(const void* base, uint32_t bytes)
       : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000)) {}
-  __device__ __forceinline__ float ld(uint32_t voff, uint32_t soff) const {
-    if constexpr (std::is_same<S, float>::value) {
-      return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
-    } else {
-      const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
-      return (float)__builtin_bit_cast(S, h);
-    }
+  // storage bits of one value, and their conversion to FP32
+  using Raw = typename std::conditional<std::is_same<S, float>::value, unsigned, unsigned short>::type;
+  __device__ __forceinline__ Raw ldr(uint32_t voff, uint32_t soff) const {
+    if constexpr (std::is_same<S, float>::value) return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+    else return __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
   }
+  static __device__ __forceinline__ float cvt(Raw h) {
+    if constexpr (std::is_same<S, float>::value) return __builtin_bit_cast(float, h);
+    else return (float)__builtin_bit_cast(S, h);
+  }
+  __device__ __forceinline__ float ld(uint32_t voff, uint32_t soff) const { return cvt(ldr(voff, soff)); }
   __device__ __forceinline__ void st(uint32_t voff, uint32_t soff, float v) const {
     if constexpr (std::is_same<S, float>::value) {
       __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
@@ -204,20 +220,23 @@ struct Slot {
   uint32_t v, s;
 };
 
-// Slot holding f_I(t, x) at parity ODD.
-template <int I, bool ODD, class S>
+// Slot holding f_I(t, x) at parity ODD (INR: the cell is interior, q.bo set;
+// the plane offsets are at least nc * SB, so the uniform parts stay >= 0).
+template <int I, bool ODD, class S, bool INR = false>
 __device__ __forceinline__ Slot slot_in(const Params& p, uint32_t c, uint32_t lk, const Pos& q) {
   constexpr uint32_t SB = sizeof(S);
   if (!ODD || I == 0) return {c * SB, p.plb[I]};
+  if (INR) return {q.bo[PK[I]], p.plb[OPP[I]] - (uint32_t)(CX[I] * (int)SB)};
   const bool bb = (lk >> I) & 1u;
   return {bb ? p.plb[I] + c * SB : p.plb[OPP[I]] + src_of<I>(p, q) * SB, 0u};
 }
 // Slot receiving q_I(x) at parity ODD.
-template <int I, bool ODD, class S>
+template <int I, bool ODD, class S, bool INR = false>
 __device__ __forceinline__ Slot slot_out(const Params& p, uint32_t c, uint32_t lk, const Pos& q) {
   constexpr uint32_t SB = sizeof(S);
   constexpr int J = OPP[I];
   if (!ODD || I == 0) return {c * SB, p.plb[J]};
+  if (INR) return {q.bo[PK[J]], p.plb[I] + (uint32_t)(CX[I] * (int)SB)};
   const bool wall = (lk >> J) & 1u;  // x + c_I = x - c_J is not a fluid cell
   return {wall ? p.plb[J] + c * SB : p.plb[I] + src_of<J>(p, q) * SB, 0u};
 }
@@ -225,28 +244,42 @@ __device__ __forceinline__ Slot slot_out(const Params& p, uint32_t c, uint32_t l
 // Pull: v_i(x) = f_i(t, x) (the cell's own opposite output across a wall; the
 // open-face unknowns are then replaced by the Zou-He fill).  Unless UNI, also
 // pt[j] = porosity of x + c_j (phi(x) across walls) for the producer side.
-template <class S, bool SHW, bool UNI, bool ODD>
-__device__ __forceinline__ void pull(const Params& p, const Pop<S>& A, const float* __restrict__ phi, uint32_t c,
-                                     uint32_t lk, const Pos& q, float phx, float v[Q], float pt[Q]) {
-  auto ld = [&](Slot a) { return A.ld(a.v, a.s); };
-  v[0] = ld(slot_in<0, ODD, S>(p, c, lk, q));
+// pull_raw issues the loads and keeps the storage bits; pull_cvt converts.
+template <class S, bool UNI, bool ODD, bool INR = false>
+__device__ __forceinline__ void pull_raw(const Params& p, const Pop<S>& A, const float* __restrict__ phi,
+                                         uint32_t c, uint32_t lk, const Pos& q, float phx,
+                                         typename Pop<S>::Raw r[Q], float pt[Q]) {
+  auto ld = [&](Slot a) { return A.ldr(a.v, a.s); };
+  r[0] = ld(slot_in<0, ODD, S, INR>(p, c, lk, q));
   pt[0] = phx;
   sfor<1, Q>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
     constexpr int J = OPP[I];
-    v[I] = ld(slot_in<I, ODD, S>(p, c, lk, q));
+    r[I] = ld(slot_in<I, ODD, S, INR>(p, c, lk, q));
     if (!UNI) {
-      const bool bb = (lk >> I) & 1u;
+      const bool bb = !INR && ((lk >> I) & 1u);
       pt[J] = ldo(phi, bb ? c : src_of<I>(p, q));
     } else {
       pt[J] = phx;
     }
   });
+}
+template <class S, bool SHW>
+__device__ __forceinline__ void pull_cvt(const Params& p, const typename Pop<S>::Raw r[Q], float phx, float v[Q]) {
+#pragma unroll
+  for (int i = 0; i < Q; ++i) v[i] = Pop<S>::cvt(r[i]);
   if (SHW) {
     const float s = p.f.ks * (phx - 1.0f);
 #pragma unroll
     for (int i = 0; i < Q; ++i) v[i] -= kw(i) * s;
   }
+}
+template <class S, bool SHW, bool UNI, bool ODD, bool INR = false>
+__device__ __forceinline__ void pull(const Params& p, const Pop<S>& A, const float* __restrict__ phi, uint32_t c,
+                                     uint32_t lk, const Pos& q, float phx, float v[Q], float pt[Q]) {
+  typename Pop<S>::Raw r[Q];
+  pull_raw<S, UNI, ODD, INR>(p, A, phi, c, lk, q, phx, r, pt);
+  pull_cvt<S, SHW>(p, r, phx, v);
 }
 
 // Inflow amplitude at step t, in FP64, rounded once to FP32 (the simulation
@@ -500,22 +533,22 @@ __device__ __forceinline__ void macro_sums(const Params& p, float phx_f, const S
     Fz = rho * (gz - dd * kdz - df * khz);
   } else {
     const R C0 = (R)0.5 + (R)0.25 * dark;
-    R den, fcoef;
+    // drag = phi^2 nu/k + phi^3 C_F |u|/sqrt(k); the Forchheimer part stays
+    // inside its branch (evaluated unconditionally it costs every cell the
+    // square root's correction sequence)
+    R drag = phx * dark;
     if (p.forch) {
       const R sik = rsqrt_(invk);
       const R cf = (R)1.75 * rsqrt_(iphi * iphi * iphi * (R)(1.0 / 150.0));
       const R C1 = (R)0.5 * phx * phx * cf * sik;
       const R vn = rsqrt_(vx * vx + vy * vy + vz * vz);
-      den = C0 + rsqrt_(C0 * C0 + C1 * vn);
-      fcoef = phx * phx * phx * cf * sik;        // times |u| below
+      const R iden = fast_rcp(C0 + rsqrt_(C0 * C0 + C1 * vn));
+      ux = vx * iden; uy = vy * iden; uz = vz * iden;
+      drag += phx * phx * phx * cf * sik * rsqrt_(ux * ux + uy * uy + uz * uz);
     } else {
-      den = (R)2 * C0;
-      fcoef = (R)0;
+      const R iden = fast_rcp((R)2 * C0);
+      ux = vx * iden; uy = vy * iden; uz = vz * iden;
     }
-    const R iden = fast_rcp(den);
-    ux = vx * iden; uy = vy * iden; uz = vz * iden;
-    const R uu0 = ux * ux + uy * uy + uz * uz;
-    const R drag = phx * dark + (p.forch ? fcoef * rsqrt_(uu0) : (R)0);  // phi^2 nu/k + phi^3 C_F |u|/sqrt(k)
     Fx = rho * (gx - drag * ux); Fy = rho * (gy - drag * uy); Fz = rho * (gz - drag * uz);
   }
   const R uu = ux * ux + uy * uy + uz * uz;
@@ -593,7 +626,7 @@ __device__ __forceinline__ R region_wss(uint32_t lk, const Macro<R>& M) {
 // difference to the intended momentum (input momentum + force + porosity-jump
 // momentum) onto the three axis pairs, leaving only the final rounding of
 // each stored value.
-template <class S, bool SHW, bool UNI, bool ODD, class R, bool PROJ>
+template <class S, bool SHW, bool UNI, bool ODD, class R, bool PROJ, bool INR = false>
 __device__ __forceinline__ void collide_store(const Params& p, const Pop<S>& A, uint32_t c, uint32_t lk, const Pos& q,
                                               float phx_f, float d[Q], const float pt[Q], const Macro<R>& M) {
   const R phx = (R)phx_f;
@@ -679,7 +712,7 @@ __device__ __forceinline__ void collide_store(const Params& p, const Pop<S>& A, 
   }
   sfor<0, Q>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
-    const Slot a = slot_out<I, ODD, S>(p, c, lk, q);
+    const Slot a = slot_out<I, ODD, S, INR>(p, c, lk, q);
     A.st(a.v, a.s, o[I]);
   });
 }
@@ -742,16 +775,34 @@ __device__ __forceinline__ void diag_terms(const Params& p, float phx, const flo
 }
 
 // Body of the step for one cell (UNI: the whole wave has uniform neighbour
-// porosity).
-template <class S, bool SHW, bool UNI, bool ODD, int DIAG, bool REC, class R, bool PROJ, bool AN>
-__device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32_t c, uint32_t lk, uint32_t t,
-                                          double (&dv)[NDIAGP], float& ke_reg) {
-  Pos q = position(p, c, b.code[c]);
-  if (ODD || !UNI) load_deltas(b.delta, q);
-  const float phx = ldo(b.phi, c);
-  float d[Q], pt[Q];
+// porosity; INR: every cell of the wave is interior).
+// The cell's loads (position, porosities, pulled storage bits, omega_prev),
+// issued by step_fetch and consumed by step_finish.
+template <class S>
+struct Fetched {
+  Pos q;
+  float phx, omp;
+  typename Pop<S>::Raw r[Q];
+  float pt[Q];
+};
+template <class S, bool UNI, bool ODD, bool INR>
+__device__ __forceinline__ void step_fetch(const Params& p, const Bufs& b, uint32_t c, uint32_t lk, Fetched<S>& F) {
+  F.q = position(p, c, b.code[c]);
+  if (ODD || !UNI) load_deltas(b.delta, F.q);
+  if (INR) interior_offsets<S>(F.q);
+  F.phx = ldo(b.phi, c);
+  pull_raw<S, UNI, ODD, INR>(p, Pop<S>(b.A, p.abytes), b.phi, c, lk, F.q, F.phx, F.r, F.pt);
+  F.omp = b.omega[c];
+}
+template <class S, bool SHW, bool UNI, bool ODD, int DIAG, bool REC, class R, bool PROJ, bool AN, bool INR = false>
+__device__ __forceinline__ void step_finish(const Params& p, const Bufs& b, uint32_t c, uint32_t lk, uint32_t t,
+                                            const Fetched<S>& F, double (&dv)[NDIAGP], float& ke_reg) {
+  const Pos& q = F.q;
+  const float phx = F.phx;
+  float d[Q];
+  const float* pt = F.pt;
   const Pop<S> A(b.A, p.abytes);
-  pull<S, SHW, UNI, ODD>(p, A, b.phi, c, lk, q, phx, d, pt);
+  pull_cvt<S, SHW>(p, F.r, phx, d);
   if (REC) {
     // the segment record is read once, by the reverse step: stream it past the caches
 #pragma unroll
@@ -760,7 +811,7 @@ __device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32
   const size_t half = (size_t)p.nrow * 10;
   open_fill(p, q.row, lk, t, b.shape, b.wave, b.side + (ODD ? half : 0), d);
   if (p.outlet == 2 && (lk & (LK_OUT | LK_UPS))) outflow_keep(p, q.row, lk, phx, d, b.side + (ODD ? 0 : half));
-  const float omp = b.omega[c];
+  const float omp = F.omp;
   Macro<R> M;
   macro<R, AN>(p, phx, d, omp, M);
   b.omega[c] = (float)M.omega;
@@ -772,7 +823,14 @@ __device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32
   if (DIAG == 1) diag_terms<R>(p, phx, d, M, lk, true, dv);
   if (DIAG == 2) ke_reg = reg ? (float)((R)0.5 * M.rho * M.uu) : 0.0f;
   if (DIAG == 3) ke_reg = (float)region_wss<R>(lk, M);
-  collide_store<S, SHW, UNI, ODD, R, PROJ>(p, A, c, lk, q, phx, d, pt, M);
+  collide_store<S, SHW, UNI, ODD, R, PROJ, INR>(p, A, c, lk, q, phx, d, pt, M);
+}
+template <class S, bool SHW, bool UNI, bool ODD, int DIAG, bool REC, class R, bool PROJ, bool AN, bool INR = false>
+__device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32_t c, uint32_t lk, uint32_t t,
+                                          double (&dv)[NDIAGP], float& ke_reg) {
+  Fetched<S> F;
+  step_fetch<S, UNI, ODD, INR>(p, b, c, lk, F);
+  step_finish<S, SHW, UNI, ODD, DIAG, REC, R, PROJ, AN, INR>(p, b, c, lk, t, F, dv, ke_reg);
 }
 
 // ---------------------------------------------------------------------------
@@ -792,7 +850,13 @@ __global__ __launch_bounds__(NT) void k_step(Params p, Bufs b) {
   float ke_reg = 0.0f;
   const bool uni = !active || (lk & LK_UNI);
   if (__all(uni)) {
-    if (active) step_cell<S, SHW, true, ODD, DIAG, REC, R, PROJ, AN>(p, b, c, lk, t, dv, ke_reg);
+    // odd steps address the neighbours: interior waves (most of a vessel's
+    // waves) need no per-direction bounce-back selects
+    if (ODD && __all(!active || (lk & LK_INR))) {
+      if (active) step_cell<S, SHW, true, ODD, DIAG, REC, R, PROJ, AN, true>(p, b, c, lk, t, dv, ke_reg);
+    } else {
+      if (active) step_cell<S, SHW, true, ODD, DIAG, REC, R, PROJ, AN>(p, b, c, lk, t, dv, ke_reg);
+    }
   } else {
     if (active) step_cell<S, SHW, false, ODD, DIAG, REC, R, PROJ, AN>(p, b, c, lk, t, dv, ke_reg);
   }
