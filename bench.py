@@ -125,9 +125,9 @@ def time_adjoint(torch, case, T: int, ckpt: int):
     return dt, ok
 
 
-def cpu_baseline(case, budget_s: float):
-    """The FP64 oracle (as it stands) on a bounded number of steps of the same
-    geometry, on this host's cores."""
+def _oracle_rate(case, budget_s: float, max_steps: int = 400):
+    """Steps of the oracle within about budget_s (after one untimed step):
+    (MLUPS, steps, seconds, fluid cells)."""
     import oracle
 
     o = oracle.Oracle(case)
@@ -135,13 +135,60 @@ def cpu_baseline(case, budget_s: float):
     t0 = time.perf_counter()
     o.run(f, om, 0, 1)
     one = time.perf_counter() - t0
-    n = max(1, min(400, int(budget_s / max(one, 1e-3))))
+    n = max(1, min(max_steps, int(budget_s / max(one, 1e-3))))
     t0 = time.perf_counter()
     o.run(f, om, 1, n)
     dt = time.perf_counter() - t0
-    return dict(value=round(o.nf * n / dt / 1e6, 3), unit="MLUPS", cores=oracle.threads(), kind="oracle",
+    return o.nf * n / dt / 1e6, n, dt, o.nf
+
+
+def cpu_baseline(case, budget_s: float):
+    """The FP64 oracle (as it stands) on a bounded number of steps of the same
+    geometry, on this host's cores, and on one thread."""
+    import oracle
+
+    v, n, dt, nf = _oracle_rate(case, budget_s)
+    cores = oracle.threads()
+    prev = oracle.set_threads(1)
+    try:
+        v1, n1, dt1, _ = _oracle_rate(case, budget_s / 3)
+    finally:
+        oracle.set_threads(prev)
+    return dict(value=round(v, 3), unit="MLUPS", cores=cores, kind="oracle",
                 sample=f"{n} steps (after 1 untimed) of the full {case.nx}x{case.ny}x{case.nz} geometry, "
-                       f"{o.nf} fluid cells, FP64, {dt:.1f} s")
+                       f"{nf} fluid cells, FP64, {dt:.1f} s",
+                single_thread={"value": round(v1, 3), "sample": f"{n1} steps, {dt1:.1f} s"})
+
+
+def cpu_cases(budget_s: float):
+    """The oracle on the other workloads (bounded samples, all cores and one
+    thread), and its reverse sweep on the gradient workload."""
+    import oracle
+    from synth import make_config
+
+    out = {}
+    cores = oracle.threads()
+    for key, steps in (("c0", 2000), ("c1", 1000), ("c2c", 400)):
+        case = make_config(key)
+        v, n, dt, nf = _oracle_rate(case, budget_s, steps)
+        prev = oracle.set_threads(1)
+        try:
+            v1, n1, dt1, _ = _oracle_rate(case, budget_s / 3, steps)
+        finally:
+            oracle.set_threads(prev)
+        out[key] = {"fluid_cells": nf, "mlups": round(v, 3), "steps": n, "seconds": round(dt, 2),
+                    "mlups_1thread": round(v1, 3), "steps_1thread": n1}
+        log(f"[bench] oracle {key}: {v:.2f} MLUPS on {cores} threads ({n} steps), {v1:.3f} on one ({n1} steps)")
+    case = make_config("c4")
+    T, ck = 40, 10
+    o = oracle.Oracle(case)
+    t0 = time.perf_counter()
+    o.grad_reverse(T, T // 2, T, ck)
+    dt = time.perf_counter() - t0
+    out["c4_reverse"] = {"fluid_cells": o.nf, "T": T, "ckpt": ck, "seconds": round(dt, 2),
+                         "cell_steps_per_s": round(o.nf * T / dt, 1)}
+    log(f"[bench] oracle c4 forward + reverse sweep, T={T}: {dt:.1f} s ({o.nf * T / dt / 1e6:.3f} M cell-steps/s)")
+    return out
 
 
 def main():
@@ -155,6 +202,8 @@ def main():
     ap.add_argument("--adj-ckpt", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-cases", action="store_true",
+                    help="also time the oracle on the channel, small and coarse aneurysm workloads and its reverse sweep")
     ap.add_argument("--only", default=None, help="time one storage form only (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -225,7 +274,10 @@ def main():
     if not args.no_cpu:
         log("[bench] oracle CPU baseline")
         cpu = cpu_baseline(case, args.cpu_budget)
-        log(f"[bench] oracle: {cpu['value']} MLUPS on {cpu['cores']} threads")
+        log(f"[bench] oracle: {cpu['value']} MLUPS on {cpu['cores']} threads, "
+            f"{cpu['single_thread']['value']} on one")
+        if args.cpu_cases:
+            cpu["cases"] = cpu_cases(args.cpu_budget / 3)
 
     nf = case.n_fluid
     traffic = traffic_for(f"k_step_{head_form}_{args.config}")

@@ -90,6 +90,8 @@ def lib(q: int = 19):
         L.oracle_grad_dual.argtypes = [vp, i32, i32, i32, vp, i32, vp, vp, i32]
         L.oracle_grad_reverse.argtypes = [vp, i32, i32, i32, i32, vp, vp, i32]
         L.oracle_threads.restype = i32
+        L.oracle_set_threads.restype = i32
+        L.oracle_set_threads.argtypes = [i32]
         L.oracle_q.restype = i32
         assert L.oracle_q() == q
         _libs[q] = L
@@ -269,3 +271,11 @@ def lattice(q: int = 19):
 
 def threads() -> int:
     return int(lib().oracle_threads())
+
+
+def set_threads(n: int) -> int:
+    """Thread count of the oracle's later parallel loops, in both velocity-set
+    libraries; returns the previous count."""
+    prev = int(lib(19).oracle_set_threads(int(n)))
+    lib(27).oracle_set_threads(int(n))
+    return prev

@@ -948,6 +948,12 @@ void oracle_grad_reverse(void* h, int T, int tb, int te, int ckpt, double* J, do
 }
 
 int oracle_threads(void) { return omp_get_max_threads(); }
+// Thread count of later parallel loops (n < 1: one per processor); returns the previous count.
+int oracle_set_threads(int n) {
+  const int prev = omp_get_max_threads();
+  omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+  return prev;
+}
 int oracle_q(void) { return Q; }
 
 }  // extern "C"
