@@ -195,17 +195,14 @@ struct Pop {
   __amdgpu_buffer_rsrc_t r;
   __device__ __forceinline__ Pop(const void* base, uint32_t bytes)
       : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000)) {}
-  // storage bits of one value, and their conversion to FP32
-  using Raw = typename std::conditional<std::is_same<S, float>::value, unsigned, unsigned short>::type;
-  __device__ __forceinline__ Raw ldr(uint32_t voff, uint32_t soff) const {
-    if constexpr (std::is_same<S, float>::value) return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
-    else return __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
+  __device__ __forceinline__ float ld(uint32_t voff, uint32_t soff) const {
+    if constexpr (std::is_same<S, float>::value) {
+      return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    } else {
+      const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
+      return (float)__builtin_bit_cast(S, h);
+    }
   }
-  static __device__ __forceinline__ float cvt(Raw h) {
-    if constexpr (std::is_same<S, float>::value) return __builtin_bit_cast(float, h);
-    else return (float)__builtin_bit_cast(S, h);
-  }
-  __device__ __forceinline__ float ld(uint32_t voff, uint32_t soff) const { return cvt(ldr(voff, soff)); }
   __device__ __forceinline__ void st(uint32_t voff, uint32_t soff, float v) const {
     if constexpr (std::is_same<S, float>::value) {
       __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
@@ -244,18 +241,16 @@ __device__ __forceinline__ Slot slot_out(const Params& p, uint32_t c, uint32_t l
 // Pull: v_i(x) = f_i(t, x) (the cell's own opposite output across a wall; the
 // open-face unknowns are then replaced by the Zou-He fill).  Unless UNI, also
 // pt[j] = porosity of x + c_j (phi(x) across walls) for the producer side.
-// pull_raw issues the loads and keeps the storage bits; pull_cvt converts.
-template <class S, bool UNI, bool ODD, bool INR = false>
-__device__ __forceinline__ void pull_raw(const Params& p, const Pop<S>& A, const float* __restrict__ phi,
-                                         uint32_t c, uint32_t lk, const Pos& q, float phx,
-                                         typename Pop<S>::Raw r[Q], float pt[Q]) {
-  auto ld = [&](Slot a) { return A.ldr(a.v, a.s); };
-  r[0] = ld(slot_in<0, ODD, S, INR>(p, c, lk, q));
+template <class S, bool SHW, bool UNI, bool ODD, bool INR = false>
+__device__ __forceinline__ void pull(const Params& p, const Pop<S>& A, const float* __restrict__ phi, uint32_t c,
+                                     uint32_t lk, const Pos& q, float phx, float v[Q], float pt[Q]) {
+  auto ld = [&](Slot a) { return A.ld(a.v, a.s); };
+  v[0] = ld(slot_in<0, ODD, S, INR>(p, c, lk, q));
   pt[0] = phx;
   sfor<1, Q>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
     constexpr int J = OPP[I];
-    r[I] = ld(slot_in<I, ODD, S, INR>(p, c, lk, q));
+    v[I] = ld(slot_in<I, ODD, S, INR>(p, c, lk, q));
     if (!UNI) {
       const bool bb = !INR && ((lk >> I) & 1u);
       pt[J] = ldo(phi, bb ? c : src_of<I>(p, q));
@@ -263,23 +258,11 @@ __device__ __forceinline__ void pull_raw(const Params& p, const Pop<S>& A, const
       pt[J] = phx;
     }
   });
-}
-template <class S, bool SHW>
-__device__ __forceinline__ void pull_cvt(const Params& p, const typename Pop<S>::Raw r[Q], float phx, float v[Q]) {
-#pragma unroll
-  for (int i = 0; i < Q; ++i) v[i] = Pop<S>::cvt(r[i]);
   if (SHW) {
     const float s = p.f.ks * (phx - 1.0f);
 #pragma unroll
     for (int i = 0; i < Q; ++i) v[i] -= kw(i) * s;
   }
-}
-template <class S, bool SHW, bool UNI, bool ODD, bool INR = false>
-__device__ __forceinline__ void pull(const Params& p, const Pop<S>& A, const float* __restrict__ phi, uint32_t c,
-                                     uint32_t lk, const Pos& q, float phx, float v[Q], float pt[Q]) {
-  typename Pop<S>::Raw r[Q];
-  pull_raw<S, UNI, ODD, INR>(p, A, phi, c, lk, q, phx, r, pt);
-  pull_cvt<S, SHW>(p, r, phx, v);
 }
 
 // Inflow amplitude at step t, in FP64, rounded once to FP32 (the simulation
@@ -776,33 +759,16 @@ __device__ __forceinline__ void diag_terms(const Params& p, float phx, const flo
 
 // Body of the step for one cell (UNI: the whole wave has uniform neighbour
 // porosity; INR: every cell of the wave is interior).
-// The cell's loads (position, porosities, pulled storage bits, omega_prev),
-// issued by step_fetch and consumed by step_finish.
-template <class S>
-struct Fetched {
-  Pos q;
-  float phx, omp;
-  typename Pop<S>::Raw r[Q];
-  float pt[Q];
-};
-template <class S, bool UNI, bool ODD, bool INR>
-__device__ __forceinline__ void step_fetch(const Params& p, const Bufs& b, uint32_t c, uint32_t lk, Fetched<S>& F) {
-  F.q = position(p, c, b.code[c]);
-  if (ODD || !UNI) load_deltas(b.delta, F.q);
-  if (INR) interior_offsets<S>(F.q);
-  F.phx = ldo(b.phi, c);
-  pull_raw<S, UNI, ODD, INR>(p, Pop<S>(b.A, p.abytes), b.phi, c, lk, F.q, F.phx, F.r, F.pt);
-  F.omp = b.omega[c];
-}
 template <class S, bool SHW, bool UNI, bool ODD, int DIAG, bool REC, class R, bool PROJ, bool AN, bool INR = false>
-__device__ __forceinline__ void step_finish(const Params& p, const Bufs& b, uint32_t c, uint32_t lk, uint32_t t,
-                                            const Fetched<S>& F, double (&dv)[NDIAGP], float& ke_reg) {
-  const Pos& q = F.q;
-  const float phx = F.phx;
-  float d[Q];
-  const float* pt = F.pt;
+__device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32_t c, uint32_t lk, uint32_t t,
+                                          double (&dv)[NDIAGP], float& ke_reg) {
+  Pos q = position(p, c, b.code[c]);
+  if (ODD || !UNI) load_deltas(b.delta, q);
+  if (INR) interior_offsets<S>(q);
+  const float phx = ldo(b.phi, c);
+  float d[Q], pt[Q];
   const Pop<S> A(b.A, p.abytes);
-  pull_cvt<S, SHW>(p, F.r, phx, d);
+  pull<S, SHW, UNI, ODD, INR>(p, A, b.phi, c, lk, q, phx, d, pt);
   if (REC) {
     // the segment record is read once, by the reverse step: stream it past the caches
 #pragma unroll
@@ -811,7 +777,7 @@ __device__ __forceinline__ void step_finish(const Params& p, const Bufs& b, uint
   const size_t half = (size_t)p.nrow * 10;
   open_fill(p, q.row, lk, t, b.shape, b.wave, b.side + (ODD ? half : 0), d);
   if (p.outlet == 2 && (lk & (LK_OUT | LK_UPS))) outflow_keep(p, q.row, lk, phx, d, b.side + (ODD ? 0 : half));
-  const float omp = F.omp;
+  const float omp = b.omega[c];
   Macro<R> M;
   macro<R, AN>(p, phx, d, omp, M);
   b.omega[c] = (float)M.omega;
@@ -824,13 +790,6 @@ __device__ __forceinline__ void step_finish(const Params& p, const Bufs& b, uint
   if (DIAG == 2) ke_reg = reg ? (float)((R)0.5 * M.rho * M.uu) : 0.0f;
   if (DIAG == 3) ke_reg = (float)region_wss<R>(lk, M);
   collide_store<S, SHW, UNI, ODD, R, PROJ, INR>(p, A, c, lk, q, phx, d, pt, M);
-}
-template <class S, bool SHW, bool UNI, bool ODD, int DIAG, bool REC, class R, bool PROJ, bool AN, bool INR = false>
-__device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32_t c, uint32_t lk, uint32_t t,
-                                          double (&dv)[NDIAGP], float& ke_reg) {
-  Fetched<S> F;
-  step_fetch<S, UNI, ODD, INR>(p, b, c, lk, F);
-  step_finish<S, SHW, UNI, ODD, DIAG, REC, R, PROJ, AN, INR>(p, b, c, lk, t, F, dv, ke_reg);
 }
 
 // ---------------------------------------------------------------------------
