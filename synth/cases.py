@@ -295,7 +295,41 @@ def tiny_case(kind: str = "open", seed: int = 0, nx: int = 9, ny: int = 7, nz: i
     ``open_wave``: ``open`` with a 6-step pre-run ramp and a sampled 9-point
     inflow waveform of period 13 steps.  ``open_extrap``: ``open`` with the
     extrapolation outflow and one outflow cell whose -x neighbour is solid.
+    ``bulk``: long rows (260 x 6 x 5, periodic in y and z, open in x) whose
+    middles are wall-free, with uniform porosity 0.8 (1 near the open faces),
+    a random-porosity patch and two solid voxels, so that whole waves of
+    interior cells occur with uniform and with varying porosity.
+    ``degenerate``: a 2 x 1 x 3 box periodic in all axes (both x neighbours
+    are one cell, y neighbours are the cell's own row), random porosity.
     """
+    if kind == "bulk":
+        nx, ny, nz = 260, 6, 5
+        rng = np.random.default_rng(1000 + seed)
+        solid = np.zeros((nz, ny, nx), np.uint8)
+        solid[2, 3, 230] = 1
+        solid[4, 0, 20] = 1
+        phi = np.full((nz, ny, nx), 0.8, np.float32)
+        phi[:, :, :3] = 1.0
+        phi[:, :, nx - 3:] = 1.0
+        patch = rng.uniform(0.6, 1.0, (nz, ny, 30)).astype(np.float32)
+        rows = (np.add.outer(np.arange(nz), np.arange(ny)) % 3 == 0)
+        phi[:, :, 150:180] = np.where(rows[:, :, None], patch, phi[:, :, 150:180])
+        shape = rng.uniform(0.2, 1.0, (nz, ny)).astype(np.float32)
+        case = Case(name=f"tiny_bulk{seed}", nx=nx, ny=ny, nz=nz, periodic=(False, True, True),
+                    solid=solid, phi=phi, sac=rng.random((nz, ny, nx)) < 0.5, inlet=True, outlet=True,
+                    inlet_shape=shape, wave=(0.03, 0.5, 40.0), rho_out=1.0,
+                    porous=dict(nu_d=0.1, kc=180.0, d=2.0, forchheimer=0, g=(0.0, 0.0, 0.0)))
+        case.phi = np.where(case.solid == 0, case.phi, 0.0).astype(np.float32)
+        case.sac = case.sac & (case.solid == 0)
+        return case
+    if kind == "degenerate":
+        nx, ny, nz = 2, 1, 3
+        rng = np.random.default_rng(1000 + seed)
+        return Case(name=f"tiny_degenerate{seed}", nx=nx, ny=ny, nz=nz, periodic=(True, True, True),
+                    solid=np.zeros((nz, ny, nx), np.uint8),
+                    phi=rng.uniform(0.6, 1.0, (nz, ny, nx)).astype(np.float32),
+                    sac=np.ones((nz, ny, nx), bool),
+                    porous=dict(nu_d=0.1, kc=180.0, d=2.0, forchheimer=0, g=(1e-5, 2e-5, -1e-5)))
     rng = np.random.default_rng(1000 + seed)
     solid = (rng.random((nz, ny, nx)) < 0.15).astype(np.uint8)
     phi = rng.uniform(0.6, 1.0, (nz, ny, nx)).astype(np.float32)

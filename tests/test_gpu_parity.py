@@ -57,13 +57,16 @@ def _tiny_any(kind, seed):
 
 
 @pytest.mark.parametrize("kind", ["open", "open_wave", "open_extrap", "periodic", "periodic_aniso", "periodic3",
-                                  "open_q27", "open_extrap_q27", "periodic_q27", "periodic3_q27"])
+                                  "bulk", "degenerate", "open_q27", "open_extrap_q27", "periodic_q27",
+                                  "periodic3_q27", "bulk_q27", "degenerate_q27"])
 @pytest.mark.parametrize("seed", [0, 1])
-def test_one_step_from_random_state(kind, seed):
-    """Every cell type (walls, open faces, periodic wrap, porosity jumps): one
-    step from a random non-equilibrium state, on D3Q19 and D3Q27."""
+@pytest.mark.parametrize("t0", [0, 1])
+def test_one_step_from_random_state(kind, seed, t0):
+    """Every cell type (walls, open faces, periodic wrap, porosity jumps, waves
+    of interior cells): one step, even (t0 = 0) or odd (t0 = 1), from a random
+    non-equilibrium state, on D3Q19 and D3Q27."""
     case = _tiny_any(kind, seed)
-    say(f"one step: {case.name} seed={seed} box={case.nx}x{case.ny}x{case.nz}")
+    say(f"one step: {case.name} seed={seed} t0={t0} box={case.nx}x{case.ny}x{case.nz}")
     o = oracle.Oracle(case)
     f0, om0 = o.init()
     rng = np.random.default_rng(seed)
@@ -72,12 +75,13 @@ def test_one_step_from_random_state(kind, seed):
     om = np.ascontiguousarray((om0 * (1 + 0.2 * rng.random(o.nf))).astype(np.float32).astype(np.float64))
     s = Solver.from_case(case)
     assert np.array_equal(s.fluid_index(), o.cells())
+    s.step(t0)
     s.set_state(f, om.astype(np.float32))
     g0, gom0 = s.get_state()
     assert np.abs(g0 - f).max() < 1e-8
     s.step(1)
     g1, gom1 = s.get_state()
-    o.run(f, om, 0, 1)
+    o.run(f, om, t0, 1)
     assert np.all(g1[~known] == 0)
     err = np.abs(g1 - f).max()
     say(f"  max |f_gpu - f_oracle| = {err:.3e}, omega err = {np.abs(gom1 - om).max():.3e}")

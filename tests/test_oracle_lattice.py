@@ -28,7 +28,8 @@ def _dense(case, cells, f, om):
 
 
 @pytest.mark.parametrize("kind", ["open", "open_wave", "open_extrap", "periodic", "periodic_aniso", "periodic3",
-                                  "open_q27", "open_extrap_q27", "periodic_q27", "periodic3_q27"])
+                                  "bulk", "degenerate", "open_q27", "open_extrap_q27", "periodic_q27",
+                                  "periodic3_q27", "bulk_q27", "degenerate_q27"])
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_matches_dense_bruteforce(kind, seed):
     """Compact-list C++ oracle vs dense-array NumPy transcription: 1 and 10 steps
