@@ -249,11 +249,13 @@ lbm_status lbm_reset(lbm_ctx* ctx);
  * back through the segments (recompute forward, then reverse steps).  The
  * forward passes compute the collision in FP64 (LBM_ARITH_FP64) whatever the
  * context's arithmetic mode; the reverse steps are FP64 arithmetic with FP32
- * adjoint populations.  Needs a workspace sized for (T, ckpt_every) or
- * larger; FP32 storage, shift mode 0, no Forchheimer drag, no extrapolation
- * outflow (for the gradient), isotropic permeability, a region with a fluid cell (with a wall cell for
- * LBM_OBJ_WSS), 0 <= t_begin < t_end <= T.  At a wall cell where tau = 0 the
- * WSS term contributes no gradient (|tau| is not differentiable there).
+ * adjoint populations.  Either outflow kind; with the extrapolation outflow
+ * the outflow cells' unknowns are state, and their dependence on the previous
+ * step's values is part of the reverse sweep.  Needs a workspace sized for
+ * (T, ckpt_every) or larger; FP32 storage, shift mode 0, no Forchheimer drag,
+ * isotropic permeability, D3Q19, a region with a fluid cell (with a wall cell
+ * for LBM_OBJ_WSS), 0 <= t_begin < t_end <= T.  At a wall cell where tau = 0
+ * the WSS term contributes no gradient (|tau| is not differentiable there).
  *   J:       host, 1 double
  *   dJ_dphi: device, nx*ny*nz floats (box layout, 0 off the fluid), or NULL:
  *            then only J is computed (the forward pass, no checkpoints; the

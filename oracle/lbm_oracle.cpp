@@ -839,16 +839,16 @@ void oracle_grad_dual(void* h, int T, int tb, int te, const int64_t* boxcells, i
 //   (19 pre-collision populations, previous omega, phi(x), 18 neighbour phi)
 //   -> (19 post-collision populations, new omega, kinetic-energy term)
 // is taken with 39-component dual numbers and its transpose applied to the
-// output adjoints; the streaming transpose gathers along +c_i.
+// output adjoints; the streaming transpose gathers along +c_i.  With the
+// extrapolation outflow the outflow cells' unknowns are state that step n
+// computes linearly from step n-1's values (see extrapolate_outlet); that map
+// is transposed after the local maps.
 void oracle_grad_reverse(void* h, int T, int tb, int te, int ckpt, double* J, double* grad_box, int kind) {
   const int NI = 2 * Q + 1;
   typedef Dual<NI> D;
   Ctx* C = (Ctx*)h;
   const int64_t nf = C->nf;
-  if (C->c.outlet == 2) {  // the local maps below assume a cell-local open-face fill
-    *J = std::nan("");
-    return;
-  }
+  const bool extrap = C->c.outlet == 2;
   std::vector<double> ph = fluid_phi(*C), f, om;
   rest_state(*C, ph, f, om);
   // forward with checkpoints
@@ -898,7 +898,7 @@ void oracle_grad_reverse(void* h, int T, int tb, int te, int ckpt, double* J, do
         if (C->kind[x] == 1) {
           double ux = amplitude(*C, t) * C->shape[C->yc[x] + (int64_t)C->c.ny * C->zc[x]];
           zouhe_inlet(fl, ux, 0.0, 0.0);
-        } else if (C->kind[x] == 2) {
+        } else if (C->kind[x] == 2 && !extrap) {
           zouhe_outlet(fl, C->c.rho_out);
         }
         CellResult<D> r;
@@ -931,15 +931,30 @@ void oracle_grad_reverse(void* h, int T, int tb, int te, int ckpt, double* J, do
           int nb = C->nbr[i * nf + x];
           if (nb >= 0) phh[nb] += nbcontrib[i * nf + x];
         }
+      // transpose of the extrapolation: f_i(t+1, x_b) = (1 - c_s) f_i(t, x_b) + c_s f_i(t, x_b - e_x)
+      if (extrap) {
+        const double cs = std::sqrt(CS2);
+        for (int64_t x = 0; x < nf; ++x) {
+          if (C->kind[x] != 2) continue;
+          const int up = C->nbr[2 * nf + x];
+          for (int i = 0; i < Q; ++i) {
+            if (CV[i][0] != -1 || C->nbr[opposite(i) * nf + x] != NB_OPEN) continue;
+            const double a = fh[i * nf + x];
+            fh_new[i * nf + x] += (up >= 0 ? 1.0 - cs : 1.0) * a;
+            if (up >= 0) fh_new[i * nf + up] += cs * a;
+          }
+        }
+      }
       fh.swap(fh_new);
       oh.swap(oh_new);
     }
   }
-  // initial state f_i(0, x) = w_i phi(x) on the known links
+  // initial state f_i(0, x) = w_i phi(x) on the known links (and on the
+  // extrapolation outflow's unknowns, which are state)
   for (int64_t x = 0; x < nf; ++x)
     for (int i = 0; i < Q; ++i) {
       int o = opposite(i);
-      if (C->nbr[o * nf + x] == NB_OPEN) continue;
+      if (C->nbr[o * nf + x] == NB_OPEN && !(C->kind[x] == 2 && extrap)) continue;
       phh[x] += WT[i] * fh[i * nf + x];
     }
   const int64_t nb = (int64_t)C->c.nx * C->c.ny * C->c.nz;

@@ -16,6 +16,13 @@
 // contribution is gathered by the consumer cell from the producer's recorded
 // density of the previous step, so no atomics are needed.
 //
+// With the extrapolation outflow, an outflow cell's unknowns (c_x = -1) are
+// state: step n computes them as (1 - c_s) times the cell's own value of step
+// n-1 plus c_s times the -x neighbour's pulled value of step n-1.  The reverse
+// step of n leaves the unknowns' total adjoints per row (aside_out); the reverse
+// step of n-1 adds (1 - c_s) of them to the outflow cell's unknowns and c_s of
+// them to the -x neighbour's pulled values.
+//
 // Supported: FP32 storage, shift mode 0, no Forchheimer drag.  The recompute
 // uses the same arithmetic type as the forward step.
 #pragma once
@@ -30,12 +37,14 @@ struct AdjBufs {
   const float* phi;       // porosity per compact cell
   const float* shape;     // inflow profile per row
   const double* wave;     // sampled inflow waveform
-  const float* rec;       // record of step n: [19][nc] pulled values (before the fill), [nc] omega_prev
+  const float* rec;       // record of step n: [19][nc] pulled values (after the fill), [nc] omega_prev
   const float* rho_prev;  // density of step n-1 per compact cell (null for n = 0)
   const float* ph_next;   // adjoint of the pulled populations of step n+1, [19][nc]
   float* ph_out;          // adjoint of the pulled populations of step n, [19][nc]
   float* omh;             // per cell: in adjoint of omega_n, out adjoint of omega_{n-1}
   double* phih;           // per cell: porosity adjoint accumulator
+  const double* aside_in; // extrapolation outflow: per row, adjoints of the 5 c_x = -1 unknowns of step n+1
+  double* aside_out;      // the same for step n
 };
 
 // One reverse step at every fluid cell.  Arithmetic in FP64 (the adjoint
@@ -58,7 +67,10 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, uint32_t
 #pragma unroll
   for (int i = 0; i < Q; ++i) d[i] = a.rec[(size_t)i * p.nc + c];
   const float omp = a.rec[(size_t)Q * p.nc + c];
-  open_fill(p, q.row, lk, t, a.shape, a.wave, nullptr, d);
+  // the record holds the filled values; the Zou-He fills are recomputed for
+  // their transposes below (the extrapolation's unknowns are inputs)
+  const bool extrap = p.outlet == 2;
+  if (!(extrap && (lk & LK_OUT))) open_fill(p, q.row, lk, t, a.shape, a.wave, nullptr, d);
   Macro<R> M;
   macro<R>(p, phx_f, d, omp, M);
   const R phx = (R)phx_f;
@@ -241,9 +253,30 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, uint32_t
             2.0 * ((R)(cx * cy) * G[3] + (R)(cx * cz) * G[4] + (R)(cy * cz) * G[5]);
   });
 
+  // the -x neighbour of an extrapolation-outflow cell: its c_x = -1 pulled
+  // values enter the next step's unknowns with weight c_s
+  if (extrap && (lk & LK_UPS)) {
+    const double* e = a.aside_in + (size_t)q.row * 5;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) fh[XOUT[k]] += (R)CS * e[k];
+  }
   // transpose of the open-face fill: the unknowns' adjoints flow to the knowns
   const bool in = (lk & LK_IN) != 0;
   const bool outl = (lk & LK_OUT) != 0;
+  if (outl && extrap) {
+    // kept unknowns: total adjoint = this step's part + (1 - c_s) (or 1
+    // without a fluid -x neighbour) times the next step's; it goes to the row
+    // buffer, not to the pulled-value adjoints (no producer streams there)
+    const double* e = a.aside_in + (size_t)q.row * 5;
+    double* o = a.aside_out + (size_t)q.row * 5;
+    const R wo = ((lk >> 1) & 1u) ? (R)1 : (R)1 - (R)CS;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const bool unk = (lk >> (LK_UNK + k)) & 1u;
+      o[k] = unk ? (double)(fh[XOUT[k]] + wo * e[k]) : 0.0;
+      if (unk) fh[XOUT[k]] = 0.0;
+    }
+  }
   if (in) {
     const R uin = (R)inflow_amplitude(p, a.wave, t) * (R)a.shape[q.row];
     fh[2] += fh[1]; fh[8] += fh[7]; fh[10] += fh[9]; fh[12] += fh[11]; fh[14] += fh[13];
@@ -255,7 +288,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, uint32_t
     fh[3] += nyh; fh[4] -= nyh; fh[15] += nyh; fh[16] -= nyh; fh[17] += nyh; fh[18] -= nyh;
     fh[5] += nzh; fh[6] -= nzh; fh[15] += nzh; fh[16] -= nzh; fh[17] -= nzh; fh[18] += nzh;
     fh[1] = 0.0; fh[7] = 0.0; fh[9] = 0.0; fh[11] = 0.0; fh[13] = 0.0;
-  } else if (outl) {
+  } else if (outl && !extrap) {
     const R ro = kc.rho_out;
     fh[1] += fh[2]; fh[7] += fh[8]; fh[9] += fh[10]; fh[11] += fh[12]; fh[13] += fh[14];
     const R uxh = -ro * (1.0 / 3.0) * fh[2] - ro * (1.0 / 6.0) * (fh[8] + fh[10] + fh[12] + fh[14]);
@@ -285,18 +318,24 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, uint32_t
   a.phih[c] += phh;
 }
 
-// Rest state f_i(0, x) = w_i phi(x) on the known links, then scatter the total
-// into the box-layout gradient.
+// Rest state f_i(0, x) = w_i phi(x) on the known links (and on the
+// extrapolation outflow's unknowns, whose adjoints of step 0 are in aside0),
+// then scatter the total into the box-layout gradient.
 __global__ __launch_bounds__(BLOCK) void k_adj_final(Params p, const uint32_t* code, const uint32_t* links,
                                                      const uint32_t* rowbox, const float* ph0, const double* total,
-                                                     float* grad) {
+                                                     const double* aside0, float* grad) {
   const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
   if (c >= (uint32_t)p.nc) return;
-  if (links[c] & LK_DEAD) return;
+  const uint32_t lk = links[c];
+  if (lk & LK_DEAD) return;
   const Pos q = position(p, c, code[c]);
   double s = total[c];
 #pragma unroll
   for (int i = 0; i < Q; ++i) s += (double)kw(i) * (1.0 / 36.0) * (double)ldo(ph0, (uint32_t)i * (uint32_t)p.nc + c);
+  if (p.outlet == 2 && (lk & LK_OUT)) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) s += (double)kw(XOUT[k]) * (1.0 / 36.0) * aside0[(size_t)q.row * 5 + k];
+  }
   grad[(size_t)rowbox[q.row] + (size_t)q.x] = (float)s;
 }
 

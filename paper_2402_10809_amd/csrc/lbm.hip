@@ -51,7 +51,7 @@ int qof(const lbm_grid& g) { return g.velocity_set == 27 ? 27 : 19; }
 struct Layout {
   size_t A, code, links, phi, omega, delta, shape, rowbox, stage, part, diag, obj, tc, wave, side;
   // adjoint
-  size_t ck, rec, rho, ah0, ah1, omh, phih;
+  size_t ck, rec, rho, ah0, ah1, omh, phih, aside;
   int nck, ckpt, T;
   size_t total;
 };
@@ -134,6 +134,7 @@ Layout make_layout(const lbm_grid& g, int64_t nc, int64_t nrow, int T, int ckpt)
     L.ah1 = take(Q * (size_t)nc * 4);
     L.omh = take((size_t)nc * 4);
     L.phih = take((size_t)nc * 8);
+    L.aside = take((size_t)2 * nrow * 5 * 8);
   }
   L.total = o;
   return L;

@@ -769,13 +769,15 @@ __device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32
   float d[Q], pt[Q];
   const Pop<S> A(b.A, p.abytes);
   pull<S, SHW, UNI, ODD, INR>(p, A, b.phi, c, lk, q, phx, d, pt);
+  const size_t half = (size_t)p.nrow * 10;
+  open_fill(p, q.row, lk, t, b.shape, b.wave, b.side + (ODD ? half : 0), d);
   if (REC) {
-    // the segment record is read once, by the reverse step: stream it past the caches
+    // the segment record (after the open-face fill, so that it holds the
+    // extrapolation outflow's unknowns) is read once, by the reverse step:
+    // stream it past the caches
 #pragma unroll
     for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(d[i], &b.rec[(size_t)i * p.nc + c]);
   }
-  const size_t half = (size_t)p.nrow * 10;
-  open_fill(p, q.row, lk, t, b.shape, b.wave, b.side + (ODD ? half : 0), d);
   if (p.outlet == 2 && (lk & (LK_OUT | LK_UPS))) outflow_keep(p, q.row, lk, phx, d, b.side + (ODD ? 0 : half));
   const float omp = b.omega[c];
   Macro<R> M;

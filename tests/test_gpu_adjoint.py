@@ -23,14 +23,16 @@ def say(msg):
 
 def _tiny(kind, seed):
     c = tiny_case(kind, seed=seed)
-    if kind == "open":
+    if kind.startswith("open"):
         c.wave = (0.04, 0.5, 20.0)
     c.rheology = dict(c.rheology, lam=200.0)
     return c
 
 
 @pytest.mark.parametrize("kind,seed,objective", [("open", 0, "ke"), ("open", 1, "ke"), ("periodic", 0, "ke"),
-                                                 ("open", 0, "wss"), ("open", 1, "wss"), ("periodic", 0, "wss")])
+                                                 ("open", 0, "wss"), ("open", 1, "wss"), ("periodic", 0, "wss"),
+                                                 ("open_extrap", 0, "ke"), ("open_extrap", 1, "ke"),
+                                                 ("open_extrap", 0, "wss")])
 def test_adjoint_matches_oracle_reverse_sweep(kind, seed, objective):
     case = _tiny(kind, seed)
     T, tb, te, ck = 30, 15, 30, 7
@@ -51,9 +53,11 @@ def test_adjoint_matches_oracle_reverse_sweep(kind, seed, objective):
     s.step(3)
 
 
-def test_adjoint_checkpoint_independent():
-    """The gradient does not depend on the checkpoint interval (recompute is exact)."""
-    case = _tiny("open", 2)
+@pytest.mark.parametrize("kind", ["open", "open_extrap"])
+def test_adjoint_checkpoint_independent(kind):
+    """The gradient does not depend on the checkpoint interval (recompute is
+    exact, also with the extrapolation outflow's kept unknowns)."""
+    case = _tiny(kind, 2)
     T, tb, te = 26, 10, 26
     J1, g1 = Solver.from_case(case, adjoint_T=T, ckpt=1).adjoint(tb, te, T, 1)
     J2, g2 = Solver.from_case(case, adjoint_T=T, ckpt=26).adjoint(tb, te, T, 26)
@@ -80,15 +84,26 @@ def test_adjoint_rejects_unsupported():
         s3.adjoint(2, 10, 10, 5)   # anisotropic permeability
 
 
-@pytest.mark.parametrize("objective", ["ke", "wss"])
-def test_adjoint_small_aneurysm_dual(objective):
+@pytest.mark.parametrize("objective,outlet", [("ke", 1), ("wss", 1), ("ke", 2), ("wss", 2)])
+def test_adjoint_small_aneurysm_dual(objective, outlet):
     """48x40x40 tube-and-sac aneurysm from the same generator (pulsatile Zou-He
-    inflow, density outflow, GRF sac porosity): GPU gradient at 16 seeded sac
-    voxels against the oracle's exact dual-number derivative."""
+    inflow, density or extrapolation outflow, GRF sac porosity): GPU gradient
+    at 16 seeded voxels (with the extrapolation outflow, 12 in the sac and 4 on
+    and next to the outflow face) against the oracle's exact dual-number
+    derivative."""
     case = aneurysm_case(48, 40, 40, R=5, Rs=8, ell=3, seed=4, wave=(0.05, 0.5, 200.0), name="mini")
+    case.outlet = outlet
     T, tb, te, ck = 300, 200, 300, 16
-    vox = fd_voxels(case, 16, seed=16)
-    say(f"adjoint ({objective}) mini aneurysm ({case.n_fluid} cells): T={T} window=[{tb},{te}), {len(vox)} voxels")
+    if outlet == 1:
+        vox = fd_voxels(case, 16, seed=16)
+    else:
+        nx, ny = case.nx, case.ny
+        face = [(nx - 1, 20, 20), (nx - 1, 17, 21), (nx - 2, 20, 20), (nx - 2, 22, 18)]
+        extra = np.array([x + nx * (y + ny * z) for x, y, z in face], np.int64)
+        assert np.all(case.solid.reshape(-1)[extra] == 0)
+        vox = np.concatenate([fd_voxels(case, 12, seed=16), extra])
+    say(f"adjoint ({objective}, outlet {outlet}) mini aneurysm ({case.n_fluid} cells): T={T} "
+        f"window=[{tb},{te}), {len(vox)} voxels")
     o = oracle.Oracle(case)
     J_ref, gd = o.grad_dual(T, tb, te, vox, objective)
     s = Solver.from_case(case, adjoint_T=T, ckpt=ck)

@@ -13,17 +13,19 @@ import oracle
 from synth import fd_voxels, tiny_case
 
 
-def _case(seed):
-    c = tiny_case("open", seed=seed)
+def _case(seed, lattice="open"):
+    c = tiny_case(lattice, seed=seed)
     c.wave = (0.04, 0.5, 20.0)
     c.rheology = dict(c.rheology, lam=200.0)  # shear-thinning active at these speeds
     return c
 
 
 @pytest.mark.parametrize("kind", ["ke", "wss"])
-@pytest.mark.parametrize("seed", [0, 1])
-def test_reverse_sweep_matches_dual_and_fd(seed, kind):
-    case = _case(seed)
+@pytest.mark.parametrize("seed,lattice", [(0, "open"), (1, "open"), (0, "open_extrap"), (1, "open_extrap")])
+def test_reverse_sweep_matches_dual_and_fd(seed, lattice, kind):
+    """Also with the extrapolation outflow, whose unknowns are state carried
+    from step to step."""
+    case = _case(seed, lattice)
     T, tb, te, ckpt = 24, 12, 24, 5
     o = oracle.Oracle(case)
     J, grad = o.grad_reverse(T, tb, te, ckpt, kind)
