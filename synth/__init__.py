@@ -14,6 +14,7 @@ from .cases import (  # noqa: F401
     coil_cases,
     periodic_box_case,
     tiny_case,
+    tiny_random,
     fd_voxels,
     sampled_waveform,
     aniso_shape,

@@ -389,6 +389,44 @@ def tiny_case(kind: str = "open", seed: int = 0, nx: int = 9, ny: int = 7, nz: i
     return case
 
 
+def tiny_random(seed: int) -> Case:
+    """A random small lattice for broad parity checks: each extent in 1..10
+    (x at least 2 with open faces), random periodic axes, an inflow and a
+    constant-density or extrapolation outflow when x is not periodic, 0-30 %
+    solid voxels, uniform or random porosity (1 on the open faces), random
+    body force and Carreau-Yasuda lambda.  At least one fluid cell."""
+    rng = np.random.default_rng(5000 + seed)
+    per = tuple(bool(b) for b in rng.random(3) < 0.5)
+    open_x = not per[0] and rng.random() < 0.7
+    nx = int(rng.integers(2 if open_x else 1, 11))
+    ny, nz = (int(v) for v in rng.integers(1, 11, 2))
+    solid = (rng.random((nz, ny, nx)) < rng.uniform(0.0, 0.3)).astype(np.uint8)
+    if open_x:
+        solid[:, :, 0] = rng.random((nz, ny)) < 0.2
+        solid[:, :, nx - 1] = rng.random((nz, ny)) < 0.2
+    if solid.all():
+        solid[nz // 2, ny // 2, nx // 2] = 0
+    if rng.random() < 0.3:
+        phi = np.full((nz, ny, nx), rng.uniform(0.6, 1.0), np.float32)
+    else:
+        phi = rng.uniform(0.6, 1.0, (nz, ny, nx)).astype(np.float32)
+    g = tuple(float(v) for v in rng.uniform(-2e-5, 2e-5, 3))
+    case = Case(name=f"tiny_random{seed}", nx=nx, ny=ny, nz=nz, periodic=per, solid=solid, phi=phi,
+                sac=rng.random((nz, ny, nx)) < 0.5,
+                rheology=dict(CY_DEFAULT, lam=float(rng.uniform(10.0, 200.0))),
+                porous=dict(nu_d=0.1, kc=180.0, d=2.0, forchheimer=0, g=g))
+    if open_x:
+        case.phi[:, :, 0] = 1.0
+        case.phi[:, :, nx - 1] = 1.0
+        case.inlet = True
+        case.outlet = int(rng.integers(1, 3))
+        case.inlet_shape = np.where(solid[:, :, 0] == 0, rng.uniform(0.2, 1.0, (nz, ny)), 0.0).astype(np.float32)
+        case.wave = (0.03, 0.5, 40.0)
+    case.phi = np.where(case.solid == 0, case.phi, 0.0).astype(np.float32)
+    case.sac = case.sac & (case.solid == 0)
+    return case
+
+
 def as_d3q27(case: Case) -> Case:
     """The same case on the D3Q27 velocity set."""
     case.lattice = 27

@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 from paper_2402_10809_amd import Solver, lbm
-from synth import as_d3q27, channel_case, make_config, tiny_case
+from synth import as_d3q27, channel_case, make_config, tiny_case, tiny_random
 
 pytestmark = pytest.mark.gpu
 
@@ -87,6 +87,37 @@ def test_one_step_from_random_state(kind, seed, t0):
     say(f"  max |f_gpu - f_oracle| = {err:.3e}, omega err = {np.abs(gom1 - om).max():.3e}")
     assert err < 2e-6
     assert np.abs(gom1 - om).max() < 2e-6
+
+
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("seed", range(32))
+def test_one_step_random_lattices(seed, q):
+    """Random small lattices (extents 1..10, random periodic axes, open faces
+    with either outflow, random solids and porosity): an even and an odd step
+    from a random state against the oracle."""
+    case = tiny_random(seed)
+    if q == 27:
+        case = as_d3q27(case)
+    say(f"random lattice: {case.name} q={q} box={case.nx}x{case.ny}x{case.nz} periodic={case.periodic} "
+        f"outlet={case.outlet}")
+    o = oracle.Oracle(case)
+    f0, om0 = o.init()
+    rng = np.random.default_rng(seed)
+    known = f0 != 0
+    s = Solver.from_case(case)
+    assert np.array_equal(s.fluid_index(), o.cells())
+    for t0 in (0, 1):
+        f = np.ascontiguousarray(f0 * (1 + 0.1 * rng.standard_normal(f0.shape)) * known)
+        om = np.ascontiguousarray((om0 * (1 + 0.2 * rng.random(o.nf))).astype(np.float32).astype(np.float64))
+        s.reset()
+        s.step(t0)
+        s.set_state(f, om.astype(np.float32))
+        s.step(1)
+        g1, gom1 = s.get_state()
+        o.run(f, om, t0, 1)
+        assert np.all(g1[~known] == 0)
+        assert np.abs(g1 - f).max() < 2e-6
+        assert np.abs(gom1 - om).max() < 2e-6
 
 
 @pytest.mark.parametrize("arith,steps,bound", [
