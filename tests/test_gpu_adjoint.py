@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 from paper_2402_10809_amd import Solver, lbm
-from synth import aneurysm_case, fd_voxels, tiny_case
+from synth import aneurysm_case, fd_voxels, tiny_case, tiny_random
 
 pytestmark = pytest.mark.gpu
 
@@ -51,6 +51,32 @@ def test_adjoint_matches_oracle_reverse_sweep(kind, seed, objective):
     # the context is left at the rest state and still steps
     assert s.t == 0
     s.step(3)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_adjoint_random_lattices(seed):
+    """The kinetic-energy gradient on the seeded random small lattices (random
+    extents, periodic axes, either outflow, solids and porosity) against the
+    oracle's reverse sweep.  The body force is raised 50-fold so that the
+    closed lattices reach lattice speeds of order 1e-3 within T steps: at
+    speeds of 1e-6 the gradient is a small remainder of O(1)-weighted adjoint
+    sums, and the FP32 adjoint populations leave ~1e-4 of it."""
+    case = tiny_random(seed)
+    case.porous = dict(case.porous, g=tuple(50.0 * v for v in case.porous["g"]))
+    T, tb, te, ck = 16, 8, 16, 5
+    say(f"adjoint random lattice {case.name} box={case.nx}x{case.ny}x{case.nz} periodic={case.periodic} "
+        f"outlet={case.outlet}")
+    o = oracle.Oracle(case)
+    J_ref, g_ref = o.grad_reverse(T, tb, te, ck, "ke")
+    s = Solver.from_case(case, adjoint_T=T, ckpt=ck)
+    J, g = s.adjoint(tb, te, T, ck, kind="ke")
+    g = g.cpu().numpy()
+    fluid = case.solid == 0
+    scale = np.abs(g_ref)[fluid].max()
+    err = np.abs(g - g_ref)[fluid].max() / scale
+    say(f"  J gpu {J:.10e} oracle {J_ref:.10e}; grad max-rel {err:.3e}")
+    assert abs(J - J_ref) <= 1e-5 * abs(J_ref) + 1e-30
+    assert err < 1e-4
 
 
 @pytest.mark.parametrize("kind", ["open", "open_extrap"])
