@@ -33,7 +33,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak
 # algorithmic bytes per fluid-cell update: populations read + written, porosity,
 # relaxation rate read + written
-B_ALG = {"fp32": 164, "fp16": 88, "bf16": 88, "fp32_aniso": 164, "fp16_aniso": 88,
+B_ALG = {"fp32": 164, "fp16": 88, "bf16": 88, "fp32_aniso": 164, "fp16_aniso": 88, "fp16_nearest": 88,
+         "bf16_nearest": 88,
          # D3Q27: 27 populations read + written
          "fp32_q27": 27 * 8 + 12, "fp16_q27": 27 * 4 + 12, "bf16_q27": 27 * 4 + 12}
 # the adjoint call per fluid cell and time step: forward pass (164), recompute
@@ -197,7 +198,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--config", default="c2")
-    ap.add_argument("--forms", default="fp16,bf16,fp32_aniso,fp32_q27,fp16_q27,adjoint")
+    ap.add_argument("--forms", default="fp16,fp16_nearest,bf16,fp32_aniso,fp32_q27,fp16_q27,adjoint")
     ap.add_argument("--adj-T", type=int, default=400)
     ap.add_argument("--adj-ckpt", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
@@ -252,6 +253,9 @@ def main():
 
             from synth import with_anisotropic_drag
             s = Solver.from_case(with_anisotropic_drag(copy.copy(case)), storage=storage)
+        elif form.endswith("_nearest"):
+            # 16-bit storage rounded to nearest value by value (the default conserves mass and momentum)
+            s = Solver.from_case(case, storage=storage, rounding="nearest")
         else:
             s = Solver.from_case(case, storage=storage)
         log(f"[bench] {form}: timing {args.steps} steps after {args.warmup} warmup")

@@ -83,8 +83,19 @@ typedef enum {
  * deviation of each population from a rest value (see shift_mode), with
  * U = 36 (so that U w_i is an exact integer for every direction) and an extra
  * factor 2^10 for FP16 (keeps typical deviations in the normal range).  FP16
- * and BF16 round to nearest even. */
+ * and BF16 round as lbm_grid.rounding says. */
 typedef enum { LBM_STORE_FP32 = 0, LBM_STORE_FP16 = 1, LBM_STORE_BF16 = 2 } lbm_storage;
+
+/* Rounding of FP16/BF16 storage.  CONSERVE (default): each cell's outputs are
+ * rounded so that its stored mass and momentum carry one rounding each: the
+ * non-axis values round to nearest even, their momentum residual moves onto
+ * the axis pairs before those round, and the whole mass residual onto the rest
+ * value, rounded last; every stored value stays within one unit in the last
+ * place.  With NEAREST every value rounds to nearest even on its own, and the
+ * rounding residuals of mass and momentum random-walk step after step (about
+ * 2-4 times the velocity error at 1000 steps on the aneurysms).  FP32 storage
+ * ignores the field. */
+typedef enum { LBM_ROUND_CONSERVE = 0, LBM_ROUND_NEAREST = 1 } lbm_rounding;
 
 /* Arithmetic of the moments, velocity, force and collision (the Carreau-Yasuda
  * transcendentals are FP32 in every mode).  FP32 rounding of the per-cell
@@ -108,6 +119,7 @@ typedef struct {
                           FP16/BF16 storage; FP64 is only available with FP32 storage */
   int velocity_set;    /* 19 (or 0): D3Q19; 27: D3Q27, the method section's lattice (weights
                           8/27, 2/27, 1/54, 1/216; no adjoint, no anisotropic permeability) */
+  int rounding;        /* lbm_rounding of FP16/BF16 storage (0: conserving, the default) */
 } lbm_grid;
 
 /* Carreau-Yasuda law (eq. carreau) in kinematic lattice units:

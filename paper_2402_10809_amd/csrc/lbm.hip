@@ -160,6 +160,15 @@ void with_storage(int storage, int shw, Fn&& fn) {
   }
 }
 
+// Rounding of the 16-bit storage forms: conserving (the default) or to
+// nearest; FP32 storage has one form.
+template <class S, class Fn>
+void with_rounding(int rounding, Fn&& fn) {
+  if constexpr (std::is_same<S, float>::value) fn(std::false_type{});
+  else if (rounding == LBM_ROUND_NEAREST) fn(std::false_type{});
+  else fn(std::true_type{});
+}
+
 // Storage type, shift mode and arithmetic: the FP64 and projected forms only
 // exist for FP32 storage.  mode: 0 FP32, 1 FP32 + projection, 2 FP64.
 template <class Fn>
@@ -305,6 +314,8 @@ lbm_status validate_grid(const lbm_grid* g) {
   if (g->nx > 2048 || g->ny > 1024 || g->nz > 1024) return fail(LBM_E_INVALID, "grid exceeds 2048 x 1024 x 1024");
   if (g->storage < 0 || g->storage > 2) return fail(LBM_E_INVALID, "unknown storage format");
   if (g->shift_mode < 0 || g->shift_mode > 1) return fail(LBM_E_INVALID, "shift_mode must be 0 or 1");
+  if (g->rounding != LBM_ROUND_CONSERVE && g->rounding != LBM_ROUND_NEAREST)
+    return fail(LBM_E_INVALID, "rounding must be LBM_ROUND_CONSERVE or LBM_ROUND_NEAREST");
   if (g->arith < 0 || g->arith > 2) return fail(LBM_E_INVALID, "unknown arithmetic mode");
   if (g->arith == LBM_ARITH_FP64 && g->storage != LBM_STORE_FP32)
     return fail(LBM_E_INVALID, "FP64 arithmetic is only available with FP32 storage");
@@ -540,12 +551,15 @@ lbm_status launch_step27(lbm_ctx* c, int diag) {
     constexpr bool SH = decltype(shw)::value;
     constexpr int NT = std::is_same<S, float>::value ? 256 : 64;
     const dim3 grid(c->sblk), block(NT);
-    with_parity(c->t, [&](auto odd) {
-      constexpr bool OD = decltype(odd)::value;
-      if (diag == 0)
-        hipLaunchKernelGGL((q27::k_step<S, SH, OD, 0, R, PJ, NT>), grid, block, 0, c->stream, c->P, b);
-      else
-        hipLaunchKernelGGL((q27::k_step<S, SH, OD, 1, R, PJ, NT>), grid, block, 0, c->stream, c->P, b);
+    with_rounding<S>(c->grid.rounding, [&](auto cr) {
+      constexpr bool CR = decltype(cr)::value;
+      with_parity(c->t, [&](auto odd) {
+        constexpr bool OD = decltype(odd)::value;
+        if (diag == 0)
+          hipLaunchKernelGGL((q27::k_step<S, SH, OD, 0, R, PJ, NT, CR>), grid, block, 0, c->stream, c->P, b);
+        else
+          hipLaunchKernelGGL((q27::k_step<S, SH, OD, 1, R, PJ, NT, CR>), grid, block, 0, c->stream, c->P, b);
+      });
     });
   });
   HIP_TRY(c, hipGetLastError());
@@ -568,26 +582,34 @@ lbm_status launch_step(lbm_ctx* c, int diag, float* rec, float* rho_rec) {
     constexpr bool SH = decltype(shw)::value;
     constexpr int NT = std::is_same<S, float>::value ? 256 : 64;
     const dim3 grid(c->sblk), block(NT);
-    with_parity(c->t, [&](auto odd) {
-      constexpr bool OD = decltype(odd)::value;
-      if (c->P.an_iters > 0) {
-        // anisotropic permeability: plain steps and diagnostics checks only
-        if (diag == 0)
-          hipLaunchKernelGGL((k_step<S, SH, OD, 0, false, R, PJ, NT, true>), grid, block, 0, c->stream, c->P, b);
-        else
-          hipLaunchKernelGGL((k_step<S, SH, OD, 1, false, R, PJ, NT, true>), grid, block, 0, c->stream, c->P, b);
-      } else if (rec) {
-        if constexpr (std::is_same<S, float>::value && !SH)
-          hipLaunchKernelGGL((k_step<S, false, OD, 0, true, R, PJ, NT>), grid, block, 0, c->stream, c->P, b);
-      } else if (diag == 0) {
-        hipLaunchKernelGGL((k_step<S, SH, OD, 0, false, R, PJ, NT>), grid, block, 0, c->stream, c->P, b);
-      } else if (diag == 1) {
-        hipLaunchKernelGGL((k_step<S, SH, OD, 1, false, R, PJ, NT>), grid, block, 0, c->stream, c->P, b);
-      } else if (diag == 2) {
-        hipLaunchKernelGGL((k_step<S, SH, OD, 2, false, R, PJ, NT>), grid, block, 0, c->stream, c->P, b);
-      } else {
-        hipLaunchKernelGGL((k_step<S, SH, OD, 3, false, R, PJ, NT>), grid, block, 0, c->stream, c->P, b);
-      }
+    with_rounding<S>(c->grid.rounding, [&](auto cr) {
+      constexpr bool CR = decltype(cr)::value;
+      with_parity(c->t, [&](auto odd) {
+        constexpr bool OD = decltype(odd)::value;
+        if (c->P.an_iters > 0) {
+          // anisotropic permeability: plain steps and diagnostics checks only
+          if (diag == 0)
+            hipLaunchKernelGGL((k_step<S, SH, OD, 0, false, R, PJ, NT, true, CR>), grid, block, 0, c->stream, c->P,
+                               b);
+          else
+            hipLaunchKernelGGL((k_step<S, SH, OD, 1, false, R, PJ, NT, true, CR>), grid, block, 0, c->stream, c->P,
+                               b);
+        } else if (diag == 0 && !rec) {
+          hipLaunchKernelGGL((k_step<S, SH, OD, 0, false, R, PJ, NT, false, CR>), grid, block, 0, c->stream, c->P, b);
+        } else if (diag == 1) {
+          hipLaunchKernelGGL((k_step<S, SH, OD, 1, false, R, PJ, NT, false, CR>), grid, block, 0, c->stream, c->P, b);
+        } else if constexpr (std::is_same<S, float>::value) {
+          // the adjoint's forms (FP32 storage only)
+          if (rec) {
+            if constexpr (!SH)
+              hipLaunchKernelGGL((k_step<S, false, OD, 0, true, R, PJ, NT>), grid, block, 0, c->stream, c->P, b);
+          } else if (diag == 2) {
+            hipLaunchKernelGGL((k_step<S, SH, OD, 2, false, R, PJ, NT>), grid, block, 0, c->stream, c->P, b);
+          } else {
+            hipLaunchKernelGGL((k_step<S, SH, OD, 3, false, R, PJ, NT>), grid, block, 0, c->stream, c->P, b);
+          }
+        }
+      });
     });
   });
   HIP_TRY(c, hipGetLastError());

@@ -203,6 +203,10 @@ struct Pop {
       return (float)__builtin_bit_cast(S, h);
     }
   }
+  // a 16-bit storage value given as its bits
+  __device__ __forceinline__ void st_bits(uint32_t voff, uint32_t soff, unsigned short h) const {
+    __builtin_amdgcn_raw_buffer_store_b16(h, r, voff, soff, 0);
+  }
   __device__ __forceinline__ void st(uint32_t voff, uint32_t soff, float v) const {
     if constexpr (std::is_same<S, float>::value) {
       __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
@@ -595,6 +599,46 @@ __device__ __forceinline__ R region_wss(uint32_t lk, const Macro<R>& M) {
   return wall_tau(M, n, tau);
 }
 
+// 16-bit storage, conserving rounding: every value is rounded to nearest
+// except that the rounding residuals of the cell's mass and momentum are
+// carried.  The non-axis values (directions 7.. in opposite pairs) are
+// rounded first; their momentum residual moves onto the three axis pairs (as
+// pair differences, which carry no mass) before those are rounded; the whole
+// mass residual moves onto the rest value, rounded last.  Every stored value
+// stays within one unit in the last place of its exact output, while the
+// cell's stored mass and momentum each carry one rounding instead of the sum
+// of all of them: with plain rounding to nearest the momentum of the 16-bit
+// forms random-walks with the storage rounding, step after step.  Works for
+// any velocity set ordered rest, axis pairs, then opposite pairs.
+template <class S, int NQ>
+__device__ __forceinline__ void conserving_round(const int (&cx)[NQ], const int (&cy)[NQ], const int (&cz)[NQ],
+                                                 const float o[NQ], unsigned short hb[NQ]) {
+  // hb[i] = v rounded to nearest in S; returns the residual (exact in FP32)
+  auto rn = [&](int i, float v) {
+    const S h = (S)v;
+    hb[i] = __builtin_bit_cast(unsigned short, h);
+    return v - (float)h;
+  };
+  float m = 0.0f, rx = 0.0f, ry = 0.0f, rz = 0.0f;
+  // the pair sum carries mass, the difference momentum along c_I
+  sfor<0, (NQ - 7) / 2>([&](auto kc) {
+    constexpr int I = 7 + 2 * decltype(kc)::value;
+    const float a = rn(I, o[I]), b = rn(I + 1, o[I + 1]);
+    m += a + b;
+    const float d = a - b;
+    if (cx[I]) rx += cx[I] > 0 ? d : -d;
+    if (cy[I]) ry += cy[I] > 0 ? d : -d;
+    if (cz[I]) rz += cz[I] > 0 ? d : -d;
+  });
+  m += rn(1, o[1] + 0.5f * rx);
+  m += rn(2, o[2] - 0.5f * rx);
+  m += rn(3, o[3] + 0.5f * ry);
+  m += rn(4, o[4] - 0.5f * ry);
+  m += rn(5, o[5] + 0.5f * rz);
+  m += rn(6, o[6] - 0.5f * rz);
+  rn(0, o[0] + m);
+}
+
 // BGK + Guo + porosity-jump collision, stored as deviations for the consumer.
 // Directions come in opposite pairs: with e = c.u and h = c.F the even part
 // (omega (A0 + C e^2) - K3 u.F + K9 e h) is shared and the odd part
@@ -609,7 +653,7 @@ __device__ __forceinline__ R region_wss(uint32_t lk, const Macro<R>& M) {
 // difference to the intended momentum (input momentum + force + porosity-jump
 // momentum) onto the three axis pairs, leaving only the final rounding of
 // each stored value.
-template <class S, bool SHW, bool UNI, bool ODD, class R, bool PROJ, bool INR = false>
+template <class S, bool SHW, bool UNI, bool ODD, class R, bool PROJ, bool INR = false, bool CR = false>
 __device__ __forceinline__ void collide_store(const Params& p, const Pop<S>& A, uint32_t c, uint32_t lk, const Pos& q,
                                               float phx_f, float d[Q], const float pt[Q], const Macro<R>& M) {
   const R phx = (R)phx_f;
@@ -693,11 +737,21 @@ __device__ __forceinline__ void collide_store(const Params& p, const Pop<S>& A, 
 #pragma unroll
     for (int i = 0; i < Q; ++i) o[i] += ksf * kw(i) * ((UNI ? phx_f : pt[i]) - 1.0f);
   }
-  sfor<0, Q>([&](auto ic) {
-    constexpr int I = decltype(ic)::value;
-    const Slot a = slot_out<I, ODD, S, INR>(p, c, lk, q);
-    A.st(a.v, a.s, o[I]);
-  });
+  if constexpr (!std::is_same<S, float>::value && CR) {
+    unsigned short hb[Q];
+    conserving_round<S, Q>(CX, CY, CZ, o, hb);
+    sfor<0, Q>([&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      const Slot a = slot_out<I, ODD, S, INR>(p, c, lk, q);
+      A.st_bits(a.v, a.s, hb[I]);
+    });
+  } else {
+    sfor<0, Q>([&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      const Slot a = slot_out<I, ODD, S, INR>(p, c, lk, q);
+      A.st(a.v, a.s, o[I]);
+    });
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -758,8 +812,9 @@ __device__ __forceinline__ void diag_terms(const Params& p, float phx, const flo
 }
 
 // Body of the step for one cell (UNI: the whole wave has uniform neighbour
-// porosity; INR: every cell of the wave is interior).
-template <class S, bool SHW, bool UNI, bool ODD, int DIAG, bool REC, class R, bool PROJ, bool AN, bool INR = false>
+// porosity; INR: every cell of the wave is interior; CR: conserving rounding
+// of 16-bit storage).
+template <class S, bool SHW, bool UNI, bool ODD, int DIAG, bool REC, class R, bool PROJ, bool AN, bool INR, bool CR>
 __device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32_t c, uint32_t lk, uint32_t t,
                                           double (&dv)[NDIAGP], float& ke_reg) {
   Pos q = position(p, c, b.code[c]);
@@ -791,7 +846,7 @@ __device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32
   if (DIAG == 1) diag_terms<R>(p, phx, d, M, lk, true, dv);
   if (DIAG == 2) ke_reg = reg ? (float)((R)0.5 * M.rho * M.uu) : 0.0f;
   if (DIAG == 3) ke_reg = (float)region_wss<R>(lk, M);
-  collide_store<S, SHW, UNI, ODD, R, PROJ, INR>(p, A, c, lk, q, phx, d, pt, M);
+  collide_store<S, SHW, UNI, ODD, R, PROJ, INR, CR>(p, A, c, lk, q, phx, d, pt, M);
 }
 
 // ---------------------------------------------------------------------------
@@ -801,7 +856,7 @@ __device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32
 // part[block].  REC: also record the pulled
 // values and omega_prev ([20][nc]) and rho.
 // ---------------------------------------------------------------------------
-template <class S, bool SHW, bool ODD, int DIAG, bool REC, class R, bool PROJ, int NT, bool AN = false>
+template <class S, bool SHW, bool ODD, int DIAG, bool REC, class R, bool PROJ, int NT, bool AN = false, bool CR = false>
 __global__ __launch_bounds__(NT) void k_step(Params p, Bufs b) {
   const uint32_t c = xcd_block(blockIdx.x, gridDim.x) * NT + threadIdx.x;
   const uint32_t t = b.tc[ODD ? 1 : 0];
@@ -814,12 +869,12 @@ __global__ __launch_bounds__(NT) void k_step(Params p, Bufs b) {
     // odd steps address the neighbours: interior waves (most of a vessel's
     // waves) need no per-direction bounce-back selects
     if (ODD && __all(!active || (lk & LK_INR))) {
-      if (active) step_cell<S, SHW, true, ODD, DIAG, REC, R, PROJ, AN, true>(p, b, c, lk, t, dv, ke_reg);
+      if (active) step_cell<S, SHW, true, ODD, DIAG, REC, R, PROJ, AN, true, CR>(p, b, c, lk, t, dv, ke_reg);
     } else {
-      if (active) step_cell<S, SHW, true, ODD, DIAG, REC, R, PROJ, AN>(p, b, c, lk, t, dv, ke_reg);
+      if (active) step_cell<S, SHW, true, ODD, DIAG, REC, R, PROJ, AN, false, CR>(p, b, c, lk, t, dv, ke_reg);
     }
   } else {
-    if (active) step_cell<S, SHW, false, ODD, DIAG, REC, R, PROJ, AN>(p, b, c, lk, t, dv, ke_reg);
+    if (active) step_cell<S, SHW, false, ODD, DIAG, REC, R, PROJ, AN, false, CR>(p, b, c, lk, t, dv, ke_reg);
   }
   if (DIAG == 1) {
     if (!active) {

@@ -21,6 +21,8 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 LBM_OK, LBM_E_INVALID, LBM_E_DEVICE, LBM_E_UNSTABLE, LBM_E_STATE, LBM_E_WORKSPACE = range(6)
 STORAGE = {"fp32": 0, "fp16": 1, "bf16": 2}
 ARITH = {"auto": 0, "fp32": 1, "fp64": 2}
+ROUNDING = {"conserve": 0, "nearest": 1}
+LBM_ROUND_CONSERVE, LBM_ROUND_NEAREST = 0, 1
 NDIAG = 12
 DIAG_NAMES = ["mass", "mom_x", "mom_y", "mom_z", "ke", "ke_region", "max_u", "min_omega", "max_omega",
               "nonfinite", "t", "wss_region"]
@@ -29,7 +31,8 @@ OBJECTIVE = {"ke": 0, "wss": 1}
 
 class lbm_grid(ct.Structure):
     _fields_ = [("nx", ct.c_int), ("ny", ct.c_int), ("nz", ct.c_int), ("periodic", ct.c_int * 3),
-                ("storage", ct.c_int), ("shift_mode", ct.c_int), ("arith", ct.c_int), ("velocity_set", ct.c_int)]
+                ("storage", ct.c_int), ("shift_mode", ct.c_int), ("arith", ct.c_int), ("velocity_set", ct.c_int),
+                ("rounding", ct.c_int)]
 
 
 class lbm_rheology(ct.Structure):
@@ -133,11 +136,12 @@ class Solver:
     outlet: None, rho_out (constant-density outflow) or "extrapolation" (the non-reflecting outflow).
     adjoint_T/ckpt: reserve workspace for lbm_adjoint runs of up to adjoint_T steps.
     lattice: 19 (D3Q19) or 27 (D3Q27).
+    rounding: "conserve" (default) or "nearest", the rounding of FP16/BF16 storage.
     """
 
     def __init__(self, solid, phi, *, periodic=(False, False, False), storage="fp32", shift_mode=0, arith="auto",
                  region=None, rheology=None, porous=None, inlet=None, outlet=None, adjoint_T=0, ckpt=64,
-                 lattice=19, device=None, stream=None):
+                 lattice=19, rounding="conserve", device=None, stream=None):
         import torch
 
         self.torch = torch
@@ -155,6 +159,7 @@ class Solver:
         g.shift_mode = int(shift_mode)
         g.arith = ARITH[arith]
         g.velocity_set = int(lattice)
+        g.rounding = ROUNDING[rounding]
         self.q = 27 if int(lattice) == 27 else 19
         self.grid = g
         self.storage = storage

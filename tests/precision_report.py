@@ -2,7 +2,8 @@
 resolved-versus-averaged coil comparison.  Not a test: it prints tables.
 
 Part A, for the 192x128x128 aneurysm and the 2x-coarsened copy of the
-512x320x320 aneurysm: every storage form (FP32, FP16, BF16) and shift mode,
+512x320x320 aneurysm: every storage form (FP32, FP16, BF16), shift mode and
+16-bit rounding (conserving "c", to nearest "n"),
 max-relative and relative-L2 errors of u and of the shear rate against the
 oracle after 1000 steps and at the final step (20 000 by default).
 
@@ -37,7 +38,10 @@ import oracle  # noqa: E402
 from paper_2402_10809_amd import Solver  # noqa: E402
 from synth import make_config  # noqa: E402
 
-FORMS = [("fp32", 0), ("fp32", 1), ("fp16", 0), ("fp16", 1), ("bf16", 0), ("bf16", 1)]
+# (storage, shift mode, 16-bit rounding)
+FORMS = [("fp32", 0, "conserve"), ("fp32", 1, "conserve"),
+         ("fp16", 0, "conserve"), ("fp16", 1, "conserve"), ("fp16", 0, "nearest"), ("fp16", 1, "nearest"),
+         ("bf16", 0, "conserve"), ("bf16", 1, "conserve"), ("bf16", 0, "nearest"), ("bf16", 1, "nearest")]
 
 
 def say(msg):
@@ -81,15 +85,16 @@ def part_a(steps_final):
             refs[tc] = (m["u"], m["shear"])
             say(f"   oracle at step {tc} ({time.time() - t0:.0f} s)")
         say(f"   {'form':10s} {'step':>6s} {'u max-rel':>10s} {'u rel-L2':>10s} {'g max-rel':>10s} {'g rel-L2':>10s}")
-        for storage, shift in FORMS:
-            s = Solver.from_case(case, storage=storage, shift_mode=shift)
+        for storage, shift, rounding in FORMS:
+            s = Solver.from_case(case, storage=storage, shift_mode=shift, rounding=rounding)
+            label = f"{storage}/{shift}" + ("" if storage == "fp32" else f"/{rounding[0]}")
             t = 0
             for tc in checkpoints:
                 s.step(tc - t)
                 t = tc
                 u, g = gpu_fields(s)
                 ur, gr = refs[tc]
-                say(f"   {storage + '/' + str(shift):10s} {tc:6d} {max_rel(u, ur):10.3e} {rel_l2(u, ur):10.3e} "
+                say(f"   {label:10s} {tc:6d} {max_rel(u, ur):10.3e} {rel_l2(u, ur):10.3e} "
                     f"{max_rel(g, gr):10.3e} {rel_l2(g, gr):10.3e}")
             s.close()
 

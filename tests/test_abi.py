@@ -55,6 +55,12 @@ def test_workspace_size_and_validation():
         lbm.lbm_workspace_size(_grid(nx=4096), np.zeros((5, 6, 4096), np.uint8))
     with pytest.raises(lbm.LBMError):
         lbm.lbm_workspace_size(g, np.ones((5, 6, 8), np.uint8))  # no fluid
+    g_round = _grid(storage=1)
+    g_round.rounding = lbm.LBM_ROUND_NEAREST
+    assert lbm.lbm_workspace_size(g_round, solid) == lbm.lbm_workspace_size(g16, solid)
+    g_round.rounding = 2  # neither conserving nor nearest
+    with pytest.raises(lbm.LBMError):
+        lbm.lbm_workspace_size(g_round, solid)
     # more compact cells than 32-bit byte offsets into 19 FP32 planes allow
     # (58.7 M all-fluid cells); the same box with a sparse mask is accepted
     big = np.zeros((224, 512, 512), np.uint8)
