@@ -264,10 +264,12 @@ lbm_status lbm_reset(lbm_ctx* ctx);
  * adjoint populations.  Either outflow kind; with the extrapolation outflow
  * the outflow cells' unknowns are state, and their dependence on the previous
  * step's values is part of the reverse sweep.  Needs a workspace sized for
- * (T, ckpt_every) or larger; FP32 storage, shift mode 0, no Forchheimer drag,
- * isotropic permeability, D3Q19, a region with a fluid cell (with a wall cell
- * for LBM_OBJ_WSS), 0 <= t_begin < t_end <= T.  At a wall cell where tau = 0
- * the WSS term contributes no gradient (|tau| is not differentiable there).
+ * (T, ckpt_every) or larger; FP32 storage, shift mode 0, isotropic
+ * permeability (with or without Forchheimer drag), D3Q19, a region with a
+ * fluid cell (with a wall cell for LBM_OBJ_WSS), 0 <= t_begin < t_end <= T.
+ * Non-differentiable points take derivative 0: tau = 0 at a wall cell (|tau|),
+ * u = 0 and v = 0 in the Forchheimer drag (|u|, |v|); at phi = 1 the
+ * derivative is the one from below (phi <= 1).
  *   J:       host, 1 double
  *   dJ_dphi: device, nx*ny*nz floats (box layout, 0 off the fluid), or NULL:
  *            then only J is computed (the forward pass, no checkpoints; the

@@ -415,19 +415,23 @@ void cell_update(const oracle_case& c, const Shape& S, const T f[Q], T omega_pre
   // that phi = 1 (no medium) gives 1/k = 0
   T om = 1.0 - phi;
   T invk = c.kc * om * om / (c.d * c.d * phi * phi * phi);
+  // sqrt(1/k), written for 0 < phi <= 1 as sqrt(K_c) (1 - phi) / (d phi^(3/2)):
+  // the same value, and differentiable at phi = 1 from below (the square root
+  // of (1 - phi)^2 has a kink there, which the dual numbers would flatten)
+  T sik = std::sqrt(c.kc) * om / (c.d * phi * Sqrt(phi));
   T CF = 0;
   if (c.forchheimer) CF = 1.75 / Sqrt(150.0 * phi * phi * phi);
   if (!S.on) {
     // explicit velocity: u = v / (C0 + sqrt(C0^2 + C1 |v|))
     T C0 = 0.5 + phi * c.nu_d * invk / 4.0;
-    T C1 = phi * phi * CF * Sqrt(invk) / 2.0;
+    T C1 = phi * phi * CF * sik / 2.0;
     T vn = Sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
     T den = C0 + Sqrt(C0 * C0 + C1 * vn);
     for (int a = 0; a < 3; ++a) r.u[a] = v[a] / den;
     // force density rho f(u): body force, Darcy and Forchheimer drag
     T un = Sqrt(r.u[0] * r.u[0] + r.u[1] * r.u[1] + r.u[2] * r.u[2]);
     for (int a = 0; a < 3; ++a)
-      r.F[a] = rho * (c.g[a] - phi * phi * c.nu_d * invk * r.u[a] - phi * phi * phi * CF * Sqrt(invk) * un * r.u[a]);
+      r.F[a] = rho * (c.g[a] - phi * phi * c.nu_d * invk * r.u[a] - phi * phi * phi * CF * sik * un * r.u[a]);
   } else {
     // anisotropic: A = Id + (phi nu / 2) K^-1, B = (phi^2 C_F / 2) K^-1/2,
     // u_{m+1} = (A + |u_m| B)^-1 v from u_0 = v (the Remark's fixed point)
@@ -435,7 +439,7 @@ void cell_update(const oracle_case& c, const Shape& S, const T f[Q], T omega_pre
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) {
         Ki[i][j] = invk * S.Minv[i][j];
-        Kh[i][j] = Sqrt(invk) * S.Mhi[i][j];
+        Kh[i][j] = sik * S.Mhi[i][j];
       }
     T A[3][3], B[3][3];
     for (int i = 0; i < 3; ++i)

@@ -23,8 +23,9 @@
 // step of n-1 adds (1 - c_s) of them to the outflow cell's unknowns and c_s of
 // them to the -x neighbour's pulled values.
 //
-// Supported: FP32 storage, shift mode 0, no Forchheimer drag.  The recompute
-// uses the same arithmetic type as the forward step.
+// Supported: FP32 storage, shift mode 0, isotropic permeability (with or
+// without Forchheimer drag), D3Q19.  The recompute uses the same arithmetic
+// type as the forward step.
 #pragma once
 #include "step.hpp"
 
@@ -223,15 +224,50 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, uint32_t
   const R eh = (reg && kind == 0) ? (R)ew : 0.0;
   rhoh += eh * 0.5 * uu;
   uhx += eh * rho * ux; uhy += eh * rho * uy; uhz += eh * rho * uz;
-  // force F = rho (g - D u), D = phi^2 nu / k
+  // force F = rho (g - D u - E |u| u), D = phi^2 nu / k and, with Forchheimer
+  // drag, E = phi^3 C_F sqrt(1/k) = K2 (1 - phi) for 0 < phi <= 1 (C_F = 1.75 /
+  // sqrt(150 phi^3)), K2 = 1.75 sqrt(K_c / (150 d^2)); d|u|/du := 0 at u = 0
+  const bool forch = p.forch != 0;
+  const R K2 = 1.75 * rsqrt_(kc.kcd * (1.0 / 150.0));
+  const R E = forch ? K2 * om1 : 0.0;
+  const R un = forch ? rsqrt_(uu) : 0.0;
   rhoh += (Fhx * Fx + Fhy * Fy + Fhz * Fz) * irho;
   uhx -= rho * D * Fhx; uhy -= rho * D * Fhy; uhz -= rho * D * Fhz;
   const R Dh = -rho * (Fhx * ux + Fhy * uy + Fhz * uz);
   phh += Dh * (-kn * (1.0 - phx * phx) * iphi * iphi);
-  // u = v / (2 C0), C0 = 1/2 + (phi nu / k)/4
-  const R i2c = fast_rcp(2.0 * C0);
-  const R vhx = uhx * i2c, vhy = uhy * i2c, vhz = uhz * i2c;
-  const R C0h = -(uhx * ux + uhy * uy + uhz * uz) * 2.0 * i2c;
+  if (forch && un > 0.0) {
+    const R ku = rho * E * (Fhx * ux + Fhy * uy + Fhz * uz) / un;
+    uhx -= rho * E * un * Fhx + ku * ux;
+    uhy -= rho * E * un * Fhy + ku * uy;
+    uhz -= rho * E * un * Fhz + ku * uz;
+    phh -= Dh * un * K2;
+  }
+  // u = v / den: without Forchheimer den = 2 C0; with it den = C0 + sqrt(C0^2
+  // + C1 |v|), C1 = phi^2 C_F sqrt(1/k) / 2 = K2 (1 - phi) / (2 phi)
+  R vhx, vhy, vhz, C0h;
+  if (!forch) {
+    const R i2c = fast_rcp(2.0 * C0);
+    vhx = uhx * i2c; vhy = uhy * i2c; vhz = uhz * i2c;
+    C0h = -(uhx * ux + uhy * uy + uhz * uz) * 2.0 * i2c;
+  } else {
+    const R C1 = 0.5 * K2 * om1 * iphi;
+    const R vx = mx * fast_rcp(S) + 0.5 * kc.gx * iphi, vy = my * fast_rcp(S) + 0.5 * kc.gy * iphi,
+            vz = mz * fast_rcp(S) + 0.5 * kc.gz * iphi;
+    const R vn = rsqrt_(vx * vx + vy * vy + vz * vz);
+    const R sq = rsqrt_(C0 * C0 + C1 * vn);
+    const R iden = fast_rcp(C0 + sq);
+    vhx = uhx * iden; vhy = uhy * iden; vhz = uhz * iden;
+    const R denh = -(uhx * ux + uhy * uy + uhz * uz) * iden;
+    const R isq = sq > 0.0 ? 0.5 * fast_rcp(sq) : 0.0;
+    C0h = denh * (1.0 + 2.0 * C0 * isq);
+    const R C1h = denh * vn * isq;
+    const R vnh = denh * C1 * isq;
+    if (vn > 0.0) {
+      const R g = vnh * fast_rcp(vn);
+      vhx += g * vx; vhy += g * vy; vhz += g * vz;
+    }
+    phh += C1h * (-0.5 * K2 * iphi * iphi);
+  }
   phh += 0.25 * C0h * (-2.0 * kn * om1 * iphi * iphi * iphi);
   // v = m / S + g / (2 phi)
   const R iS = fast_rcp(S);

@@ -14,17 +14,21 @@ from synth import fd_voxels, tiny_case
 
 
 def _case(seed, lattice="open"):
-    c = tiny_case(lattice, seed=seed)
+    forch = lattice.endswith("_forch")
+    c = tiny_case(lattice[:-6] if forch else lattice, seed=seed)
+    if forch:
+        c.porous = dict(c.porous, forchheimer=1)
     c.wave = (0.04, 0.5, 20.0)
     c.rheology = dict(c.rheology, lam=200.0)  # shear-thinning active at these speeds
     return c
 
 
 @pytest.mark.parametrize("kind", ["ke", "wss"])
-@pytest.mark.parametrize("seed,lattice", [(0, "open"), (1, "open"), (0, "open_extrap"), (1, "open_extrap")])
+@pytest.mark.parametrize("seed,lattice", [(0, "open"), (1, "open"), (0, "open_extrap"), (1, "open_extrap"),
+                                          (0, "open_forch"), (1, "open_forch")])
 def test_reverse_sweep_matches_dual_and_fd(seed, lattice, kind):
     """Also with the extrapolation outflow, whose unknowns are state carried
-    from step to step."""
+    from step to step, and with Forchheimer drag."""
     case = _case(seed, lattice)
     T, tb, te, ckpt = 24, 12, 24, 5
     o = oracle.Oracle(case)
