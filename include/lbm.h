@@ -264,8 +264,9 @@ lbm_status lbm_reset(lbm_ctx* ctx);
  * adjoint populations.  Either outflow kind; with the extrapolation outflow
  * the outflow cells' unknowns are state, and their dependence on the previous
  * step's values is part of the reverse sweep.  Needs a workspace sized for
- * (T, ckpt_every) or larger; FP32 storage, shift mode 0, isotropic
- * permeability (with or without Forchheimer drag), D3Q19, a region with a
+ * (T, ckpt_every) or larger; FP32 storage, shift mode 0, D3Q19 (with or
+ * without Forchheimer drag, isotropic or anisotropic permeability: the
+ * fixed-point iterates are differentiated as iterated), a region with a
  * fluid cell (with a wall cell for LBM_OBJ_WSS), 0 <= t_begin < t_end <= T.
  * Non-differentiable points take derivative 0: tau = 0 at a wall cell (|tau|),
  * u = 0 and v = 0 in the Forchheimer drag (|u|, |v|); at phi = 1 the

@@ -23,9 +23,12 @@
 // step of n-1 adds (1 - c_s) of them to the outflow cell's unknowns and c_s of
 // them to the -x neighbour's pulled values.
 //
-// Supported: FP32 storage, shift mode 0, isotropic permeability (with or
-// without Forchheimer drag), D3Q19.  The recompute uses the same arithmetic
-// type as the forward step.
+// AN: the anisotropic permeability of the method section's Remark, whose
+// fixed-point iterates are recomputed from v inside the reverse step.
+//
+// Supported: FP32 storage, shift mode 0, with or without Forchheimer drag,
+// isotropic or anisotropic permeability, D3Q19.  The recompute uses the same
+// arithmetic type as the forward step.
 #pragma once
 #include "step.hpp"
 
@@ -52,6 +55,7 @@ struct AdjBufs {
 // recursion has the same slow modes as the forward map, so FP32 rounding of
 // per-cell scalars would accumulate the same way); the adjoint populations are
 // stored in FP32.
+template <bool AN>
 __global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, uint32_t t, float ew, int kind) {
   using R = double;
   const uint32_t c = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
@@ -73,7 +77,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, uint32_t
   const bool extrap = p.outlet == 2;
   if (!(extrap && (lk & LK_OUT))) open_fill(p, q.row, lk, t, a.shape, a.wave, nullptr, d);
   Macro<R> M;
-  macro<R>(p, phx_f, d, omp, M);
+  macro<R, AN>(p, phx_f, d, omp, M);
   const R phx = (R)phx_f;
   const R iphi = fast_rcp(phx);
   const Sums<R> sm = moment_sums<R>(d);
@@ -226,51 +230,127 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, uint32_t
   uhx += eh * rho * ux; uhy += eh * rho * uy; uhz += eh * rho * uz;
   // force F = rho (g - D u - E |u| u), D = phi^2 nu / k and, with Forchheimer
   // drag, E = phi^3 C_F sqrt(1/k) = K2 (1 - phi) for 0 < phi <= 1 (C_F = 1.75 /
-  // sqrt(150 phi^3)), K2 = 1.75 sqrt(K_c / (150 d^2)); d|u|/du := 0 at u = 0
+  // sqrt(150 phi^3)), K2 = 1.75 sqrt(K_c / (150 d^2)); d|u|/du := 0 at u = 0.
+  // Anisotropic (AN): F = rho (g - D M^-1 u - E |u| M^-1/2 u).
   const bool forch = p.forch != 0;
   const R K2 = 1.75 * rsqrt_(kc.kcd * (1.0 / 150.0));
   const R E = forch ? K2 * om1 : 0.0;
-  const R un = forch ? rsqrt_(uu) : 0.0;
+  const R un = rsqrt_(uu);
+  const R dD = -kn * (1.0 - phx * phx) * iphi * iphi;      // dD/dphi
+  const R ddark = -2.0 * kn * om1 * iphi * iphi * iphi;    // d(phi nu / k)/dphi
   rhoh += (Fhx * Fx + Fhy * Fy + Fhz * Fz) * irho;
-  uhx -= rho * D * Fhx; uhy -= rho * D * Fhy; uhz -= rho * D * Fhz;
-  const R Dh = -rho * (Fhx * ux + Fhy * uy + Fhz * uz);
-  phh += Dh * (-kn * (1.0 - phx * phx) * iphi * iphi);
-  if (forch && un > 0.0) {
-    const R ku = rho * E * (Fhx * ux + Fhy * uy + Fhz * uz) / un;
-    uhx -= rho * E * un * Fhx + ku * ux;
-    uhy -= rho * E * un * Fhy + ku * uy;
-    uhz -= rho * E * un * Fhz + ku * uz;
-    phh -= Dh * un * K2;
-  }
-  // u = v / den: without Forchheimer den = 2 C0; with it den = C0 + sqrt(C0^2
-  // + C1 |v|), C1 = phi^2 C_F sqrt(1/k) / 2 = K2 (1 - phi) / (2 phi)
-  R vhx, vhy, vhz, C0h;
-  if (!forch) {
-    const R i2c = fast_rcp(2.0 * C0);
-    vhx = uhx * i2c; vhy = uhy * i2c; vhz = uhz * i2c;
-    C0h = -(uhx * ux + uhy * uy + uhz * uz) * 2.0 * i2c;
-  } else {
-    const R C1 = 0.5 * K2 * om1 * iphi;
-    const R vx = mx * fast_rcp(S) + 0.5 * kc.gx * iphi, vy = my * fast_rcp(S) + 0.5 * kc.gy * iphi,
-            vz = mz * fast_rcp(S) + 0.5 * kc.gz * iphi;
-    const R vn = rsqrt_(vx * vx + vy * vy + vz * vz);
-    const R sq = rsqrt_(C0 * C0 + C1 * vn);
-    const R iden = fast_rcp(C0 + sq);
-    vhx = uhx * iden; vhy = uhy * iden; vhz = uhz * iden;
-    const R denh = -(uhx * ux + uhy * uy + uhz * uz) * iden;
-    const R isq = sq > 0.0 ? 0.5 * fast_rcp(sq) : 0.0;
-    C0h = denh * (1.0 + 2.0 * C0 * isq);
-    const R C1h = denh * vn * isq;
-    const R vnh = denh * C1 * isq;
-    if (vn > 0.0) {
-      const R g = vnh * fast_rcp(vn);
-      vhx += g * vx; vhy += g * vy; vhz += g * vz;
-    }
-    phh += C1h * (-0.5 * K2 * iphi * iphi);
-  }
-  phh += 0.25 * C0h * (-2.0 * kn * om1 * iphi * iphi * iphi);
-  // v = m / S + g / (2 phi)
+  R vhx, vhy, vhz;
   const R iS = fast_rcp(S);
+  const R vx = mx * iS + 0.5 * kc.gx * iphi, vy = my * iS + 0.5 * kc.gy * iphi, vz = mz * iS + 0.5 * kc.gz * iphi;
+  if constexpr (AN) {
+    R kdx, kdy, kdz, khx, khy, khz, mfx, mfy, mfz, hfx, hfy, hfz;
+    sym_mv(kc.Mi, ux, uy, uz, kdx, kdy, kdz);
+    sym_mv(kc.Mh, ux, uy, uz, khx, khy, khz);
+    sym_mv(kc.Mi, Fhx, Fhy, Fhz, mfx, mfy, mfz);
+    sym_mv(kc.Mh, Fhx, Fhy, Fhz, hfx, hfy, hfz);
+    uhx -= rho * (D * mfx + E * un * hfx);
+    uhy -= rho * (D * mfy + E * un * hfy);
+    uhz -= rho * (D * mfz + E * un * hfz);
+    const R Fkd = Fhx * kdx + Fhy * kdy + Fhz * kdz, Fkh = Fhx * khx + Fhy * khy + Fhz * khz;
+    if (forch && un > 0.0) {
+      const R t = rho * E * Fkh / un;
+      uhx -= t * ux; uhy -= t * uy; uhz -= t * uz;
+      phh += rho * un * Fkh * K2;
+    }
+    phh -= rho * Fkd * dD;
+    // the fixed-point iterates u_{m+1} = X_m^-1 v, X_m = A + |u_m| B, u_0 = v,
+    // A = Id + (phi nu / 2k) M^-1, B = C1 M^-1/2: back through the iterates,
+    // recomputing u_m from v each time
+    const R ha = 0.5 * dark, hb = forch ? 0.5 * K2 * om1 * iphi : 0.0;
+    R Am[6], Bm[6], Ah[6], Bh[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      Am[k] = ha * kc.Mi[k] + (k < 3 ? 1.0 : 0.0);
+      Bm[k] = hb * kc.Mh[k];
+      Ah[k] = 0.0;
+      Bh[k] = 0.0;
+    }
+    // y = X^-1 b for X = A + n B (symmetric: the adjugate over the determinant)
+    auto solve = [&](R n, R bx, R by, R bz, R& yx, R& yy, R& yz) {
+      R X[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) X[k] = Am[k] + n * Bm[k];
+      const R a00 = X[1] * X[2] - X[5] * X[5], a11 = X[0] * X[2] - X[4] * X[4], a22 = X[0] * X[1] - X[3] * X[3];
+      const R a01 = X[4] * X[5] - X[3] * X[2], a02 = X[3] * X[5] - X[4] * X[1], a12 = X[3] * X[4] - X[0] * X[5];
+      const R idet = fast_rcp(X[0] * a00 + X[3] * a01 + X[4] * a02);
+      yx = (a00 * bx + a01 * by + a02 * bz) * idet;
+      yy = (a01 * bx + a11 * by + a12 * bz) * idet;
+      yz = (a02 * bx + a12 * by + a22 * bz) * idet;
+    };
+    R ubx = uhx, uby = uhy, ubz = uhz;  // adjoint of u_{m+1}
+    vhx = 0.0; vhy = 0.0; vhz = 0.0;
+    for (int m = p.an_iters - 1; m >= 0; --m) {
+      R ax = vx, ay = vy, az = vz;  // u_m
+      for (int j = 0; j < m; ++j) solve(rsqrt_(ax * ax + ay * ay + az * az), vx, vy, vz, ax, ay, az);
+      const R n = rsqrt_(ax * ax + ay * ay + az * az);
+      R bx, by, bz, wx, wy, wz;
+      solve(n, vx, vy, vz, bx, by, bz);     // u_{m+1}
+      solve(n, ubx, uby, ubz, wx, wy, wz);  // X^-1 applied to the adjoint (X symmetric)
+      vhx += wx; vhy += wy; vhz += wz;
+      const R Xh[6] = {-wx * bx, -wy * by, -wz * bz, -(wx * by + wy * bx), -(wx * bz + wz * bx),
+                       -(wy * bz + wz * by)};
+      R nh = 0.0;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        Ah[k] += Xh[k];
+        Bh[k] += n * Xh[k];
+        nh += Xh[k] * Bm[k];
+      }
+      const R g = n > 0.0 ? nh * fast_rcp(n) : 0.0;
+      ubx = g * ax; uby = g * ay; ubz = g * az;
+    }
+    vhx += ubx; vhy += uby; vhz += ubz;  // u_0 = v
+    R aM = 0.0, bM = 0.0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      aM += Ah[k] * kc.Mi[k];
+      bM += Bh[k] * kc.Mh[k];
+    }
+    phh += aM * 0.5 * ddark;
+    if (forch) phh += bM * (-0.5 * K2 * iphi * iphi);
+  } else {
+    uhx -= rho * D * Fhx; uhy -= rho * D * Fhy; uhz -= rho * D * Fhz;
+    const R Dh = -rho * (Fhx * ux + Fhy * uy + Fhz * uz);
+    phh += Dh * dD;
+    if (forch && un > 0.0) {
+      const R ku = rho * E * (Fhx * ux + Fhy * uy + Fhz * uz) / un;
+      uhx -= rho * E * un * Fhx + ku * ux;
+      uhy -= rho * E * un * Fhy + ku * uy;
+      uhz -= rho * E * un * Fhz + ku * uz;
+      phh -= Dh * un * K2;
+    }
+    // u = v / den: without Forchheimer den = 2 C0; with it den = C0 + sqrt(C0^2
+    // + C1 |v|), C1 = phi^2 C_F sqrt(1/k) / 2 = K2 (1 - phi) / (2 phi)
+    R C0h;
+    if (!forch) {
+      const R i2c = fast_rcp(2.0 * C0);
+      vhx = uhx * i2c; vhy = uhy * i2c; vhz = uhz * i2c;
+      C0h = -(uhx * ux + uhy * uy + uhz * uz) * 2.0 * i2c;
+    } else {
+      const R C1 = 0.5 * K2 * om1 * iphi;
+      const R vn = rsqrt_(vx * vx + vy * vy + vz * vz);
+      const R sq = rsqrt_(C0 * C0 + C1 * vn);
+      const R iden = fast_rcp(C0 + sq);
+      vhx = uhx * iden; vhy = uhy * iden; vhz = uhz * iden;
+      const R denh = -(uhx * ux + uhy * uy + uhz * uz) * iden;
+      const R isq = sq > 0.0 ? 0.5 * fast_rcp(sq) : 0.0;
+      C0h = denh * (1.0 + 2.0 * C0 * isq);
+      const R C1h = denh * vn * isq;
+      const R vnh = denh * C1 * isq;
+      if (vn > 0.0) {
+        const R g = vnh * fast_rcp(vn);
+        vhx += g * vx; vhy += g * vy; vhz += g * vz;
+      }
+      phh += C1h * (-0.5 * K2 * iphi * iphi);
+    }
+    phh += 0.25 * C0h * ddark;
+  }
+  // v = m / S + g / (2 phi)
   const R mhx = vhx * iS, mhy = vhy * iS, mhz = vhz * iS;
   R Sh = -(vhx * mx + vhy * my + vhz * mz) * iS * iS;
   phh -= (vhx * kc.gx + vhy * kc.gy + vhz * kc.gz) * 0.5 * iphi * iphi;

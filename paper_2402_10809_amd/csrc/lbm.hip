@@ -586,29 +586,30 @@ lbm_status launch_step(lbm_ctx* c, int diag, float* rec, float* rho_rec) {
       constexpr bool CR = decltype(cr)::value;
       with_parity(c->t, [&](auto odd) {
         constexpr bool OD = decltype(odd)::value;
-        if (c->P.an_iters > 0) {
-          // anisotropic permeability: plain steps and diagnostics checks only
-          if (diag == 0)
-            hipLaunchKernelGGL((k_step<S, SH, OD, 0, false, R, PJ, NT, true, CR>), grid, block, 0, c->stream, c->P,
+        // AN: anisotropic permeability (every form, the adjoint's included)
+        auto go = [&](auto an) {
+          constexpr bool AN = decltype(an)::value;
+          if (diag == 0 && !rec) {
+            hipLaunchKernelGGL((k_step<S, SH, OD, 0, false, R, PJ, NT, AN, CR>), grid, block, 0, c->stream, c->P,
                                b);
-          else
-            hipLaunchKernelGGL((k_step<S, SH, OD, 1, false, R, PJ, NT, true, CR>), grid, block, 0, c->stream, c->P,
+          } else if (diag == 1) {
+            hipLaunchKernelGGL((k_step<S, SH, OD, 1, false, R, PJ, NT, AN, CR>), grid, block, 0, c->stream, c->P,
                                b);
-        } else if (diag == 0 && !rec) {
-          hipLaunchKernelGGL((k_step<S, SH, OD, 0, false, R, PJ, NT, false, CR>), grid, block, 0, c->stream, c->P, b);
-        } else if (diag == 1) {
-          hipLaunchKernelGGL((k_step<S, SH, OD, 1, false, R, PJ, NT, false, CR>), grid, block, 0, c->stream, c->P, b);
-        } else if constexpr (std::is_same<S, float>::value) {
-          // the adjoint's forms (FP32 storage only)
-          if (rec) {
-            if constexpr (!SH)
-              hipLaunchKernelGGL((k_step<S, false, OD, 0, true, R, PJ, NT>), grid, block, 0, c->stream, c->P, b);
-          } else if (diag == 2) {
-            hipLaunchKernelGGL((k_step<S, SH, OD, 2, false, R, PJ, NT>), grid, block, 0, c->stream, c->P, b);
-          } else {
-            hipLaunchKernelGGL((k_step<S, SH, OD, 3, false, R, PJ, NT>), grid, block, 0, c->stream, c->P, b);
+          } else if constexpr (std::is_same<S, float>::value) {
+            // the adjoint's forms (FP32 storage only)
+            if (rec) {
+              if constexpr (!SH)
+                hipLaunchKernelGGL((k_step<S, false, OD, 0, true, R, PJ, NT, AN>), grid, block, 0, c->stream, c->P,
+                                   b);
+            } else if (diag == 2) {
+              hipLaunchKernelGGL((k_step<S, SH, OD, 2, false, R, PJ, NT, AN>), grid, block, 0, c->stream, c->P, b);
+            } else {
+              hipLaunchKernelGGL((k_step<S, SH, OD, 3, false, R, PJ, NT, AN>), grid, block, 0, c->stream, c->P, b);
+            }
           }
-        }
+        };
+        if (c->P.an_iters > 0) go(std::true_type{});
+        else go(std::false_type{});
       });
     });
   });

@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 from paper_2402_10809_amd import Solver, lbm
-from synth import aneurysm_case, fd_voxels, tiny_case, tiny_random
+from synth import aneurysm_case, aniso_shape, fd_voxels, tiny_case, tiny_random
 
 pytestmark = pytest.mark.gpu
 
@@ -23,15 +23,18 @@ def say(msg):
 
 def _tiny(kind, seed):
     forch = kind.endswith("_forch")
-    c = tiny_case(kind[:-6] if forch else kind, seed=seed)
+    aniso = kind.endswith("_aniso")
+    c = tiny_case(kind.rsplit("_", 1)[0] if (forch or aniso) else kind, seed=seed)
     if kind.startswith("open"):
         c.wave = (0.04, 0.5, 20.0)
-    if forch:
+    if forch or aniso:
         # grain size 0.5 and a 0.1 inflow: the Forchheimer terms move the
         # gradient by 39 % of its maximum here, so each of them is resolved
         c.porous = dict(c.porous, forchheimer=1, d=0.5)
         if kind.startswith("open"):
             c.wave = (0.1, 0.5, 20.0)
+    if aniso:
+        c.porous = dict(c.porous, aniso=aniso_shape(), aniso_iters=6)
     c.rheology = dict(c.rheology, lam=200.0)
     return c
 
@@ -41,7 +44,8 @@ def _tiny(kind, seed):
                                                  ("open_extrap", 0, "ke"), ("open_extrap", 1, "ke"),
                                                  ("open_extrap", 0, "wss"), ("open_forch", 0, "ke"),
                                                  ("open_forch", 1, "ke"), ("open_forch", 0, "wss"),
-                                                 ("periodic_forch", 0, "ke")])
+                                                 ("periodic_forch", 0, "ke"), ("open_aniso", 0, "ke"),
+                                                 ("open_aniso", 1, "ke"), ("open_aniso", 0, "wss")])
 def test_adjoint_matches_oracle_reverse_sweep(kind, seed, objective):
     case = _tiny(kind, seed)
     T, tb, te, ck = 30, 15, 30, 7
@@ -112,11 +116,10 @@ def test_adjoint_rejects_unsupported():
         s2.adjoint(2, 12, 10, 5)   # window beyond T
     with pytest.raises(lbm.LBMError):
         s2.adjoint(2, 10, 40, 5)   # workspace sized for T = 10
-    an = _tiny("open", 3)
-    an.porous = dict(an.porous, aniso=(1.0, 2.0, 1.0, 0.1, 0.0, 0.0), aniso_iters=4)
-    s3 = Solver.from_case(an, adjoint_T=10, ckpt=5)
+    from synth import as_d3q27
+    s3 = Solver.from_case(as_d3q27(_tiny("open", 3)), adjoint_T=10, ckpt=5)
     with pytest.raises(lbm.LBMError):
-        s3.adjoint(2, 10, 10, 5)   # anisotropic permeability
+        s3.adjoint(2, 10, 10, 5)   # D3Q27
 
 
 @pytest.mark.parametrize("objective,outlet", [("ke", 1), ("wss", 1), ("ke", 2), ("wss", 2)])
