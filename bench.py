@@ -208,7 +208,7 @@ def main():
     ap.add_argument("--only", default=None, help="time one storage form only (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path.",
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the solver runs on one GPU; its sharding is a design only.",
               file=sys.stderr)
         sys.exit(2)
 
