@@ -208,7 +208,7 @@ def main():
     ap.add_argument("--only", default=None, help="time one storage form only (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the solver runs on one GPU; its sharding is a design only.",
+        print(f"bench.py measures one GPU (got --gpus {args.gpus}): the solver runs on one GPU, and its sharding is a design only.",
               file=sys.stderr)
         sys.exit(2)
 
