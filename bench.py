@@ -198,7 +198,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--config", default="c2")
-    ap.add_argument("--forms", default="fp16,fp16_nearest,bf16,fp32_aniso,fp32_q27,fp16_q27,adjoint")
+    ap.add_argument("--forms", default="fp16,fp16_nearest,bf16,fp32_aniso,fp32_q27,fp16_q27,adjoint,adjoint_aniso")
     ap.add_argument("--adj-T", type=int, default=400)
     ap.add_argument("--adj-ckpt", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
@@ -229,17 +229,26 @@ def main():
     forms = ["fp32"] + [f for f in args.forms.split(",") if f]
     if args.only:
         forms = [args.only]
-    adjoint = None
-    if "adjoint" in forms:
-        forms.remove("adjoint")
+    adjoints = {}
+    for aform in [f for f in forms if f.startswith("adjoint")]:
+        forms.remove(aform)
         T, ck = args.adj_T, args.adj_ckpt
-        log(f"[bench] adjoint: T={T}, checkpoint every {ck}, window [{T // 2}, {T})")
-        dt, ok = time_adjoint(torch, case, T, ck)
+        acase = case
+        if aform == "adjoint_aniso":
+            # the anisotropic medium (Forchheimer on, 6 fixed-point iterations):
+            # the same bytes per cell-step, more arithmetic in both directions
+            import copy
+            from synth import with_anisotropic_drag
+            acase = with_anisotropic_drag(copy.copy(case))
+        elif aform != "adjoint":
+            raise SystemExit(f"unknown adjoint form {aform}")
+        log(f"[bench] {aform}: T={T}, checkpoint every {ck}, window [{T // 2}, {T})")
+        dt, ok = time_adjoint(torch, acase, T, ck)
         mlups = case.n_fluid * T / dt / 1e6
         gbs = mlups * 1e6 * B_ALG_ADJ / 1e9
-        adjoint = dict(T=T, ckpt=ck, seconds=round(dt, 4), mlups=round(mlups, 1), bytes_per_update=B_ALG_ADJ,
-                       alg_GBps=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4), finite=ok)
-        log(f"[bench] adjoint: {dt * 1e3:.1f} ms, {mlups:.0f} M cell-steps/s, {gbs:.0f} GB/s algorithmic")
+        adjoints[aform] = dict(T=T, ckpt=ck, seconds=round(dt, 4), mlups=round(mlups, 1), bytes_per_update=B_ALG_ADJ,
+                               alg_GBps=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4), finite=ok)
+        log(f"[bench] {aform}: {dt * 1e3:.1f} ms, {mlups:.0f} M cell-steps/s, {gbs:.0f} GB/s algorithmic")
     for form in forms:
         storage = form.split("_")[0]
         if form.endswith("_q27"):
@@ -311,8 +320,7 @@ def main():
                       "ms_per_step": round(v["ms_per_step"], 5)} for k, v in results.items()},
         "copy_probe_GBps": round(probe, 1),
     }
-    if adjoint is not None:
-        line["forms"]["adjoint"] = adjoint
+    line["forms"].update(adjoints)
     print(json.dumps(line), flush=True)
 
 

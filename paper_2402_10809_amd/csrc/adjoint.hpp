@@ -55,8 +55,14 @@ struct AdjBufs {
 // recursion has the same slow modes as the forward map, so FP32 rounding of
 // per-cell scalars would accumulate the same way); the adjoint populations are
 // stored in FP32.
+//
+// The anisotropic instantiation needs 256 VGPRs plus 21 AGPRs as compiled
+// freely (1 wave per SIMD); held to 2 waves it spills 23 registers to scratch
+// and still runs the reverse step about 1.4x faster.  The isotropic one fits
+// 2 waves (243 VGPRs) by itself.
 template <bool AN>
-__global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, uint32_t t, float ew, int kind) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(AN ? 2 : 1)))
+void k_adjoint(Params p, AdjBufs a, uint32_t t, float ew, int kind) {
   using R = double;
   const uint32_t c = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   if (c >= (uint32_t)p.nc) return;
@@ -262,19 +268,14 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, uint32_t
     // A = Id + (phi nu / 2k) M^-1, B = C1 M^-1/2: back through the iterates,
     // recomputing u_m from v each time
     const R ha = 0.5 * dark, hb = forch ? 0.5 * K2 * om1 * iphi : 0.0;
-    R Am[6], Bm[6], Ah[6], Bh[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      Am[k] = ha * kc.Mi[k] + (k < 3 ? 1.0 : 0.0);
-      Bm[k] = hb * kc.Mh[k];
-      Ah[k] = 0.0;
-      Bh[k] = 0.0;
-    }
-    // y = X^-1 b for X = A + n B (symmetric: the adjugate over the determinant)
+    // y = X^-1 b for X = A + n B (symmetric: the adjugate over the determinant).
+    // X is formed from the uniform shape matrices at each solve rather than
+    // kept per work-item, which keeps the kernel's registers down.
     auto solve = [&](R n, R bx, R by, R bz, R& yx, R& yy, R& yz) {
       R X[6];
+      const R nb = n * hb;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) X[k] = Am[k] + n * Bm[k];
+      for (int k = 0; k < 6; ++k) X[k] = ha * kc.Mi[k] + nb * kc.Mh[k] + (k < 3 ? 1.0 : 0.0);
       const R a00 = X[1] * X[2] - X[5] * X[5], a11 = X[0] * X[2] - X[4] * X[4], a22 = X[0] * X[1] - X[3] * X[3];
       const R a01 = X[4] * X[5] - X[3] * X[2], a02 = X[3] * X[5] - X[4] * X[1], a12 = X[3] * X[4] - X[0] * X[5];
       const R idet = fast_rcp(X[0] * a00 + X[3] * a01 + X[4] * a02);
@@ -284,6 +285,9 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, uint32_t
     };
     R ubx = uhx, uby = uhy, ubz = uhz;  // adjoint of u_{m+1}
     vhx = 0.0; vhy = 0.0; vhz = 0.0;
+    // only two contractions of the adjoints of A and B are needed:
+    // aM = sum_m Xh_m : M^-1 and bM = sum_m n_m Xh_m : M^-1/2
+    R aM = 0.0, bM = 0.0;
     for (int m = p.an_iters - 1; m >= 0; --m) {
       R ax = vx, ay = vy, az = vz;  // u_m
       for (int j = 0; j < m; ++j) solve(rsqrt_(ax * ax + ay * ay + az * az), vx, vy, vz, ax, ay, az);
@@ -294,23 +298,19 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(Params p, AdjBufs a, uint32_t
       vhx += wx; vhy += wy; vhz += wz;
       const R Xh[6] = {-wx * bx, -wy * by, -wz * bz, -(wx * by + wy * bx), -(wx * bz + wz * bx),
                        -(wy * bz + wz * by)};
-      R nh = 0.0;
+      R xi = 0.0, xh = 0.0;
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
-        Ah[k] += Xh[k];
-        Bh[k] += n * Xh[k];
-        nh += Xh[k] * Bm[k];
+        xi += Xh[k] * kc.Mi[k];
+        xh += Xh[k] * kc.Mh[k];
       }
-      const R g = n > 0.0 ? nh * fast_rcp(n) : 0.0;
+      aM += xi;
+      bM += n * xh;
+      // d/dn of X = n B, contracted with Xh, then through n = |u_m|
+      const R g = n > 0.0 ? hb * xh * fast_rcp(n) : 0.0;
       ubx = g * ax; uby = g * ay; ubz = g * az;
     }
     vhx += ubx; vhy += uby; vhz += ubz;  // u_0 = v
-    R aM = 0.0, bM = 0.0;
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      aM += Ah[k] * kc.Mi[k];
-      bM += Bh[k] * kc.Mh[k];
-    }
     phh += aM * 0.5 * ddark;
     if (forch) phh += bM * (-0.5 * K2 * iphi * iphi);
   } else {
