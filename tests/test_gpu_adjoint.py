@@ -92,10 +92,35 @@ def test_adjoint_random_lattices(seed):
     assert err < 1e-4
 
 
-@pytest.mark.parametrize("kind", ["open", "open_extrap"])
+@pytest.mark.parametrize("seed", range(6))
+def test_adjoint_random_lattices_anisotropic(seed):
+    """As above with the anisotropic medium on top (Forchheimer drag, grain
+    size 0.5, a seeded 3:1 shape, 6 fixed-point iterations): the reverse of
+    the iterates on random extents, periodic axes, outflows and solids."""
+    case = tiny_random(seed)
+    case.porous = dict(case.porous, g=tuple(50.0 * v for v in case.porous["g"]), forchheimer=1, d=0.5,
+                       aniso=aniso_shape(seed), aniso_iters=6)
+    T, tb, te, ck = 16, 8, 16, 5
+    say(f"adjoint random anisotropic lattice {case.name} box={case.nx}x{case.ny}x{case.nz} "
+        f"periodic={case.periodic} outlet={case.outlet}")
+    o = oracle.Oracle(case)
+    J_ref, g_ref = o.grad_reverse(T, tb, te, ck, "ke")
+    s = Solver.from_case(case, adjoint_T=T, ckpt=ck)
+    J, g = s.adjoint(tb, te, T, ck, kind="ke")
+    g = g.cpu().numpy()
+    fluid = case.solid == 0
+    scale = np.abs(g_ref)[fluid].max()
+    err = np.abs(g - g_ref)[fluid].max() / scale
+    say(f"  J gpu {J:.10e} oracle {J_ref:.10e}; grad max-rel {err:.3e}")
+    assert abs(J - J_ref) <= 1e-5 * abs(J_ref) + 1e-30
+    assert err < 1e-4
+
+
+@pytest.mark.parametrize("kind", ["open", "open_extrap", "open_aniso"])
 def test_adjoint_checkpoint_independent(kind):
     """The gradient does not depend on the checkpoint interval (recompute is
-    exact, also with the extrapolation outflow's kept unknowns)."""
+    exact, also with the extrapolation outflow's kept unknowns and through the
+    anisotropic fixed-point iterates)."""
     case = _tiny(kind, 2)
     T, tb, te = 26, 10, 26
     J1, g1 = Solver.from_case(case, adjoint_T=T, ckpt=1).adjoint(tb, te, T, 1)
