@@ -148,3 +148,18 @@ def test_create_rejects_bad_inputs_before_device_work():
     g27 = _grid()
     g27.velocity_set = 27
     assert _create(g27, solid, phi, aniso=(2.0, 1.0, 1.0, 0.3, 0.0, 0.0)) == lbm.LBM_E_INVALID
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU: asked for more it exits with status 2 and a
+    message, before touching a device."""
+    import os
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], cwd=root,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
