@@ -1,3 +1,11 @@
+// lbm_adjoint: the reverse kernel and its checkpointing driver.
+#include <algorithm>
+
+#include "adjoint.hpp"
+#include "runtime.hpp"
+
+using namespace lbmrt;
+
 // Host side of lbm_adjoint: forward pass with checkpoints, then segment-wise
 // recompute (recording pulled values, omega_prev and density) and reverse
 // steps.  The checkpoint of segment s (s >= 1) is the state one step before
@@ -55,7 +63,7 @@ extern "C" lbm_status lbm_adjoint(lbm_ctx* c, const lbm_objective* obj, int T, i
   auto load_ck = [&](int s) -> lbm_status {
     const float* src = ck + (size_t)s * (Q + 1) * nc;
     c->t = (int64_t)s * ckpt - 1;
-    hipLaunchKernelGGL(k_set_time, dim3(1), dim3(64), 0, c->stream, (uint32_t*)(c->ws + c->L.tc), (uint32_t)c->t);
+    launch_set_time(c->stream, (uint32_t*)(c->ws + c->L.tc), (uint32_t)c->t);
     lbm_status st = scatter_state(c, src);
     if (st != LBM_OK) return st;
     HIP_TRY(c, hipMemcpyAsync(c->ws + c->L.omega, src + Q * nc, nc * 4, hipMemcpyDeviceToDevice, c->stream));

@@ -19,26 +19,30 @@
 #include <type_traits>
 #include <vector>
 
-#include "step.hpp"
-#include "step27.hpp"
-#include "adjoint.hpp"
+#include "runtime.hpp"
 
 using namespace lbm;
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
+
+namespace lbmrt {
 
 lbm_status fail(lbm_status s, const std::string& msg) {
   g_err = msg;
   return s;
 }
 
+}  // namespace lbmrt
+
+using namespace lbmrt;
+
+namespace {
+
 constexpr int CHECK_EVERY = 1000;                       // steps between stability checks
 constexpr double MAX_SPEED = 0.3 / 1.7320508075688772;  // 0.3 c_s
 
-size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
-size_t store_bytes(int storage) { return storage == LBM_STORE_FP32 ? 4 : 2; }
 // Storage unit U: stored value = U (f - rest).  36 w_i is an integer; FP16 adds
 // 2^10 so that typical deviations sit in the normal range.
 // (2^9 on D3Q27, whose rest weight is larger relative to U.)
@@ -46,34 +50,6 @@ double storage_unit(int storage, int q) {
   if (q == 27) return storage == LBM_STORE_FP16 ? 216.0 * 512.0 : 216.0;
   return storage == LBM_STORE_FP16 ? 36.0 * 1024.0 : 36.0;
 }
-int qof(const lbm_grid& g) { return g.velocity_set == 27 ? 27 : 19; }
-
-struct Layout {
-  size_t A, code, links, phi, omega, delta, shape, rowbox, stage, part, diag, obj, tc, wave, side;
-  // adjoint
-  size_t ck, rec, rho, ah0, ah1, omh, phih, aside;
-  int nck, ckpt, T;
-  size_t total;
-};
-
-int blocks_for(int64_t n) { return (int)((n + BLOCK - 1) / BLOCK); }
-int blocks_for_nt(int64_t n, int nt) { return (int)((n + nt - 1) / nt); }
-
-// Workgroup size of the step kernel: 256 work-items with FP32 storage, 64 with
-// the 16-bit forms (measured fastest for each on the large aneurysm).
-constexpr int STEP_NT_MIN = 64;
-constexpr int MAX_WAVE_TABLE = 1024;  // samples of a sampled inflow waveform
-int step_nt(int storage) { return storage == LBM_STORE_FP32 ? 256 : 64; }
-
-// Rows of the compact layout: every (y, z) line holding fluid, ordered by z
-// then y, with the x range from its first to its last fluid cell.
-struct Rows {
-  std::vector<int> y, z, x0, x1;
-  std::vector<int64_t> cb;  // compact start of each row
-  int64_t nc = 0;           // compact cells (fluid + dead)
-  int64_t nf = 0;           // fluid cells
-};
-
 Rows find_rows(const lbm_grid& g, const uint8_t* solid) {
   Rows r;
   const int nx = g.nx;
@@ -99,90 +75,6 @@ int xbits_for(int nx) {
   int b = 1;
   while ((1 << b) < nx) ++b;
   return b;
-}
-
-Layout make_layout(const lbm_grid& g, int64_t nc, int64_t nrow, int T, int ckpt) {
-  Layout L{};
-  const size_t ss = store_bytes(g.storage);
-  size_t o = 0;
-  auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
-  const int q = qof(g);
-  L.A = take((size_t)q * (size_t)nc * ss);
-  L.code = take((size_t)nc * 4);
-  L.links = take((size_t)nc * (q == 27 ? 8 : 4));
-  L.phi = take((size_t)nc * 4);
-  L.omega = take((size_t)nc * 4);
-  L.delta = take((size_t)nrow * 8 * 4);
-  L.shape = take((size_t)nrow * 4);
-  L.rowbox = take((size_t)nrow * 4);
-  L.stage = take((size_t)(q + 1) * nc * 4);
-  const size_t nbmax = (size_t)blocks_for_nt(nc, STEP_NT_MIN);  // most blocks any launch uses
-  L.part = take(nbmax * NDIAGP * 8);
-  L.diag = take(64 * 8);
-  L.obj = take(nbmax * 8);
-  L.tc = take(2 * sizeof(uint32_t));
-  L.wave = take(MAX_WAVE_TABLE * sizeof(double));
-  L.side = take((size_t)2 * nrow * (q == 27 ? 18 : 10) * sizeof(float));
-  L.T = T;
-  L.ckpt = ckpt;
-  if (T > 0) {
-    L.nck = (T + ckpt - 1) / ckpt;
-    L.ck = take((size_t)L.nck * (Q + 1) * nc * 4);
-    L.rec = take((size_t)(ckpt + 1) * (Q + 1) * nc * 4);
-    L.rho = take((size_t)(ckpt + 1) * nc * 4);
-    L.ah0 = take(Q * (size_t)nc * 4);
-    L.ah1 = take(Q * (size_t)nc * 4);
-    L.omh = take((size_t)nc * 4);
-    L.phih = take((size_t)nc * 8);
-    L.aside = take((size_t)2 * nrow * 5 * 8);
-  }
-  L.total = o;
-  return L;
-}
-
-struct TF32 { using T = float; };
-struct TF16 { using T = _Float16; };
-struct TBF16 { using T = __bf16; };
-// Arithmetic of the collision: FP32, FP32 with the FP64 momentum projection,
-// or FP64.
-struct RF32 { using T = float; static constexpr bool proj = false; };
-struct RF32P { using T = float; static constexpr bool proj = true; };
-struct RF64 { using T = double; static constexpr bool proj = false; };
-
-template <class Fn>
-void with_storage(int storage, int shw, Fn&& fn) {
-  if (storage == LBM_STORE_FP32) {
-    if (shw) fn(TF32{}, std::true_type{}); else fn(TF32{}, std::false_type{});
-  } else if (storage == LBM_STORE_FP16) {
-    if (shw) fn(TF16{}, std::true_type{}); else fn(TF16{}, std::false_type{});
-  } else {
-    if (shw) fn(TBF16{}, std::true_type{}); else fn(TBF16{}, std::false_type{});
-  }
-}
-
-// Rounding of the 16-bit storage forms: conserving (the default) or to
-// nearest; FP32 storage has one form.
-template <class S, class Fn>
-void with_rounding(int rounding, Fn&& fn) {
-  if constexpr (std::is_same<S, float>::value) fn(std::false_type{});
-  else if (rounding == LBM_ROUND_NEAREST) fn(std::false_type{});
-  else fn(std::true_type{});
-}
-
-// Storage type, shift mode and arithmetic: the FP64 and projected forms only
-// exist for FP32 storage.  mode: 0 FP32, 1 FP32 + projection, 2 FP64.
-template <class Fn>
-void with_config(int storage, int shw, int mode, Fn&& fn) {
-  with_storage(storage, shw, [&](auto tag, auto sh) {
-    using S = typename decltype(tag)::T;
-    if constexpr (std::is_same<S, float>::value) {
-      if (mode == 2) fn(tag, sh, RF64{});
-      else if (mode == 1) fn(tag, sh, RF32P{});
-      else fn(tag, sh, RF32{});
-    } else {
-      fn(tag, sh, RF32{});
-    }
-  });
 }
 
 // Symmetric 3x3 matrices as full arrays: inverse by the adjugate.
@@ -238,55 +130,46 @@ bool aniso_shape(const double m6[6], double inv6[6], double ihalf6[6]) {
 
 }  // namespace
 
-struct lbm_ctx {
-  lbm_grid grid{};
-  lbm_rheology rh{};
-  lbm_porous po{};
-  lbm_open op{};
-  size_t nbox = 0;
-  int64_t nf = 0;                 // fluid cells
-  int64_t nc = 0;                 // compact cells (fluid + dead)
-  int64_t nrow = 0;
-  int nblk = 0;                   // blocks of BLOCK work-items over the compact cells
-  int sblk = 0;                   // blocks of the step kernel
-  int64_t nreg = 0;
-  int64_t nwss = 0;               // region cells on the wall (with a wall normal)
-  int q = 19;                     // velocity set
-  double U = 36.0;
-  Rows rows;
-  std::vector<int64_t> fluid_box; // box index per fluid cell (ascending)
-  std::vector<int64_t> fluid_c;   // compact index per fluid cell
-  std::vector<double> phi_f;      // porosity per fluid cell (host, for state transfer)
-  std::vector<uint8_t> solid;     // host copy of the mask
-  std::vector<uint8_t> region_f;  // per fluid cell
-  std::vector<uint8_t> openface;  // per fluid cell: 1 inlet, 2 outlet
-  hipStream_t stream = nullptr;
-  char* ws = nullptr;
-  size_t ws_bytes = 0;
+namespace lbmrt {
+
+Layout make_layout(const lbm_grid& g, int64_t nc, int64_t nrow, int T, int ckpt) {
   Layout L{};
-  int64_t t = 0;                  // time; its parity selects the slot layout
-  bool poisoned = false;
-  Params P{};
-  float omega0 = 1.0f;
-  int amode = 1;                  // collision arithmetic: 0 FP32, 1 FP32 + projection, 2 FP64
-};
-
-namespace {
-
-#define HIP_TRY(ctx, expr)                                                                      \
-  do {                                                                                          \
-    hipError_t e_ = (expr);                                                                     \
-    if (e_ != hipSuccess) {                                                                     \
-      if (ctx) (ctx)->poisoned = true;                                                          \
-      return fail(LBM_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));             \
-    }                                                                                           \
-  } while (0)
-
-#define CTX_CHECK(ctx)                                                                          \
-  do {                                                                                          \
-    if (!(ctx)) return fail(LBM_E_INVALID, "null context");                                     \
-    if ((ctx)->poisoned) return fail(LBM_E_STATE, "context poisoned by an earlier device error"); \
-  } while (0)
+  const size_t ss = store_bytes(g.storage);
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+  const int q = qof(g);
+  L.A = take((size_t)q * (size_t)nc * ss);
+  L.code = take((size_t)nc * 4);
+  L.links = take((size_t)nc * (q == 27 ? 8 : 4));
+  L.phi = take((size_t)nc * 4);
+  L.omega = take((size_t)nc * 4);
+  L.delta = take((size_t)nrow * 8 * 4);
+  L.shape = take((size_t)nrow * 4);
+  L.rowbox = take((size_t)nrow * 4);
+  L.stage = take((size_t)(q + 1) * nc * 4);
+  const size_t nbmax = (size_t)blocks_for_nt(nc, STEP_NT_MIN);  // most blocks any launch uses
+  L.part = take(nbmax * NDIAGP * 8);
+  L.diag = take(64 * 8);
+  L.obj = take(nbmax * 8);
+  L.tc = take(2 * sizeof(uint32_t));
+  L.wave = take(MAX_WAVE_TABLE * sizeof(double));
+  L.side = take((size_t)2 * nrow * (q == 27 ? 18 : 10) * sizeof(float));
+  L.T = T;
+  L.ckpt = ckpt;
+  if (T > 0) {
+    L.nck = (T + ckpt - 1) / ckpt;
+    L.ck = take((size_t)L.nck * (Q + 1) * nc * 4);
+    L.rec = take((size_t)(ckpt + 1) * (Q + 1) * nc * 4);
+    L.rho = take((size_t)(ckpt + 1) * nc * 4);
+    L.ah0 = take(Q * (size_t)nc * 4);
+    L.ah1 = take(Q * (size_t)nc * 4);
+    L.omh = take((size_t)nc * 4);
+    L.phih = take((size_t)nc * 8);
+    L.aside = take((size_t)2 * nrow * 5 * 8);
+  }
+  L.total = o;
+  return L;
+}
 
 Bufs bufs(lbm_ctx* c) {
   Bufs b{};
@@ -307,6 +190,27 @@ Bufs bufs(lbm_ctx* c) {
   return b;
 }
 
+
+q27::Bufs27 bufs27(lbm_ctx* c) {
+  q27::Bufs27 b{};
+  b.A = c->ws + c->L.A;
+  b.code = (const uint32_t*)(c->ws + c->L.code);
+  b.links = (const uint64_t*)(c->ws + c->L.links);
+  b.delta = (const int*)(c->ws + c->L.delta);
+  b.phi = (const float*)(c->ws + c->L.phi);
+  b.omega = (float*)(c->ws + c->L.omega);
+  b.shape = (const float*)(c->ws + c->L.shape);
+  b.rowbox = (const uint32_t*)(c->ws + c->L.rowbox);
+  b.part = (double*)(c->ws + c->L.part);
+  b.tc = (uint32_t*)(c->ws + c->L.tc);
+  b.wave = (const double*)(c->ws + c->L.wave);
+  b.side = (float*)(c->ws + c->L.side);
+  return b;
+}
+
+}  // namespace lbmrt
+
+namespace {
 
 lbm_status validate_grid(const lbm_grid* g) {
   if (!g) return fail(LBM_E_INVALID, "grid is NULL");
@@ -472,23 +376,6 @@ int64_t build_links27(const lbm_ctx* c, const std::vector<float>& phib, std::vec
   return nwss;
 }
 
-q27::Bufs27 bufs27(lbm_ctx* c) {
-  q27::Bufs27 b{};
-  b.A = c->ws + c->L.A;
-  b.code = (const uint32_t*)(c->ws + c->L.code);
-  b.links = (const uint64_t*)(c->ws + c->L.links);
-  b.delta = (const int*)(c->ws + c->L.delta);
-  b.phi = (const float*)(c->ws + c->L.phi);
-  b.omega = (float*)(c->ws + c->L.omega);
-  b.shape = (const float*)(c->ws + c->L.shape);
-  b.rowbox = (const uint32_t*)(c->ws + c->L.rowbox);
-  b.part = (double*)(c->ws + c->L.part);
-  b.tc = (uint32_t*)(c->ws + c->L.tc);
-  b.wave = (const double*)(c->ws + c->L.wave);
-  b.side = (float*)(c->ws + c->L.side);
-  return b;
-}
-
 // Upload the porosity and the link words (which depend on it).
 lbm_status upload_phi(lbm_ctx* c, const float* phi) {
   std::vector<float> box(c->nbox, 0.0f), comp(c->nc, 0.0f);
@@ -513,121 +400,85 @@ lbm_status upload_phi(lbm_ctx* c, const float* phi) {
   return LBM_OK;
 }
 
+}  // namespace
+
+namespace lbmrt {
+
 lbm_status launch_init(lbm_ctx* c) {
-  Bufs b = bufs(c);
-  with_storage(c->grid.storage, c->grid.shift_mode, [&](auto tag, auto shw) {
+  with_storage(c->grid.storage, [&](auto tag) {
     using S = typename decltype(tag)::T;
-    if (c->q == 27)
-      hipLaunchKernelGGL((q27::k_init<S, decltype(shw)::value>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P,
-                         bufs27(c), c->omega0);
-    else
-      hipLaunchKernelGGL((k_init<S, decltype(shw)::value>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b,
-                         c->omega0);
+    if (c->q == 27) init27<S>(c, bufs27(c));
+    else init19<S>(c, bufs(c));
   });
   HIP_TRY(c, hipGetLastError());
   // extrapolation outflow: the kept values of the rest state (phi = 1 on the
   // outflow cells, so w_i, i.e. deviation 0; the -x neighbour's values are
   // those the rest state's outflow populations extrapolate from)
-  HIP_TRY(c, hipMemsetAsync(b.side, 0, (size_t)2 * c->nrow * (c->q == 27 ? 18 : 10) * sizeof(float), c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->ws + c->L.side, 0, (size_t)2 * c->nrow * (c->q == 27 ? 18 : 10) * sizeof(float),
+                            c->stream));
   c->t = 0;
   return LBM_OK;
 }
 
-template <class Fn>
-void with_parity(int64_t t, Fn&& fn) {
-  if (t & 1) fn(std::true_type{}); else fn(std::false_type{});
-}
-
 // One step at time t (in place).  diag: 0 none, 1 diagnostics partials, 2
 // region kinetic energy, 3 region wall shear stress, accumulated into the
-// objective partials.  rec: record the
-// step for the adjoint (FP32, shift mode 0 only).
-lbm_status launch_step27(lbm_ctx* c, int diag) {
-  const q27::Bufs27 b = bufs27(c);
-  with_config(c->grid.storage, c->grid.shift_mode, c->amode, [&](auto tag, auto shw, auto rt) {
-    using S = typename decltype(tag)::T;
-    using R = typename decltype(rt)::T;
-    constexpr bool PJ = decltype(rt)::proj;
-    constexpr bool SH = decltype(shw)::value;
-    constexpr int NT = std::is_same<S, float>::value ? 256 : 64;
-    const dim3 grid(c->sblk), block(NT);
-    with_rounding<S>(c->grid.rounding, [&](auto cr) {
-      constexpr bool CR = decltype(cr)::value;
-      with_parity(c->t, [&](auto odd) {
-        constexpr bool OD = decltype(odd)::value;
-        if (diag == 0)
-          hipLaunchKernelGGL((q27::k_step<S, SH, OD, 0, R, PJ, NT, CR>), grid, block, 0, c->stream, c->P, b);
-        else
-          hipLaunchKernelGGL((q27::k_step<S, SH, OD, 1, R, PJ, NT, CR>), grid, block, 0, c->stream, c->P, b);
-      });
-    });
-  });
-  HIP_TRY(c, hipGetLastError());
-  c->t += 1;
-  return LBM_OK;
-}
-
+// objective partials.  rec: record the step for the adjoint (FP32, shift
+// mode 0 only).
 lbm_status launch_step(lbm_ctx* c, int diag, float* rec, float* rho_rec) {
-  if (c->q == 27) return launch_step27(c, diag);
-  Bufs b = bufs(c);
-  if (diag >= 2) b.part = (double*)(c->ws + c->L.obj);
-  if (rec) {
-    b.rec = rec;
-    b.rho_rec = rho_rec;
+  if (c->q == 27) {
+    const q27::Bufs27 b = bufs27(c);
+    with_storage(c->grid.storage, [&](auto tag) { step27<typename decltype(tag)::T>(c, b, diag); });
+  } else {
+    Bufs b = bufs(c);
+    if (diag >= 2) b.part = (double*)(c->ws + c->L.obj);
+    if (rec) {
+      b.rec = rec;
+      b.rho_rec = rho_rec;
+    }
+    with_storage(c->grid.storage, [&](auto tag) { step19<typename decltype(tag)::T>(c, b, diag, rec != nullptr); });
   }
-  with_config(c->grid.storage, c->grid.shift_mode, c->amode, [&](auto tag, auto shw, auto rt) {
-    using S = typename decltype(tag)::T;
-    using R = typename decltype(rt)::T;
-    constexpr bool PJ = decltype(rt)::proj;
-    constexpr bool SH = decltype(shw)::value;
-    constexpr int NT = std::is_same<S, float>::value ? 256 : 64;
-    const dim3 grid(c->sblk), block(NT);
-    with_rounding<S>(c->grid.rounding, [&](auto cr) {
-      constexpr bool CR = decltype(cr)::value;
-      with_parity(c->t, [&](auto odd) {
-        constexpr bool OD = decltype(odd)::value;
-        // AN: anisotropic permeability (every form, the adjoint's included)
-        auto go = [&](auto an) {
-          constexpr bool AN = decltype(an)::value;
-          if (diag == 0 && !rec) {
-            hipLaunchKernelGGL((k_step<S, SH, OD, 0, false, R, PJ, NT, AN, CR>), grid, block, 0, c->stream, c->P,
-                               b);
-          } else if (diag == 1) {
-            hipLaunchKernelGGL((k_step<S, SH, OD, 1, false, R, PJ, NT, AN, CR>), grid, block, 0, c->stream, c->P,
-                               b);
-          } else if constexpr (std::is_same<S, float>::value) {
-            // the adjoint's forms (FP32 storage only)
-            if (rec) {
-              if constexpr (!SH)
-                hipLaunchKernelGGL((k_step<S, false, OD, 0, true, R, PJ, NT, AN>), grid, block, 0, c->stream, c->P,
-                                   b);
-            } else if (diag == 2) {
-              hipLaunchKernelGGL((k_step<S, SH, OD, 2, false, R, PJ, NT, AN>), grid, block, 0, c->stream, c->P, b);
-            } else {
-              hipLaunchKernelGGL((k_step<S, SH, OD, 3, false, R, PJ, NT, AN>), grid, block, 0, c->stream, c->P, b);
-            }
-          }
-        };
-        if (c->P.an_iters > 0) go(std::true_type{});
-        else go(std::false_type{});
-      });
-    });
-  });
   HIP_TRY(c, hipGetLastError());
   c->t += 1;
   return LBM_OK;
 }
-
-const uint32_t DIAG_OPS = (1u << 12) | (2u << 14) | (1u << 16);  // max |u|, min omega, max omega; rest sums
 
 lbm_status finalize(lbm_ctx* c, const double* part, int nparts, int n, uint32_t ops, double* host_out) {
   double* dout = (double*)(c->ws + c->L.diag);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(BLOCK), 0, c->stream, part, nparts, n, ops, dout);
+  launch_finalize(c->stream, part, nparts, n, ops, dout);
   HIP_TRY(c, hipGetLastError());
   HIP_TRY(c, hipMemcpyAsync(host_out, dout, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return LBM_OK;
 }
+
+// Pulled state of time t (raw stored values as FP32, [19][nc], compact order)
+// into dst (device).
+lbm_status gather_state(lbm_ctx* c, float* dst) {
+  with_storage(c->grid.storage, [&](auto tag) {
+    using S = typename decltype(tag)::T;
+    if (c->q == 27) gather27<S>(c, bufs27(c), dst);
+    else gather19<S>(c, bufs(c), dst);
+  });
+  HIP_TRY(c, hipGetLastError());
+  return LBM_OK;
+}
+
+// Inverse of gather_state, into the slots of time t's parity.
+lbm_status scatter_state(lbm_ctx* c, const float* src) {
+  with_storage(c->grid.storage, [&](auto tag) {
+    using S = typename decltype(tag)::T;
+    if (c->q == 27) scatter27<S>(c, bufs27(c), src);
+    else scatter19<S>(c, bufs(c), src);
+  });
+  HIP_TRY(c, hipGetLastError());
+  return LBM_OK;
+}
+
+}  // namespace lbmrt
+
+namespace {
+
+const uint32_t DIAG_OPS = (1u << 12) | (2u << 14) | (1u << 16);  // max |u|, min omega, max omega; rest sums
 
 // nparts: the block count of the launch that wrote the partials
 lbm_status read_diag(lbm_ctx* c, int nparts, double* out) {
@@ -646,75 +497,10 @@ lbm_status check_stable(lbm_ctx* c, const double* dg) {
 
 lbm_status moments_launch(lbm_ctx* c, bool diag, float* rho, float* u, float* shear, float* omega, float* sigma,
                           float* tau) {
-  Bufs b = bufs(c);
-  const uint32_t t = (uint32_t)c->t;
-  with_config(c->grid.storage, c->grid.shift_mode, c->amode == 2 ? 2 : 0, [&](auto tag, auto shw, auto rt) {
+  with_storage(c->grid.storage, [&](auto tag) {
     using S = typename decltype(tag)::T;
-    using R = typename decltype(rt)::T;
-    constexpr bool SH = decltype(shw)::value;
-    with_parity(c->t, [&](auto odd) {
-      constexpr bool OD = decltype(odd)::value;
-      if (c->q == 27) {
-        const q27::Bufs27 b27 = bufs27(c);
-        if (diag)
-          hipLaunchKernelGGL((q27::k_moments<S, SH, OD, true, R>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P,
-                             b27, t, c->nbox, rho, u, shear, omega, sigma, tau);
-        else
-          hipLaunchKernelGGL((q27::k_moments<S, SH, OD, false, R>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P,
-                             b27, t, c->nbox, rho, u, shear, omega, sigma, tau);
-        return;
-      }
-      const bool an = c->P.an_iters > 0;
-      if (diag && an)
-        hipLaunchKernelGGL((k_moments<S, SH, OD, true, R, true>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b,
-                           t, c->nbox, rho, u, shear, omega, sigma, tau);
-      else if (diag)
-        hipLaunchKernelGGL((k_moments<S, SH, OD, true, R>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, t,
-                           c->nbox, rho, u, shear, omega, sigma, tau);
-      else if (an)
-        hipLaunchKernelGGL((k_moments<S, SH, OD, false, R, true>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b,
-                           t, c->nbox, rho, u, shear, omega, sigma, tau);
-      else
-        hipLaunchKernelGGL((k_moments<S, SH, OD, false, R>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, b, t,
-                           c->nbox, rho, u, shear, omega, sigma, tau);
-    });
-  });
-  HIP_TRY(c, hipGetLastError());
-  return LBM_OK;
-}
-
-// Pulled state of time t (raw stored values as FP32, [19][nc], compact order)
-// into dst (device).
-lbm_status gather_state(lbm_ctx* c, float* dst) {
-  Bufs b = bufs(c);
-  with_storage(c->grid.storage, 0, [&](auto tag, auto) {
-    using S = typename decltype(tag)::T;
-    with_parity(c->t, [&](auto odd) {
-      if (c->q == 27)
-        hipLaunchKernelGGL((q27::k_gather_state<S, decltype(odd)::value>), dim3(c->nblk), dim3(BLOCK), 0, c->stream,
-                           c->P, bufs27(c), dst);
-      else
-        hipLaunchKernelGGL((k_gather_state<S, decltype(odd)::value>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P,
-                           b, dst);
-    });
-  });
-  HIP_TRY(c, hipGetLastError());
-  return LBM_OK;
-}
-
-// Inverse of gather_state, into the slots of time t's parity.
-lbm_status scatter_state(lbm_ctx* c, const float* src) {
-  Bufs b = bufs(c);
-  with_storage(c->grid.storage, 0, [&](auto tag, auto) {
-    using S = typename decltype(tag)::T;
-    with_parity(c->t, [&](auto odd) {
-      if (c->q == 27)
-        hipLaunchKernelGGL((q27::k_scatter_state<S, decltype(odd)::value>), dim3(c->nblk), dim3(BLOCK), 0, c->stream,
-                           c->P, bufs27(c), src);
-      else
-        hipLaunchKernelGGL((k_scatter_state<S, decltype(odd)::value>), dim3(c->nblk), dim3(BLOCK), 0, c->stream,
-                           c->P, b, src);
-    });
+    if (c->q == 27) moments27<S>(c, bufs27(c), diag, rho, u, shear, omega, sigma, tau);
+    else moments19<S>(c, bufs(c), diag, rho, u, shear, omega, sigma, tau);
   });
   HIP_TRY(c, hipGetLastError());
   return LBM_OK;
@@ -1059,8 +845,7 @@ lbm_status lbm_copy_probe(void* dst, const void* src, size_t bytes, void* stream
   size_t blocks = (n + BLOCK - 1) / BLOCK;
   if (blocks > 65536) blocks = 65536;
   if (blocks == 0) return LBM_OK;
-  hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(BLOCK), 0, (hipStream_t)stream, (const uint4*)src,
-                     (uint4*)dst, n);
+  launch_copy((hipStream_t)stream, src, dst, n, (unsigned)blocks);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(LBM_E_DEVICE, std::string("copy probe: ") + hipGetErrorString(e));
   return LBM_OK;
@@ -1070,4 +855,3 @@ void lbm_destroy(lbm_ctx* c) { delete c; }
 
 }  // extern "C"
 
-#include "adjoint_host.inc"

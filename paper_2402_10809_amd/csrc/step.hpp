@@ -952,31 +952,6 @@ __global__ __launch_bounds__(BLOCK) void k_moments(Params p, Bufs b, uint32_t t,
   }
 }
 
-// Reduce per-block partials (single workgroup, fixed order: deterministic).
-// opmask holds 2 bits per entry: 0 sum, 1 max, 2 min.
-__global__ __launch_bounds__(BLOCK) void k_finalize(const double* part, int nblk, int n, uint32_t opmask, double* out) {
-  __shared__ double sh[BLOCK];
-  for (int k = 0; k < n; ++k) {
-    const int op = (int)((opmask >> (2 * k)) & 3u);
-    double r = op == 0 ? 0.0 : (op == 1 ? -1e300 : 1e300);
-    for (int i = threadIdx.x; i < nblk; i += BLOCK) {
-      const double v = part[(size_t)i * n + k];
-      r = op == 0 ? r + v : (op == 1 ? fmax(r, v) : fmin(r, v));
-    }
-    sh[threadIdx.x] = r;
-    __syncthreads();
-    for (int s = BLOCK / 2; s > 0; s >>= 1) {
-      if (threadIdx.x < s) {
-        const double a = sh[threadIdx.x], c2 = sh[threadIdx.x + s];
-        sh[threadIdx.x] = op == 0 ? a + c2 : (op == 1 ? fmax(a, c2) : fmin(a, c2));
-      }
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) out[k] = sh[0];
-    __syncthreads();
-  }
-}
-
 // Rest state at even parity: slot (i, x) holds f_i(x) = w_i phi(x), which is
 // 0 in shift mode 0 and U w_i (phi(x) - 1) in shift mode 1.
 template <class S, bool SHW>
@@ -991,11 +966,6 @@ __global__ __launch_bounds__(BLOCK) void k_init(Params p, Bufs b, float omega0) 
   for (int i = 0; i < Q; ++i) A.st(c * (uint32_t)sizeof(S), p.plb[i], SHW ? ks * kw(i) * (phx - 1.0f) : 0.0f);
   b.omega[c] = omega0;
   if (c == 0) b.tc[0] = 0u;
-}
-
-// Set the time counter slot of parity t & 1 to t (one work-item).
-__global__ void k_set_time(uint32_t* tc, uint32_t t) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) tc[t & 1u] = t;
 }
 
 // Whether the state keeps the open-face unknown I: the extrapolation outflow's.
@@ -1059,13 +1029,6 @@ __global__ __launch_bounds__(BLOCK) void k_scatter_state(Params p, Bufs b, const
       A.st(a.v, a.s, v);
     }
   });
-}
-
-// Plain streaming copy (16-byte vectors), the achievable-bandwidth reference.
-__global__ __launch_bounds__(BLOCK) void k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, size_t n) {
-  size_t i = (size_t)blockIdx.x * BLOCK + threadIdx.x;
-  const size_t stride = (size_t)gridDim.x * BLOCK;
-  for (; i < n; i += stride) dst[i] = src[i];
 }
 
 }  // namespace lbm
