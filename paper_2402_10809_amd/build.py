@@ -38,13 +38,26 @@ def _compile(src: str) -> tuple:
     return src, obj, r.returncode, _filter(r.stdout), cmd
 
 
-def build(verbose: bool = False, jobs: int = 0) -> str:
+def _stale(src: str, newest_header: float) -> bool:
+    obj = os.path.join(OBJDIR, os.path.basename(src)[:-4] + ".o")
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return t < os.path.getmtime(src) or t < newest_header
+
+
+def build(verbose: bool = False, jobs: int = 0, force: bool = True) -> str:
+    """Compile every unit (force=False: only those older than their source or
+    than the newest header) and link liblbm.so."""
     os.makedirs(OBJDIR, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
-    jobs = jobs or min(len(srcs), max(1, min(8, os.cpu_count() or 1)))
+    headers = glob.glob(os.path.join(CSRC, "*.hpp")) + glob.glob(os.path.join(ROOT, "include", "*.h"))
+    newest = max(os.path.getmtime(h) for h in headers)
+    todo = srcs if force else [s for s in srcs if _stale(s, newest)]
+    jobs = jobs or max(1, min(len(todo), 8, os.cpu_count() or 1))
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        results = list(ex.map(_compile, srcs))
-    objs = []
+        results = list(ex.map(_compile, todo))
+    objs = [os.path.join(OBJDIR, os.path.basename(s)[:-4] + ".o") for s in srcs]
     for src, obj, rc, out, cmd in results:
         if verbose:
             print(" ".join(cmd), flush=True)
@@ -52,7 +65,6 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
             raise RuntimeError(f"hipcc failed on {os.path.basename(src)}:\n{out}")
         if verbose and out.strip():
             print(out)
-        objs.append(obj)
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
