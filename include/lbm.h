@@ -239,6 +239,22 @@ lbm_status lbm_moments(lbm_ctx* ctx, float* rho, float* u, float* shear, float* 
 /* FP64 diagnostics of the current state into out[LBM_NDIAG] (host); syncs. */
 lbm_status lbm_diagnostics(lbm_ctx* ctx, double* out);
 
+/* For callers that cannot allocate device memory or set aside workspace for
+ * scratch (code under HIP graph capture, allocation-free serving loops):
+ * lbm_diagnostics with its scratch -- the per-block partials and the reduced
+ * vector -- in a fixed device array of LBM_NOALLOC_SCRATCH_BYTES that the
+ * library holds on each GPU it runs on until the process ends, instead of the
+ * context's workspace.  Same kernels and the same fixed reduction order, so the
+ * result equals lbm_diagnostics' bit for bit.  Allocates nothing.
+ * Limit: contexts of at most 3 049 472 compact cells (the partials of one
+ * block per 256 cells must fit); larger ones get LBM_E_INVALID, naming the
+ * bytes needed.  Every call on a GPU shares that GPU's array: calls that
+ * overlap on one GPU (other host threads, other streams) race; one call at a
+ * time per GPU.  The array needs no clearing (every block writes all of its
+ * partials).  Syncs the context's stream. */
+#define LBM_NOALLOC_SCRATCH_BYTES (1u << 20)
+lbm_status lbm_diagnostics_noalloc(lbm_ctx* ctx, double* out);
+
 /* State transfer (host memory, per fluid cell): f[19][n_fluid] pre-collision
  * populations (unshifted, FP64), omega[n_fluid] the relaxation rate of the
  * previous step.  Populations that would arrive through an open face are

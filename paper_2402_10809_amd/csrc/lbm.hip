@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -442,8 +443,9 @@ lbm_status launch_step(lbm_ctx* c, int diag, float* rec, float* rho_rec) {
   return LBM_OK;
 }
 
-lbm_status finalize(lbm_ctx* c, const double* part, int nparts, int n, uint32_t ops, double* host_out) {
-  double* dout = (double*)(c->ws + c->L.diag);
+lbm_status finalize(lbm_ctx* c, const double* part, int nparts, int n, uint32_t ops, double* host_out,
+                    double* dev_out) {
+  double* dout = dev_out ? dev_out : (double*)(c->ws + c->L.diag);
   launch_finalize(c->stream, part, nparts, n, ops, dout);
   HIP_TRY(c, hipGetLastError());
   HIP_TRY(c, hipMemcpyAsync(host_out, dout, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -480,6 +482,40 @@ namespace {
 
 const uint32_t DIAG_OPS = (1u << 12) | (2u << 14) | (1u << 16);  // max |u|, min omega, max omega; rest sums
 
+// Fixed device scratch of lbm_diagnostics_noalloc: the per-block partials and
+// the reduced vector.  Each GPU the library runs on holds its own copy for the
+// life of the process; host code reaches it only through the address that
+// hipGetSymbolAddress returns on that device (kept per device below).
+constexpr size_t STATIC_SCRATCH_BYTES = size_t(1) << 20;
+constexpr int MAX_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+std::mutex g_scratch_mu;
+void* g_scratch_dev[MAX_DEVICES] = {};
+
+// Largest compact-cell count whose partials fit the static scratch.
+size_t noalloc_need(int64_t nblk) { return align_up((size_t)nblk * NDIAGP * sizeof(double)) + NDIAGP * sizeof(double); }
+int64_t max_noalloc_cells() {
+  int64_t nb = (int64_t)(STATIC_SCRATCH_BYTES / (NDIAGP * sizeof(double)));
+  while (nb > 0 && noalloc_need(nb) > STATIC_SCRATCH_BYTES) --nb;
+  return nb * BLOCK;
+}
+
+// The device address of `scratch` on the current device `dev`, looked up once
+// per device.
+lbm_status scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(LBM_E_DEVICE, "device index out of range for the static scratch");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(LBM_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return LBM_OK;
+}
+
 // nparts: the block count of the launch that wrote the partials
 lbm_status read_diag(lbm_ctx* c, int nparts, double* out) {
   return finalize(c, (const double*)(c->ws + c->L.part), nparts, NDIAGP, DIAG_OPS, out);
@@ -495,12 +531,20 @@ lbm_status check_stable(lbm_ctx* c, const double* dg) {
   return LBM_OK;
 }
 
+// part: where the diagnostics partials go (nullptr: the workspace's area)
 lbm_status moments_launch(lbm_ctx* c, bool diag, float* rho, float* u, float* shear, float* omega, float* sigma,
-                          float* tau) {
+                          float* tau, double* part = nullptr) {
   with_storage(c->grid.storage, [&](auto tag) {
     using S = typename decltype(tag)::T;
-    if (c->q == 27) moments27<S>(c, bufs27(c), diag, rho, u, shear, omega, sigma, tau);
-    else moments19<S>(c, bufs(c), diag, rho, u, shear, omega, sigma, tau);
+    if (c->q == 27) {
+      q27::Bufs27 b = bufs27(c);
+      if (part) b.part = part;
+      moments27<S>(c, b, diag, rho, u, shear, omega, sigma, tau);
+    } else {
+      Bufs b = bufs(c);
+      if (part) b.part = part;
+      moments19<S>(c, b, diag, rho, u, shear, omega, sigma, tau);
+    }
   });
   HIP_TRY(c, hipGetLastError());
   return LBM_OK;
@@ -633,6 +677,18 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* solid, const float* p
   c->rows = std::move(rows);
   s = check_phi(c, phi);
   if (s != LBM_OK) { delete c; return s; }
+  {
+    // the device that holds the workspace (current now), and its copy of the
+    // static scratch of lbm_diagnostics_noalloc
+    const hipError_t e = hipGetDevice(&c->device);
+    void* sp = nullptr;
+    if (e != hipSuccess) {
+      delete c;
+      return fail(LBM_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    }
+    s = scratch_address(c->device, &sp);
+    if (s != LBM_OK) { delete c; return s; }
+  }
   c->nblk = blocks_for(c->nc);
   c->sblk = blocks_for_nt(c->nc, step_nt(grid->storage));
   c->L = L0;
@@ -743,6 +799,32 @@ lbm_status lbm_diagnostics(lbm_ctx* c, double* out) {
   if (s != LBM_OK) return s;
   double dg[NDIAGP];
   s = read_diag(c, c->nblk, dg);
+  if (s != LBM_OK) return s;
+  for (int k = 0; k < 10; ++k) out[k] = dg[k];
+  out[10] = (double)c->t;
+  out[11] = c->nwss > 0 ? dg[10] / (double)c->nwss : 0.0;
+  return LBM_OK;
+}
+
+lbm_status lbm_diagnostics_noalloc(lbm_ctx* c, double* out) {
+  CTX_CHECK(c);
+  if (!out) return fail(LBM_E_INVALID, "out is NULL");
+  const size_t part_bytes = align_up((size_t)c->nblk * NDIAGP * sizeof(double));
+  const size_t need = noalloc_need(c->nblk);
+  if (need > STATIC_SCRATCH_BYTES)
+    return fail(LBM_E_INVALID, "lbm_diagnostics_noalloc needs " + std::to_string(need) +
+                                   " bytes of scratch; the static area holds " +
+                                   std::to_string(STATIC_SCRATCH_BYTES) + " (at most " +
+                                   std::to_string(max_noalloc_cells()) + " compact cells)");
+  void* base = nullptr;
+  lbm_status s = scratch_address(c->device, &base);
+  if (s != LBM_OK) return s;
+  double* part = (double*)base;                      // every block writes all its partials
+  double* dout = (double*)((char*)base + part_bytes);
+  s = moments_launch(c, true, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, part);
+  if (s != LBM_OK) return s;
+  double dg[NDIAGP];
+  s = finalize(c, part, c->nblk, NDIAGP, DIAG_OPS, dg, dout);
   if (s != LBM_OK) return s;
   for (int k = 0; k < 10; ++k) out[k] = dg[k];
   out[10] = (double)c->t;

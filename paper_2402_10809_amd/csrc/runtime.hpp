@@ -182,7 +182,9 @@ void launch_copy(hipStream_t s, const void* src, void* dst, size_t n16, unsigned
 // Runtime operations shared by the ABI functions (lbm.hip).
 lbm_status launch_init(lbm_ctx* c);
 lbm_status launch_step(lbm_ctx* c, int diag, float* rec, float* rho_rec);
-lbm_status finalize(lbm_ctx* c, const double* part, int nparts, int n, uint32_t ops, double* host_out);
+// dev_out: device area of the reduced vector (nullptr: the workspace's)
+lbm_status finalize(lbm_ctx* c, const double* part, int nparts, int n, uint32_t ops, double* host_out,
+                    double* dev_out = nullptr);
 lbm_status gather_state(lbm_ctx* c, float* dst);
 lbm_status scatter_state(lbm_ctx* c, const float* src);
 

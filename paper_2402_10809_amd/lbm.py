@@ -79,6 +79,7 @@ def lib():
         L.lbm_step.argtypes = [vp, i32]
         L.lbm_moments.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.lbm_diagnostics.argtypes = [vp, vp]
+        L.lbm_diagnostics_noalloc.argtypes = [vp, vp]
         L.lbm_get_state.argtypes = [vp, vp, vp]
         L.lbm_set_state.argtypes = [vp, vp, vp]
         L.lbm_set_porosity.argtypes = [vp, vp]
@@ -92,6 +93,7 @@ def lib():
         L.lbm_destroy.argtypes = [vp]
         L.lbm_destroy.restype = None
         for name in ("lbm_workspace_size", "lbm_create", "lbm_step", "lbm_moments", "lbm_diagnostics",
+                     "lbm_diagnostics_noalloc",
                      "lbm_get_state", "lbm_set_state", "lbm_set_porosity", "lbm_reset", "lbm_adjoint",
                      "lbm_fluid_cells", "lbm_fluid_index", "lbm_time", "lbm_copy_probe"):
             getattr(L, name).restype = ct.c_int
@@ -271,6 +273,13 @@ class Solver:
     def diagnostics(self) -> dict:
         out = np.zeros(NDIAG, np.float64)
         check(lib().lbm_diagnostics(self.ctx, _p(out)))
+        return dict(zip(DIAG_NAMES, out.tolist()))
+
+    def diagnostics_noalloc(self) -> dict:
+        """As diagnostics(), through lbm_diagnostics_noalloc (scratch in the
+        library's fixed device array instead of the workspace)."""
+        out = np.zeros(NDIAG, np.float64)
+        check(lib().lbm_diagnostics_noalloc(self.ctx, _p(out)))
         return dict(zip(DIAG_NAMES, out.tolist()))
 
     def get_state(self):

@@ -27,7 +27,7 @@ def test_header_symbols_exported():
     for n in names:
         assert hasattr(L, n), n
     # and nothing else with the lbm_ prefix is required by the binding
-    assert len(names) == 16
+    assert len(names) == 17
 
 
 def _grid(nx=8, ny=6, nz=5, storage=0, periodic=(0, 0, 0)):
