@@ -11,9 +11,16 @@ weighted moments, drag-corrected velocity, equilibrium and Pi, Carreau-Yasuda
 relaxation rate, collision and store (plus the FP64 stability reduction every
 1000th step).
 
-Timing: inputs resident in device memory, ``--warmup`` untimed steps, then
-exactly ``--steps`` steps between HIP events on the solver's stream, bracketed
-by device synchronisation.
+Timing: inputs resident in device memory; the flow is first spun up from rest
+for ``--spinup`` steps (2000: the pulsatile flow is developed, so the timed
+steps see its working state rather than the near-rest start), then
+``--warmup`` untimed steps, then exactly ``--steps`` steps between HIP events
+on the solver's stream, bracketed by device synchronisation.
+
+Beyond the cache: the aneurysm's FP32 working set (about 217 MB) fits the
+256 MB Infinity Cache, so its rate is not an HBM figure; the ``*_hbm`` forms
+time the same step on the 512x320x320 all-fluid periodic box (52.4 M cells,
+porosity random everywhere), whose state far exceeds the cache.
 """
 
 from __future__ import annotations
@@ -33,16 +40,20 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak
 # algorithmic bytes per fluid-cell update: populations read + written, porosity,
 # relaxation rate read + written
-B_ALG = {"fp32": 164, "fp16": 88, "bf16": 88, "fp32_aniso": 164, "fp16_aniso": 88, "fp16_nearest": 88,
-         "bf16_nearest": 88,
+B_ALG = {"fp32": 164, "fp16": 88, "bf16": 88,
          # D3Q27: 27 populations read + written
          "fp32_q27": 27 * 8 + 12, "fp16_q27": 27 * 4 + 12, "bf16_q27": 27 * 4 + 12}
-# the adjoint call per fluid cell and time step: forward pass (164), recompute
-# with the record written (164 + 19*4 pulled values + omega_prev 4 + rho 4 = 248)
-# and the reverse step (record 80, adjoint populations gathered 76 and written
-# 76, porosity 4, neighbour rho 4, omega adjoint r/w 8, FP64 porosity adjoint
-# r/w 16 = 264)
-B_ALG_ADJ = 164 + 248 + 264
+# The adjoint per reverse cell-step, as the scope of the method counts it:
+# the reverse step (pulled values 76, adjoint populations gathered 76 and
+# written 76, omega_prev 4, porosity 4, neighbour rho 4, omega adjoint r/w 8,
+# porosity adjoint r/w 8 = 256) and the segment recompute (a forward step 164 +
+# the rho record 4 = 168); the initial forward pass is implementation overhead.
+B_ALG_ADJ = 256 + 168
+# what this implementation moves per cell and time step: forward pass 164,
+# recompute with the record written (164 + 19 pulled values + omega_prev + rho
+# = 248), reverse step (record 80, adjoint populations 152, porosity 4,
+# neighbour rho 4, omega adjoint 8, FP64 porosity adjoint 16 = 264)
+B_IMPL_ADJ = 164 + 248 + 264
 
 
 def log(msg):
@@ -73,8 +84,8 @@ def traffic_for(key: str):
     return None if e is None else e.get("bytes_per_launch")
 
 
-def time_steps(torch, solver, steps: int, warmup: int):
-    solver.step(warmup)
+def time_steps(torch, solver, steps: int, warmup: int, spinup: int = 0):
+    solver.step(spinup + warmup)
     torch.cuda.synchronize()
     stream = solver.stream
     e0 = torch.cuda.Event(enable_timing=True)
@@ -86,29 +97,39 @@ def time_steps(torch, solver, steps: int, warmup: int):
     return e0.elapsed_time(e1) / steps  # ms per step
 
 
-def copy_probe(torch, nbytes=4 << 30, reps=10):
+def probes(torch, nbytes=4 << 30, reps=10):
+    """Achievable bandwidth on this machine: the plain 16-byte copy, a copy with
+    four vectors in flight per work-item and non-temporal accesses, a read-only
+    and a write-only stream, each over 4 GiB (GB/s of bytes moved)."""
     from paper_2402_10809_amd import lbm
 
     a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     a.fill_(1)
     st = torch.cuda.current_stream()
-    lbm.lbm_copy_probe(b.data_ptr(), a.data_ptr(), nbytes, st.cuda_stream)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(st)
-    for _ in range(reps):
-        lbm.lbm_copy_probe(b.data_ptr(), a.data_ptr(), nbytes, st.cuda_stream)
-    e1.record(st)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+    out = {}
+    for kind in ("copy", "copy_nt", "read", "write"):
+        dst = b.data_ptr()
+        lbm.lbm_bandwidth_probe(kind, dst, a.data_ptr(), nbytes, st.cuda_stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            lbm.lbm_bandwidth_probe(kind, dst, a.data_ptr(), nbytes, st.cuda_stream)
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        moved = 2 * nbytes if kind.startswith("copy") else nbytes
+        out[kind] = round(moved / (ms * 1e-3) / 1e9, 1)
     del a, b
-    return 2 * nbytes / (ms * 1e-3) / 1e9
+    torch.cuda.empty_cache()
+    return out
 
 
 def time_adjoint(torch, case, T: int, ckpt: int):
     """Wall time of one lbm_adjoint call (forward pass with checkpoints,
     segment recompute and reverse sweep) over T steps, window [T/2, T)."""
+    # the call starts from rest by definition (the forward pass is part of it)
     from paper_2402_10809_amd import Solver
 
     s = Solver.from_case(case, adjoint_T=T, ckpt=ckpt)
@@ -192,20 +213,61 @@ def cpu_cases(budget_s: float):
     return out
 
 
+def parse_form(name: str):
+    """A form name: storage (fp32, fp16, bf16), then optional modifiers: q27
+    (D3Q27), aniso (the anisotropic medium), conserve / nearest (16-bit
+    rounding other than the default stochastic one), hbm (the all-fluid box
+    beyond the cache)."""
+    parts = name.split("_")
+    storage, mods = parts[0], set(parts[1:])
+    if storage not in ("fp32", "fp16", "bf16") or not mods <= {"q27", "aniso", "conserve", "nearest", "hbm"}:
+        raise SystemExit(f"unknown form {name}")
+    rounding = "conserve" if "conserve" in mods else ("nearest" if "nearest" in mods else "stochastic")
+    return storage, mods, rounding
+
+
+def bytes_of(name: str) -> int:
+    storage, mods, _ = parse_form(name)
+    return B_ALG[storage + ("_q27" if "q27" in mods else "")]
+
+
+def make_solver(name: str, case, hbm_case):
+    import copy
+
+    from paper_2402_10809_amd import Solver
+    from synth import as_d3q27, with_anisotropic_drag
+
+    storage, mods, rounding = parse_form(name)
+    c = hbm_case if "hbm" in mods else case
+    if "q27" in mods:
+        c = as_d3q27(copy.copy(c))
+    if "aniso" in mods:
+        # the Remark's anisotropic drag: Forchheimer on, 6 fixed-point iterations
+        c = with_anisotropic_drag(copy.copy(c))
+    return Solver.from_case(c, storage=storage, rounding=rounding)
+
+
+DEFAULT_FORMS = ("fp16,fp16_conserve,fp16_nearest,bf16,fp32_aniso,fp32_q27,fp16_q27,"
+                 "fp32_hbm,fp16_hbm,bf16_hbm,adjoint,adjoint_aniso")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--spinup", type=int, default=2000,
+                    help="steps from rest before the warm-up (the timed flow is the developed one)")
     ap.add_argument("--config", default="c2")
-    ap.add_argument("--forms", default="fp16,fp16_nearest,bf16,fp32_aniso,fp32_q27,fp16_q27,adjoint,adjoint_aniso")
+    ap.add_argument("--forms", default=DEFAULT_FORMS)
     ap.add_argument("--adj-T", type=int, default=400)
     ap.add_argument("--adj-ckpt", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-probe", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--cpu-cases", action="store_true",
                     help="also time the oracle on the channel, small and coarse aneurysm workloads and its reverse sweep")
-    ap.add_argument("--only", default=None, help="time one storage form only (profiling runs)")
+    ap.add_argument("--only", default=None, help="time one form only (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU (got --gpus {args.gpus}): the solver runs on one GPU, and its sharding is a design only.",
@@ -214,7 +276,6 @@ def main():
 
     import torch
 
-    from paper_2402_10809_amd import Solver
     from synth import make_config
 
     if not torch.cuda.is_available():
@@ -225,11 +286,15 @@ def main():
     log(f"[bench] geometry {case.name} {case.nx}x{case.ny}x{case.nz}: {case.n_fluid} fluid cells "
         f"({time.perf_counter() - t0:.1f} s)")
 
-    results = {}
     forms = ["fp32"] + [f for f in args.forms.split(",") if f]
     if args.only:
         forms = [args.only]
-    adjoints = {}
+    hbm_case = None
+    if any("hbm" in f for f in forms):
+        t0 = time.perf_counter()
+        hbm_case = make_config("hbm")
+        log(f"[bench] geometry {hbm_case.name}: {hbm_case.n_fluid} cells ({time.perf_counter() - t0:.1f} s)")
+    results, adjoints, skipped = {}, {}, {}
     for aform in [f for f in forms if f.startswith("adjoint")]:
         forms.remove(aform)
         T, ck = args.adj_T, args.adj_ckpt
@@ -244,34 +309,29 @@ def main():
             raise SystemExit(f"unknown adjoint form {aform}")
         log(f"[bench] {aform}: T={T}, checkpoint every {ck}, window [{T // 2}, {T})")
         dt, ok = time_adjoint(torch, acase, T, ck)
-        mlups = case.n_fluid * T / dt / 1e6
-        gbs = mlups * 1e6 * B_ALG_ADJ / 1e9
-        adjoints[aform] = dict(T=T, ckpt=ck, seconds=round(dt, 4), mlups=round(mlups, 1), bytes_per_update=B_ALG_ADJ,
-                               alg_GBps=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4), finite=ok)
-        log(f"[bench] {aform}: {dt * 1e3:.1f} ms, {mlups:.0f} M cell-steps/s, {gbs:.0f} GB/s algorithmic")
+        rate = case.n_fluid * T / dt
+        gbs = rate * B_ALG_ADJ / 1e9
+        adjoints[aform] = dict(T=T, ckpt=ck, seconds=round(dt, 4), us_per_step=round(dt / T * 1e6, 1),
+                               reverse_cell_steps_per_s=round(rate, 0), bytes_per_update=B_ALG_ADJ,
+                               alg_GBps=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4),
+                               impl_bytes_per_update=B_IMPL_ADJ, impl_GBps=round(rate * B_IMPL_ADJ / 1e9, 1),
+                               finite=ok)
+        log(f"[bench] {aform}: {dt * 1e3:.1f} ms ({dt / T * 1e6:.0f} us per time step), {rate / 1e9:.2f} G "
+            f"reverse cell-steps/s, {gbs:.0f} GB/s algorithmic")
     for form in forms:
-        storage = form.split("_")[0]
-        if form.endswith("_q27"):
-            import copy
-
-            from synth import as_d3q27
-            s = Solver.from_case(as_d3q27(copy.copy(case)), storage=storage)
-        elif form.endswith("_aniso"):
-            # the Remark's anisotropic drag: Forchheimer on, 6 fixed-point iterations
-            import copy
-
-            from synth import with_anisotropic_drag
-            s = Solver.from_case(with_anisotropic_drag(copy.copy(case)), storage=storage)
-        elif form.endswith("_nearest"):
-            # 16-bit storage rounded to nearest value by value (the default conserves mass and momentum)
-            s = Solver.from_case(case, storage=storage, rounding="nearest")
-        else:
-            s = Solver.from_case(case, storage=storage)
-        log(f"[bench] {form}: timing {args.steps} steps after {args.warmup} warmup")
-        ms = time_steps(torch, s, args.steps, args.warmup)
+        storage, mods, rounding = parse_form(form)
+        if "q27" in mods and "hbm" in mods:
+            skipped[form] = ("D3Q27 on the all-fluid box exceeds the 32-bit population offsets "
+                             "(39.7 M compact cells at most)")
+            log(f"[bench] {form}: skipped ({skipped[form]})")
+            continue
+        s = make_solver(form, case, hbm_case)
+        spin = args.spinup
+        log(f"[bench] {form}: {spin} spin-up steps, then timing {args.steps} steps after {args.warmup} warmup")
+        ms = time_steps(torch, s, args.steps, args.warmup, spin)
         mlups = s.n_fluid / (ms * 1e-3) / 1e6
-        gbs = mlups * 1e6 * B_ALG[form] / 1e9
-        results[form] = dict(ms_per_step=ms, mlups=mlups, alg_GBps=gbs, frac=gbs / HBM_PEAK_GBS)
+        gbs = mlups * 1e6 * bytes_of(form) / 1e9
+        results[form] = dict(ms_per_step=ms, mlups=mlups, alg_GBps=gbs, frac=gbs / HBM_PEAK_GBS, cells=s.n_fluid)
         log(f"[bench] {form}: {ms * 1e3:.1f} us/step, {mlups:.0f} MLUPS, {gbs:.0f} GB/s algorithmic")
         d = s.diagnostics()
         assert d["nonfinite"] == 0
@@ -279,10 +339,11 @@ def main():
         del s
         torch.cuda.empty_cache()
 
-    head = results.get("fp32") or next(iter(results.values()))
-    head_form = "fp32" if "fp32" in results else forms[0]
-    probe = copy_probe(torch)
-    log(f"[bench] copy probe: {probe:.0f} GB/s")
+    head_form = "fp32" if "fp32" in results else next(iter(results))
+    head = results[head_form]
+    probe = None if args.no_probe else probes(torch)
+    if probe:
+        log(f"[bench] bandwidth probes (GB/s): {probe}")
     cpu = None
     if not args.no_cpu:
         log("[bench] oracle CPU baseline")
@@ -294,6 +355,18 @@ def main():
 
     nf = case.n_fluid
     traffic = traffic_for(f"k_step_{head_form}_{args.config}")
+    # working set of the headline form: populations, per-cell code, link word,
+    # porosity and relaxation rate, in bytes
+    ws_mb = round(nf * (19 * (4 if head_form == "fp32" else 2) + 16) / 1e6, 1)
+    roof = {"bound": "hbm", "achieved": round(head["alg_GBps"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(head["frac"], 4), "traffic": traffic,
+            "working_set_MB": ws_mb, "cache_resident": ws_mb < 256.0}
+    hb = results.get(f"{head_form}_hbm")
+    if hb:
+        roof["beyond_cache"] = {"workload": f"all-fluid periodic box {hbm_case.nx}x{hbm_case.ny}x{hbm_case.nz}",
+                                "achieved": round(hb["alg_GBps"], 1), "frac": round(hb["frac"], 4)}
+    if probe:
+        roof["achievable_GBps"] = max(probe.values())
     line = {
         "metric": "fluid MLUPS + % HBM peak, D3Q19 VANSE-CY: FP32 vs FP16-store vs adjoint",
         "value": round(head["mlups"], 1),
@@ -310,17 +383,18 @@ def main():
         "config": {"workload": f"aneurysm {case.nx}x{case.ny}x{case.nz}, tube R={case.extra.get('R')}, "
                                f"sac R={case.extra.get('Rs')}, GRF porosity ell={case.extra.get('ell')}, "
                                f"Carreau-Yasuda, pulsatile Zou-He inlet, density outlet",
-                   "fluid_cells": nf, "storage": head_form, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": round(head["alg_GBps"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(head["frac"], 4),
-                     "traffic": traffic},
+                   "fluid_cells": nf, "storage": head_form, "spinup_steps": args.spinup,
+                   "parallelism": "single GPU"},
+        "roofline": roof,
         "cpu_baseline": cpu,
         "forms": {k: {"mlups": round(v["mlups"], 1), "alg_GBps": round(v["alg_GBps"], 1),
-                      "frac": round(v["frac"], 4), "bytes_per_update": B_ALG[k],
-                      "ms_per_step": round(v["ms_per_step"], 5)} for k, v in results.items()},
-        "copy_probe_GBps": round(probe, 1),
+                      "frac": round(v["frac"], 4), "bytes_per_update": bytes_of(k),
+                      "ms_per_step": round(v["ms_per_step"], 5), "cells": v["cells"]} for k, v in results.items()},
+        "bandwidth_probes_GBps": probe,
     }
     line["forms"].update(adjoints)
+    if skipped:
+        line["skipped"] = skipped
     print(json.dumps(line), flush=True)
 
 

@@ -23,14 +23,14 @@ from __future__ import annotations
 
 from typing import Optional
 
-import numpy as np
 import torch
 
 
 class RegionObjective(torch.autograd.Function):
     @staticmethod
     def forward(ctx, phi: torch.Tensor, solver, t_begin: int, t_end: int, T: int, ckpt: Optional[int], kind: str):
-        solver.set_porosity(phi.detach().to("cpu", torch.float32).numpy().astype(np.float32))
+        # device to device: the library reads phi in place (no host copy)
+        solver.set_porosity(phi.detach().to(solver.device, torch.float32).contiguous())
         ctx.phi_device = phi.device
         if ctx.needs_input_grad[0]:
             J, g = solver.adjoint(t_begin, t_end, T, ckpt, kind=kind)

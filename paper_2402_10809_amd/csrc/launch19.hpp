@@ -15,17 +15,17 @@ void step19(lbm_ctx* c, const lbm::Bufs& b, int diag, bool rec) {
       using R = typename decltype(rt)::T;
       constexpr bool PJ = decltype(rt)::proj;
       with_rounding<S>(c->grid.rounding, [&](auto cr) {
-        constexpr bool CR = decltype(cr)::value;
+        constexpr int RM = decltype(cr)::value;
         with_parity(c->t, [&](auto odd) {
           constexpr bool OD = decltype(odd)::value;
           // AN: anisotropic permeability (every form, the adjoint's included)
           auto go = [&](auto an) {
             constexpr bool AN = decltype(an)::value;
             if (diag == 0 && !rec) {
-              hipLaunchKernelGGL((k_step<S, SH, OD, 0, false, R, PJ, NT, AN, CR>), grid, block, 0, c->stream, c->P,
+              hipLaunchKernelGGL((k_step<S, SH, OD, 0, false, R, PJ, NT, AN, RM>), grid, block, 0, c->stream, c->P,
                                  b);
             } else if (diag == 1) {
-              hipLaunchKernelGGL((k_step<S, SH, OD, 1, false, R, PJ, NT, AN, CR>), grid, block, 0, c->stream, c->P,
+              hipLaunchKernelGGL((k_step<S, SH, OD, 1, false, R, PJ, NT, AN, RM>), grid, block, 0, c->stream, c->P,
                                  b);
             } else if constexpr (std::is_same<S, float>::value) {
               // the adjoint's forms (FP32 storage only)

@@ -15,13 +15,13 @@ void step27(lbm_ctx* c, const lbm::q27::Bufs27& b, int diag) {
       using R = typename decltype(rt)::T;
       constexpr bool PJ = decltype(rt)::proj;
       with_rounding<S>(c->grid.rounding, [&](auto cr) {
-        constexpr bool CR = decltype(cr)::value;
+        constexpr int RM = decltype(cr)::value;
         with_parity(c->t, [&](auto odd) {
           constexpr bool OD = decltype(odd)::value;
           if (diag == 0)
-            hipLaunchKernelGGL((q27::k_step<S, SH, OD, 0, R, PJ, NT, CR>), grid, block, 0, c->stream, c->P, b);
+            hipLaunchKernelGGL((q27::k_step<S, SH, OD, 0, R, PJ, NT, RM>), grid, block, 0, c->stream, c->P, b);
           else
-            hipLaunchKernelGGL((q27::k_step<S, SH, OD, 1, R, PJ, NT, CR>), grid, block, 0, c->stream, c->P, b);
+            hipLaunchKernelGGL((q27::k_step<S, SH, OD, 1, R, PJ, NT, RM>), grid, block, 0, c->stream, c->P, b);
         });
       });
     });

@@ -219,8 +219,8 @@ lbm_status validate_grid(const lbm_grid* g) {
   if (g->nx > 2048 || g->ny > 1024 || g->nz > 1024) return fail(LBM_E_INVALID, "grid exceeds 2048 x 1024 x 1024");
   if (g->storage < 0 || g->storage > 2) return fail(LBM_E_INVALID, "unknown storage format");
   if (g->shift_mode < 0 || g->shift_mode > 1) return fail(LBM_E_INVALID, "shift_mode must be 0 or 1");
-  if (g->rounding != LBM_ROUND_CONSERVE && g->rounding != LBM_ROUND_NEAREST)
-    return fail(LBM_E_INVALID, "rounding must be LBM_ROUND_CONSERVE or LBM_ROUND_NEAREST");
+  if (g->rounding < LBM_ROUND_STOCHASTIC || g->rounding > LBM_ROUND_NEAREST)
+    return fail(LBM_E_INVALID, "rounding must be one of the lbm_rounding values");
   if (g->arith < 0 || g->arith > 2) return fail(LBM_E_INVALID, "unknown arithmetic mode");
   if (g->arith == LBM_ARITH_FP64 && g->storage != LBM_STORE_FP32)
     return fail(LBM_E_INVALID, "FP64 arithmetic is only available with FP32 storage");
@@ -550,6 +550,18 @@ lbm_status moments_launch(lbm_ctx* c, bool diag, float* rho, float* u, float* sh
   return LBM_OK;
 }
 
+// The host copy of the porosity per fluid cell (for the state transfer's rest
+// values), refreshed from the device after lbm_set_porosity.
+lbm_status refresh_phi_host(lbm_ctx* c) {
+  if (!c->phi_stale) return LBM_OK;
+  std::vector<float> comp(c->nc);
+  HIP_TRY(c, hipMemcpyAsync(comp.data(), c->ws + c->L.phi, comp.size() * 4, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (int64_t k = 0; k < c->nf; ++k) c->phi_f[k] = comp[c->fluid_c[k]];
+  c->phi_stale = false;
+  return LBM_OK;
+}
+
 double rest_value(const lbm_ctx* c, int i, int64_t k) {
   const double w = c->q == 27 ? q27::kw(i) / 216.0 : (i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0));
   return w * (c->grid.shift_mode ? 1.0 : c->phi_f[k]);
@@ -835,6 +847,10 @@ lbm_status lbm_diagnostics_noalloc(lbm_ctx* c, double* out) {
 lbm_status lbm_get_state(lbm_ctx* c, double* f, float* omega) {
   CTX_CHECK(c);
   if (!f && !omega) return fail(LBM_E_INVALID, "nothing to get");
+  if (f) {
+    lbm_status s = refresh_phi_host(c);
+    if (s != LBM_OK) return s;
+  }
   float* stage = (float*)(c->ws + c->L.stage);
   const size_t nf = (size_t)c->nf, nc = (size_t)c->nc;
   if (f) {
@@ -863,6 +879,10 @@ lbm_status lbm_get_state(lbm_ctx* c, double* f, float* omega) {
 lbm_status lbm_set_state(lbm_ctx* c, const double* f, const float* omega) {
   CTX_CHECK(c);
   if (!f && !omega) return fail(LBM_E_INVALID, "nothing to set");
+  if (f) {
+    lbm_status s = refresh_phi_host(c);
+    if (s != LBM_OK) return s;
+  }
   float* stage = (float*)(c->ws + c->L.stage);
   const size_t nf = (size_t)c->nf, nc = (size_t)c->nc;
   if (f) {
@@ -893,10 +913,16 @@ lbm_status lbm_reset(lbm_ctx* c) {
 lbm_status lbm_set_porosity(lbm_ctx* c, const float* phi) {
   CTX_CHECK(c);
   if (!phi) return fail(LBM_E_INVALID, "phi is NULL");
-  lbm_status s = check_phi(c, phi);
+  uint32_t bad = 0;
+  lbm_status s = set_porosity_device(c, phi, &bad);
   if (s != LBM_OK) return s;
-  s = upload_phi(c, phi);
-  if (s != LBM_OK) return s;
+  if (bad != 0xffffffffu) {
+    const auto it = std::lower_bound(c->fluid_c.begin(), c->fluid_c.end(), (int64_t)bad);
+    const int64_t box = it != c->fluid_c.end() && *it == (int64_t)bad ? c->fluid_box[it - c->fluid_c.begin()] : -1;
+    return fail(LBM_E_INVALID, "porosity must lie in (0, 1] on every fluid cell and be 1 on open-face cells "
+                               "(box index " + std::to_string(box) + ")");
+  }
+  c->phi_stale = true;
   return launch_init(c);
 }
 
@@ -930,6 +956,18 @@ lbm_status lbm_copy_probe(void* dst, const void* src, size_t bytes, void* stream
   launch_copy((hipStream_t)stream, src, dst, n, (unsigned)blocks);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(LBM_E_DEVICE, std::string("copy probe: ") + hipGetErrorString(e));
+  return LBM_OK;
+}
+
+lbm_status lbm_bandwidth_probe(int kind, void* dst, const void* src, size_t bytes, void* stream) {
+  if (kind < LBM_PROBE_COPY || kind > LBM_PROBE_WRITE) return fail(LBM_E_INVALID, "unknown probe kind");
+  if (bytes % 16 != 0 || bytes == 0) return fail(LBM_E_INVALID, "probe bytes must be a positive multiple of 16");
+  if (!dst || (kind != LBM_PROBE_WRITE && !src)) return fail(LBM_E_INVALID, "probe buffers must not be NULL");
+  const size_t n = bytes / 16;
+  const unsigned blocks = LBM_PROBE_BLOCKS;
+  launch_probe((hipStream_t)stream, kind, src, dst, n, blocks);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(LBM_E_DEVICE, std::string("bandwidth probe: ") + hipGetErrorString(e));
   return LBM_OK;
 }
 

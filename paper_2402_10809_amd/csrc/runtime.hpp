@@ -73,6 +73,7 @@ struct lbm_ctx {
   std::vector<int64_t> fluid_box; // box index per fluid cell (ascending)
   std::vector<int64_t> fluid_c;   // compact index per fluid cell
   std::vector<double> phi_f;      // porosity per fluid cell (host, for state transfer)
+  bool phi_stale = false;         // phi_f predates a device-side porosity update
   std::vector<uint8_t> solid;     // host copy of the mask
   std::vector<uint8_t> region_f;  // per fluid cell
   std::vector<uint8_t> openface;  // per fluid cell: 1 inlet, 2 outlet
@@ -118,13 +119,15 @@ void with_shift(int shw, Fn&& fn) {
   if (shw) fn(std::true_type{}); else fn(std::false_type{});
 }
 
-// Rounding of the 16-bit storage forms: conserving or to nearest; FP32
-// storage has one form.
+// Rounding of the 16-bit storage forms (lbm_rounding, see round16 in
+// step.hpp); FP32 storage has one form.
 template <class S, class Fn>
 void with_rounding(int rounding, Fn&& fn) {
-  if constexpr (std::is_same<S, float>::value) fn(std::false_type{});
-  else if (rounding == LBM_ROUND_NEAREST) fn(std::false_type{});
-  else fn(std::true_type{});
+  using std::integral_constant;
+  if constexpr (std::is_same<S, float>::value) fn(integral_constant<int, 0>{});
+  else if (rounding == LBM_ROUND_NEAREST) fn(integral_constant<int, 0>{});
+  else if (rounding == LBM_ROUND_CONSERVE) fn(integral_constant<int, 1>{});
+  else fn(integral_constant<int, 2>{});
 }
 
 // Arithmetic for storage S: the FP64 and projected forms only exist for FP32
@@ -178,6 +181,8 @@ void with_storage(int storage, Fn&& fn) {
 void launch_finalize(hipStream_t s, const double* part, int nparts, int n, uint32_t ops, double* out);
 void launch_set_time(hipStream_t s, uint32_t* tc, uint32_t t);
 void launch_copy(hipStream_t s, const void* src, void* dst, size_t n16, unsigned blocks);
+void launch_probe(hipStream_t s, int kind, const void* src, void* dst, size_t n16, unsigned blocks);
+lbm_status set_porosity_device(lbm_ctx* c, const float* phib, uint32_t* bad_cell);
 
 // Runtime operations shared by the ABI functions (lbm.hip).
 lbm_status launch_init(lbm_ctx* c);

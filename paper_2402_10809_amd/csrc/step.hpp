@@ -599,44 +599,118 @@ __device__ __forceinline__ R region_wss(uint32_t lk, const Macro<R>& M) {
   return wall_tau(M, n, tau);
 }
 
-// 16-bit storage, conserving rounding: every value is rounded to nearest
-// except that the rounding residuals of the cell's mass and momentum are
-// carried.  The non-axis values (directions 7.. in opposite pairs) are
-// rounded first; their momentum residual moves onto the three axis pairs (as
-// pair differences, which carry no mass) before those are rounded; the whole
-// mass residual moves onto the rest value, rounded last.  Every stored value
-// stays within one unit in the last place of its exact output, while the
-// cell's stored mass and momentum each carry one rounding instead of the sum
-// of all of them: with plain rounding to nearest the momentum of the 16-bit
-// forms random-walks with the storage rounding, step after step.  Works for
-// any velocity set ordered rest, axis pairs, then opposite pairs.
-template <class S, int NQ>
-__device__ __forceinline__ void conserving_round(const int (&cx)[NQ], const int (&cy)[NQ], const int (&cz)[NQ],
-                                                 const float o[NQ], unsigned short hb[NQ]) {
-  // hb[i] = v rounded to nearest in S; returns the residual (exact in FP32)
-  auto rn = [&](int i, float v) {
-    const S h = (S)v;
-    hb[i] = __builtin_bit_cast(unsigned short, h);
-    return v - (float)h;
+// Rounding of the 16-bit storage forms (RM):
+//   0 nearest: every value rounds to nearest even on its own;
+//   1 conserving: every value is rounded to nearest except that the rounding
+//     residuals of the cell's mass and momentum are carried.  The non-axis
+//     values (directions 7.. in opposite pairs) are rounded first; their
+//     momentum residual moves onto the three axis pairs (as pair differences,
+//     which carry no mass) before those are rounded; the whole mass residual
+//     moves onto the rest value, rounded last.  The cell's stored mass and
+//     momentum each carry one rounding instead of the sum of all of them;
+//   2 stochastic: every value rounds up or down with probabilities given by
+//     its distance to the two neighbours (the hardware's stochastic-rounding
+//     conversion, v_cvt_sr), so every rounding error has mean zero.
+// Deterministic rounding of a smooth, nearly periodic flow makes the same
+// error at the same place step after step: a steady forcing, which the slowly
+// damped modes at an open face integrate (the staggered velocity mode next to
+// a constant-density outflow grows to ~1e-4 of u in 20 000 steps).  Stochastic
+// rounding turns that forcing into zero-mean noise.  Works for any velocity set
+// ordered rest, axis pairs, then opposite pairs.
+//
+// Random bits: a per-(cell, step) seed from an integer hash (the "lowbias32"
+// finaliser of C. Wellons' hash-prospector), then Marsaglia's xorshift32
+// sequence, one word per opposite pair (the conversion reads the top 13 bits
+// for FP16, the top 16 for BF16, so the word shifted left by 13 or 16 serves
+// the pair's second value) and one for the rest value.
+__device__ __forceinline__ uint32_t hash32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+__device__ __forceinline__ uint32_t xorshift32(uint32_t x) {
+  x ^= x << 13;
+  x ^= x >> 17;
+  x ^= x << 5;
+  return x;
+}
+// Seed of the rounding sequence of cell c at step t (never zero).
+__device__ __forceinline__ uint32_t round_seed(uint32_t c, uint32_t t) {
+  return hash32(c ^ hash32(t * 0x9e3779b9u + 0x632be5abu)) | 1u;
+}
+// v rounded stochastically to S (FP16 or BF16) with the random word r.
+template <class S>
+__device__ __forceinline__ unsigned short round_sr(float v, uint32_t r) {
+  if constexpr (std::is_same<S, _Float16>::value) {
+    typedef _Float16 v2 __attribute__((ext_vector_type(2)));
+    v2 a = {};
+    a = __builtin_amdgcn_cvt_sr_f16_f32(a, v, r, false);
+    return __builtin_bit_cast(unsigned short, a[0]);
+  } else {
+    typedef __bf16 v2 __attribute__((ext_vector_type(2)));
+    v2 a = {};
+    a = __builtin_amdgcn_cvt_sr_bf16_f32(a, v, r, false);
+    return __builtin_bit_cast(unsigned short, a[0]);
+  }
+}
+template <class S, int NQ, int RM>
+__device__ __forceinline__ void round16(const int (&cx)[NQ], const int (&cy)[NQ], const int (&cz)[NQ],
+                                        const float o[NQ], unsigned short hb[NQ], uint32_t seed) {
+  constexpr bool SR = RM == 2;
+  constexpr int SH = std::is_same<S, _Float16>::value ? 13 : 16;  // second window of a random word
+  uint32_t st = seed;
+  // the next random word (unused without stochastic rounding)
+  auto word = [&]() -> uint32_t {
+    if constexpr (SR) {
+      st = xorshift32(st);
+      return st;
+    } else {
+      return 0u;
+    }
   };
+  // hb[i] = v rounded in S; returns the residual (exact in FP32)
+  auto rn = [&](int i, float v, uint32_t r) {
+    unsigned short h;
+    if constexpr (SR) h = round_sr<S>(v, r);
+    else h = __builtin_bit_cast(unsigned short, (S)v);
+    hb[i] = h;
+    return v - (float)__builtin_bit_cast(S, h);
+  };
+  if constexpr (RM != 1) {
+    sfor<0, (NQ - 1) / 2>([&](auto kc) {
+      constexpr int I = 1 + 2 * decltype(kc)::value;
+      const uint32_t r = word();
+      rn(I, o[I], r);
+      rn(I + 1, o[I + 1], r << SH);
+    });
+    rn(0, o[0], word());
+    return;
+  }
   float m = 0.0f, rx = 0.0f, ry = 0.0f, rz = 0.0f;
   // the pair sum carries mass, the difference momentum along c_I
   sfor<0, (NQ - 7) / 2>([&](auto kc) {
     constexpr int I = 7 + 2 * decltype(kc)::value;
-    const float a = rn(I, o[I]), b = rn(I + 1, o[I + 1]);
+    const uint32_t r = word();
+    const float a = rn(I, o[I], r), b = rn(I + 1, o[I + 1], r << SH);
     m += a + b;
     const float d = a - b;
     if (cx[I]) rx += cx[I] > 0 ? d : -d;
     if (cy[I]) ry += cy[I] > 0 ? d : -d;
     if (cz[I]) rz += cz[I] > 0 ? d : -d;
   });
-  m += rn(1, o[1] + 0.5f * rx);
-  m += rn(2, o[2] - 0.5f * rx);
-  m += rn(3, o[3] + 0.5f * ry);
-  m += rn(4, o[4] - 0.5f * ry);
-  m += rn(5, o[5] + 0.5f * rz);
-  m += rn(6, o[6] - 0.5f * rz);
-  rn(0, o[0] + m);
+  uint32_t r = word();
+  m += rn(1, o[1] + 0.5f * rx, r);
+  m += rn(2, o[2] - 0.5f * rx, r << SH);
+  r = word();
+  m += rn(3, o[3] + 0.5f * ry, r);
+  m += rn(4, o[4] - 0.5f * ry, r << SH);
+  r = word();
+  m += rn(5, o[5] + 0.5f * rz, r);
+  m += rn(6, o[6] - 0.5f * rz, r << SH);
+  rn(0, o[0] + m, word());
 }
 
 // BGK + Guo + porosity-jump collision, stored as deviations for the consumer.
@@ -653,9 +727,10 @@ __device__ __forceinline__ void conserving_round(const int (&cx)[NQ], const int 
 // difference to the intended momentum (input momentum + force + porosity-jump
 // momentum) onto the three axis pairs, leaving only the final rounding of
 // each stored value.
-template <class S, bool SHW, bool UNI, bool ODD, class R, bool PROJ, bool INR = false, bool CR = false>
+template <class S, bool SHW, bool UNI, bool ODD, class R, bool PROJ, bool INR = false, int RM = 0>
 __device__ __forceinline__ void collide_store(const Params& p, const Pop<S>& A, uint32_t c, uint32_t lk, const Pos& q,
-                                              float phx_f, float d[Q], const float pt[Q], const Macro<R>& M) {
+                                              float phx_f, float d[Q], const float pt[Q], const Macro<R>& M,
+                                              uint32_t seed = 0u) {
   const R phx = (R)phx_f;
   const R om = M.omega;
   const R pr = phx * M.rho;
@@ -737,9 +812,9 @@ __device__ __forceinline__ void collide_store(const Params& p, const Pop<S>& A, 
 #pragma unroll
     for (int i = 0; i < Q; ++i) o[i] += ksf * kw(i) * ((UNI ? phx_f : pt[i]) - 1.0f);
   }
-  if constexpr (!std::is_same<S, float>::value && CR) {
+  if constexpr (!std::is_same<S, float>::value && RM != 0) {
     unsigned short hb[Q];
-    conserving_round<S, Q>(CX, CY, CZ, o, hb);
+    round16<S, Q, RM>(CX, CY, CZ, o, hb, seed);
     sfor<0, Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
       const Slot a = slot_out<I, ODD, S, INR>(p, c, lk, q);
@@ -812,9 +887,9 @@ __device__ __forceinline__ void diag_terms(const Params& p, float phx, const flo
 }
 
 // Body of the step for one cell (UNI: the whole wave has uniform neighbour
-// porosity; INR: every cell of the wave is interior; CR: conserving rounding
-// of 16-bit storage).
-template <class S, bool SHW, bool UNI, bool ODD, int DIAG, bool REC, class R, bool PROJ, bool AN, bool INR, bool CR>
+// porosity; INR: every cell of the wave is interior; RM: rounding of 16-bit
+// storage, see round16).
+template <class S, bool SHW, bool UNI, bool ODD, int DIAG, bool REC, class R, bool PROJ, bool AN, bool INR, int RM>
 __device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32_t c, uint32_t lk, uint32_t t,
                                           double (&dv)[NDIAGP], float& ke_reg) {
   Pos q = position(p, c, b.code[c]);
@@ -846,7 +921,7 @@ __device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32
   if (DIAG == 1) diag_terms<R>(p, phx, d, M, lk, true, dv);
   if (DIAG == 2) ke_reg = reg ? (float)((R)0.5 * M.rho * M.uu) : 0.0f;
   if (DIAG == 3) ke_reg = (float)region_wss<R>(lk, M);
-  collide_store<S, SHW, UNI, ODD, R, PROJ, INR, CR>(p, A, c, lk, q, phx, d, pt, M);
+  collide_store<S, SHW, UNI, ODD, R, PROJ, INR, RM>(p, A, c, lk, q, phx, d, pt, M, RM == 2 ? round_seed(c, t) : 0u);
 }
 
 // ---------------------------------------------------------------------------
@@ -859,7 +934,7 @@ __device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32
 // The 16-bit odd step needs 97 VGPRs as compiled freely (4 waves per SIMD);
 // asked for 5 waves the compiler fits it in 96 without scratch, and the step
 // runs 1-2 % faster.  Other instantiations would spill at 5 and keep the default.
-template <class S, bool SHW, bool ODD, int DIAG, bool REC, class R, bool PROJ, int NT, bool AN = false, bool CR = false>
+template <class S, bool SHW, bool ODD, int DIAG, bool REC, class R, bool PROJ, int NT, bool AN = false, int RM = 0>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu((ODD && sizeof(S) == 2 && DIAG == 0 && !REC) ? 5 : 1)))
 void k_step(Params p, Bufs b) {
   const uint32_t c = xcd_block(blockIdx.x, gridDim.x) * NT + threadIdx.x;
@@ -873,12 +948,12 @@ void k_step(Params p, Bufs b) {
     // odd steps address the neighbours: interior waves (most of a vessel's
     // waves) need no per-direction bounce-back selects
     if (ODD && __all(!active || (lk & LK_INR))) {
-      if (active) step_cell<S, SHW, true, ODD, DIAG, REC, R, PROJ, AN, true, CR>(p, b, c, lk, t, dv, ke_reg);
+      if (active) step_cell<S, SHW, true, ODD, DIAG, REC, R, PROJ, AN, true, RM>(p, b, c, lk, t, dv, ke_reg);
     } else {
-      if (active) step_cell<S, SHW, true, ODD, DIAG, REC, R, PROJ, AN, false, CR>(p, b, c, lk, t, dv, ke_reg);
+      if (active) step_cell<S, SHW, true, ODD, DIAG, REC, R, PROJ, AN, false, RM>(p, b, c, lk, t, dv, ke_reg);
     }
   } else {
-    if (active) step_cell<S, SHW, false, ODD, DIAG, REC, R, PROJ, AN, false, CR>(p, b, c, lk, t, dv, ke_reg);
+    if (active) step_cell<S, SHW, false, ODD, DIAG, REC, R, PROJ, AN, false, RM>(p, b, c, lk, t, dv, ke_reg);
   }
   if (DIAG == 1) {
     if (!active) {

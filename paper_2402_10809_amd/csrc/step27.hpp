@@ -241,9 +241,10 @@ __device__ __forceinline__ bool wall_normal(uint64_t lk, float n[3]) {
 
 // Collision and store, as in step.hpp (deviation form, optional FP64 momentum
 // projection onto the axis pairs, shift mode 1 conversion).
-template <class S, bool SHW, bool UNI, bool ODD, class R, bool PROJ, bool CR>
+template <class S, bool SHW, bool UNI, bool ODD, class R, bool PROJ, int RM>
 __device__ __forceinline__ void collide_store(const Params& p, const Pop<S>& A, uint32_t c, uint64_t lk, const Pos& q,
-                                              float phx_f, float d[Q], const float pt[Q], const Macro<R>& M) {
+                                              float phx_f, float d[Q], const float pt[Q], const Macro<R>& M,
+                                              uint32_t seed) {
   const R phx = (R)phx_f;
   const R om = M.omega;
   const R pr = phx * M.rho;
@@ -298,9 +299,9 @@ __device__ __forceinline__ void collide_store(const Params& p, const Pop<S>& A, 
 #pragma unroll
     for (int i = 0; i < Q; ++i) o[i] += ksf * (float)kw(i) * ((UNI ? phx_f : pt[i]) - 1.0f);
   }
-  if constexpr (!std::is_same<S, float>::value && CR) {
+  if constexpr (!std::is_same<S, float>::value && RM != 0) {
     unsigned short hb[Q];
-    conserving_round<S, Q>(CX, CY, CZ, o, hb);
+    round16<S, Q, RM>(CX, CY, CZ, o, hb, seed);
     sfor<0, Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
       const Slot a = slot_out<I, ODD, S>(p, c, lk, q);
@@ -344,7 +345,7 @@ __device__ __forceinline__ void diag_terms(const Params& p, float phx, const flo
   v[10] = (reg && wall_normal(lk, n)) ? (double)wall_tau(M, n, tau) : 0.0;
 }
 
-template <class S, bool SHW, bool UNI, bool ODD, int DIAG, class R, bool PROJ, bool CR>
+template <class S, bool SHW, bool UNI, bool ODD, int DIAG, class R, bool PROJ, int RM>
 __device__ __forceinline__ void step_cell(const Params& p, const Bufs27& b, uint32_t c, uint64_t lk, uint32_t t,
                                           double (&dv)[NDIAGP]) {
   Pos q = position(p, c, b.code[c]);
@@ -361,11 +362,11 @@ __device__ __forceinline__ void step_cell(const Params& p, const Bufs27& b, uint
   macro_sums<R>(p, phx, moment_sums<R>(d), omp, M);
   b.omega[c] = (float)M.omega;
   if (DIAG == 1) diag_terms<R>(p, phx, d, M, lk, true, dv);
-  collide_store<S, SHW, UNI, ODD, R, PROJ, CR>(p, A, c, lk, q, phx, d, pt, M);
+  collide_store<S, SHW, UNI, ODD, R, PROJ, RM>(p, A, c, lk, q, phx, d, pt, M, RM == 2 ? round_seed(c, t) : 0u);
 }
 
 // One D3Q27 step at parity ODD.  DIAG: 0 none, 1 diagnostics partials.
-template <class S, bool SHW, bool ODD, int DIAG, class R, bool PROJ, int NT, bool CR = false>
+template <class S, bool SHW, bool ODD, int DIAG, class R, bool PROJ, int NT, int RM = 0>
 __global__ __launch_bounds__(NT) void k_step(Params p, Bufs27 b) {
   const uint32_t c = xcd_block(blockIdx.x, gridDim.x) * NT + threadIdx.x;
   const uint32_t t = b.tc[ODD ? 1 : 0];
@@ -374,9 +375,9 @@ __global__ __launch_bounds__(NT) void k_step(Params p, Bufs27 b) {
   double dv[NDIAGP];
   const bool uni = !active || (lk & L_UNI);
   if (__all(uni)) {
-    if (active) step_cell<S, SHW, true, ODD, DIAG, R, PROJ, CR>(p, b, c, lk, t, dv);
+    if (active) step_cell<S, SHW, true, ODD, DIAG, R, PROJ, RM>(p, b, c, lk, t, dv);
   } else {
-    if (active) step_cell<S, SHW, false, ODD, DIAG, R, PROJ, CR>(p, b, c, lk, t, dv);
+    if (active) step_cell<S, SHW, false, ODD, DIAG, R, PROJ, RM>(p, b, c, lk, t, dv);
   }
   if (DIAG == 1) {
     if (!active) {

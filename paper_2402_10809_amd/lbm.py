@@ -21,8 +21,8 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 LBM_OK, LBM_E_INVALID, LBM_E_DEVICE, LBM_E_UNSTABLE, LBM_E_STATE, LBM_E_WORKSPACE = range(6)
 STORAGE = {"fp32": 0, "fp16": 1, "bf16": 2}
 ARITH = {"auto": 0, "fp32": 1, "fp64": 2}
-ROUNDING = {"conserve": 0, "nearest": 1}
-LBM_ROUND_CONSERVE, LBM_ROUND_NEAREST = 0, 1
+ROUNDING = {"stochastic": 0, "conserve": 1, "nearest": 2}
+LBM_ROUND_STOCHASTIC, LBM_ROUND_CONSERVE, LBM_ROUND_NEAREST = 0, 1, 2
 NDIAG = 12
 DIAG_NAMES = ["mass", "mom_x", "mom_y", "mom_z", "ke", "ke_region", "max_u", "min_omega", "max_omega",
               "nonfinite", "t", "wss_region"]
@@ -89,13 +89,14 @@ def lib():
         L.lbm_fluid_index.argtypes = [vp, vp]
         L.lbm_time.argtypes = [vp, P(i64)]
         L.lbm_copy_probe.argtypes = [vp, vp, sz, vp]
+        L.lbm_bandwidth_probe.argtypes = [i32, vp, vp, sz, vp]
         L.lbm_last_error.restype = ct.c_char_p
         L.lbm_destroy.argtypes = [vp]
         L.lbm_destroy.restype = None
         for name in ("lbm_workspace_size", "lbm_create", "lbm_step", "lbm_moments", "lbm_diagnostics",
                      "lbm_diagnostics_noalloc",
                      "lbm_get_state", "lbm_set_state", "lbm_set_porosity", "lbm_reset", "lbm_adjoint",
-                     "lbm_fluid_cells", "lbm_fluid_index", "lbm_time", "lbm_copy_probe"):
+                     "lbm_fluid_cells", "lbm_fluid_index", "lbm_time", "lbm_copy_probe", "lbm_bandwidth_probe"):
             getattr(L, name).restype = ct.c_int
         _lib = L
     return _lib
@@ -128,6 +129,15 @@ def lbm_copy_probe(dst_ptr: int, src_ptr: int, nbytes: int, stream_ptr: int = 0)
                                ct.c_void_p(stream_ptr)))
 
 
+PROBE = {"copy": 0, "copy_nt": 1, "read": 2, "write": 3}
+PROBE_BLOCKS = 8192
+
+
+def lbm_bandwidth_probe(kind: str, dst_ptr: int, src_ptr: int, nbytes: int, stream_ptr: int = 0):
+    check(lib().lbm_bandwidth_probe(PROBE[kind], ct.c_void_p(dst_ptr), ct.c_void_p(src_ptr), ct.c_size_t(nbytes),
+                                    ct.c_void_p(stream_ptr)))
+
+
 class Solver:
     """One simulation context on the current HIP device.
 
@@ -138,12 +148,12 @@ class Solver:
     outlet: None, rho_out (constant-density outflow) or "extrapolation" (the non-reflecting outflow).
     adjoint_T/ckpt: reserve workspace for lbm_adjoint runs of up to adjoint_T steps.
     lattice: 19 (D3Q19) or 27 (D3Q27).
-    rounding: "conserve" (default) or "nearest", the rounding of FP16/BF16 storage.
+    rounding: the rounding of FP16/BF16 storage: "stochastic" (default), "conserve" or "nearest".
     """
 
     def __init__(self, solid, phi, *, periodic=(False, False, False), storage="fp32", shift_mode=0, arith="auto",
                  region=None, rheology=None, porous=None, inlet=None, outlet=None, adjoint_T=0, ckpt=64,
-                 lattice=19, rounding="conserve", device=None, stream=None):
+                 lattice=19, rounding="stochastic", device=None, stream=None):
         import torch
 
         self.torch = torch
@@ -293,9 +303,20 @@ class Solver:
         oa = None if omega is None else np.ascontiguousarray(omega, dtype=np.float32)
         check(lib().lbm_set_state(self.ctx, _p(fa), _p(oa)))
 
-    def set_porosity(self, phi: np.ndarray):
-        ph = np.ascontiguousarray(phi, dtype=np.float32)
-        check(lib().lbm_set_porosity(self.ctx, _p(ph)))
+    def set_porosity(self, phi):
+        """Replace the porosity (box layout (nz, ny, nx)) and reset to rest.  A
+        torch tensor on the solver's device is passed as is (FP32, contiguous);
+        anything else is first copied to the device."""
+        t = self.torch
+        if not (isinstance(phi, t.Tensor) and phi.device == self.device and phi.dtype == t.float32
+                and phi.is_contiguous()):
+            phi = t.as_tensor(np.ascontiguousarray(phi, dtype=np.float32) if not isinstance(phi, t.Tensor) else phi,
+                              dtype=t.float32).to(self.device).contiguous()
+        if phi.numel() != self.nbox:
+            raise ValueError(f"porosity has {phi.numel()} values, the box {self.nbox}")
+        # the copy above (if any) runs on torch's current stream: order it before the library's
+        t.cuda.current_stream(self.device).synchronize()
+        check(lib().lbm_set_porosity(self.ctx, ct.c_void_p(phi.data_ptr())))
 
     def objective(self, t_begin: int, t_end: int, T: int, kind: str = "ke") -> float:
         """J alone (forward pass from rest, no gradient); the context ends at rest.

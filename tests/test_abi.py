@@ -27,7 +27,7 @@ def test_header_symbols_exported():
     for n in names:
         assert hasattr(L, n), n
     # and nothing else with the lbm_ prefix is required by the binding
-    assert len(names) == 17
+    assert len(names) == 18
 
 
 def _grid(nx=8, ny=6, nz=5, storage=0, periodic=(0, 0, 0)):
@@ -58,7 +58,10 @@ def test_workspace_size_and_validation():
     g_round = _grid(storage=1)
     g_round.rounding = lbm.LBM_ROUND_NEAREST
     assert lbm.lbm_workspace_size(g_round, solid) == lbm.lbm_workspace_size(g16, solid)
-    g_round.rounding = 2  # neither conserving nor nearest
+    g_round.rounding = 3  # not an lbm_rounding value
+    with pytest.raises(lbm.LBMError):
+        lbm.lbm_workspace_size(g_round, solid)
+    g_round.rounding = -1
     with pytest.raises(lbm.LBMError):
         lbm.lbm_workspace_size(g_round, solid)
     # more compact cells than 32-bit byte offsets into 19 FP32 planes allow

@@ -256,3 +256,84 @@ def test_adjoint_full_size_against_stored_references(objective):
     assert n_fd < 1e-4 and n_dual < 1e-4
     assert e_fd.max() < 1e-3 and e_dual.max() < 1e-3
     assert e_l2 < 1e-5
+
+
+def _perturbed_phi(case, seed):
+    """The case's porosity scaled by a seeded factor in [0.85, 1) on the fluid
+    cells off the open faces (open-face cells keep porosity 1)."""
+    rng = np.random.default_rng(seed)
+    phi = case.phi.astype(np.float32).copy()
+    x = np.arange(case.nx)[None, None, :]
+    inner = (case.solid == 0) & (x > 0) & (x < case.nx - 1)
+    phi[inner] = np.clip(phi[inner] * (0.85 + 0.15 * rng.random(np.count_nonzero(inner))), 0.05, 1.0)
+    return phi.astype(np.float32)
+
+
+def test_device_porosity_matches_host_path():
+    """lbm_set_porosity reads the porosity from device memory in place: the
+    autograd forward and backward with a device tensor give, bit for bit, the
+    J and gradient of a context created from the same porosity in host memory,
+    and the states stepped afterwards agree bit for bit."""
+    import torch
+
+    from paper_2402_10809_amd.autograd import sac_kinetic_energy
+
+    case = _tiny("open", 0)
+    T, tb, te, ck = 30, 15, 30, 7
+    phi2 = _perturbed_phi(case, 3)
+    host = Solver.from_case(case.with_(phi=phi2), adjoint_T=T, ckpt=ck)
+    J_h, g_h = host.adjoint(tb, te, T, ck)
+    dev = Solver.from_case(case, adjoint_T=T, ckpt=ck)
+    phi_t = torch.tensor(phi2, device="cuda", requires_grad=True)
+    J = sac_kinetic_energy(phi_t, dev, tb, te, T, ck)
+    J.backward()
+    say(f"  J device path {float(J):.12e} host path {J_h:.12e}")
+    assert float(J.detach()) == J_h
+    assert torch.equal(phi_t.grad, g_h)
+    host.step(9)
+    dev.step(9)
+    fh, oh = host.get_state()
+    fd, od = dev.get_state()
+    assert np.array_equal(fh, fd) and np.array_equal(oh, od)
+
+
+@pytest.mark.parametrize("lattice", [19, 27])
+def test_device_porosity_rejects_bad_values(lattice):
+    """Invalid porosity (0 on a fluid cell, or not 1 on an open-face cell) is
+    found on the device and rejected with LBM_E_INVALID; the context keeps its
+    state and porosity."""
+    import torch
+
+    from synth import as_d3q27
+
+    case = tiny_case("open", seed=1)
+    if lattice == 27:
+        case = as_d3q27(case)
+    s = Solver.from_case(case)
+    s.step(6)
+    f0, o0 = s.get_state()
+    fluid = np.argwhere(case.solid == 0)
+    z, y, x = [int(v) for v in fluid[len(fluid) // 2]]
+    bad = case.phi.astype(np.float32).copy()
+    bad[z, y, x] = 0.0
+    with pytest.raises(lbm.LBMError) as e:
+        s.set_porosity(torch.tensor(bad, device="cuda"))
+    assert e.value.status == lbm.LBM_E_INVALID
+    assert f"box index {x + case.nx * (y + case.ny * z)}" in str(e.value)
+    face = np.argwhere((case.solid == 0) & (np.arange(case.nx)[None, None, :] == 0))[0]
+    bad2 = case.phi.astype(np.float32).copy()
+    bad2[tuple(face)] = 0.9
+    with pytest.raises(lbm.LBMError):
+        s.set_porosity(torch.tensor(bad2, device="cuda"))
+    f1, o1 = s.get_state()
+    assert s.t == 6 and np.array_equal(f0, f1) and np.array_equal(o0, o1)
+    # a valid update then steps like the oracle with that porosity
+    phi2 = _perturbed_phi(case, 5)
+    s.set_porosity(torch.tensor(phi2, device="cuda"))
+    assert s.t == 0
+    o = oracle.Oracle(case.with_(phi=phi2))
+    f, om = o.init()
+    o.run(f, om, 0, 10)
+    s.step(10)
+    g, _ = s.get_state()
+    assert np.abs(g - f).max() < 2e-6
