@@ -1,0 +1,99 @@
+"""GPU parity in the regimes the small cases do not reach.
+
+* A population buffer above 2 GiB: one even and one odd step from a random
+  non-equilibrium state on all-fluid periodic boxes with a random porosity field,
+  320x320x280 (28.7 M cells; 19 FP32 planes = 2.18 GB) on D3Q19 and 280x280x256
+  (20.1 M cells; 27 planes = 2.17 GB) on D3Q27, cell by cell against the oracle.
+  The population buffer is addressed through 32-bit byte offsets and a buffer
+  resource whose size field holds the buffer's byte count.
+* The coil pair (384x256x256): the fully resolved coil (wire voxels solid, so
+  heavy bounce-back) and its volume-averaged twin (porosity 1 - box filter of
+  the wire, with sharp porosity jumps), 1000 steps against the oracle: FP32 by
+  max-relative error (1e-5 velocity, 1e-4 shear rate), FP16 by relative L2
+  (1e-3)."""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2402_10809_amd import Solver
+from synth import as_d3q27, make_config, periodic_box_case
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("q,dims", [(19, (320, 320, 280)), (27, (280, 280, 256))])
+def test_one_step_beyond_2gib_population_buffer(q, dims):
+    nx, ny, nz = dims
+    case = periodic_box_case(nx=nx, ny=ny, nz=nz, ell=6.0, g=1e-5)
+    if q == 27:
+        case = as_d3q27(case)
+    planes = q * case.n_fluid * 4
+    say(f"beyond 2 GiB: D3Q{q} {nx}x{ny}x{nz}, {case.n_fluid} cells, population buffer {planes / 2**30:.3f} GiB")
+    assert planes > 2 ** 31
+    o = oracle.Oracle(case)
+    f0, om0 = o.init()
+    s = Solver.from_case(case)
+    rng = np.random.default_rng(7)
+    for t0 in (0, 1):
+        f = f0 * (1.0 + 0.1 * rng.standard_normal(f0.shape))
+        om = (om0 * (1.0 + 0.2 * rng.random(o.nf))).astype(np.float32)
+        s.reset()
+        s.step(t0)
+        s.set_state(f, om)
+        s.step(1)
+        g, gom = s.get_state()
+        omd = om.astype(np.float64)
+        o.run(f, omd, t0, 1)
+        err = float(np.abs(g - f).max())
+        say(f"  t0={t0}: max |f_gpu - f_oracle| = {err:.3e}, omega {np.abs(gom - omd).max():.3e}")
+        assert err < 2e-6
+        assert np.abs(gom - omd).max() < 2e-6
+        del g, f
+    s.close()
+
+
+def _max_rel(a, ref):
+    if a.ndim == 2:
+        return float(np.sqrt(((a - ref) ** 2).sum(0)).max() / np.sqrt((ref ** 2).sum(0)).max())
+    return float(np.abs(a - ref).max() / np.abs(ref).max())
+
+
+def _rel_l2(a, ref):
+    return float(np.sqrt(((a - ref) ** 2).sum()) / np.sqrt((ref ** 2).sum()))
+
+
+@pytest.fixture(scope="module")
+def coil_pair():
+    return make_config("c3")
+
+
+@pytest.mark.parametrize("which", ["resolved", "averaged"])
+def test_coil_pair_1000_steps(coil_pair, which):
+    case = coil_pair[0] if which == "resolved" else coil_pair[1]
+    steps = 1000
+    say(f"coil pair, {which}: {case.nx}x{case.ny}x{case.nz}, {case.n_fluid} fluid cells, {steps} steps")
+    o = oracle.Oracle(case)
+    f, om = o.init()
+    o.run(f, om, 0, steps)
+    ref = o.moments(f, om, steps)
+    idx = o.cells()
+    for storage in ("fp32", "fp16"):
+        s = Solver.from_case(case, storage=storage)
+        assert np.array_equal(s.fluid_index(), idx)
+        s.step(steps)
+        m = s.moments()
+        u = m["u"].cpu().numpy().reshape(3, -1)[:, idx].astype(np.float64)
+        sh = m["shear"].cpu().numpy().reshape(-1)[idx].astype(np.float64)
+        mu, ms = _max_rel(u, ref["u"]), _max_rel(sh, ref["shear"])
+        lu, ls = _rel_l2(u, ref["u"]), _rel_l2(sh, ref["shear"])
+        say(f"  {storage}: u max-rel {mu:.3e} rel-L2 {lu:.3e}; shear max-rel {ms:.3e} rel-L2 {ls:.3e}")
+        if storage == "fp32":
+            assert mu < 1e-5 and ms < 1e-4
+        else:
+            assert lu < 1e-3 and ls < 5e-3
+        s.close()
