@@ -18,22 +18,30 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.cpp")
-# one library per velocity set (the source is compiled with ORACLE_Q = 19 / 27)
-_LIBS = {19: os.path.join(_HERE, "liboracle.so"), 27: os.path.join(_HERE, "liboracle27.so")}
+# one library per velocity set (the source is compiled with ORACLE_Q = 19 / 27);
+# ORACLE_LIB_DIR selects another directory of the same two libraries (the
+# sanitizer builds of tests/test_sanitizers.py)
+_DIR = os.environ.get("ORACLE_LIB_DIR", _HERE)
+_LIBS = {19: os.path.join(_DIR, "liboracle.so"), 27: os.path.join(_DIR, "liboracle27.so")}
 _LIB = _LIBS[19]
 Q = 19
+SANITIZE_FLAGS = ["-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"]
 
 
-def build(force: bool = True) -> str:
+def build(force: bool = True, out_dir: str = None, sanitize: bool = False) -> str:
     """Compile the oracle into ``oracle/liboracle.so`` (D3Q19) and
-    ``oracle/liboracle27.so`` (D3Q27) (g++, OpenMP)."""
-    for q, path in _LIBS.items():
+    ``oracle/liboracle27.so`` (D3Q27) (g++, OpenMP); into ``out_dir`` instead
+    if given, and with AddressSanitizer and UndefinedBehaviorSanitizer if
+    ``sanitize``."""
+    libs = _LIBS if out_dir is None else {q: os.path.join(out_dir, os.path.basename(p)) for q, p in _LIBS.items()}
+    for q, path in libs.items():
         if force or not os.path.exists(path):
-            cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", f"-DORACLE_Q={q}", "-o",
-                   path + ".tmp", _SRC]
+            opt = SANITIZE_FLAGS if sanitize else ["-O2"]
+            cmd = ["g++"] + opt + ["-std=c++17", "-fopenmp", "-fPIC", "-shared", f"-DORACLE_Q={q}", "-o",
+                                   path + ".tmp", _SRC]
             subprocess.check_call(cmd)
             os.replace(path + ".tmp", path)
-    return _LIB
+    return libs[19]
 
 
 class _Case(ct.Structure):

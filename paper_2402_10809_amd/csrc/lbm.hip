@@ -51,33 +51,6 @@ double storage_unit(int storage, int q) {
   if (q == 27) return storage == LBM_STORE_FP16 ? 216.0 * 512.0 : 216.0;
   return storage == LBM_STORE_FP16 ? 36.0 * 1024.0 : 36.0;
 }
-Rows find_rows(const lbm_grid& g, const uint8_t* solid) {
-  Rows r;
-  const int nx = g.nx;
-  for (int z = 0; z < g.nz; ++z)
-    for (int y = 0; y < g.ny; ++y) {
-      const uint8_t* line = solid + ((size_t)z * g.ny + y) * nx;
-      int lo = -1, hi = -1;
-      for (int x = 0; x < nx; ++x)
-        if (!line[x]) {
-          if (lo < 0) lo = x;
-          hi = x;
-          r.nf += 1;
-        }
-      if (lo < 0) continue;
-      r.y.push_back(y); r.z.push_back(z); r.x0.push_back(lo); r.x1.push_back(hi + 1);
-      r.cb.push_back(r.nc);
-      r.nc += hi + 1 - lo;
-    }
-  return r;
-}
-
-int xbits_for(int nx) {
-  int b = 1;
-  while ((1 << b) < nx) ++b;
-  return b;
-}
-
 // Symmetric 3x3 matrices as full arrays: inverse by the adjugate.
 using M3 = std::array<std::array<double, 3>, 3>;
 bool inv3(const M3& a, M3& r) {
@@ -256,127 +229,6 @@ lbm_status check_phi(const lbm_ctx* c, const float* phi) {
   return LBM_OK;
 }
 
-// Link word of every compact cell (see step.hpp): dead flag, bounce-back mask
-// of the pulls, uniform-neighbour-porosity flag, open-face role, region,
-// open-face unknowns.  Returns the number of region cells on the wall (a wall
-// link that is not an open-face unknown, and a nonzero weighted link sum).
-int64_t build_links(const lbm_ctx* c, const std::vector<float>& phib, std::vector<uint32_t>& links) {
-  int64_t nwss = 0;
-  const int nx = c->grid.nx, ny = c->grid.ny, nz = c->grid.nz;
-  const int per[3] = {c->grid.periodic[0] != 0, c->grid.periodic[1] != 0, c->grid.periodic[2] != 0};
-  const int dims[3] = {nx, ny, nz};
-  links.assign(c->nc, LK_DEAD);
-  for (int64_t k = 0; k < c->nf; ++k) {
-    const int64_t b = c->fluid_box[k];
-    const int X[3] = {(int)(b % nx), (int)((b / nx) % ny), (int)(b / ((int64_t)nx * ny))};
-    uint32_t lk = 0;
-    bool uni = true;
-    const float ph = phib[b];
-    uint32_t unk = 0;
-    int m[3] = {0, 0, 0};  // sum over wall links x + c_j of 36 w_j c_j
-    for (int i = 1; i < Q; ++i) {
-      const int cv[3] = {CX[i], CY[i], CZ[i]};
-      for (int sgn = -1; sgn <= 1; sgn += 2) {  // -1: pull source x - c_i; +1: neighbour x + c_i
-        int s[3];
-        bool out = false, out_yz = false;
-        for (int a = 0; a < 3; ++a) {
-          s[a] = X[a] + sgn * cv[a];
-          if (s[a] < 0 || s[a] >= dims[a]) {
-            if (per[a]) s[a] = (s[a] + dims[a]) % dims[a];
-            else { out = true; if (a > 0) out_yz = true; }
-          }
-        }
-        const int64_t sb = out ? -1 : (int64_t)s[0] + (int64_t)nx * ((int64_t)s[1] + (int64_t)ny * s[2]);
-        const bool wall = out || c->solid[sb];
-        if (sgn < 0) {
-          if (wall) lk |= 1u << i;
-          // open-face unknown: the source lies beyond the inflow/outflow face only
-          const bool open = out && !out_yz && c->openface[k];
-          if (open) {
-            const int* xs = c->openface[k] == 1 ? XIN : XOUT;
-            for (int j = 0; j < 5; ++j)
-              if (xs[j] == i) unk |= 1u << j;
-          }
-          if (wall && !open)
-            for (int a = 0; a < 3; ++a) m[a] -= (int)kw(i) * cv[a];
-        } else if (!wall && phib[sb] != ph) {
-          uni = false;
-        }
-      }
-    }
-    if (uni) lk |= LK_UNI;
-    // interior: every pull source is fluid and none wraps around x
-    if ((lk & 0x7fffeu) == 0 && !(per[0] && (X[0] == 0 || X[0] == nx - 1))) lk |= LK_INR;
-    if (c->openface[k] == 1) lk |= LK_IN;
-    if (c->openface[k] == 2) lk |= LK_OUT;
-    // -x neighbour of an extrapolation-outflow cell
-    if (c->P.outlet == 2 && X[0] == nx - 2 && !c->solid[b + 1]) lk |= LK_UPS;
-    if (c->region_f[k]) lk |= LK_REG;
-    lk |= unk << LK_UNK;
-    links[c->fluid_c[k]] = lk;
-    if (c->region_f[k] && (m[0] | m[1] | m[2]) != 0) ++nwss;
-  }
-  return nwss;
-}
-
-// The 64-bit link words of the D3Q27 kernels (layout in step27.hpp); returns
-// the number of region cells on the wall.
-int64_t build_links27(const lbm_ctx* c, const std::vector<float>& phib, std::vector<uint64_t>& links) {
-  namespace L = q27;
-  const int nx = c->grid.nx, ny = c->grid.ny, nz = c->grid.nz;
-  const int per[3] = {c->grid.periodic[0] != 0, c->grid.periodic[1] != 0, c->grid.periodic[2] != 0};
-  const int dims[3] = {nx, ny, nz};
-  int64_t nwss = 0;
-  links.assign(c->nc, L::L_DEAD);
-  for (int64_t k = 0; k < c->nf; ++k) {
-    const int64_t b = c->fluid_box[k];
-    const int X[3] = {(int)(b % nx), (int)((b / nx) % ny), (int)(b / ((int64_t)nx * ny))};
-    uint64_t lk = 0;
-    bool uni = true;
-    const float ph = phib[b];
-    uint64_t unk = 0;
-    int m[3] = {0, 0, 0};
-    for (int i = 1; i < L::Q; ++i) {
-      const int cv[3] = {L::CX[i], L::CY[i], L::CZ[i]};
-      for (int sgn = -1; sgn <= 1; sgn += 2) {  // -1: pull source x - c_i; +1: neighbour x + c_i
-        int sidx[3];
-        bool out = false, out_yz = false;
-        for (int a = 0; a < 3; ++a) {
-          sidx[a] = X[a] + sgn * cv[a];
-          if (sidx[a] < 0 || sidx[a] >= dims[a]) {
-            if (per[a]) sidx[a] = (sidx[a] + dims[a]) % dims[a];
-            else { out = true; if (a > 0) out_yz = true; }
-          }
-        }
-        const int64_t sb = out ? -1 : (int64_t)sidx[0] + (int64_t)nx * ((int64_t)sidx[1] + (int64_t)ny * sidx[2]);
-        const bool wall = out || c->solid[sb];
-        if (sgn < 0) {
-          if (wall) lk |= 1ull << i;
-          const bool open = out && !out_yz && c->openface[k];
-          if (open) {
-            const int* xs = c->openface[k] == 1 ? L::XIN : L::XOUT;
-            for (int j = 0; j < L::NX; ++j)
-              if (xs[j] == i) unk |= 1ull << j;
-          }
-          if (wall && !open)
-            for (int a = 0; a < 3; ++a) m[a] -= L::kw(i) * cv[a];
-        } else if (!wall && phib[sb] != ph) {
-          uni = false;
-        }
-      }
-    }
-    if (uni) lk |= L::L_UNI;
-    if (c->openface[k] == 1) lk |= L::L_IN;
-    if (c->openface[k] == 2) lk |= L::L_OUT;
-    if (c->P.outlet == 2 && X[0] == nx - 2 && !c->solid[b + 1]) lk |= L::L_UPS;
-    if (c->region_f[k]) lk |= L::L_REG;
-    lk |= unk << L::L_UNK;
-    links[c->fluid_c[k]] = lk;
-    if (c->region_f[k] && (m[0] | m[1] | m[2]) != 0) ++nwss;
-  }
-  return nwss;
-}
-
 // Upload the porosity and the link words (which depend on it).
 lbm_status upload_phi(lbm_ctx* c, const float* phi) {
   std::vector<float> box(c->nbox, 0.0f), comp(c->nc, 0.0f);
@@ -389,8 +241,8 @@ lbm_status upload_phi(lbm_ctx* c, const float* phi) {
   }
   std::vector<uint32_t> links;
   std::vector<uint64_t> links64;
-  if (c->q == 27) c->nwss = build_links27(c, box, links64);
-  else c->nwss = build_links(c, box, links);
+  if (c->q == 27) c->nwss = build_links27(*c, box, links64);
+  else c->nwss = build_links(*c, box, links);
   HIP_TRY(c, hipMemcpyAsync(c->ws + c->L.phi, comp.data(), comp.size() * 4, hipMemcpyHostToDevice, c->stream));
   if (c->q == 27)
     HIP_TRY(c, hipMemcpyAsync(c->ws + c->L.links, links64.data(), links64.size() * 8, hipMemcpyHostToDevice,
@@ -639,54 +491,14 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* solid, const float* p
   c->op.shape_yz = nullptr;
   c->op.wave_table = nullptr;
   c->nbox = (size_t)grid->nx * grid->ny * grid->nz;
-  c->solid.assign(solid, solid + c->nbox);
   c->stream = (hipStream_t)stream;
   c->q = qof(*grid);
   c->U = storage_unit(grid->storage, c->q);
-  c->nf = rows.nf;
-  c->nc = rows.nc;
-  c->nrow = nrow;
-  const int nx = grid->nx, xb = xbits_for(nx);
-  std::vector<uint32_t> code(c->nc, 0u), rowbox(nrow);
-  std::vector<int> delta((size_t)nrow * 8, 0);
+  build_host_layout(*c, *grid, solid, region, op && op->inlet, op ? op->outlet : 0);
+  const int nx = grid->nx, xb = c->xbits;
   std::vector<float> shape(nrow, 0.0f);
-  std::vector<int64_t> rowid((size_t)grid->ny * grid->nz, -1);
-  c->fluid_box.reserve(c->nf);
-  c->fluid_c.reserve(c->nf);
-  for (int64_t r = 0; r < nrow; ++r) {
-    const int y = rows.y[r], z = rows.z[r];
-    rowid[(size_t)z * grid->ny + y] = r;
-    const size_t base = ((size_t)z * grid->ny + y) * nx;
-    rowbox[r] = (uint32_t)base;
-    if (op && op->inlet) shape[r] = op->shape_yz[(size_t)z * grid->ny + y];
-    for (int x = rows.x0[r]; x < rows.x1[r]; ++x) {
-      const int64_t ci = rows.cb[r] + x - rows.x0[r];
-      code[ci] = ((uint32_t)r << xb) | (uint32_t)x;
-      const size_t b = base + x;
-      if (solid[b]) continue;
-      c->fluid_box.push_back((int64_t)b);
-      c->fluid_c.push_back(ci);
-      c->region_f.push_back(region && region[b] ? 1 : 0);
-      uint8_t of = 0;
-      if (op && op->inlet && x == 0) of = 1;
-      else if (op && op->outlet && x == nx - 1) of = 2;
-      c->openface.push_back(of);
-      c->nreg += (region && region[b]) ? 1 : 0;
-    }
-  }
-  // neighbour-row deltas: the row (y - cy, z - cz) of pair k, wrapped on periodic axes
-  for (int64_t r = 0; r < nrow; ++r) {
-    for (int k = 1; k < NPAIR; ++k) {
-      int sy = rows.y[r] - PCY[k], sz = rows.z[r] - PCZ[k];
-      if (grid->periodic[1]) sy = (sy + grid->ny) % grid->ny;
-      if (grid->periodic[2]) sz = (sz + grid->nz) % grid->nz;
-      if (sy < 0 || sy >= grid->ny || sz < 0 || sz >= grid->nz) continue;
-      const int64_t rr = rowid[(size_t)sz * grid->ny + sy];
-      if (rr < 0) continue;
-      delta[(size_t)r * 8 + (k - 1)] = (int)(rows.cb[rr] - rows.x0[rr]);
-    }
-  }
-  c->rows = std::move(rows);
+  if (op && op->inlet)
+    for (int64_t r = 0; r < nrow; ++r) shape[r] = op->shape_yz[(size_t)c->rows.z[r] * grid->ny + c->rows.y[r]];
   s = check_phi(c, phi);
   if (s != LBM_OK) { delete c; return s; }
   {
@@ -756,10 +568,10 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* solid, const float* p
   } while (0)
   // slots that no consumer reads are never written by the kernels; clear them once
   HIP_TRY0(hipMemsetAsync(c->ws + c->L.A, 0, c->L.code - c->L.A, c->stream));
-  HIP_TRY0(hipMemcpyAsync(c->ws + c->L.code, code.data(), code.size() * 4, hipMemcpyHostToDevice, c->stream));
-  HIP_TRY0(hipMemcpyAsync(c->ws + c->L.delta, delta.data(), delta.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY0(hipMemcpyAsync(c->ws + c->L.code, c->code.data(), c->code.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY0(hipMemcpyAsync(c->ws + c->L.delta, c->delta.data(), c->delta.size() * 4, hipMemcpyHostToDevice, c->stream));
   HIP_TRY0(hipMemcpyAsync(c->ws + c->L.shape, shape.data(), shape.size() * 4, hipMemcpyHostToDevice, c->stream));
-  HIP_TRY0(hipMemcpyAsync(c->ws + c->L.rowbox, rowbox.data(), rowbox.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY0(hipMemcpyAsync(c->ws + c->L.rowbox, c->rowbox.data(), c->rowbox.size() * 4, hipMemcpyHostToDevice, c->stream));
   if (P.in_table > 0)
     HIP_TRY0(hipMemcpyAsync(c->ws + c->L.wave, op->wave_table, (size_t)P.in_table * sizeof(double),
                             hipMemcpyHostToDevice, c->stream));

@@ -12,6 +12,7 @@
 #include <type_traits>
 #include <vector>
 
+#include "layout.hpp"
 #include "step.hpp"
 #include "step27.hpp"
 
@@ -42,41 +43,24 @@ struct Layout {
   size_t total;
 };
 
-// Rows of the compact layout: every (y, z) line holding fluid, ordered by z
-// then y, with the x range from its first to its last fluid cell.
-struct Rows {
-  std::vector<int> y, z, x0, x1;
-  std::vector<int64_t> cb;  // compact start of each row
-  int64_t nc = 0;           // compact cells (fluid + dead)
-  int64_t nf = 0;           // fluid cells
-};
-
 }  // namespace lbmrt
 
-struct lbm_ctx {
+// A context: its host layout (box, rows, per-cell tables, fluid-cell lists)
+// plus the run's parameters, workspace and state.
+struct lbm_ctx : lbmrt::HostLayout {
   lbm_grid grid{};
   lbm_rheology rh{};
   lbm_porous po{};
   lbm_open op{};
   size_t nbox = 0;
-  int64_t nf = 0;                 // fluid cells
-  int64_t nc = 0;                 // compact cells (fluid + dead)
-  int64_t nrow = 0;
   int nblk = 0;                   // blocks of BLOCK work-items over the compact cells
   int sblk = 0;                   // blocks of the step kernel
-  int64_t nreg = 0;
   int64_t nwss = 0;               // region cells on the wall (with a wall normal)
   int q = 19;                     // velocity set
   double U = 36.0;
   int device = 0;                 // HIP device of the workspace (current at lbm_create)
-  lbmrt::Rows rows;
-  std::vector<int64_t> fluid_box; // box index per fluid cell (ascending)
-  std::vector<int64_t> fluid_c;   // compact index per fluid cell
   std::vector<double> phi_f;      // porosity per fluid cell (host, for state transfer)
   bool phi_stale = false;         // phi_f predates a device-side porosity update
-  std::vector<uint8_t> solid;     // host copy of the mask
-  std::vector<uint8_t> region_f;  // per fluid cell
-  std::vector<uint8_t> openface;  // per fluid cell: 1 inlet, 2 outlet
   hipStream_t stream = nullptr;
   char* ws = nullptr;
   size_t ws_bytes = 0;
