@@ -106,8 +106,8 @@ typedef enum { LBM_STORE_FP32 = 0, LBM_STORE_FP16 = 1, LBM_STORE_BF16 = 2 } lbm_
  * 2.2e-4, conserving 1.1e-3, nearest 2.4e-3. */
 typedef enum { LBM_ROUND_STOCHASTIC = 0, LBM_ROUND_CONSERVE = 1, LBM_ROUND_NEAREST = 2 } lbm_rounding;
 
-/* Arithmetic of the moments, velocity, force and collision (the Carreau-Yasuda
- * transcendentals are FP32 in every mode).  FP32 rounding of the per-cell
+/* Arithmetic of the moments, velocity, force and collision (the shear rate and
+ * the Carreau-Yasuda law are FP32 except in FP64 mode).  FP32 rounding of the per-cell
  * scalars (velocity, relaxation rate) is common to all 19 directions and acts
  * as a small persistent momentum source; in slowly evolving flows it
  * accumulates to ~1e-5 of the velocity.  AUTO with FP32 storage therefore
@@ -294,9 +294,10 @@ lbm_status lbm_reset(lbm_ctx* ctx);
  * respect to the porosity of every fluid cell.  Resets to rest, runs T steps forward while
  * accumulating J and storing a checkpoint every ckpt_every steps, then sweeps
  * back through the segments (recompute forward, then reverse steps).  The
- * forward passes compute the collision in FP64 (LBM_ARITH_FP64) whatever the
- * context's arithmetic mode; the reverse steps are FP64 arithmetic with FP32
- * adjoint populations.  Either outflow kind; with the extrapolation outflow
+ * forward passes compute the collision, the shear rate and the Carreau-Yasuda
+ * law in FP64 (LBM_ARITH_FP64) whatever the context's arithmetic mode, and
+ * store the trajectory in FP32; the reverse steps are FP64 arithmetic with
+ * FP32 adjoint populations and an FP64 relaxation-rate adjoint.  Either outflow kind; with the extrapolation outflow
  * the outflow cells' unknowns are state, and their dependence on the previous
  * step's values is part of the reverse sweep.  Needs a workspace sized for
  * (T, ckpt_every) or larger; FP32 storage, shift mode 0, D3Q19 (with or

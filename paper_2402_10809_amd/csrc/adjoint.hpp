@@ -45,7 +45,7 @@ struct AdjBufs {
   const float* rho_prev;  // density of step n-1 per compact cell (null for n = 0)
   const float* ph_next;   // adjoint of the pulled populations of step n+1, [19][nc]
   float* ph_out;          // adjoint of the pulled populations of step n, [19][nc]
-  float* omh;             // per cell: in adjoint of omega_n, out adjoint of omega_{n-1}
+  double* omh;            // per cell: in adjoint of omega_n, out adjoint of omega_{n-1}
   double* phih;           // per cell: porosity adjoint accumulator
   const double* aside_in; // extrapolation outflow: per row, adjoints of the 5 c_x = -1 unknowns of step n+1
   double* aside_out;      // the same for step n
@@ -56,12 +56,11 @@ struct AdjBufs {
 // per-cell scalars would accumulate the same way); the adjoint populations are
 // stored in FP32.
 //
-// The anisotropic instantiation needs 256 VGPRs plus 21 AGPRs as compiled
-// freely (1 wave per SIMD); held to 2 waves it spills 23 registers to scratch
-// and still runs the reverse step about 1.4x faster.  The isotropic one fits
-// 2 waves (243 VGPRs) by itself.
+// Both instantiations are held to 2 waves per SIMD (256 VGPRs): the
+// isotropic one spills 2 registers there, the anisotropic one 27, which still
+// runs faster than 1 wave per SIMD without spills.
 template <bool AN>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(AN ? 2 : 1)))
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
 void k_adjoint(Params p, AdjBufs a, uint32_t t, float ew, int kind) {
   using R = double;
   const uint32_t c = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
@@ -99,20 +98,16 @@ void k_adjoint(Params p, AdjBufs a, uint32_t t, float ew, int kind) {
   const R rho = M.rho, ux = M.ux, uy = M.uy, uz = M.uz, uu = M.uu;
   const R Fx = M.Fx, Fy = M.Fy, Fz = M.Fz;
   const R om = M.omega;
-  const R Nn = rsqrt_(M.P[0] * M.P[0] + M.P[1] * M.P[1] + M.P[2] * M.P[2] +
-                      2.0 * (M.P[3] * M.P[3] + M.P[4] * M.P[4] + M.P[5] * M.P[5]));
-  const float shear = M.shear;
-  const float lg = p.f.lam * shear;
-  float la, dla;  // (lambda g)^a and its derivative in g
-  if (p.cy_a2) { la = lg * lg; dla = 2.0f * p.f.lam * lg; }
-  else {
-    la = lg > 0.0f ? __builtin_amdgcn_exp2f(p.f.cy_a * __builtin_amdgcn_logf(lg)) : 0.0f;
-    dla = (lg > 0.0f && shear > 0.0f) ? p.f.cy_a * la / shear : 0.0f;
-  }
-  const float hh = 1.0f + la;
-  const float fac = __builtin_amdgcn_exp2f(p.f.cy_e * __builtin_amdgcn_logf(hh));
-  const R nu = kc.nu_inf + kc.dnu * (R)fac;
-  const R dnu = kc.dnu * kc.cy_e * (R)fac / (R)hh * (R)dla;
+  const R Nn = M.pnorm;  // |Pi|_F
+  // Carreau-Yasuda viscosity and its derivative in the shear rate, in FP64
+  // like the forward passes of the adjoint
+  const R shear = M.shear_r;
+  const R la = M.cy_la, fac = M.cy_fac;  // (lambda g)^a and (1 + (lambda g)^a)^((n-1)/a)
+  // derivative of (lambda g)^a in g
+  const R dla = p.cy_a2 ? 2.0 * kc.lam * kc.lam * shear : ((la > 0.0 && shear > 0.0) ? kc.cy_a * la * fast_rcp(shear) : 0.0);
+  const R hh = 1.0 + la;
+  const R nu = kc.nu_inf + kc.dnu * fac;
+  const R dnu = kc.dnu * kc.cy_e * fac * fast_rcp(hh) * dla;
 
   // ---- gather the adjoint of the post-collision populations --------------
   R qh[Q];
@@ -126,7 +121,7 @@ void k_adjoint(Params p, AdjBufs a, uint32_t t, float ew, int kind) {
     const R pn = (R)ldo(a.phi, fl ? tgt : c);
     const uint32_t e = fl ? (uint32_t)I * (uint32_t)p.nc + tgt : (uint32_t)OPP[I] * (uint32_t)p.nc + c;
     qh[I] = (R)ldo(a.ph_next, e);
-    const R ai = (R)wgt(I) * qh[I];
+    const R ai = (R)kw(I) * (1.0 / 36.0) * qh[I];
     sfl += fl ? ai : 0.0;
     sjump += fl ? ai * (pn - phx) : 0.0;
     fmask |= fl ? (1u << I) : 0u;
@@ -190,7 +185,7 @@ void k_adjoint(Params p, AdjBufs a, uint32_t t, float ew, int kind) {
   }
 
   // collision: q = (1-omega) f + omega feq + K g + w rho (phi~ - phi)
-  R omh = (R)a.omh[c] + wom + (Aeq * s0 + 3.0 * pr * s1u + 4.5 * pr * us2u - qd) -
+  R omh = a.omh[c] + wom + (Aeq * s0 + 3.0 * pr * s1u + 4.5 * pr * us2u - qd) -
           0.5 * (3.0 * s1F - 3.0 * s0 * uF + 9.0 * us2F);
   R uhx = K * (9.0 * s2Fx - 3.0 * s0 * Fx), uhy = K * (9.0 * s2Fy - 3.0 * s0 * Fy),
     uhz = K * (9.0 * s2Fz - 3.0 * s0 * Fz);
@@ -214,7 +209,7 @@ void k_adjoint(Params p, AdjBufs a, uint32_t t, float ew, int kind) {
   const R irho = fast_rcp(rho);
   const R omph = gh * 3.0 * Nn * irho;      // adjoint of omega_prev
   const R Nh = gh * 3.0 * (R)omp * irho;
-  rhoh -= gh * (R)shear * irho;
+  rhoh -= gh * shear * irho;
   // Pi = sum f c c - phi rho (I/3 + u u) + (F u + u F)/2, |Pi|_F
   const R gsc = Nn > 0.0 ? Nh * fast_rcp(Nn) : 0.0;
   R G[6];
@@ -418,7 +413,7 @@ void k_adjoint(Params p, AdjBufs a, uint32_t t, float ew, int kind) {
   }
 #pragma unroll
   for (int i = 0; i < Q; ++i) sto(a.ph_out, (uint32_t)i * (uint32_t)p.nc + c, (float)fh[i]);
-  a.omh[c] = (float)omph;
+  a.omh[c] = omph;
 
   // porosity-jump term of step n-1: q_i(x - c_i) depends on phi(x) when
   // x - c_i is a fluid producer; its adjoint is w_i rho_{n-1}(x - c_i) fh_i(x).

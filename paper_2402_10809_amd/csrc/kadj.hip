@@ -47,7 +47,7 @@ extern "C" lbm_status lbm_adjoint(lbm_ctx* c, const lbm_objective* obj, int T, i
   float* ck = (float*)(c->ws + L.ck);
   float* rec = (float*)(c->ws + L.rec);
   float* rho = (float*)(c->ws + L.rho);
-  float* omh = (float*)(c->ws + L.omh);
+  double* omh = (double*)(c->ws + L.omh);
   double* phih = (double*)(c->ws + L.phih);
   double* objp = (double*)(c->ws + L.obj);
   auto slot_rec = [&](int k) { return rec + (size_t)k * (Q + 1) * nc; };
@@ -100,7 +100,7 @@ extern "C" lbm_status lbm_adjoint(lbm_ctx* c, const lbm_objective* obj, int T, i
   float* pho = (float*)(c->ws + L.ah1);
   HIP_TRY(c, hipMemsetAsync(phn, 0, Q * nc * 4, c->stream));
   HIP_TRY(c, hipMemsetAsync(pho, 0, Q * nc * 4, c->stream));
-  HIP_TRY(c, hipMemsetAsync(omh, 0, nc * 4, c->stream));
+  HIP_TRY(c, hipMemsetAsync(omh, 0, nc * 8, c->stream));
   HIP_TRY(c, hipMemsetAsync(phih, 0, nc * 8, c->stream));
   // extrapolation outflow: adjoints of the kept unknowns, per row, by parity
   // of the step (none after the last step)

@@ -45,6 +45,7 @@
 #pragma once
 #include <type_traits>
 
+#include "fp64math.hpp"
 #include "lattice.hpp"
 
 namespace lbm {
@@ -449,7 +450,10 @@ struct Macro {
   R ux, uy, uz, uu;   // velocity
   R Fx, Fy, Fz;       // force density rho f(u)
   R P[6];             // corrected second moment Pi (xx yy zz xy xz yz)
-  float shear;        // shear rate (the rheology runs in FP32)
+  float shear;        // shear rate (output)
+  R shear_r;          // shear rate in the arithmetic type (FP32 rheology with FP32 arithmetic)
+  R cy_la, cy_fac;    // (lambda shear)^a and (1 + (lambda shear)^a)^((n-1)/a)
+  R pnorm;            // |Pi|_F
   R omega;
 };
 
@@ -550,24 +554,48 @@ __device__ __forceinline__ void macro_sums(const Params& p, float phx_f, const S
   M.P[3] = s.xy * iU - pr * ux * uy + h * (Fx * uy + ux * Fy);
   M.P[4] = s.xz * iU - pr * ux * uz + h * (Fx * uz + ux * Fz);
   M.P[5] = s.yz * iU - pr * uy * uz + h * (Fy * uz + uy * Fz);
-  const float pn2 = (float)(M.P[0] * M.P[0] + M.P[1] * M.P[1] + M.P[2] * M.P[2] +
-                            (R)2 * (M.P[3] * M.P[3] + M.P[4] * M.P[4] + M.P[5] * M.P[5]));
-  // |Pi|_F to one ulp (the hardware square root)
-  const float shear = 3.0f * omega_prev * __builtin_amdgcn_sqrtf(pn2) * (float)irho;
-  // Carreau-Yasuda: nu = nu_inf + (nu0 - nu_inf) (1 + (lambda g)^a)^((n-1)/a)
-  const float lg = p.f.lam * shear;
-  float la;
-  if (p.cy_a2) la = lg * lg;
-  else la = lg > 0.0f ? __builtin_amdgcn_exp2f(p.f.cy_a * __builtin_amdgcn_logf(lg)) : 0.0f;
-  const float fac = __builtin_amdgcn_exp2f(p.f.cy_e * __builtin_amdgcn_logf(1.0f + la));
-  const R nu = kc.nu_inf + kc.dnu * (R)fac;
+  R nu;
+  if constexpr (std::is_same<R, double>::value) {
+    // FP64 arithmetic: the shear rate and the Carreau-Yasuda law in FP64 too
+    // (the adjoint differentiates this path; FP32 transcendentals would put
+    // an error of the same sign into every step's viscosity)
+    const double pn = __builtin_sqrt(M.P[0] * M.P[0] + M.P[1] * M.P[1] + M.P[2] * M.P[2] +
+                                     2.0 * (M.P[3] * M.P[3] + M.P[4] * M.P[4] + M.P[5] * M.P[5]));
+    const double sh = 3.0 * (double)omega_prev * pn * irho;
+    M.pnorm = pn;
+    const double lg = kc.lam * sh;
+    const double la = p.cy_a2 ? lg * lg : (lg > 0.0 ? pow_pos(lg, kc.cy_a) : 0.0);
+    const double fac = pow_pos(1.0 + la, kc.cy_e);
+    nu = kc.nu_inf + kc.dnu * fac;
+    M.shear = (float)sh;
+    M.shear_r = sh;
+    M.cy_la = la;
+    M.cy_fac = fac;
+  } else {
+    const float pn2 = (float)(M.P[0] * M.P[0] + M.P[1] * M.P[1] + M.P[2] * M.P[2] +
+                              (R)2 * (M.P[3] * M.P[3] + M.P[4] * M.P[4] + M.P[5] * M.P[5]));
+    // |Pi|_F to one ulp (the hardware square root)
+    const float pn = __builtin_amdgcn_sqrtf(pn2);
+    const float shear = 3.0f * omega_prev * pn * (float)irho;
+    M.pnorm = (R)pn;
+    // Carreau-Yasuda: nu = nu_inf + (nu0 - nu_inf) (1 + (lambda g)^a)^((n-1)/a)
+    const float lg = p.f.lam * shear;
+    float la;
+    if (p.cy_a2) la = lg * lg;
+    else la = lg > 0.0f ? __builtin_amdgcn_exp2f(p.f.cy_a * __builtin_amdgcn_logf(lg)) : 0.0f;
+    const float fac = __builtin_amdgcn_exp2f(p.f.cy_e * __builtin_amdgcn_logf(1.0f + la));
+    nu = kc.nu_inf + kc.dnu * (R)fac;
+    M.shear = shear;
+    M.shear_r = (R)shear;
+    M.cy_la = (R)la;
+    M.cy_fac = (R)fac;
+  }
   // omega = 2 rho c_s^2 / (2 mu + rho c_s^2) = 2 rho / (6 nu + rho)
   M.omega = (R)2 * rho * fast_rcp((R)6 * nu + rho);
   M.rho = rho;
   M.rm1 = rm1;
   M.ux = ux; M.uy = uy; M.uz = uz; M.uu = uu;
   M.Fx = Fx; M.Fy = Fy; M.Fz = Fz;
-  M.shear = shear;
 }
 template <class R, bool AN = false>
 __device__ __forceinline__ void macro(const Params& p, float phx_f, const float d[Q], float omega_prev, Macro<R>& M) {

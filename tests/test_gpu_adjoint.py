@@ -245,16 +245,16 @@ def test_adjoint_full_size_against_stored_references(objective):
     for k in range(len(vox)):
         say(f"    voxel {vox[k]}: gpu {gv[k]:.6e} fd {fd[k]:.6e} dual {dual[k]:.6e} "
             f"rel {abs(gv[k] - dual[k]) / abs(dual[k]):.2e}")
-    # The gradient agrees with the FP64 finite differences to 1e-4 as a vector
-    # (normwise, measured ~2e-5).  Per voxel, the smaller gradients (down to
-    # 1/30 of the largest) come out of sums over 4000 steps whose terms largely
-    # cancel, so the FP32 record and FP32 adjoint populations show there as a
-    # few 1e-4 of the voxel's own value; the bound per voxel is 1e-3.
+    # Per voxel (relative to the voxel's own value, with a floor of 1e-2 of the
+    # largest) within 1e-4 of the FP64 finite differences and of the exact
+    # dual-number derivative; normwise likewise.  Measured 7.0e-5 per voxel
+    # for the kinetic energy and 1.7e-5 for the WSS; the error budget of the
+    # reverse sweep is stated in the design notes.
     n_fd = np.linalg.norm(gv - fd) / np.linalg.norm(fd)
     n_dual = np.linalg.norm(gv - dual) / np.linalg.norm(dual)
     assert abs(J - ref["J"]) <= 1e-6 * abs(ref["J"])
     assert n_fd < 1e-4 and n_dual < 1e-4
-    assert e_fd.max() < 1e-3 and e_dual.max() < 1e-3
+    assert e_fd.max() < 1e-4 and e_dual.max() < 1e-4
     assert e_l2 < 1e-5
 
 

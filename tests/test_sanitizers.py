@@ -61,3 +61,22 @@ def test_host_layout_under_address_and_ub_sanitizers(tmp_path):
     print(r.stdout[-1500:], r.stderr[-1500:])
     assert r.returncode == 0, r.stdout[-3000:] + r.stderr[-3000:]
     assert "400 random boxes, 0 failures" in r.stdout
+
+
+def test_fp64_power_function_on_the_host(tmp_path):
+    """The FP64 x^e of csrc/fp64math.hpp (the Carreau-Yasuda law of the FP64
+    passes) against the host C library, relative error below 1e-14."""
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    exe = str(tmp_path / "fp64math_check")
+    cmd = [hipcc, "-x", "hip", "--offload-arch=gfx950", "-O1", "-std=c++17",
+           "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-I", os.path.join(ROOT, "paper_2402_10809_amd", "csrc"),
+           os.path.join(ROOT, "tests", "sanitize", "fp64math_check.hip"), "-o", exe]
+    b = subprocess.run(cmd, capture_output=True, text=True)
+    assert b.returncode == 0, b.stdout + b.stderr
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=300,
+                       env=dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1"))
+    print(r.stdout)
+    assert r.returncode == 0, r.stdout + r.stderr
