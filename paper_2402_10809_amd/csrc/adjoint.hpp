@@ -234,9 +234,9 @@ void k_adjoint(Params p, AdjBufs a, uint32_t t, float ew, int kind) {
   // sqrt(150 phi^3)), K2 = 1.75 sqrt(K_c / (150 d^2)); d|u|/du := 0 at u = 0.
   // Anisotropic (AN): F = rho (g - D M^-1 u - E |u| M^-1/2 u).
   const bool forch = p.forch != 0;
-  const R K2 = 1.75 * rsqrt_(kc.kcd * (1.0 / 150.0));
+  const R K2 = kc.fk2;
   const R E = forch ? K2 * om1 : 0.0;
-  const R un = rsqrt_(uu);
+  const R un = forch ? rsqrt_(uu) : 0.0;
   const R dD = -kn * (1.0 - phx * phx) * iphi * iphi;      // dD/dphi
   const R ddark = -2.0 * kn * om1 * iphi * iphi * iphi;    // d(phi nu / k)/dphi
   rhoh += (Fhx * Fx + Fhy * Fy + Fhz * Fz) * irho;

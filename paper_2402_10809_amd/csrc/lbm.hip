@@ -537,10 +537,11 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* solid, const float* p
     k.nu_d = po->nu_darcy; k.kcd = po->kc / (po->d * po->d);
     k.gx = po->g[0]; k.gy = po->g[1]; k.gz = po->g[2];
     k.rho_out = (op && op->outlet == 1) ? op->rho_out : 1.0;
+    k.fk2 = 1.75 * std::sqrt(k.kcd / 150.0);
     P.d = k;
     P.f = Params::K<float>{(float)k.U, (float)k.iU, (float)k.ks, (float)k.nu0, (float)k.nu_inf, (float)k.dnu,
                            (float)k.lam, (float)k.cy_e, (float)k.cy_a, (float)k.nu_d, (float)k.kcd,
-                           (float)k.gx, (float)k.gy, (float)k.gz, (float)k.rho_out};
+                           (float)k.gx, (float)k.gy, (float)k.gz, (float)k.rho_out, (float)k.fk2};
   }
   P.in_a0 = (op && op->inlet) ? op->a0 : 0.0;
   P.in_a1 = (op && op->inlet) ? op->a1 : 0.0;

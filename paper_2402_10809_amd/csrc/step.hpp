@@ -89,6 +89,7 @@ struct Params {
     T nu_d, kcd;                 // Darcy viscosity, kc/d^2
     T gx, gy, gz;                // body force
     T rho_out;
+    T fk2;                       // 1.75 sqrt(kc / (150 d^2)): phi^3 C_F sqrt(1/k) = fk2 (1 - phi)
     T Mi[6], Mh[6];              // anisotropic permeability shape: M^-1, M^-1/2 (xx yy zz xy xz yz)
   };
   K<float> f;
