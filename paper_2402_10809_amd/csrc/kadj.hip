@@ -13,6 +13,10 @@ using namespace lbmrt;
 // before the segment, which the porosity-jump gather of the segment's first
 // reverse step needs.  Checkpoints hold the gathered (layout-independent)
 // state; the slot layout of a restored state follows the parity of its time.
+// The forward pass records the last segment itself (that segment needs no
+// checkpoint and no recompute); with one segment (ckpt_every >= T) nothing is
+// recomputed.  The recompute reproduces the forward trajectory bit for bit,
+// so the records are the same either way.
 extern "C" lbm_status lbm_adjoint(lbm_ctx* c, const lbm_objective* obj, int T, int ckpt, double* J,
                                   float* dJ_dphi) {
   CTX_CHECK(c);
@@ -74,13 +78,23 @@ extern "C" lbm_status lbm_adjoint(lbm_ctx* c, const lbm_objective* obj, int T, i
   lbm_status st = launch_init(c);
   if (st != LBM_OK) return st;
   HIP_TRY(c, hipMemsetAsync(objp, 0, (size_t)c->sblk * 8, c->stream));
+  const int s_last = nseg - 1, t0_last = s_last * ckpt;
   for (int t = 0; t < T; ++t) {
-    if (want_grad && (t + 1) % ckpt == 0 && t + 1 < T) {
+    if (want_grad && (t + 1) % ckpt == 0 && (t + 1) / ckpt < s_last) {
       st = save_ck((t + 1) / ckpt);
       if (st != LBM_OK) return st;
     }
     const bool in = t >= obj->t_begin && t < obj->t_end;
-    st = launch_step(c, in ? (okind == LBM_OBJ_WSS ? 3 : 2) : 0, nullptr, nullptr);
+    float* r = nullptr;
+    float* rr = nullptr;
+    if (want_grad && s_last >= 1 && t == t0_last - 1) {
+      r = slot_rec(0);
+      rr = slot_rho(0);
+    } else if (want_grad && t >= t0_last) {
+      r = slot_rec(t - t0_last + 1);
+      rr = slot_rho(t - t0_last + 1);
+    }
+    st = launch_step(c, in ? (okind == LBM_OBJ_WSS ? 3 : 2) : 0, r, rr);
     if (st != LBM_OK) return st;
   }
   double jsum = 0.0;
@@ -117,18 +131,20 @@ extern "C" lbm_status lbm_adjoint(lbm_ctx* c, const lbm_objective* obj, int T, i
   ab.phih = phih;
   for (int s = nseg - 1; s >= 0; --s) {
     const int t0 = s * ckpt, t1 = std::min(T, t0 + ckpt);
-    if (s == 0) {
-      st = launch_init(c);
-      if (st != LBM_OK) return st;
-    } else {
-      st = load_ck(s);
-      if (st != LBM_OK) return st;
-      st = launch_step(c, 0, slot_rec(0), slot_rho(0));
-      if (st != LBM_OK) return st;
-    }
-    for (int t = t0; t < t1; ++t) {
-      st = launch_step(c, 0, slot_rec(t - t0 + 1), slot_rho(t - t0 + 1));
-      if (st != LBM_OK) return st;
+    if (s < s_last) {
+      if (s == 0) {
+        st = launch_init(c);
+        if (st != LBM_OK) return st;
+      } else {
+        st = load_ck(s);
+        if (st != LBM_OK) return st;
+        st = launch_step(c, 0, slot_rec(0), slot_rho(0));
+        if (st != LBM_OK) return st;
+      }
+      for (int t = t0; t < t1; ++t) {
+        st = launch_step(c, 0, slot_rec(t - t0 + 1), slot_rho(t - t0 + 1));
+        if (st != LBM_OK) return st;
+      }
     }
     for (int n = t1 - 1; n >= t0; --n) {
       const int k = n - t0 + 1;

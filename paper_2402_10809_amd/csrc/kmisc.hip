@@ -140,6 +140,25 @@ __global__ __launch_bounds__(BLOCK) void k_phi_uni19(Params p, const uint32_t* c
   links[c] = uni ? (lk | LK_UNI) : (lk & ~LK_UNI);
 }
 
+// Wave records of the D3Q19 step (WaveInfo, step.hpp), one per 64 compact
+// cells, from the position codes and the link words; records past the last
+// cell get no flags.  Grid: wave_records(nc) / 4 blocks of 256.
+__global__ __launch_bounds__(BLOCK) void k_wave_info(Params p, const uint32_t* code, const uint32_t* links,
+                                                     WaveInfo* out) {
+  static_assert(BLOCK % 64 == 0, "whole waves per block");
+  const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
+  const uint32_t lane = threadIdx.x & 63u;
+  const bool in = c < (uint32_t)p.nc;
+  const uint32_t row = in ? code[c] >> p.xbits : 0xffffffffu;
+  const uint32_t prev = __shfl_up(row, 1u, 64);
+  const uint64_t starts = __ballot(in && lane > 0u && row != prev);
+  const uint32_t lk = in ? links[c] : LK_DEAD;
+  const bool plain = __all(!(lk & LK_DEAD) && (lk & LK_UNI) && !(lk & (LK_IN | LK_OUT | LK_UPS)));
+  const bool inr = __all((lk & LK_INR) != 0u);
+  const uint32_t row0 = __shfl(row, 0, 64);
+  if (lane == 0u) out[c >> 6] = WaveInfo{starts, row0, (plain ? WV_PLAIN : 0u) | (inr ? WV_INR : 0u)};
+}
+
 __global__ __launch_bounds__(BLOCK) void k_phi_uni27(Params p, const uint32_t* code, uint64_t* links,
                                                      const int* delta, const float* phi) {
   const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
@@ -221,6 +240,16 @@ lbm_status set_porosity_device(lbm_ctx* c, const float* phib, uint32_t* bad_cell
                        rowbox, phib, lbm::LK_DEAD, phi);
     hipLaunchKernelGGL(lbm::k_phi_uni19, grid, block, 0, c->stream, c->P, code, lk, delta, (const float*)phi);
   }
+  HIP_TRY(c, hipGetLastError());
+  return launch_wave_info(c);
+}
+
+lbm_status launch_wave_info(lbm_ctx* c) {
+  if (c->q == 27) return LBM_OK;  // the D3Q27 step keeps no wave records
+  const int64_t nrec = wave_records(c->nc);
+  hipLaunchKernelGGL(lbm::k_wave_info, dim3((unsigned)(nrec / (BLOCK / 64))), dim3(BLOCK), 0, c->stream, c->P,
+                     (const uint32_t*)(c->ws + c->L.code), (const uint32_t*)(c->ws + c->L.links),
+                     (lbm::WaveInfo*)(c->ws + c->L.winfo));
   HIP_TRY(c, hipGetLastError());
   return LBM_OK;
 }

@@ -7,7 +7,7 @@ namespace lbmrt {
 
 template <class S>
 void step19(lbm_ctx* c, const lbm::Bufs& b, int diag, bool rec) {
-  constexpr int NT = std::is_same<S, float>::value ? 256 : 64;
+  constexpr int NT = std::is_same<S, float>::value ? 256 : STEP_NT16;
   const dim3 grid(c->sblk), block(NT);
   with_shift(c->grid.shift_mode, [&](auto shw) {
     constexpr bool SH = decltype(shw)::value;
@@ -30,9 +30,19 @@ void step19(lbm_ctx* c, const lbm::Bufs& b, int diag, bool rec) {
             } else if constexpr (std::is_same<S, float>::value) {
               // the adjoint's forms (FP32 storage only)
               if (rec) {
-                if constexpr (!SH)
-                  hipLaunchKernelGGL((k_step<S, false, OD, 0, true, R, PJ, NT, AN>), grid, block, 0, c->stream,
-                                     c->P, b);
+                // the recording step, with the objective term when the
+                // forward pass records the last segment
+                if constexpr (!SH) {
+                  if (diag == 2)
+                    hipLaunchKernelGGL((k_step<S, false, OD, 2, true, R, PJ, NT, AN>), grid, block, 0, c->stream,
+                                       c->P, b);
+                  else if (diag == 3)
+                    hipLaunchKernelGGL((k_step<S, false, OD, 3, true, R, PJ, NT, AN>), grid, block, 0, c->stream,
+                                       c->P, b);
+                  else
+                    hipLaunchKernelGGL((k_step<S, false, OD, 0, true, R, PJ, NT, AN>), grid, block, 0, c->stream,
+                                       c->P, b);
+                }
               } else if (diag == 2) {
                 hipLaunchKernelGGL((k_step<S, SH, OD, 2, false, R, PJ, NT, AN>), grid, block, 0, c->stream, c->P,
                                    b);

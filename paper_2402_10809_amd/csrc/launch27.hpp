@@ -7,7 +7,7 @@ namespace lbmrt {
 
 template <class S>
 void step27(lbm_ctx* c, const lbm::q27::Bufs27& b, int diag) {
-  constexpr int NT = std::is_same<S, float>::value ? 256 : 64;
+  constexpr int NT = std::is_same<S, float>::value ? 256 : STEP_NT16;
   const dim3 grid(c->sblk), block(NT);
   with_shift(c->grid.shift_mode, [&](auto shw) {
     constexpr bool SH = decltype(shw)::value;

@@ -13,6 +13,15 @@ namespace lbmrt {
 
 using namespace lbm;
 
+// Cells per population plane: the compact count rounded up to a multiple of 64,
+// so that every plane starts on a 128-byte boundary (16-bit storage; 256 bytes
+// for FP32) and a wave's access to one plane covers whole cache lines.  The
+// padding slots are never read or written.
+inline int64_t plane_cells(int64_t nc) { return (nc + 63) & ~int64_t(63); }
+// Wave records (lbm::WaveInfo) of the D3Q19 step: one per 64 compact cells of
+// the largest step grid (blocks of 256).
+inline int64_t wave_records(int64_t nc) { return (nc + 255) / 256 * 4; }
+
 // Rows of the compact layout: every (y, z) line holding fluid, ordered by z
 // then y, with the x range from its first to its last fluid cell.
 struct Rows {
@@ -38,6 +47,7 @@ struct HostLayout {
   std::vector<uint32_t> code;     // per compact cell
   std::vector<uint32_t> rowbox;   // box index of (x = 0) of each row
   std::vector<int> delta;         // [nrow][8]: compact start - first x of the neighbour row of pair k
+  std::vector<int> rel;           // [nrow][8]: delta minus (compact start - first x) of the row itself
   std::vector<int64_t> fluid_box; // box index per fluid cell (ascending)
   std::vector<int64_t> fluid_c;   // compact index per fluid cell
   std::vector<uint8_t> region_f;  // per fluid cell
@@ -90,6 +100,7 @@ inline void build_host_layout(HostLayout& L, const lbm_grid& g, const uint8_t* s
   L.code.assign(L.nc, 0u);
   L.rowbox.assign(L.nrow, 0u);
   L.delta.assign((size_t)L.nrow * 8, 0);
+  L.rel.assign((size_t)L.nrow * 8, 0);
   std::vector<int64_t> rowid((size_t)g.ny * g.nz, -1);
   L.fluid_box.clear(); L.fluid_c.clear(); L.region_f.clear(); L.openface.clear();
   L.fluid_box.reserve(L.nf);
@@ -125,6 +136,9 @@ inline void build_host_layout(HostLayout& L, const lbm_grid& g, const uint8_t* s
       const int64_t rr = rowid[(size_t)sz * g.ny + sy];
       if (rr < 0) continue;
       L.delta[(size_t)r * 8 + (k - 1)] = (int)(L.rows.cb[rr] - L.rows.x0[rr]);
+      // (x, row rr) sits at c + rel from (x, row r) = c
+      L.rel[(size_t)r * 8 + (k - 1)] =
+          (int)((L.rows.cb[rr] - L.rows.x0[rr]) - (L.rows.cb[r] - L.rows.x0[r]));
     }
   }
 }

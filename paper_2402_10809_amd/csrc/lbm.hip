@@ -112,12 +112,14 @@ Layout make_layout(const lbm_grid& g, int64_t nc, int64_t nrow, int T, int ckpt)
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
   const int q = qof(g);
-  L.A = take((size_t)q * (size_t)nc * ss);
+  L.A = take((size_t)q * (size_t)plane_cells(nc) * ss);
   L.code = take((size_t)nc * 4);
   L.links = take((size_t)nc * (q == 27 ? 8 : 4));
   L.phi = take((size_t)nc * 4);
   L.omega = take((size_t)nc * 4);
   L.delta = take((size_t)nrow * 8 * 4);
+  L.rel = take((size_t)nrow * 8 * 4);
+  L.winfo = take((size_t)wave_records(nc) * sizeof(lbm::WaveInfo));
   L.shape = take((size_t)nrow * 4);
   L.rowbox = take((size_t)nrow * 4);
   L.stage = take((size_t)(q + 1) * nc * 4);
@@ -151,6 +153,8 @@ Bufs bufs(lbm_ctx* c) {
   b.code = (const uint32_t*)(c->ws + c->L.code);
   b.links = (const uint32_t*)(c->ws + c->L.links);
   b.delta = (const int*)(c->ws + c->L.delta);
+  b.rel = (const int*)(c->ws + c->L.rel);
+  b.winfo = (const WaveInfo*)(c->ws + c->L.winfo);
   b.phi = (const float*)(c->ws + c->L.phi);
   b.omega = (float*)(c->ws + c->L.omega);
   b.shape = (const float*)(c->ws + c->L.shape);
@@ -206,7 +210,7 @@ lbm_status validate_grid(const lbm_grid* g) {
 // population planes (also the FP32 adjoint planes) and the position code.
 lbm_status check_rows(const lbm_grid* g, const Rows& r) {
   if (r.nf == 0) return fail(LBM_E_INVALID, "no fluid cell");
-  if ((double)r.nc * qof(*g) * 4.0 >= 4294967296.0)
+  if ((double)plane_cells(r.nc) * qof(*g) * 4.0 >= 4294967296.0)
     return fail(LBM_E_INVALID, std::string("more than ") + (qof(*g) == 27 ? "39.7" : "56.5") +
                                    " M compact cells (kernels address the population planes with 32-bit byte "
                                    "offsets)");
@@ -249,6 +253,8 @@ lbm_status upload_phi(lbm_ctx* c, const float* phi) {
                               c->stream));
   else
     HIP_TRY(c, hipMemcpyAsync(c->ws + c->L.links, links.data(), links.size() * 4, hipMemcpyHostToDevice, c->stream));
+  lbm_status s = launch_wave_info(c);
+  if (s != LBM_OK) return s;
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return LBM_OK;
 }
@@ -527,8 +533,9 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* solid, const float* p
   P.outlet = op ? op->outlet : 0;
   P.nrow = (int)nrow;
   P.xbits = xb;
-  for (int i = 0; i < c->q; ++i) P.plb[i] = (uint32_t)((size_t)i * c->nc * store_bytes(grid->storage));
-  P.abytes = (uint32_t)((size_t)c->q * c->nc * store_bytes(grid->storage));
+  const size_t pc = (size_t)plane_cells(c->nc);
+  for (int i = 0; i < c->q; ++i) P.plb[i] = (uint32_t)((size_t)i * pc * store_bytes(grid->storage));
+  P.abytes = (uint32_t)((size_t)c->q * pc * store_bytes(grid->storage));
   {
     Params::K<double> k{};
     k.U = c->U; k.iU = 1.0 / c->U; k.ks = c->U / (c->q == 27 ? 216.0 : 36.0);  // U w_i = ks * (integer weight)
@@ -571,6 +578,7 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* solid, const float* p
   HIP_TRY0(hipMemsetAsync(c->ws + c->L.A, 0, c->L.code - c->L.A, c->stream));
   HIP_TRY0(hipMemcpyAsync(c->ws + c->L.code, c->code.data(), c->code.size() * 4, hipMemcpyHostToDevice, c->stream));
   HIP_TRY0(hipMemcpyAsync(c->ws + c->L.delta, c->delta.data(), c->delta.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY0(hipMemcpyAsync(c->ws + c->L.rel, c->rel.data(), c->rel.size() * 4, hipMemcpyHostToDevice, c->stream));
   HIP_TRY0(hipMemcpyAsync(c->ws + c->L.shape, shape.data(), shape.size() * 4, hipMemcpyHostToDevice, c->stream));
   HIP_TRY0(hipMemcpyAsync(c->ws + c->L.rowbox, c->rowbox.data(), c->rowbox.size() * 4, hipMemcpyHostToDevice, c->stream));
   if (P.in_table > 0)

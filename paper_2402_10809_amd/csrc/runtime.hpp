@@ -33,10 +33,11 @@ inline int blocks_for_nt(int64_t n, int nt) { return (int)((n + nt - 1) / nt); }
 // the 16-bit forms (measured fastest for each on the large aneurysm).
 constexpr int STEP_NT_MIN = 64;
 constexpr int MAX_WAVE_TABLE = 1024;  // samples of a sampled inflow waveform
-inline int step_nt(int storage) { return storage == LBM_STORE_FP32 ? 256 : 64; }
+constexpr int STEP_NT16 = 256;  // work-items per workgroup of the 16-bit step kernels
+inline int step_nt(int storage) { return storage == LBM_STORE_FP32 ? 256 : STEP_NT16; }
 
 struct Layout {
-  size_t A, code, links, phi, omega, delta, shape, rowbox, stage, part, diag, obj, tc, wave, side;
+  size_t A, code, links, phi, omega, delta, rel, winfo, shape, rowbox, stage, part, diag, obj, tc, wave, side;
   // adjoint
   size_t ck, rec, rho, ah0, ah1, omh, phih, aside;
   int nck, ckpt, T;
@@ -167,6 +168,7 @@ void launch_set_time(hipStream_t s, uint32_t* tc, uint32_t t);
 void launch_copy(hipStream_t s, const void* src, void* dst, size_t n16, unsigned blocks);
 void launch_probe(hipStream_t s, int kind, const void* src, void* dst, size_t n16, unsigned blocks);
 lbm_status set_porosity_device(lbm_ctx* c, const float* phib, uint32_t* bad_cell);
+lbm_status launch_wave_info(lbm_ctx* c);
 
 // Runtime operations shared by the ABI functions (lbm.hip).
 lbm_status launch_init(lbm_ctx* c);

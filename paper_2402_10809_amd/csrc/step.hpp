@@ -101,11 +101,28 @@ struct Params {
   }
 };
 
+// Per wave of 64 compact cells (cells 64w .. 64w + 63): the row of its first
+// cell, a bit per lane that starts a new row, and flags.  WV_PLAIN: every
+// lane is a fluid cell with uniform neighbour porosity and no open-face role;
+// WV_INR: every lane is interior.  The step of a plain wave needs neither the
+// position codes nor the link words: even steps touch only the cells' own
+// slots, and on odd steps an interior lane's row follows from the row starts
+// and its neighbour rows from the per-row offsets rel.
+struct WaveInfo {
+  uint64_t starts;
+  uint32_t row0;
+  uint32_t flags;
+};
+constexpr uint32_t WV_PLAIN = 1u;
+constexpr uint32_t WV_INR = 2u;
+
 struct Bufs {
   void* A;                // populations, [19][nc], in place
   const uint32_t* code;   // (row << xbits) | x per compact cell
   const uint32_t* links;  // link word per compact cell
   const int* delta;       // [nrow][8]: neighbour-row deltas for pairs 1..8
+  const int* rel;         // [nrow][8]: compact index of (x, neighbour row k) minus that of (x, row)
+  const WaveInfo* winfo;  // per wave of 64 compact cells
   const float* phi;       // porosity per compact cell
   float* omega;           // per compact cell, previous relaxation rate
   const float* shape;     // inflow profile per row
@@ -756,10 +773,11 @@ __device__ __forceinline__ void round16(const int (&cx)[NQ], const int (&cy)[NQ]
 // difference to the intended momentum (input momentum + force + porosity-jump
 // momentum) onto the three axis pairs, leaving only the final rounding of
 // each stored value.
-template <class S, bool SHW, bool UNI, bool ODD, class R, bool PROJ, bool INR = false, int RM = 0>
-__device__ __forceinline__ void collide_store(const Params& p, const Pop<S>& A, uint32_t c, uint32_t lk, const Pos& q,
-                                              float phx_f, float d[Q], const float pt[Q], const Macro<R>& M,
-                                              uint32_t seed = 0u) {
+// collide_values: the outputs, in place of the pulled values d; collide_store
+// also rounds and stores them.
+template <bool SHW, bool UNI, class R, bool PROJ>
+__device__ __forceinline__ void collide_values(const Params& p, float phx_f, float d[Q], const float pt[Q],
+                                               const Macro<R>& M) {
   const R phx = (R)phx_f;
   const R om = M.omega;
   const R pr = phx * M.rho;
@@ -841,6 +859,14 @@ __device__ __forceinline__ void collide_store(const Params& p, const Pop<S>& A, 
 #pragma unroll
     for (int i = 0; i < Q; ++i) o[i] += ksf * kw(i) * ((UNI ? phx_f : pt[i]) - 1.0f);
   }
+}
+
+template <class S, bool SHW, bool UNI, bool ODD, class R, bool PROJ, bool INR = false, int RM = 0>
+__device__ __forceinline__ void collide_store(const Params& p, const Pop<S>& A, uint32_t c, uint32_t lk, const Pos& q,
+                                              float phx_f, float d[Q], const float pt[Q], const Macro<R>& M,
+                                              uint32_t seed = 0u) {
+  collide_values<SHW, UNI, R, PROJ>(p, phx_f, d, pt, M);
+  const float* o = d;
   if constexpr (!std::is_same<S, float>::value && RM != 0) {
     unsigned short hb[Q];
     round16<S, Q, RM>(CX, CY, CZ, o, hb, seed);
@@ -918,12 +944,29 @@ __device__ __forceinline__ void diag_terms(const Params& p, float phx, const flo
 // Body of the step for one cell (UNI: the whole wave has uniform neighbour
 // porosity; INR: every cell of the wave is interior; RM: rounding of 16-bit
 // storage, see round16).
-template <class S, bool SHW, bool UNI, bool ODD, int DIAG, bool REC, class R, bool PROJ, bool AN, bool INR, int RM>
+template <class S, bool SHW, bool UNI, bool ODD, int DIAG, bool REC, class R, bool PROJ, bool AN, bool INR, int RM,
+          bool PL = false>
 __device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32_t c, uint32_t lk, uint32_t t,
-                                          double (&dv)[NDIAGP], float& ke_reg) {
-  Pos q = position(p, c, b.code[c]);
-  if (ODD || !UNI) load_deltas(b.delta, q);
-  if (INR) interior_offsets<S>(q);
+                                          double (&dv)[NDIAGP], float& ke_reg, uint32_t row = 0u) {
+  Pos q;
+  if constexpr (PL) {
+    // a plain wave (lk synthesised: uniform, interior on odd steps); row given
+    q.row = row;
+    if constexpr (ODD) {
+      const int4* r4 = (const int4*)(b.rel + (size_t)row * 8);
+      const int4 a = r4[0], e = r4[1];
+      const int rl[NPAIR] = {0, a.x, a.y, a.z, a.w, e.x, e.y, e.z, e.w};
+#pragma unroll
+      for (int k = 0; k < NPAIR; ++k) q.bo[k] = (c + (uint32_t)rl[k]) * (uint32_t)sizeof(S);
+    }
+  } else {
+    // an even step of a uniform-porosity cell touches only its own slots: its
+    // position is needed only for an open-face row's data
+    const bool where = ODD || !UNI || (lk & (LK_IN | LK_OUT | LK_UPS));
+    q = position(p, c, where ? b.code[c] : 0u);
+    if (ODD || !UNI) load_deltas(b.delta, q);
+    if (INR) interior_offsets<S>(q);
+  }
   const float phx = ldo(b.phi, c);
   float d[Q], pt[Q];
   const Pop<S> A(b.A, p.abytes);
@@ -953,6 +996,30 @@ __device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32
   collide_store<S, SHW, UNI, ODD, R, PROJ, INR, RM>(p, A, c, lk, q, phx, d, pt, M, RM == 2 ? round_seed(c, t) : 0u);
 }
 
+// The step of cell c (any cell of the compact range or past it) through its
+// link word, with the wave-uniform choice of the uniform-porosity and
+// interior forms; returns whether c is a fluid cell.  Every lane of the wave
+// takes part.
+template <class S, bool SHW, bool ODD, int DIAG, bool REC, class R, bool PROJ, bool AN, int RM>
+__device__ __forceinline__ bool step_any(const Params& p, const Bufs& b, uint32_t c, uint32_t t,
+                                         double (&dv)[NDIAGP], float& ke_reg) {
+  const uint32_t lk = c < (uint32_t)p.nc ? b.links[c] : LK_DEAD;
+  const bool active = !(lk & LK_DEAD);
+  const bool uni = !active || (lk & LK_UNI);
+  if (__all(uni)) {
+    // odd steps address the neighbours: interior waves (most of a vessel's
+    // waves) need no per-direction bounce-back selects
+    if (ODD && __all(!active || (lk & LK_INR))) {
+      if (active) step_cell<S, SHW, true, ODD, DIAG, REC, R, PROJ, AN, true, RM>(p, b, c, lk, t, dv, ke_reg);
+    } else {
+      if (active) step_cell<S, SHW, true, ODD, DIAG, REC, R, PROJ, AN, false, RM>(p, b, c, lk, t, dv, ke_reg);
+    }
+  } else {
+    if (active) step_cell<S, SHW, false, ODD, DIAG, REC, R, PROJ, AN, false, RM>(p, b, c, lk, t, dv, ke_reg);
+  }
+  return active;
+}
+
 // ---------------------------------------------------------------------------
 // The step at parity ODD (t odd), NT work-items per workgroup.  DIAG: 0 none,
 // 1 diagnostics of the pre-collision state into part[block][NDIAGP], 2 region
@@ -968,22 +1035,22 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu((ODD && size
 void k_step(Params p, Bufs b) {
   const uint32_t c = xcd_block(blockIdx.x, gridDim.x) * NT + threadIdx.x;
   const uint32_t t = b.tc[ODD ? 1 : 0];
-  const uint32_t lk = c < (uint32_t)p.nc ? b.links[c] : LK_DEAD;
-  const bool active = !(lk & LK_DEAD);
   double dv[NDIAGP];
   float ke_reg = 0.0f;
-  const bool uni = !active || (lk & LK_UNI);
-  if (__all(uni)) {
-    // odd steps address the neighbours: interior waves (most of a vessel's
-    // waves) need no per-direction bounce-back selects
-    if (ODD && __all(!active || (lk & LK_INR))) {
-      if (active) step_cell<S, SHW, true, ODD, DIAG, REC, R, PROJ, AN, true, RM>(p, b, c, lk, t, dv, ke_reg);
-    } else {
-      if (active) step_cell<S, SHW, true, ODD, DIAG, REC, R, PROJ, AN, false, RM>(p, b, c, lk, t, dv, ke_reg);
+  // plain waves (FP32 storage; the 16-bit steps measured faster without the
+  // record lookup in front of their loads)
+  if constexpr (DIAG == 0 && sizeof(S) == 4) {
+    const WaveInfo wi = b.winfo[__builtin_amdgcn_readfirstlane(c >> 6)];
+    if ((wi.flags & WV_PLAIN) && (!ODD || (wi.flags & WV_INR))) {
+      const uint32_t lane = threadIdx.x & 63u;
+      const uint32_t row = wi.row0 + (uint32_t)__popcll(wi.starts & ((2ull << lane) - 2ull));
+      step_cell<S, SHW, true, ODD, DIAG, REC, R, PROJ, AN, ODD, RM, true>(p, b, c, LK_UNI | (ODD ? LK_INR : 0u), t,
+                                                                           dv, ke_reg, row);
+      if (blockIdx.x == 0 && threadIdx.x == 0) b.tc[ODD ? 0 : 1] = t + 1u;
+      return;
     }
-  } else {
-    if (active) step_cell<S, SHW, false, ODD, DIAG, REC, R, PROJ, AN, false, RM>(p, b, c, lk, t, dv, ke_reg);
   }
+  const bool active = step_any<S, SHW, ODD, DIAG, REC, R, PROJ, AN, RM>(p, b, c, t, dv, ke_reg);
   if (DIAG == 1) {
     if (!active) {
       float d[Q] = {};

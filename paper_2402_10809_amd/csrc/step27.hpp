@@ -348,7 +348,10 @@ __device__ __forceinline__ void diag_terms(const Params& p, float phx, const flo
 template <class S, bool SHW, bool UNI, bool ODD, int DIAG, class R, bool PROJ, int RM>
 __device__ __forceinline__ void step_cell(const Params& p, const Bufs27& b, uint32_t c, uint64_t lk, uint32_t t,
                                           double (&dv)[NDIAGP]) {
-  Pos q = position(p, c, b.code[c]);
+  // an even step of a uniform-porosity cell touches only its own slots: its
+  // position is needed only for an open-face row's data
+  const bool where = ODD || !UNI || (lk & (L_IN | L_OUT | L_UPS));
+  Pos q = position(p, c, where ? b.code[c] : 0u);
   if (ODD || !UNI) load_deltas(b.delta, q);
   const float phx = ldo(b.phi, c);
   float d[Q], pt[Q];

@@ -12,7 +12,11 @@
 //     lies in [0, n_compact), is a fluid cell, and its position code decodes to
 //     the source;
 //   - byte offsets of every population slot stay below 2^32;
-//   - uniform-neighbour-porosity, interior, open-face and unknown flags.
+//   - uniform-neighbour-porosity, interior, open-face and unknown flags;
+//   - D3Q19 interior cells: the source the interior path forms from the row
+//     offsets, c + rel[row][pair] - c_x, is the same compact index;
+//   - the row that the step derives for each lane of a 64-cell wave from the
+//     wave's first row and its row-start bits is the cell's row.
 // Exit status 0 when every check holds.
 #include <cstdio>
 #include <random>
@@ -25,6 +29,7 @@ using namespace lbmrt;
 namespace {
 
 int g_fail = 0;
+long g_inr = 0;  // interior-path sources checked
 void expect(bool ok, const char* what, int seed, long cell, int dir) {
   if (ok) return;
   if (g_fail < 20) std::printf("FAIL seed %d cell %ld dir %d: %s\n", seed, cell, dir, what);
@@ -91,8 +96,13 @@ void check_links(const HostLayout& L, const std::vector<float>& phib, const std:
                  "source position code", seed, (long)c, i);
           expect(!(links.at(src) & dead), "source is a fluid cell", seed, (long)c, i);
           // byte offsets of the slots the kernels address (plane of opp(i) at the source)
-          const uint64_t off = ((uint64_t)opp[i] * (uint64_t)L.nc + (uint64_t)src) * 4u;
+          const uint64_t off = ((uint64_t)opp[i] * (uint64_t)plane_cells(L.nc) + (uint64_t)src) * 4u;
           expect(off < (1ull << 32), "32-bit byte offset", seed, (long)c, i);
+          if (inr_bit && (lk & inr_bit) && k > 0) {
+            const int64_t isrc = c + (int64_t)L.rel.at((size_t)row * 8 + (k - 1)) - cv[i][0];
+            expect(isrc == src, "interior-path source from the row offsets", seed, (long)c, i);
+            ++g_inr;
+          }
         }
       }
       // neighbour x + c_i for the uniform-porosity flag
@@ -114,6 +124,25 @@ void check_links(const HostLayout& L, const std::vector<float>& phib, const std:
     if (inr_bit) {
       const bool inr = !any_wall && !(L.periodic[0] && (x == 0 || x == L.nx - 1));
       expect(((lk & inr_bit) != 0) == inr, "interior flag", seed, (long)c, -1);
+    }
+  }
+}
+
+// The per-wave row records as the wave-record kernel forms them (first row,
+// a bit per lane that starts a new row), decoded as the step decodes them.
+void check_wave_rows(const HostLayout& L, int seed) {
+  const int64_t nrec = wave_records(L.nc);
+  expect(nrec * 64 >= L.nc, "wave records cover the compact cells", seed, -1, -1);
+  for (int64_t w = 0; w < nrec; ++w) {
+    const int64_t c0 = w * 64;
+    if (c0 >= L.nc) break;
+    const uint32_t row0 = L.code.at(c0) >> L.xbits;
+    uint64_t starts = 0;
+    for (int l = 1; l < 64 && c0 + l < L.nc; ++l)
+      if ((L.code.at(c0 + l) >> L.xbits) != (L.code.at(c0 + l - 1) >> L.xbits)) starts |= 1ull << l;
+    for (int l = 0; l < 64 && c0 + l < L.nc; ++l) {
+      const uint32_t row = row0 + (uint32_t)__builtin_popcountll(starts & ((2ull << l) - 2ull));
+      expect(row == (L.code.at(c0 + l) >> L.xbits), "row decoded from the wave record", seed, (long)(c0 + l), -1);
     }
   }
 }
@@ -158,6 +187,7 @@ void one_case(int seed) {
   for (int i = 0; i < Q; ++i) opp19[i] = OPP[i];
   check_links<uint32_t, Q>(L, phib, l19, cv19, opp19, pk19, LK_DEAD, LK_UNI, LK_IN, LK_OUT, LK_UNK, XIN, XOUT, 5,
                            LK_INR, seed);
+  check_wave_rows(L, seed);
   check_links<uint64_t, q27::Q>(L, phib, l27, cv27, opp27, pk27, q27::L_DEAD, q27::L_UNI, q27::L_IN, q27::L_OUT,
                                 q27::L_UNK, q27::XIN, q27::XOUT, q27::NX, (uint64_t)0, seed);
 }
@@ -167,6 +197,6 @@ void one_case(int seed) {
 int main(int argc, char** argv) {
   const int n = argc > 1 ? std::atoi(argv[1]) : 400;
   for (int s = 0; s < n; ++s) one_case(s);
-  std::printf("layout check: %d random boxes, %d failures\n", n, g_fail);
-  return g_fail ? 1 : 0;
+  std::printf("layout check: %d random boxes, %ld interior-path sources, %d failures\n", n, g_inr, g_fail);
+  return (g_fail || g_inr == 0) ? 1 : 0;
 }
