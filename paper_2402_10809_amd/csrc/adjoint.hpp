@@ -75,8 +75,8 @@ void k_adjoint(Params p, AdjBufs a, uint32_t t, float ew, int kind) {
   // ---- forward recompute from the record --------------------------------
   float d[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) d[i] = a.rec[(size_t)i * p.nc + c];
-  const float omp = a.rec[(size_t)Q * p.nc + c];
+  for (int i = 0; i < Q; ++i) d[i] = __builtin_nontemporal_load(&a.rec[(size_t)i * p.nc + c]);
+  const float omp = __builtin_nontemporal_load(&a.rec[(size_t)Q * p.nc + c]);
   // the record holds the filled values; the Zou-He fills are recomputed for
   // their transposes below (the extrapolation's unknowns are inputs)
   const bool extrap = p.outlet == 2;

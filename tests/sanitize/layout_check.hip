@@ -13,8 +13,9 @@
 //     the source;
 //   - byte offsets of every population slot stay below 2^32;
 //   - uniform-neighbour-porosity, interior, open-face and unknown flags;
-//   - D3Q19 interior cells: the source the interior path forms from the row
-//     offsets, c + rel[row][pair] - c_x, is the same compact index;
+//   - interior cells: the source formed from the row offsets, c + rel[row][pair]
+//     - c_x (the plain-wave path of the D3Q19 FP32 step), is the same compact
+//     index (checked for both velocity sets);
 //   - the row that the step derives for each lane of a 64-cell wave from the
 //     wave's first row and its row-start bits is the cell's row.
 // Exit status 0 when every check holds.
@@ -59,6 +60,8 @@ void check_links(const HostLayout& L, const std::vector<float>& phib, const std:
     const int X[3] = {x, L.rows.y.at(row), L.rows.z.at(row)};
     const bool openf = x == 0 ? (lk & in_bit) != 0 : (x == L.nx - 1 ? (lk & out_bit) != 0 : false);
     bool uni = true, any_wall = false;
+    int64_t rel_src[NQ], true_src[NQ];  // per direction: source from the row offsets, and the true one
+    for (int i = 0; i < NQ; ++i) rel_src[i] = true_src[i] = -1;
     for (int i = 1; i < NQ; ++i) {
       // the pull source x - c_i, by brute force
       int s[3];
@@ -98,11 +101,9 @@ void check_links(const HostLayout& L, const std::vector<float>& phib, const std:
           // byte offsets of the slots the kernels address (plane of opp(i) at the source)
           const uint64_t off = ((uint64_t)opp[i] * (uint64_t)plane_cells(L.nc) + (uint64_t)src) * 4u;
           expect(off < (1ull << 32), "32-bit byte offset", seed, (long)c, i);
-          if (inr_bit && (lk & inr_bit) && k > 0) {
-            const int64_t isrc = c + (int64_t)L.rel.at((size_t)row * 8 + (k - 1)) - cv[i][0];
-            expect(isrc == src, "interior-path source from the row offsets", seed, (long)c, i);
-            ++g_inr;
-          }
+          if (k > 0) rel_src[i] = c + (int64_t)L.rel.at((size_t)row * 8 + (k - 1)) - cv[i][0];
+          else rel_src[i] = c - cv[i][0];
+          true_src[i] = src;
         }
       }
       // neighbour x + c_i for the uniform-porosity flag
@@ -121,9 +122,14 @@ void check_links(const HostLayout& L, const std::vector<float>& phib, const std:
       }
     }
     expect(((lk & uni_bit) != 0) == uni, "uniform-neighbour-porosity flag", seed, (long)c, -1);
-    if (inr_bit) {
-      const bool inr = !any_wall && !(L.periodic[0] && (x == 0 || x == L.nx - 1));
-      expect(((lk & inr_bit) != 0) == inr, "interior flag", seed, (long)c, -1);
+    const bool inr = !any_wall && !(L.periodic[0] && (x == 0 || x == L.nx - 1));
+    if (inr_bit) expect(((lk & inr_bit) != 0) == inr, "interior flag", seed, (long)c, -1);
+    if (inr) {
+      // the interior path of a plain wave: c + rel[row][pair] - c_x for every direction
+      for (int i = 1; i < NQ; ++i) {
+        expect(rel_src[i] == true_src[i], "interior-path source from the row offsets", seed, (long)c, i);
+        ++g_inr;
+      }
     }
   }
 }

@@ -486,6 +486,32 @@ def test_porosity_update_resets():
     assert np.abs(g - f).max() < 2e-6
 
 
+@pytest.mark.parametrize("kind", ["bulk", "bulk_q27"])
+def test_wave_records_follow_porosity_updates(kind):
+    """The per-wave records of the D3Q19 step (which waves may skip the link
+    words) are rebuilt on every porosity upload: uniform middles (plain
+    waves), then random porosity everywhere (no plain wave), then uniform
+    again, each followed by 12 steps against the oracle (D3Q27, which keeps
+    no records, as a control)."""
+    case = _tiny_any(kind, 2)
+    s = Solver.from_case(case)
+    rng = np.random.default_rng(17)
+    fluid = case.solid == 0
+    x = np.arange(case.nx)[None, None, :]
+    face = (x == 0) | (x == case.nx - 1)
+    noisy = np.where(fluid, np.where(face, 1.0, rng.uniform(0.6, 1.0, case.solid.shape)), 0.0).astype(np.float32)
+    for name, phi in (("uniform", case.phi), ("random", noisy), ("uniform again", case.phi)):
+        say(f"wave records: {case.name} porosity {name}")
+        s.set_porosity(np.ascontiguousarray(phi, dtype=np.float32))
+        s.step(12)
+        o = oracle.Oracle(case.with_(phi=phi))
+        f, om = o.init()
+        o.run(f, om, 0, 12)
+        g, _ = s.get_state()
+        known = np.isfinite(g)
+        assert np.abs(g[known] - f[known]).max() < 2e-6
+
+
 def test_instability_is_reported():
     """A non-finite population injected through lbm_set_state is caught at the
     next stability check (every 1000th step index) with LBM_E_UNSTABLE."""
