@@ -228,10 +228,12 @@ def parse_form(name: str):
     """A form name: storage (fp32, fp16, bf16), then optional modifiers: q27
     (D3Q27), aniso (the anisotropic medium), conserve / nearest (16-bit
     rounding other than the default stochastic one), hbm (the all-fluid box
-    beyond the cache)."""
+    beyond the cache), slab (the x-slices through the sac centre that hold
+    1/8 of the fluid cells, periodic in x: one GPU's share of an 8-way
+    decomposition with equal fluid counts)."""
     parts = name.split("_")
     storage, mods = parts[0], set(parts[1:])
-    if storage not in ("fp32", "fp16", "bf16") or not mods <= {"q27", "aniso", "conserve", "nearest", "hbm"}:
+    if storage not in ("fp32", "fp16", "bf16") or not mods <= {"q27", "aniso", "conserve", "nearest", "hbm", "slab"}:
         raise SystemExit(f"unknown form {name}")
     rounding = "conserve" if "conserve" in mods else ("nearest" if "nearest" in mods else "stochastic")
     return storage, mods, rounding
@@ -250,6 +252,10 @@ def make_solver(name: str, case, hbm_case):
 
     storage, mods, rounding = parse_form(name)
     c = hbm_case if "hbm" in mods else case
+    if "slab" in mods:
+        # one GPU's share of an 8-way x-decomposition with equal fluid counts
+        from synth import slab_of
+        c = slab_of(c)
     if "q27" in mods:
         c = as_d3q27(copy.copy(c))
     if "aniso" in mods:
@@ -259,7 +265,7 @@ def make_solver(name: str, case, hbm_case):
 
 
 DEFAULT_FORMS = ("fp16,fp16_conserve,fp16_nearest,bf16,fp32_aniso,fp32_q27,fp16_q27,"
-                 "fp32_hbm,fp16_hbm,bf16_hbm,adjoint,adjoint_1seg,adjoint_aniso")
+                 "fp32_hbm,fp16_hbm,bf16_hbm,fp32_slab,fp16_slab,adjoint,adjoint_1seg,adjoint_aniso")
 
 
 def main():

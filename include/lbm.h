@@ -294,7 +294,11 @@ lbm_status lbm_reset(lbm_ctx* ctx);
  * respect to the porosity of every fluid cell.  Resets to rest, runs T steps forward while
  * accumulating J and storing a checkpoint every ckpt_every steps, then sweeps
  * back through the segments (recompute forward, then reverse steps).  The
- * forward passes compute the collision, the shear rate and the Carreau-Yasuda
+ * forward pass records the last segment itself, so that segment is not
+ * recomputed; with ckpt_every >= T nothing is recomputed (the record of the
+ * whole run, 84 bytes per fluid cell and step, must then fit the workspace).
+ * J and the gradient do not depend on ckpt_every (the recompute reproduces
+ * the forward trajectory bit for bit).  The forward passes compute the collision, the shear rate and the Carreau-Yasuda
  * law in FP64 (LBM_ARITH_FP64) whatever the context's arithmetic mode, and
  * store the trajectory in FP32; the reverse steps are FP64 arithmetic with
  * FP32 adjoint populations and an FP64 relaxation-rate adjoint.  Either outflow kind; with the extrapolation outflow

@@ -6,17 +6,35 @@
 namespace lbm {
 
 // Reduce per-block partials (single workgroup, fixed order: deterministic).
-// opmask holds 2 bits per entry: 0 sum, 1 max, 2 min.
+// opmask holds 2 bits per entry: 0 sum, 1 max, 2 min.  Each work-item reads
+// whole rows (the n entries of one block, contiguous) and accumulates every
+// entry in its own register, rows i = tid, tid + BLOCK, ... in order; then one
+// tree reduction per entry in LDS.  n <= FIN_MAX.
+constexpr int FIN_MAX = 16;
 __global__ __launch_bounds__(BLOCK) void k_finalize(const double* part, int nblk, int n, uint32_t opmask, double* out) {
   __shared__ double sh[BLOCK];
-  for (int k = 0; k < n; ++k) {
+  double r[FIN_MAX];
+#pragma unroll
+  for (int k = 0; k < FIN_MAX; ++k) {
     const int op = (int)((opmask >> (2 * k)) & 3u);
-    double r = op == 0 ? 0.0 : (op == 1 ? -1e300 : 1e300);
-    for (int i = threadIdx.x; i < nblk; i += BLOCK) {
-      const double v = part[(size_t)i * n + k];
-      r = op == 0 ? r + v : (op == 1 ? fmax(r, v) : fmin(r, v));
+    r[k] = op == 0 ? 0.0 : (op == 1 ? -1e300 : 1e300);
+  }
+  for (int i = threadIdx.x; i < nblk; i += BLOCK) {
+    const double* row = part + (size_t)i * n;
+#pragma unroll
+    for (int k = 0; k < FIN_MAX; ++k) {
+      if (k < n) {
+        const int op = (int)((opmask >> (2 * k)) & 3u);
+        const double v = row[k];
+        r[k] = op == 0 ? r[k] + v : (op == 1 ? fmax(r[k], v) : fmin(r[k], v));
+      }
     }
-    sh[threadIdx.x] = r;
+  }
+#pragma unroll
+  for (int k = 0; k < FIN_MAX; ++k) {
+    if (k >= n) break;
+    const int op = (int)((opmask >> (2 * k)) & 3u);
+    sh[threadIdx.x] = r[k];
     __syncthreads();
     for (int s = BLOCK / 2; s > 0; s >>= 1) {
       if (threadIdx.x < s) {
@@ -181,6 +199,7 @@ __global__ __launch_bounds__(BLOCK) void k_phi_uni27(Params p, const uint32_t* c
 namespace lbmrt {
 
 void launch_finalize(hipStream_t s, const double* part, int nparts, int n, uint32_t ops, double* out) {
+  static_assert(NDIAGP <= lbm::FIN_MAX, "partial rows fit the reduction's registers");
   hipLaunchKernelGGL(lbm::k_finalize, dim3(1), dim3(BLOCK), 0, s, part, nparts, n, ops, out);
 }
 

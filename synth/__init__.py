@@ -19,6 +19,7 @@ from .cases import (  # noqa: F401
     sampled_waveform,
     aniso_shape,
     as_d3q27,
+    slab_of,
     with_anisotropic_drag,
     CONFIGS,
     make_config,

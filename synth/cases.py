@@ -427,6 +427,29 @@ def tiny_random(seed: int) -> Case:
     return case
 
 
+def slab_of(case: Case, parts: int = 8, g: float = 1e-6) -> Case:
+    """One GPU's share of an x-decomposition into ``parts`` slabs of equal
+    fluid-cell counts, at its real shape: the narrowest even number of x-slices
+    centred on the middle of ``case`` (for the aneurysm, through the sac centre,
+    the thinnest slab of such a cut) that holds at least 1/parts of its fluid
+    cells; periodic in x so that each cut face reads the other (standing in for
+    the halo a neighbour would send), driven by a body force along x instead of
+    the inlet."""
+    per_x = (case.solid == 0).sum(axis=(0, 1))
+    target = per_x.sum() / parts
+    width = 2
+    while width < case.nx and per_x[case.nx // 2 - width // 2: case.nx // 2 + width // 2].sum() < target:
+        width += 2
+    x0 = case.nx // 2 - width // 2
+    sl = (slice(None), slice(None), slice(x0, x0 + width))
+    porous = dict(case.porous)
+    porous["g"] = (g, 0.0, 0.0)
+    return Case(name=f"{case.name}_slab{width}", nx=width, ny=case.ny, nz=case.nz, periodic=(True, False, False),
+                solid=np.ascontiguousarray(case.solid[sl]), phi=np.ascontiguousarray(case.phi[sl]),
+                sac=np.ascontiguousarray(case.sac[sl]), rheology=dict(case.rheology), porous=porous,
+                steps=case.steps, extra=dict(case.extra, slab_x0=x0), lattice=case.lattice)
+
+
 def as_d3q27(case: Case) -> Case:
     """The same case on the D3Q27 velocity set."""
     case.lattice = 27
