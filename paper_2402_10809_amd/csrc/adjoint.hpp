@@ -110,8 +110,8 @@ void k_adjoint(Params p, AdjBufs a, uint32_t t, float ew, int kind) {
   const R dnu = kc.dnu * kc.cy_e * fac * fast_rcp(hh) * dla;
 
   // ---- gather the adjoint of the post-collision populations --------------
-  R qh[Q];
-  qh[0] = (R)ldo(a.ph_next, c);
+  float qh[Q];  // as stored (FP32); widened exactly where used, which keeps them in half the registers
+  qh[0] = ldo(a.ph_next, c);
   uint32_t fmask = 0;
   R sfl = 0.0, sjump = 0.0;
   sfor<1, Q>([&](auto ic) {
@@ -120,8 +120,8 @@ void k_adjoint(Params p, AdjBufs a, uint32_t t, float ew, int kind) {
     const uint32_t tgt = src_of<OPP[I]>(p, q);   // x + c_I
     const R pn = (R)ldo(a.phi, fl ? tgt : c);
     const uint32_t e = fl ? (uint32_t)I * (uint32_t)p.nc + tgt : (uint32_t)OPP[I] * (uint32_t)p.nc + c;
-    qh[I] = (R)ldo(a.ph_next, e);
-    const R ai = (R)kw(I) * (1.0 / 36.0) * qh[I];
+    qh[I] = ldo(a.ph_next, e);
+    const R ai = (R)kw(I) * (1.0 / 36.0) * (R)qh[I];
     sfl += fl ? ai : 0.0;
     sjump += fl ? ai * (pn - phx) : 0.0;
     fmask |= fl ? (1u << I) : 0u;
@@ -130,10 +130,10 @@ void k_adjoint(Params p, AdjBufs a, uint32_t t, float ew, int kind) {
   // moments of a_i = w_i qhat_i (exact weights 36 w_i / 36)
   R av[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) av[i] = (R)kw(i) * qh[i] * (1.0 / 36.0);
+  for (int i = 0; i < Q; ++i) av[i] = (R)kw(i) * (R)qh[i] * (1.0 / 36.0);
   R s0 = 0.0, qd = 0.0;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) { s0 += av[i]; qd += qh[i] * (R)d[i]; }
+  for (int i = 0; i < Q; ++i) { s0 += av[i]; qd += (R)qh[i] * (R)d[i]; }
   qd *= iU;  // sum qhat_i (f_i - w_i phi)
   const R s1x = (av[1] + av[7] + av[9] + av[11] + av[13]) - (av[2] + av[8] + av[10] + av[12] + av[14]);
   const R s1y = (av[3] + av[7] + av[10] + av[15] + av[17]) - (av[4] + av[8] + av[9] + av[16] + av[18]);
@@ -355,11 +355,11 @@ void k_adjoint(Params p, AdjBufs a, uint32_t t, float ew, int kind) {
 
   // adjoint of the (filled) pulled populations
   R fh[Q];
-  fh[0] = keep * qh[0] + Sh;
+  fh[0] = keep * (R)qh[0] + Sh;
   sfor<1, Q>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
     constexpr int cx = CX[I], cy = CY[I], cz = CZ[I];
-    fh[I] = keep * qh[I] + Sh + mhx * (R)cx + mhy * (R)cy + mhz * (R)cz + (R)(cx * cx) * G[0] +
+    fh[I] = keep * (R)qh[I] + Sh + mhx * (R)cx + mhy * (R)cy + mhz * (R)cz + (R)(cx * cx) * G[0] +
             (R)(cy * cy) * G[1] + (R)(cz * cz) * G[2] +
             2.0 * ((R)(cx * cy) * G[3] + (R)(cx * cz) * G[4] + (R)(cy * cz) * G[5]);
   });
