@@ -108,10 +108,11 @@ def time_steps(torch, solver, steps: int, warmup: int, spinup: int = 0):
     return e0.elapsed_time(e1) / steps  # ms per step
 
 
-def probes(torch, nbytes=4 << 30, reps=10):
+def probes(torch, nbytes=4 << 30, reps=10, kinds=("copy", "copy_nt", "read", "write")):
     """Achievable bandwidth on this machine: the plain 16-byte copy, a copy with
     four vectors in flight per work-item and non-temporal accesses, a read-only
-    and a write-only stream, each over 4 GiB (GB/s of bytes moved)."""
+    and a write-only stream, each over nbytes per buffer (4 GiB by default;
+    GB/s of bytes moved)."""
     from paper_2402_10809_amd import lbm
 
     a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
@@ -119,7 +120,7 @@ def probes(torch, nbytes=4 << 30, reps=10):
     a.fill_(1)
     st = torch.cuda.current_stream()
     out = {}
-    for kind in ("copy", "copy_nt", "read", "write"):
+    for kind in kinds:
         dst = b.data_ptr()
         lbm.lbm_bandwidth_probe(kind, dst, a.data_ptr(), nbytes, st.cuda_stream)
         torch.cuda.synchronize()
@@ -367,6 +368,14 @@ def main():
     probe = None if args.no_probe else probes(torch)
     if probe:
         log(f"[bench] bandwidth probes (GB/s): {probe}")
+    # the same copies with a footprint equal to the headline form's working set
+    # (two buffers of half of it): the achievable rate when that set stays in
+    # the Infinity Cache
+    ws_head = case.n_fluid * (19 * (4 if head_form == "fp32" else 2) + 16)
+    probe_ws = None if args.no_probe else probes(torch, nbytes=(ws_head // 2) & ~255, reps=200,
+                                                 kinds=("copy", "copy_nt"))
+    if probe_ws:
+        log(f"[bench] copy probes at the working-set footprint (GB/s): {probe_ws}")
     cpu = None
     if not args.no_cpu:
         log("[bench] oracle CPU baseline")
@@ -391,6 +400,8 @@ def main():
                                 "traffic": traffic_for(f"k_step_{head_form}_hbm")}
     if probe:
         roof["achievable_GBps"] = max(probe.values())
+    if probe_ws:
+        roof["achievable_at_working_set_GBps"] = max(probe_ws.values())
     line = {
         "metric": "fluid MLUPS + % HBM peak, D3Q19 VANSE-CY: FP32 vs FP16-store vs adjoint",
         "value": round(head["mlups"], 1),
@@ -415,6 +426,7 @@ def main():
                       "frac": round(v["frac"], 4), "bytes_per_update": bytes_of(k),
                       "ms_per_step": round(v["ms_per_step"], 5), "cells": v["cells"]} for k, v in results.items()},
         "bandwidth_probes_GBps": probe,
+        "copy_probes_at_working_set_GBps": probe_ws,
     }
     line["forms"].update(adjoints)
     if skipped:
