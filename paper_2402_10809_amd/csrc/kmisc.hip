@@ -171,10 +171,12 @@ __global__ __launch_bounds__(BLOCK) void k_wave_info(Params p, const uint32_t* c
   const uint32_t prev = __shfl_up(row, 1u, 64);
   const uint64_t starts = __ballot(in && lane > 0u && row != prev);
   const uint32_t lk = in ? links[c] : LK_DEAD;
-  const bool plain = __all(!(lk & LK_DEAD) && (lk & LK_UNI) && !(lk & (LK_IN | LK_OUT | LK_UPS)));
+  const bool fluid = __all(!(lk & LK_DEAD) && !(lk & (LK_IN | LK_OUT | LK_UPS)));
+  const bool uni = __all((lk & LK_UNI) != 0u);
   const bool inr = __all((lk & LK_INR) != 0u);
   const uint32_t row0 = __shfl(row, 0, 64);
-  if (lane == 0u) out[c >> 6] = WaveInfo{starts, row0, (plain ? WV_PLAIN : 0u) | (inr ? WV_INR : 0u)};
+  if (lane == 0u)
+    out[c >> 6] = WaveInfo{starts, row0, (fluid ? WV_FLUID : 0u) | (uni ? WV_UNI : 0u) | (inr ? WV_INR : 0u)};
 }
 
 __global__ __launch_bounds__(BLOCK) void k_phi_uni27(Params p, const uint32_t* code, uint64_t* links,

@@ -102,19 +102,22 @@ struct Params {
 };
 
 // Per wave of 64 compact cells (cells 64w .. 64w + 63): the row of its first
-// cell, a bit per lane that starts a new row, and flags.  WV_PLAIN: every
-// lane is a fluid cell with uniform neighbour porosity and no open-face role;
-// WV_INR: every lane is interior.  The step of a plain wave needs neither the
-// position codes nor the link words: even steps touch only the cells' own
-// slots, and on odd steps an interior lane's row follows from the row starts
-// and its neighbour rows from the per-row offsets rel.
+// cell, a bit per lane that starts a new row, and flags.  WV_FLUID: every
+// lane is a fluid cell without open-face role; WV_UNI: every lane has uniform
+// neighbour porosity; WV_INR: every lane is interior.  A plain wave (FLUID and
+// UNI) needs neither the position codes nor the link words: even steps touch
+// only the cells' own slots, and on odd steps an interior lane's row follows
+// from the row starts and its neighbour rows from the per-row offsets rel.
+// A FLUID and INR wave without uniform porosity needs them neither: its
+// neighbours' porosities are read through the same offsets.
 struct WaveInfo {
   uint64_t starts;
   uint32_t row0;
   uint32_t flags;
 };
-constexpr uint32_t WV_PLAIN = 1u;
+constexpr uint32_t WV_FLUID = 1u;
 constexpr uint32_t WV_INR = 2u;
+constexpr uint32_t WV_UNI = 4u;
 
 struct Bufs {
   void* A;                // populations, [19][nc], in place
@@ -275,8 +278,13 @@ __device__ __forceinline__ void pull(const Params& p, const Pop<S>& A, const flo
     constexpr int J = OPP[I];
     v[I] = ld(slot_in<I, ODD, S, INR>(p, c, lk, q));
     if (!UNI) {
-      const bool bb = !INR && ((lk >> I) & 1u);
-      pt[J] = ldo(phi, bb ? c : src_of<I>(p, q));
+      if constexpr (INR) {
+        // interior: the source x - c_I is fluid, at (x, row k) shifted by -c_x
+        pt[J] = ldo(phi, q.bo[PK[I]] / (uint32_t)sizeof(S) - (uint32_t)CX[I]);
+      } else {
+        const bool bb = (lk >> I) & 1u;
+        pt[J] = ldo(phi, bb ? c : src_of<I>(p, q));
+      }
     } else {
       pt[J] = phx;
     }
@@ -950,9 +958,10 @@ __device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32
                                           double (&dv)[NDIAGP], float& ke_reg, uint32_t row = 0u) {
   Pos q;
   if constexpr (PL) {
-    // a plain wave (lk synthesised: uniform, interior on odd steps); row given
+    // a plain wave (lk synthesised: uniform, interior on odd steps) or a
+    // non-uniform interior one; row given
     q.row = row;
-    if constexpr (ODD) {
+    if constexpr (ODD || !UNI) {
       const int4* r4 = (const int4*)(b.rel + (size_t)row * 8);
       const int4 a = r4[0], e = r4[1];
       const int rl[NPAIR] = {0, a.x, a.y, a.z, a.w, e.x, e.y, e.z, e.w};
@@ -1029,9 +1038,11 @@ __device__ __forceinline__ bool step_any(const Params& p, const Bufs& b, uint32_
 // ---------------------------------------------------------------------------
 // The 16-bit odd step needs 97 VGPRs as compiled freely (4 waves per SIMD);
 // asked for 5 waves the compiler fits it in 96 without scratch, and the step
-// runs 1-2 % faster.  Other instantiations would spill at 5 and keep the default.
+// runs 1-2 % faster.  The FP32-arithmetic step is asked for 4 waves: compiled
+// freely its odd step spills 20 bytes per lane.  Other instantiations would
+// spill at these targets and keep the default.
 template <class S, bool SHW, bool ODD, int DIAG, bool REC, class R, bool PROJ, int NT, bool AN = false, int RM = 0>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu((ODD && sizeof(S) == 2 && DIAG == 0 && !REC) ? 5 : 1)))
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu((ODD && sizeof(S) == 2 && DIAG == 0 && !REC) ? 5 : (sizeof(S) == 4 && DIAG == 0 && !REC && std::is_same<R, float>::value && !AN ? 4 : 1))))
 void k_step(Params p, Bufs b) {
   const uint32_t c = xcd_block(blockIdx.x, gridDim.x) * NT + threadIdx.x;
   const uint32_t t = b.tc[ODD ? 1 : 0];
@@ -1041,13 +1052,20 @@ void k_step(Params p, Bufs b) {
   // record lookup in front of their loads)
   if constexpr (DIAG == 0 && sizeof(S) == 4) {
     const WaveInfo wi = b.winfo[__builtin_amdgcn_readfirstlane(c >> 6)];
-    if ((wi.flags & WV_PLAIN) && (!ODD || (wi.flags & WV_INR))) {
-      const uint32_t lane = threadIdx.x & 63u;
-      const uint32_t row = wi.row0 + (uint32_t)__popcll(wi.starts & ((2ull << lane) - 2ull));
-      step_cell<S, SHW, true, ODD, DIAG, REC, R, PROJ, AN, ODD, RM, true>(p, b, c, LK_UNI | (ODD ? LK_INR : 0u), t,
-                                                                           dv, ke_reg, row);
-      if (blockIdx.x == 0 && threadIdx.x == 0) b.tc[ODD ? 0 : 1] = t + 1u;
-      return;
+    if (wi.flags & WV_FLUID) {
+      const bool uni = (wi.flags & WV_UNI) != 0, inr = (wi.flags & WV_INR) != 0;
+      if (uni ? (!ODD || inr) : inr) {
+        const uint32_t lane = threadIdx.x & 63u;
+        const uint32_t row = wi.row0 + (uint32_t)__popcll(wi.starts & ((2ull << lane) - 2ull));
+        if (uni)
+          step_cell<S, SHW, true, ODD, DIAG, REC, R, PROJ, AN, ODD, RM, true>(p, b, c, LK_UNI | (ODD ? LK_INR : 0u),
+                                                                               t, dv, ke_reg, row);
+        else
+          step_cell<S, SHW, false, ODD, DIAG, REC, R, PROJ, AN, true, RM, true>(p, b, c, LK_INR, t, dv, ke_reg,
+                                                                                row);
+        if (blockIdx.x == 0 && threadIdx.x == 0) b.tc[ODD ? 0 : 1] = t + 1u;
+        return;
+      }
     }
   }
   const bool active = step_any<S, SHW, ODD, DIAG, REC, R, PROJ, AN, RM>(p, b, c, t, dv, ke_reg);
