@@ -22,8 +22,17 @@ void step19(lbm_ctx* c, const lbm::Bufs& b, int diag, bool rec) {
           auto go = [&](auto an) {
             constexpr bool AN = decltype(an)::value;
             if (diag == 0 && !rec) {
-              hipLaunchKernelGGL((k_step<S, SH, OD, 0, false, R, PJ, NT, AN, RM>), grid, block, 0, c->stream, c->P,
-                                 b);
+              if constexpr (sizeof(S) == 2) {
+                if (c->beyond_cache)
+                  hipLaunchKernelGGL((k_step<S, SH, OD, 0, false, R, PJ, NT, AN, RM, true>), grid, block, 0,
+                                     c->stream, c->P, b);
+                else
+                  hipLaunchKernelGGL((k_step<S, SH, OD, 0, false, R, PJ, NT, AN, RM, false>), grid, block, 0,
+                                     c->stream, c->P, b);
+              } else {
+                hipLaunchKernelGGL((k_step<S, SH, OD, 0, false, R, PJ, NT, AN, RM>), grid, block, 0, c->stream,
+                                   c->P, b);
+              }
             } else if (diag == 1) {
               hipLaunchKernelGGL((k_step<S, SH, OD, 1, false, R, PJ, NT, AN, RM>), grid, block, 0, c->stream, c->P,
                                  b);

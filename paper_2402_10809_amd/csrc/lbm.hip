@@ -521,6 +521,8 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* solid, const float* p
   }
   c->nblk = blocks_for(c->nc);
   c->sblk = blocks_for_nt(c->nc, step_nt(grid->storage));
+  // populations, position code, link word, porosity and relaxation rate
+  c->beyond_cache = (size_t)c->nc * ((size_t)c->q * store_bytes(grid->storage) + 16) > INFINITY_CACHE_BYTES;
   c->L = L0;
   c->ws = (char*)workspace;
   c->ws_bytes = ws_bytes;

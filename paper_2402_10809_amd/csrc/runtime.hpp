@@ -34,6 +34,8 @@ inline int blocks_for_nt(int64_t n, int nt) { return (int)((n + nt - 1) / nt); }
 constexpr int STEP_NT_MIN = 64;
 constexpr int MAX_WAVE_TABLE = 1024;  // samples of a sampled inflow waveform
 constexpr int STEP_NT16 = 256;  // work-items per workgroup of the 16-bit step kernels
+// Infinity Cache (last-level, memory-side) of MI355X, bytes.
+constexpr size_t INFINITY_CACHE_BYTES = (size_t)256 << 20;
 inline int step_nt(int storage) { return storage == LBM_STORE_FP32 ? 256 : STEP_NT16; }
 
 struct Layout {
@@ -56,6 +58,7 @@ struct lbm_ctx : lbmrt::HostLayout {
   size_t nbox = 0;
   int nblk = 0;                   // blocks of BLOCK work-items over the compact cells
   int sblk = 0;                   // blocks of the step kernel
+  bool beyond_cache = false;      // the step's state (populations + per-cell arrays) exceeds the Infinity Cache
   int64_t nwss = 0;               // region cells on the wall (with a wall normal)
   int q = 19;                     // velocity set
   double U = 36.0;

@@ -1041,16 +1041,19 @@ __device__ __forceinline__ bool step_any(const Params& p, const Bufs& b, uint32_
 // runs 1-2 % faster.  The FP32-arithmetic step is asked for 4 waves: compiled
 // freely its odd step spills 20 bytes per lane.  Other instantiations would
 // spill at these targets and keep the default.
-template <class S, bool SHW, bool ODD, int DIAG, bool REC, class R, bool PROJ, int NT, bool AN = false, int RM = 0>
+// WR: the wave records are used (always with FP32 storage; the 16-bit steps
+// take them only when the state exceeds the Infinity Cache: on a cache-resident
+// state the record lookup in front of their loads costs more than the bytes it
+// saves).
+template <class S, bool SHW, bool ODD, int DIAG, bool REC, class R, bool PROJ, int NT, bool AN = false, int RM = 0,
+          bool WR = sizeof(S) == 4>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu((ODD && sizeof(S) == 2 && DIAG == 0 && !REC) ? 5 : (sizeof(S) == 4 && DIAG == 0 && !REC && std::is_same<R, float>::value && !AN ? 4 : 1))))
 void k_step(Params p, Bufs b) {
   const uint32_t c = xcd_block(blockIdx.x, gridDim.x) * NT + threadIdx.x;
   const uint32_t t = b.tc[ODD ? 1 : 0];
   double dv[NDIAGP];
   float ke_reg = 0.0f;
-  // plain waves (FP32 storage; the 16-bit steps measured faster without the
-  // record lookup in front of their loads)
-  if constexpr (DIAG == 0 && sizeof(S) == 4) {
+  if constexpr (DIAG == 0 && WR) {
     const WaveInfo wi = b.winfo[__builtin_amdgcn_readfirstlane(c >> 6)];
     if (wi.flags & WV_FLUID) {
       const bool uni = (wi.flags & WV_UNI) != 0, inr = (wi.flags & WV_INR) != 0;
