@@ -371,7 +371,8 @@ def main():
     # the same copies with a footprint equal to the headline form's working set
     # (two buffers of half of it): the achievable rate when that set stays in
     # the Infinity Cache
-    ws_head = case.n_fluid * (19 * (4 if head_form == "fp32" else 2) + 16)
+    h_storage = parse_form(head_form)[0]
+    ws_head = results[head_form]["cells"] * (19 * (4 if h_storage == "fp32" else 2) + 16)
     probe_ws = None if args.no_probe else probes(torch, nbytes=(ws_head // 2) & ~255, reps=200,
                                                  kinds=("copy", "copy_nt"))
     if probe_ws:
@@ -389,7 +390,7 @@ def main():
     traffic = traffic_for(f"k_step_{head_form}_{args.config}")
     # working set of the headline form: populations, per-cell code, link word,
     # porosity and relaxation rate, in bytes
-    ws_mb = round(nf * (19 * (4 if head_form == "fp32" else 2) + 16) / 1e6, 1)
+    ws_mb = round(ws_head / 1e6, 1)
     roof = {"bound": "hbm", "achieved": round(head["alg_GBps"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(head["frac"], 4), "traffic": traffic,
             "working_set_MB": ws_mb, "cache_resident": ws_mb < 256.0}
