@@ -51,18 +51,29 @@ struct AdjBufs {
   double* aside_out;      // the same for step n
 };
 
+// One FP32 value per lane from a buffer straight into LDS (the wave's 64
+// consecutive slots at lds): the load occupies no register while in flight.
+__device__ __forceinline__ void gather_to_lds(__amdgpu_buffer_rsrc_t r, float* lds, uint32_t byte_off) {
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)lds, 4, byte_off, 0, 0, 0);
+}
+
 // One reverse step at every fluid cell.  Arithmetic in FP64 (the adjoint
 // recursion has the same slow modes as the forward map, so FP32 rounding of
 // per-cell scalars would accumulate the same way); the adjoint populations are
 // stored in FP32.
 //
-// Both instantiations are held to 2 waves per SIMD (256 VGPRs): the
-// isotropic one spills 2 registers there, the anisotropic one 27, which still
-// runs faster than 1 wave per SIMD without spills.
+// Both instantiations are held to 2 waves per SIMD (at most 256 VGPRs; the
+// isotropic one needs 242, the anisotropic one 254, without scratch).
 template <bool AN>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
 void k_adjoint(Params p, AdjBufs a, uint32_t t, float ew, int kind) {
   using R = double;
+  // The neighbour gathers (adjoint populations of step n+1, porosities and,
+  // for the porosity-jump term, densities of step n-1 at x + c_I) go straight
+  // to LDS at the start, so that their latency overlaps the forward recompute
+  // at two waves per SIMD without holding registers.  Each wave reads back
+  // only the slots its own loads wrote: no barrier, one wait for the loads.
+  __shared__ float sq[Q][BLOCK], sp[Q][BLOCK], sr[Q][BLOCK];
   const uint32_t c = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   if (c >= (uint32_t)p.nc) return;
   const uint32_t lk = a.links[c];
@@ -71,6 +82,26 @@ void k_adjoint(Params p, AdjBufs a, uint32_t t, float ew, int kind) {
   load_deltas(a.delta, q);
   const bool reg = (lk & LK_REG) != 0;
   const float phx_f = ldo(a.phi, c);
+  const uint32_t tid = threadIdx.x, wb = tid & ~63u;  // this lane, and its wave's first slot
+  {
+    const uint32_t nb = (uint32_t)p.nc * 4u;
+    const __amdgpu_buffer_rsrc_t rq = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(a.ph_next), (short)0,
+                                                                        (int)(nb * (uint32_t)Q), 0x00020000);
+    const __amdgpu_buffer_rsrc_t rp = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(a.phi), (short)0,
+                                                                        (int)nb, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rr = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(a.rho_prev), (short)0,
+                                                                        (int)nb, 0x00020000);
+    gather_to_lds(rq, &sq[0][wb], c * 4u);
+    sfor<1, Q>([&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      const bool fl = ((lk >> OPP[I]) & 1u) == 0;  // x + c_I is a fluid cell
+      const uint32_t tgt = fl ? src_of<OPP[I]>(p, q) : c;  // x + c_I (the cell itself across a wall)
+      const uint32_t e = fl ? (uint32_t)I * (uint32_t)p.nc + tgt : (uint32_t)OPP[I] * (uint32_t)p.nc + c;
+      gather_to_lds(rq, &sq[I][wb], e * 4u);
+      gather_to_lds(rp, &sp[I][wb], tgt * 4u);
+      if (a.rho_prev) gather_to_lds(rr, &sr[I][wb], tgt * 4u);
+    });
+  }
 
   // ---- forward recompute from the record --------------------------------
   float d[Q];
@@ -109,18 +140,17 @@ void k_adjoint(Params p, AdjBufs a, uint32_t t, float ew, int kind) {
   const R nu = kc.nu_inf + kc.dnu * fac;
   const R dnu = kc.dnu * kc.cy_e * fac * fast_rcp(hh) * dla;
 
-  // ---- gather the adjoint of the post-collision populations --------------
+  // ---- the adjoint of the post-collision populations (staged in LDS) ------
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   float qh[Q];  // as stored (FP32); widened exactly where used, which keeps them in half the registers
-  qh[0] = ldo(a.ph_next, c);
+  qh[0] = sq[0][tid];
   uint32_t fmask = 0;
   R sfl = 0.0, sjump = 0.0;
   sfor<1, Q>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
     const bool fl = ((lk >> OPP[I]) & 1u) == 0;  // x + c_I is a fluid cell
-    const uint32_t tgt = src_of<OPP[I]>(p, q);   // x + c_I
-    const R pn = (R)ldo(a.phi, fl ? tgt : c);
-    const uint32_t e = fl ? (uint32_t)I * (uint32_t)p.nc + tgt : (uint32_t)OPP[I] * (uint32_t)p.nc + c;
-    qh[I] = ldo(a.ph_next, e);
+    const R pn = (R)sp[I][tid];
+    qh[I] = sq[I][tid];
     const R ai = (R)kw(I) * (1.0 / 36.0) * (R)qh[I];
     sfl += fl ? ai : 0.0;
     sjump += fl ? ai * (pn - phx) : 0.0;
@@ -420,10 +450,8 @@ void k_adjoint(Params p, AdjBufs a, uint32_t t, float ew, int kind) {
   if (a.rho_prev) {
     sfor<1, Q>([&](auto ic) {
       constexpr int J = decltype(ic)::value;
-      if (fmask & (1u << J)) {
-        const uint32_t tgt = src_of<OPP[J]>(p, q);   // x + c_J
-        phh += (R)kw(J) * (1.0 / 36.0) * (R)ldo(a.rho_prev, tgt) * fh[OPP[J]];
-      }
+      // rho_{n-1}(x + c_J), staged in LDS
+      if (fmask & (1u << J)) phh += (R)kw(J) * (1.0 / 36.0) * (R)sr[J][tid] * fh[OPP[J]];
     });
   }
   a.phih[c] += phh;
