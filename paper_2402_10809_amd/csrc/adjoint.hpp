@@ -83,6 +83,18 @@ void k_adjoint(Params p, AdjBufs a, uint32_t t, float ew, int kind) {
   const bool reg = (lk & LK_REG) != 0;
   const float phx_f = ldo(a.phi, c);
   const uint32_t tid = threadIdx.x, wb = tid & ~63u;  // this lane, and its wave's first slot
+  // Then the record: the forward recompute waits for these loads only, while
+  // the gathers issued after them are still in flight.  The per-cell adjoints
+  // read-modified-written at the end are fetched here too, so that neither
+  // read stalls the wave later (a wait there would also wait for the stores).
+  // Loads complete in issue order for the wait counter, so the row's deltas,
+  // which the gather addresses need, are kept ahead of all of these.
+  asm volatile("" ::: "memory");
+  float d[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) d[i] = __builtin_nontemporal_load(&a.rec[(size_t)i * p.nc + c]);
+  const float omp = __builtin_nontemporal_load(&a.rec[(size_t)Q * p.nc + c]);
+  const double omh_in = a.omh[c], phih_in = a.phih[c];
   {
     const uint32_t nb = (uint32_t)p.nc * 4u;
     const __amdgpu_buffer_rsrc_t rq = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(a.ph_next), (short)0,
@@ -104,10 +116,6 @@ void k_adjoint(Params p, AdjBufs a, uint32_t t, float ew, int kind) {
   }
 
   // ---- forward recompute from the record --------------------------------
-  float d[Q];
-#pragma unroll
-  for (int i = 0; i < Q; ++i) d[i] = __builtin_nontemporal_load(&a.rec[(size_t)i * p.nc + c]);
-  const float omp = __builtin_nontemporal_load(&a.rec[(size_t)Q * p.nc + c]);
   // the record holds the filled values; the Zou-He fills are recomputed for
   // their transposes below (the extrapolation's unknowns are inputs)
   const bool extrap = p.outlet == 2;
@@ -215,7 +223,7 @@ void k_adjoint(Params p, AdjBufs a, uint32_t t, float ew, int kind) {
   }
 
   // collision: q = (1-omega) f + omega feq + K g + w rho (phi~ - phi)
-  R omh = a.omh[c] + wom + (Aeq * s0 + 3.0 * pr * s1u + 4.5 * pr * us2u - qd) -
+  R omh = omh_in + wom + (Aeq * s0 + 3.0 * pr * s1u + 4.5 * pr * us2u - qd) -
           0.5 * (3.0 * s1F - 3.0 * s0 * uF + 9.0 * us2F);
   R uhx = K * (9.0 * s2Fx - 3.0 * s0 * Fx), uhy = K * (9.0 * s2Fy - 3.0 * s0 * Fy),
     uhz = K * (9.0 * s2Fz - 3.0 * s0 * Fz);
@@ -450,11 +458,13 @@ void k_adjoint(Params p, AdjBufs a, uint32_t t, float ew, int kind) {
   if (a.rho_prev) {
     sfor<1, Q>([&](auto ic) {
       constexpr int J = decltype(ic)::value;
-      // rho_{n-1}(x + c_J), staged in LDS
-      if (fmask & (1u << J)) phh += (R)kw(J) * (1.0 / 36.0) * (R)sr[J][tid] * fh[OPP[J]];
+      // rho_{n-1}(x + c_J), staged in LDS; every slot is read and the sum
+      // selected, so that the LDS reads are not serialised behind branches
+      const R t = fma((R)kw(J) * (1.0 / 36.0) * (R)sr[J][tid], fh[OPP[J]], phh);
+      phh = (fmask & (1u << J)) ? t : phh;
     });
   }
-  a.phih[c] += phh;
+  a.phih[c] = phih_in + phh;
 }
 
 // Rest state f_i(0, x) = w_i phi(x) on the known links (and on the
