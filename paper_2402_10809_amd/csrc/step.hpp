@@ -672,11 +672,18 @@ __device__ __forceinline__ R region_wss(uint32_t lk, const Macro<R>& M) {
 // rounding turns that forcing into zero-mean noise.  Works for any velocity set
 // ordered rest, axis pairs, then opposite pairs.
 //
-// Random bits: a per-(cell, step) seed from an integer hash (the "lowbias32"
-// finaliser of C. Wellons' hash-prospector), then Marsaglia's xorshift32
-// sequence, one word per opposite pair (the conversion reads the top 13 bits
-// for FP16, the top 16 for BF16, so the word shifted left by 13 or 16 serves
-// the pair's second value) and one for the rest value.
+// Random bits: a per-(cell, step) word A from an integer hash (the "lowbias32"
+// finaliser of C. Wellons' hash-prospector) and B, one step of Marsaglia's
+// xorshift32 from A.  Opposite pair k takes the word A ^ rotr(B, SR_ROT[k]),
+// the rest value the word after the last pair (the conversion reads the top 13
+// bits for FP16, the top 16 for BF16, so the word shifted left by 13 or 16
+// serves the pair's second value): two instructions a word.  All the words are
+// GF(2)-linear in A; the rotations are chosen so that every two FP16 windows
+// of a cell (13 bits each, 19 or 27 of them) are jointly of full rank 26,
+// i.e. pairwise independent and uniform, which is what the variance of the
+// cell's summed rounding errors depends on.  (Two 16-bit BF16 windows would
+// need all 32 bits; some pairs share a linear relation, as they do along the
+// xorshift sequence itself.)
 __device__ __forceinline__ uint32_t hash32(uint32_t x) {
   x ^= x >> 16;
   x *= 0x7feb352du;
@@ -691,21 +698,26 @@ __device__ __forceinline__ uint32_t xorshift32(uint32_t x) {
   x ^= x << 5;
   return x;
 }
-// Seed of the rounding sequence of cell c at step t (never zero).
+// The word A of cell c at step t.
 __device__ __forceinline__ uint32_t round_seed(uint32_t c, uint32_t t) {
-  return hash32(c ^ hash32(t * 0x9e3779b9u + 0x632be5abu)) | 1u;
+  return hash32(c ^ hash32(t * 0x9e3779b9u + 0x632be5abu));
 }
+constexpr int SR_ROT[14] = {3, 8, 18, 7, 21, 31, 24, 16, 4, 15, 23, 12, 20, 5};
+__device__ __forceinline__ uint32_t rotr32(uint32_t x, int r) { return r ? (x >> r) | (x << (32 - r)) : x; }
 // v rounded stochastically to S (FP16 or BF16) with the random word r.
 template <class S>
 __device__ __forceinline__ unsigned short round_sr(float v, uint32_t r) {
+  // the conversion writes one half of a register and keeps the other; only
+  // the low half is used, so the conversion overwrites the input's own
+  // register rather than a cleared one (no move)
   if constexpr (std::is_same<S, _Float16>::value) {
     typedef _Float16 v2 __attribute__((ext_vector_type(2)));
-    v2 a = {};
+    v2 a = __builtin_bit_cast(v2, v);
     a = __builtin_amdgcn_cvt_sr_f16_f32(a, v, r, false);
     return __builtin_bit_cast(unsigned short, a[0]);
   } else {
     typedef __bf16 v2 __attribute__((ext_vector_type(2)));
-    v2 a = {};
+    v2 a = __builtin_bit_cast(v2, v);
     a = __builtin_amdgcn_cvt_sr_bf16_f32(a, v, r, false);
     return __builtin_bit_cast(unsigned short, a[0]);
   }
@@ -715,12 +727,12 @@ __device__ __forceinline__ void round16(const int (&cx)[NQ], const int (&cy)[NQ]
                                         const float o[NQ], unsigned short hb[NQ], uint32_t seed) {
   constexpr bool SR = RM == 2;
   constexpr int SH = std::is_same<S, _Float16>::value ? 13 : 16;  // second window of a random word
-  uint32_t st = seed;
+  const uint32_t sb = SR ? xorshift32(seed) : 0u;
+  int iw = 0;
   // the next random word (unused without stochastic rounding)
   auto word = [&]() -> uint32_t {
     if constexpr (SR) {
-      st = xorshift32(st);
-      return st;
+      return seed ^ rotr32(sb, SR_ROT[iw++]);
     } else {
       return 0u;
     }
