@@ -63,7 +63,7 @@ __device__ __forceinline__ void gather_to_lds(__amdgpu_buffer_rsrc_t r, float* l
 // stored in FP32.
 //
 // Both instantiations are held to 2 waves per SIMD (at most 256 VGPRs; the
-// isotropic one needs 242, the anisotropic one 254, without scratch).
+// isotropic one needs 247, the anisotropic one 255, without scratch).
 template <bool AN>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
 void k_adjoint(Params p, AdjBufs a, uint32_t t, float ew, int kind) {
