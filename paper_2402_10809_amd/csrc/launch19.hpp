@@ -23,7 +23,10 @@ void step19(lbm_ctx* c, const lbm::Bufs& b, int diag, bool rec) {
             constexpr bool AN = decltype(an)::value;
             if (diag == 0 && !rec) {
               if constexpr (sizeof(S) == 2) {
-                if (c->beyond_cache)
+                // wave records: when the state exceeds the Infinity Cache, and
+                // with rounding to nearest, whose step has the fewest VALU
+                // instructions (with stochastic rounding they gain nothing)
+                if (c->beyond_cache || RM == 0)
                   hipLaunchKernelGGL((k_step<S, SH, OD, 0, false, R, PJ, NT, AN, RM, true>), grid, block, 0,
                                      c->stream, c->P, b);
                 else
