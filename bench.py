@@ -283,8 +283,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--cpu-cases", action="store_true",
-                    help="also time the oracle on the channel, small and coarse aneurysm workloads and its reverse sweep")
+    ap.add_argument("--no-cpu-cases", dest="cpu_cases", action="store_false",
+                    help="skip the oracle's bounded samples of the channel, small and coarse aneurysm workloads "
+                         "and of its reverse sweep on the gradient workload")
     ap.add_argument("--only", default=None, help="time one form only (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:

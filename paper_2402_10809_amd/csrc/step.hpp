@@ -42,6 +42,8 @@
 // open-face unknowns).  Waves whose cells all have uniform neighbour porosity
 // skip the neighbour porosity loads and the porosity-jump arithmetic; on odd
 // steps, waves of interior cells also skip the bounce-back address selects.
+// Uniform waves of pure fluid (porosity 1 in every lane, no body force) also
+// skip the drag and force terms, which vanish there.
 #pragma once
 #include <type_traits>
 
@@ -496,77 +498,89 @@ struct Macro {
 // the tensor drag -phi^2 nu K^-1 u - phi^3 C_F |u| K^-1/2 u.
 // macro_sums takes the moment sums of the cell's values (any velocity set);
 // macro forms them from the D3Q19 values.
-template <class R, bool AN = false>
+//
+// PF (pure fluid): phi = 1 and no body force.  Then 1/k = 0, so there is no
+// drag, C0 = 1/2 and the denominator of the explicit velocity is 1, and the
+// force vanishes: u = m / rho and F = 0.  The general expressions reduce to
+// these exactly (their extra terms are products with an exact zero and the
+// reciprocals of 1 are 1), so both forms give the same values.
+template <class R, bool AN = false, bool PF = false>
 __device__ __forceinline__ void macro_sums(const Params& p, float phx_f, const Sums<R>& s, float omega_prev,
                                            Macro<R>& M) {
+  static_assert(!(PF && AN), "the pure-fluid form is the isotropic one");
   const auto& kc = p.k<R>();
-  const R phx = (R)phx_f;
+  const R phx = PF ? (R)1 : (R)phx_f;
   const R one = (R)1;
-  const R iphi = fast_rcp(phx);
-  const R rm1 = s.s * (kc.iU * iphi);        // rho - 1
+  const R iphi = PF ? one : fast_rcp(phx);
+  const R rm1 = PF ? s.s * kc.iU : s.s * (kc.iU * iphi);  // rho - 1
   const R rho = one + rm1;
-  const R pr = phx * rho;                      // phi rho = sum f
+  const R pr = PF ? rho : phx * rho;           // phi rho = sum f
   const R irho = fast_rcp(rho);
-  const R iUS = kc.iU * iphi * irho;           // 1 / (U phi rho)
-  const R hg = (R)0.5 * iphi;
-  const R gx = kc.gx, gy = kc.gy, gz = kc.gz;
-  const R vx = s.mx * iUS + gx * hg, vy = s.my * iUS + gy * hg, vz = s.mz * iUS + gz * hg;
-  // 1/k = (kc/d^2) (1 - phi)^2 / phi^3
-  const R om = one - phx;
-  const R invk = kc.kcd * om * om * iphi * iphi * iphi;
-  const R dark = phx * kc.nu_d * invk;      // phi nu / k
+  const R iUS = PF ? kc.iU * irho : kc.iU * iphi * irho;  // 1 / (U phi rho)
   R ux, uy, uz, Fx, Fy, Fz;
-  if constexpr (AN) {
-    const R sik = rsqrt_(invk);
-    const R cf = p.forch ? (R)1.75 * rsqrt_(iphi * iphi * iphi * (R)(1.0 / 150.0)) : (R)0;
-    const R ha = (R)0.5 * dark, hb = (R)0.5 * phx * phx * cf * sik;
-    R Am[6], Bm[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      Am[k] = ha * kc.Mi[k] + (k < 3 ? one : (R)0);
-      Bm[k] = hb * kc.Mh[k];
-    }
-    ux = vx; uy = vy; uz = vz;
-    for (int m = 0; m < p.an_iters; ++m) {
-      const R un = rsqrt_(ux * ux + uy * uy + uz * uz);
-      R X[6];
-#pragma unroll
-      for (int k = 0; k < 6; ++k) X[k] = rfma(un, Bm[k], Am[k]);
-      // adjugate of [[X0 X3 X4] [X3 X1 X5] [X4 X5 X2]]
-      const R a00 = X[1] * X[2] - X[5] * X[5], a11 = X[0] * X[2] - X[4] * X[4], a22 = X[0] * X[1] - X[3] * X[3];
-      const R a01 = X[4] * X[5] - X[3] * X[2], a02 = X[3] * X[5] - X[4] * X[1], a12 = X[3] * X[4] - X[0] * X[5];
-      const R idet = fast_rcp(X[0] * a00 + X[3] * a01 + X[4] * a02);
-      ux = (a00 * vx + a01 * vy + a02 * vz) * idet;
-      uy = (a01 * vx + a11 * vy + a12 * vz) * idet;
-      uz = (a02 * vx + a12 * vy + a22 * vz) * idet;
-    }
-    R kdx, kdy, kdz, khx, khy, khz;
-    sym_mv(kc.Mi, ux, uy, uz, kdx, kdy, kdz);
-    sym_mv(kc.Mh, ux, uy, uz, khx, khy, khz);
-    const R dd = phx * dark;                                          // phi^2 nu / k
-    const R df = phx * phx * phx * cf * sik * rsqrt_(ux * ux + uy * uy + uz * uz);  // phi^3 C_F |u| / sqrt(k)
-    Fx = rho * (gx - dd * kdx - df * khx);
-    Fy = rho * (gy - dd * kdy - df * khy);
-    Fz = rho * (gz - dd * kdz - df * khz);
+  if constexpr (PF) {
+    ux = s.mx * iUS; uy = s.my * iUS; uz = s.mz * iUS;
+    Fx = (R)0; Fy = (R)0; Fz = (R)0;
   } else {
-    const R C0 = (R)0.5 + (R)0.25 * dark;
-    // drag = phi^2 nu/k + phi^3 C_F |u|/sqrt(k); the Forchheimer part stays
-    // inside its branch (evaluated unconditionally it costs every cell the
-    // square root's correction sequence)
-    R drag = phx * dark;
-    if (p.forch) {
+    const R hg = (R)0.5 * iphi;
+    const R gx = kc.gx, gy = kc.gy, gz = kc.gz;
+    const R vx = s.mx * iUS + gx * hg, vy = s.my * iUS + gy * hg, vz = s.mz * iUS + gz * hg;
+    // 1/k = (kc/d^2) (1 - phi)^2 / phi^3
+    const R om = one - phx;
+    const R invk = kc.kcd * om * om * iphi * iphi * iphi;
+    const R dark = phx * kc.nu_d * invk;      // phi nu / k
+    if constexpr (AN) {
       const R sik = rsqrt_(invk);
-      const R cf = (R)1.75 * rsqrt_(iphi * iphi * iphi * (R)(1.0 / 150.0));
-      const R C1 = (R)0.5 * phx * phx * cf * sik;
-      const R vn = rsqrt_(vx * vx + vy * vy + vz * vz);
-      const R iden = fast_rcp(C0 + rsqrt_(C0 * C0 + C1 * vn));
-      ux = vx * iden; uy = vy * iden; uz = vz * iden;
-      drag += phx * phx * phx * cf * sik * rsqrt_(ux * ux + uy * uy + uz * uz);
+      const R cf = p.forch ? (R)1.75 * rsqrt_(iphi * iphi * iphi * (R)(1.0 / 150.0)) : (R)0;
+      const R ha = (R)0.5 * dark, hb = (R)0.5 * phx * phx * cf * sik;
+      R Am[6], Bm[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        Am[k] = ha * kc.Mi[k] + (k < 3 ? one : (R)0);
+        Bm[k] = hb * kc.Mh[k];
+      }
+      ux = vx; uy = vy; uz = vz;
+      for (int m = 0; m < p.an_iters; ++m) {
+        const R un = rsqrt_(ux * ux + uy * uy + uz * uz);
+        R X[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) X[k] = rfma(un, Bm[k], Am[k]);
+        // adjugate of [[X0 X3 X4] [X3 X1 X5] [X4 X5 X2]]
+        const R a00 = X[1] * X[2] - X[5] * X[5], a11 = X[0] * X[2] - X[4] * X[4], a22 = X[0] * X[1] - X[3] * X[3];
+        const R a01 = X[4] * X[5] - X[3] * X[2], a02 = X[3] * X[5] - X[4] * X[1], a12 = X[3] * X[4] - X[0] * X[5];
+        const R idet = fast_rcp(X[0] * a00 + X[3] * a01 + X[4] * a02);
+        ux = (a00 * vx + a01 * vy + a02 * vz) * idet;
+        uy = (a01 * vx + a11 * vy + a12 * vz) * idet;
+        uz = (a02 * vx + a12 * vy + a22 * vz) * idet;
+      }
+      R kdx, kdy, kdz, khx, khy, khz;
+      sym_mv(kc.Mi, ux, uy, uz, kdx, kdy, kdz);
+      sym_mv(kc.Mh, ux, uy, uz, khx, khy, khz);
+      const R dd = phx * dark;                                          // phi^2 nu / k
+      const R df = phx * phx * phx * cf * sik * rsqrt_(ux * ux + uy * uy + uz * uz);  // phi^3 C_F |u| / sqrt(k)
+      Fx = rho * (gx - dd * kdx - df * khx);
+      Fy = rho * (gy - dd * kdy - df * khy);
+      Fz = rho * (gz - dd * kdz - df * khz);
     } else {
-      const R iden = fast_rcp((R)2 * C0);
-      ux = vx * iden; uy = vy * iden; uz = vz * iden;
+      const R C0 = (R)0.5 + (R)0.25 * dark;
+      // drag = phi^2 nu/k + phi^3 C_F |u|/sqrt(k); the Forchheimer part stays
+      // inside its branch (evaluated unconditionally it costs every cell the
+      // square root's correction sequence)
+      R drag = phx * dark;
+      if (p.forch) {
+        const R sik = rsqrt_(invk);
+        const R cf = (R)1.75 * rsqrt_(iphi * iphi * iphi * (R)(1.0 / 150.0));
+        const R C1 = (R)0.5 * phx * phx * cf * sik;
+        const R vn = rsqrt_(vx * vx + vy * vy + vz * vz);
+        const R iden = fast_rcp(C0 + rsqrt_(C0 * C0 + C1 * vn));
+        ux = vx * iden; uy = vy * iden; uz = vz * iden;
+        drag += phx * phx * phx * cf * sik * rsqrt_(ux * ux + uy * uy + uz * uz);
+      } else {
+        const R iden = fast_rcp((R)2 * C0);
+        ux = vx * iden; uy = vy * iden; uz = vz * iden;
+      }
+      Fx = rho * (gx - drag * ux); Fy = rho * (gy - drag * uy); Fz = rho * (gz - drag * uz);
     }
-    Fx = rho * (gx - drag * ux); Fy = rho * (gy - drag * uy); Fz = rho * (gz - drag * uz);
   }
   const R uu = ux * ux + uy * uy + uz * uz;
   // Pi = sum (f - f_eq) c c + (F u + u F)/2
@@ -574,12 +588,21 @@ __device__ __forceinline__ void macro_sums(const Params& p, float phx_f, const S
   const R iso = phx * rm1 * (R)(1.0 / 3.0);
   const R iU = kc.iU;
   const R h = (R)0.5;
-  M.P[0] = s.xx * iU - iso - pr * ux * ux + Fx * ux;
-  M.P[1] = s.yy * iU - iso - pr * uy * uy + Fy * uy;
-  M.P[2] = s.zz * iU - iso - pr * uz * uz + Fz * uz;
-  M.P[3] = s.xy * iU - pr * ux * uy + h * (Fx * uy + ux * Fy);
-  M.P[4] = s.xz * iU - pr * ux * uz + h * (Fx * uz + ux * Fz);
-  M.P[5] = s.yz * iU - pr * uy * uz + h * (Fy * uz + uy * Fz);
+  if constexpr (PF) {
+    M.P[0] = s.xx * iU - iso - pr * ux * ux;
+    M.P[1] = s.yy * iU - iso - pr * uy * uy;
+    M.P[2] = s.zz * iU - iso - pr * uz * uz;
+    M.P[3] = s.xy * iU - pr * ux * uy;
+    M.P[4] = s.xz * iU - pr * ux * uz;
+    M.P[5] = s.yz * iU - pr * uy * uz;
+  } else {
+    M.P[0] = s.xx * iU - iso - pr * ux * ux + Fx * ux;
+    M.P[1] = s.yy * iU - iso - pr * uy * uy + Fy * uy;
+    M.P[2] = s.zz * iU - iso - pr * uz * uz + Fz * uz;
+    M.P[3] = s.xy * iU - pr * ux * uy + h * (Fx * uy + ux * Fy);
+    M.P[4] = s.xz * iU - pr * ux * uz + h * (Fx * uz + ux * Fz);
+    M.P[5] = s.yz * iU - pr * uy * uz + h * (Fy * uz + uy * Fz);
+  }
   R nu;
   if constexpr (std::is_same<R, double>::value) {
     // FP64 arithmetic: the shear rate and the Carreau-Yasuda law in FP64 too
@@ -623,9 +646,9 @@ __device__ __forceinline__ void macro_sums(const Params& p, float phx_f, const S
   M.ux = ux; M.uy = uy; M.uz = uz; M.uu = uu;
   M.Fx = Fx; M.Fy = Fy; M.Fz = Fz;
 }
-template <class R, bool AN = false>
+template <class R, bool AN = false, bool PF = false>
 __device__ __forceinline__ void macro(const Params& p, float phx_f, const float d[Q], float omega_prev, Macro<R>& M) {
-  macro_sums<R, AN>(p, phx_f, moment_sums<R>(d), omega_prev, M);
+  macro_sums<R, AN, PF>(p, phx_f, moment_sums<R>(d), omega_prev, M);
 }
 
 // Wall shear stress tau = sigma n - (n . sigma n) n of a wall cell, with the
@@ -795,10 +818,13 @@ __device__ __forceinline__ void round16(const int (&cx)[NQ], const int (&cy)[NQ]
 // each stored value.
 // collide_values: the outputs, in place of the pulled values d; collide_store
 // also rounds and stores them.
-template <bool SHW, bool UNI, class R, bool PROJ>
+// PF (pure fluid, see macro_sums; implies UNI): F = 0 and phi = 1, so the Guo
+// term and the terms in u.F and c.F vanish exactly.
+template <bool SHW, bool UNI, class R, bool PROJ, bool PF = false>
 __device__ __forceinline__ void collide_values(const Params& p, float phx_f, float d[Q], const float pt[Q],
                                                const Macro<R>& M) {
-  const R phx = (R)phx_f;
+  static_assert(!PF || UNI, "a pure-fluid wave has uniform porosity");
+  const R phx = PF ? (R)1 : (R)phx_f;
   const R om = M.omega;
   const R pr = phx * M.rho;
   const R A0 = phx * M.rm1 - (R)1.5 * pr * M.uu;
@@ -807,7 +833,7 @@ __device__ __forceinline__ void collide_values(const Params& p, float phx_f, flo
   const R K3 = (R)3 * K, K9 = (R)9 * K;
   const R uF = M.ux * M.Fx + M.uy * M.Fy + M.uz * M.Fz;
   const R keep = (R)1 - om;
-  const R ev0 = om * A0 - K3 * uF;
+  const R ev0 = PF ? om * A0 : om * A0 - K3 * uF;
   const R ks = p.k<R>().ks;
   // U w_i = ks kw(i) takes two values on the moving directions (axis 2 ks,
   // edge ks): fold it into the per-pair constants once
@@ -830,8 +856,9 @@ __device__ __forceinline__ void collide_values(const Params& p, float phx_f, flo
     constexpr int J = OPP[I];
     constexpr bool AX = I < 7;
     const R kk = AX ? ka : ke;
-    const R ev = rfma(AX ? omCa : omCe, e * e, rfma(AX ? K9a : K9e, e * h, AX ? ev0a : ev0e));
-    const R od = rfma(AX ? omBa : omBe, e, (AX ? K3a : K3e) * h);
+    const R ev = PF ? rfma(AX ? omCa : omCe, e * e, AX ? ev0a : ev0e)
+                    : rfma(AX ? omCa : omCe, e * e, rfma(AX ? K9a : K9e, e * h, AX ? ev0a : ev0e));
+    const R od = PF ? (AX ? omBa : omBe) * e : rfma(AX ? omBa : omBe, e, (AX ? K3a : K3e) * h);
     if (UNI) {
       o[I] = (float)rfma(keep, (R)d[I], ev + od);
       o[J] = (float)rfma(keep, (R)d[J], ev - od);
@@ -843,17 +870,20 @@ __device__ __forceinline__ void collide_values(const Params& p, float phx_f, flo
   pair(std::integral_constant<int, 1>{}, M.ux, M.Fx);
   pair(std::integral_constant<int, 3>{}, M.uy, M.Fy);
   pair(std::integral_constant<int, 5>{}, M.uz, M.Fz);
-  pair(std::integral_constant<int, 7>{}, M.ux + M.uy, M.Fx + M.Fy);
-  pair(std::integral_constant<int, 9>{}, M.ux - M.uy, M.Fx - M.Fy);
-  pair(std::integral_constant<int, 11>{}, M.ux + M.uz, M.Fx + M.Fz);
-  pair(std::integral_constant<int, 13>{}, M.ux - M.uz, M.Fx - M.Fz);
-  pair(std::integral_constant<int, 15>{}, M.uy + M.uz, M.Fy + M.Fz);
-  pair(std::integral_constant<int, 17>{}, M.uy - M.uz, M.Fy - M.Fz);
+  pair(std::integral_constant<int, 7>{}, M.ux + M.uy, PF ? (R)0 : M.Fx + M.Fy);
+  pair(std::integral_constant<int, 9>{}, M.ux - M.uy, PF ? (R)0 : M.Fx - M.Fy);
+  pair(std::integral_constant<int, 11>{}, M.ux + M.uz, PF ? (R)0 : M.Fx + M.Fz);
+  pair(std::integral_constant<int, 13>{}, M.ux - M.uz, PF ? (R)0 : M.Fx - M.Fz);
+  pair(std::integral_constant<int, 15>{}, M.uy + M.uz, PF ? (R)0 : M.Fy + M.Fz);
+  pair(std::integral_constant<int, 17>{}, M.uy - M.uz, PF ? (R)0 : M.Fy - M.Fz);
   if constexpr (PROJ) {
     // momentum in and out (pair differences are exact in FP64)
     const Sums<double> so = moment_sums<double>(o);
     const double U = p.d.U;
-    double tx = tmx + U * (double)M.Fx, ty = tmy + U * (double)M.Fy, tz = tmz + U * (double)M.Fz;
+    double tx = tmx, ty = tmy, tz = tmz;
+    if (!PF) {
+      tx += U * (double)M.Fx; ty += U * (double)M.Fy; tz += U * (double)M.Fz;
+    }
     if (!UNI) {
       const double rm1 = (double)M.rm1, ph = (double)phx_f;
       double jx = 0.0, jy = 0.0, jz = 0.0;
@@ -873,19 +903,19 @@ __device__ __forceinline__ void collide_values(const Params& p, float phx_f, flo
     o[3] = (float)((double)o[3] + ry); o[4] = (float)((double)o[4] - ry);
     o[5] = (float)((double)o[5] + rz); o[6] = (float)((double)o[6] - rz);
   }
-  if (SHW) {
-    // stored relative to w_i instead of w_i phi~_i
+  if (SHW && !PF) {
+    // stored relative to w_i instead of w_i phi~_i (phi = 1: no change)
     const float ksf = p.f.ks;
 #pragma unroll
     for (int i = 0; i < Q; ++i) o[i] += ksf * kw(i) * ((UNI ? phx_f : pt[i]) - 1.0f);
   }
 }
 
-template <class S, bool SHW, bool UNI, bool ODD, class R, bool PROJ, bool INR = false, int RM = 0>
+template <class S, bool SHW, bool UNI, bool ODD, class R, bool PROJ, bool INR = false, int RM = 0, bool PF = false>
 __device__ __forceinline__ void collide_store(const Params& p, const Pop<S>& A, uint32_t c, uint32_t lk, const Pos& q,
                                               float phx_f, float d[Q], const float pt[Q], const Macro<R>& M,
                                               uint32_t seed = 0u) {
-  collide_values<SHW, UNI, R, PROJ>(p, phx_f, d, pt, M);
+  collide_values<SHW, UNI, R, PROJ, PF>(p, phx_f, d, pt, M);
   const float* o = d;
   if constexpr (!std::is_same<S, float>::value && RM != 0) {
     unsigned short hb[Q];
@@ -965,9 +995,9 @@ __device__ __forceinline__ void diag_terms(const Params& p, float phx, const flo
 // porosity; INR: every cell of the wave is interior; RM: rounding of 16-bit
 // storage, see round16).
 template <class S, bool SHW, bool UNI, bool ODD, int DIAG, bool REC, class R, bool PROJ, bool AN, bool INR, int RM,
-          bool PL = false>
+          bool PL = false, bool PF = false>
 __device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32_t c, uint32_t lk, uint32_t t,
-                                          double (&dv)[NDIAGP], float& ke_reg, uint32_t row = 0u) {
+                                          float phx, double (&dv)[NDIAGP], float& ke_reg, uint32_t row = 0u) {
   Pos q;
   if constexpr (PL) {
     // a plain wave (lk synthesised: uniform, interior on odd steps) or a
@@ -988,7 +1018,6 @@ __device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32
     if (ODD || !UNI) load_deltas(b.delta, q);
     if (INR) interior_offsets<S>(q);
   }
-  const float phx = ldo(b.phi, c);
   float d[Q], pt[Q];
   const Pop<S> A(b.A, p.abytes);
   pull<S, SHW, UNI, ODD, INR>(p, A, b.phi, c, lk, q, phx, d, pt);
@@ -1004,7 +1033,7 @@ __device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32
   if (p.outlet == 2 && (lk & (LK_OUT | LK_UPS))) outflow_keep(p, q.row, lk, phx, d, b.side + (ODD ? 0 : half));
   const float omp = b.omega[c];
   Macro<R> M;
-  macro<R, AN>(p, phx, d, omp, M);
+  macro<R, AN, PF>(p, phx, d, omp, M);
   b.omega[c] = (float)M.omega;
   if (REC) {
     __builtin_nontemporal_store(omp, &b.rec[(size_t)Q * p.nc + c]);
@@ -1014,7 +1043,24 @@ __device__ __forceinline__ void step_cell(const Params& p, const Bufs& b, uint32
   if (DIAG == 1) diag_terms<R>(p, phx, d, M, lk, true, dv);
   if (DIAG == 2) ke_reg = reg ? (float)((R)0.5 * M.rho * M.uu) : 0.0f;
   if (DIAG == 3) ke_reg = (float)region_wss<R>(lk, M);
-  collide_store<S, SHW, UNI, ODD, R, PROJ, INR, RM>(p, A, c, lk, q, phx, d, pt, M, RM == 2 ? round_seed(c, t) : 0u);
+  collide_store<S, SHW, UNI, ODD, R, PROJ, INR, RM, PF>(p, A, c, lk, q, phx, d, pt, M,
+                                                        RM == 2 ? round_seed(c, t) : 0u);
+}
+
+// Whether the pure-fluid form serves this wave: the plain step (FP32
+// arithmetic, isotropic, no diagnostics or record), no body force, and
+// porosity 1 at every active lane.
+template <int DIAG, bool REC, class R, bool AN>
+constexpr bool pure_form() {
+  return DIAG == 0 && !REC && !AN && std::is_same<R, float>::value;
+}
+template <int DIAG, bool REC, class R, bool AN>
+__device__ __forceinline__ bool pure_wave(const Params& p, bool active, float phx) {
+  if constexpr (!pure_form<DIAG, REC, R, AN>()) {
+    return false;
+  } else {
+    return p.f.gx == 0.0f && p.f.gy == 0.0f && p.f.gz == 0.0f && __all(!active || phx == 1.0f);
+  }
 }
 
 // The step of cell c (any cell of the compact range or past it) through its
@@ -1027,16 +1073,30 @@ __device__ __forceinline__ bool step_any(const Params& p, const Bufs& b, uint32_
   const uint32_t lk = c < (uint32_t)p.nc ? b.links[c] : LK_DEAD;
   const bool active = !(lk & LK_DEAD);
   const bool uni = !active || (lk & LK_UNI);
+  const float phx = active ? ldo(b.phi, c) : 1.0f;
   if (__all(uni)) {
     // odd steps address the neighbours: interior waves (most of a vessel's
     // waves) need no per-direction bounce-back selects
+    constexpr bool PFK = pure_form<DIAG, REC, R, AN>();
+    const bool pf = pure_wave<DIAG, REC, R, AN>(p, active, phx);
     if (ODD && __all(!active || (lk & LK_INR))) {
-      if (active) step_cell<S, SHW, true, ODD, DIAG, REC, R, PROJ, AN, true, RM>(p, b, c, lk, t, dv, ke_reg);
+      if (pf) {
+        if (active)
+          step_cell<S, SHW, true, ODD, DIAG, REC, R, PROJ, AN, true, RM, false, PFK>(p, b, c, lk, t, phx, dv, ke_reg);
+      } else {
+        if (active) step_cell<S, SHW, true, ODD, DIAG, REC, R, PROJ, AN, true, RM>(p, b, c, lk, t, phx, dv, ke_reg);
+      }
     } else {
-      if (active) step_cell<S, SHW, true, ODD, DIAG, REC, R, PROJ, AN, false, RM>(p, b, c, lk, t, dv, ke_reg);
+      if (pf) {
+        if (active)
+          step_cell<S, SHW, true, ODD, DIAG, REC, R, PROJ, AN, false, RM, false, PFK>(p, b, c, lk, t, phx, dv,
+                                                                                      ke_reg);
+      } else {
+        if (active) step_cell<S, SHW, true, ODD, DIAG, REC, R, PROJ, AN, false, RM>(p, b, c, lk, t, phx, dv, ke_reg);
+      }
     }
   } else {
-    if (active) step_cell<S, SHW, false, ODD, DIAG, REC, R, PROJ, AN, false, RM>(p, b, c, lk, t, dv, ke_reg);
+    if (active) step_cell<S, SHW, false, ODD, DIAG, REC, R, PROJ, AN, false, RM>(p, b, c, lk, t, phx, dv, ke_reg);
   }
   return active;
 }
@@ -1072,11 +1132,16 @@ void k_step(Params p, Bufs b) {
       if (uni ? (!ODD || inr) : inr) {
         const uint32_t lane = threadIdx.x & 63u;
         const uint32_t row = wi.row0 + (uint32_t)__popcll(wi.starts & ((2ull << lane) - 2ull));
-        if (uni)
-          step_cell<S, SHW, true, ODD, DIAG, REC, R, PROJ, AN, ODD, RM, true>(p, b, c, LK_UNI | (ODD ? LK_INR : 0u),
-                                                                               t, dv, ke_reg, row);
+        const float phx = ldo(b.phi, c);
+        constexpr uint32_t LKU = LK_UNI | (ODD ? LK_INR : 0u);
+        constexpr bool PFK = pure_form<DIAG, REC, R, AN>();
+        if (uni && pure_wave<DIAG, REC, R, AN>(p, true, phx))
+          step_cell<S, SHW, true, ODD, DIAG, REC, R, PROJ, AN, ODD, RM, true, PFK>(p, b, c, LKU, t, phx, dv, ke_reg,
+                                                                                     row);
+        else if (uni)
+          step_cell<S, SHW, true, ODD, DIAG, REC, R, PROJ, AN, ODD, RM, true>(p, b, c, LKU, t, phx, dv, ke_reg, row);
         else
-          step_cell<S, SHW, false, ODD, DIAG, REC, R, PROJ, AN, true, RM, true>(p, b, c, LK_INR, t, dv, ke_reg,
+          step_cell<S, SHW, false, ODD, DIAG, REC, R, PROJ, AN, true, RM, true>(p, b, c, LK_INR, t, phx, dv, ke_reg,
                                                                                 row);
         if (blockIdx.x == 0 && threadIdx.x == 0) b.tc[ODD ? 0 : 1] = t + 1u;
         return;

@@ -62,3 +62,38 @@ def test_storage_forms_over_20000_steps(key, storage, bound_u, bound_s):
         assert mr_u < bound_u and mr_s < bound_s
     else:
         assert l2_u < bound_u and l2_s < bound_s
+
+
+@pytest.fixture(scope="module")
+def full_fp32():
+    case = make_config("c2")
+    say(f"full resolution: {case.nx}x{case.ny}x{case.nz}, {case.n_fluid} fluid cells, fp32, {STEPS} steps")
+    s = Solver.from_case(case, storage="fp32")
+    s.step(STEPS)
+    m = s.moments()
+    idx = s.fluid_index()
+    u = m["u"].cpu().numpy().reshape(3, -1)[:, idx].astype(np.float64)
+    sh = m["shear"].cpu().numpy().reshape(-1)[idx].astype(np.float64)
+    s.close()
+    return case, u, sh
+
+
+@pytest.mark.parametrize("storage,bound_u,bound_s", [("fp16", 1e-3, 5e-3), ("bf16", 8e-3, 4e-2)])
+def test_full_resolution_16bit_against_fp32(full_fp32, storage, bound_u, bound_s):
+    case, uref, sref = full_fp32
+    # the pulsatile inflow (peak 0.05 at the axis) has developed: the reference is a flow, not the rest state
+    assert np.sqrt((uref ** 2).sum(0)).max() > 0.02
+    say(f"full resolution: {storage} (default rounding) against fp32, {STEPS} steps")
+    s = Solver.from_case(case, storage=storage)
+    s.step(STEPS)
+    m = s.moments()
+    idx = s.fluid_index()
+    assert idx.size == uref.shape[1]
+    u = m["u"].cpu().numpy().reshape(3, -1)[:, idx].astype(np.float64)
+    sh = m["shear"].cpu().numpy().reshape(-1)[idx].astype(np.float64)
+    s.close()
+    du = np.sqrt(((u - uref) ** 2).sum(0))
+    l2_u = float(np.sqrt((du ** 2).sum() / (uref ** 2).sum()))
+    l2_s = float(np.linalg.norm(sh - sref) / np.linalg.norm(sref))
+    say(f"  u rel-L2 {l2_u:.3e}; shear rel-L2 {l2_s:.3e}")
+    assert l2_u < bound_u and l2_s < bound_s
