@@ -1,9 +1,9 @@
 // The step on the D3Q27 velocity set (the method section's lattice): the same
 // scheme as step.hpp (compact rows, in-place AA streaming, stored scaled
 // deviations, BGK + Guo + porosity-jump collision, Carreau-Yasuda relaxation,
-// open faces), written once for 27 directions with per-direction loops that
-// the compiler unrolls.  The moments-to-relaxation part (macro_sums) is
-// shared with the D3Q19 kernels.
+// open faces), written once for 27 directions with loops over the directions
+// and over the 13 opposite pairs that the compiler unrolls.  The
+// moments-to-relaxation part (macro_sums) is shared with the D3Q19 kernels.
 //
 // Differences from D3Q19:
 //   - weights 8/27, 2/27, 1/54, 1/216; the storage unit U is a multiple of
@@ -35,6 +35,13 @@ __host__ __device__ constexpr int kw(int i) {
          : (CX[i] != 0) + (CY[i] != 0) + (CZ[i] != 0) == 2 ? 4 : 1;
 }
 __host__ __device__ constexpr int pk(int i) { return pair_of(CY[i], CZ[i]); }
+// the collision's pairing: every odd direction's opposite follows it, with the same weight
+static_assert([] {
+  for (int i = 1; i < Q; i += 2)
+    if (opp(i) != i + 1 || kw(i) != kw(i + 1) || CX[i] != -CX[i + 1] || CY[i] != -CY[i + 1] || CZ[i] != -CZ[i + 1])
+      return false;
+  return true;
+}(), "D3Q27 directions must come in opposite pairs");
 
 constexpr uint64_t L_DEAD = 1ull << 0;
 constexpr uint64_t L_UNI = 1ull << 27;
@@ -124,26 +131,41 @@ __device__ __forceinline__ void pull(const Params& p, const Pop<S>& A, const flo
   }
 }
 
-// Moment sums of the 27 values.
+// Moment sums of the 27 values, from the opposite-pair sums P = x_I + x_J
+// (even moments) and differences M = x_I - x_J (odd moments), as on D3Q19.
 template <class R>
 __device__ __forceinline__ Sums<R> moment_sums(const float d[Q]) {
   Sums<R> r{};
   r.s = (R)d[0];
-  sfor<1, Q>([&](auto ic) {
-    constexpr int I = decltype(ic)::value;
-    const R x = (R)d[I];
-    r.s += x;
-    if (CX[I]) r.mx += CX[I] * x;
-    if (CY[I]) r.my += CY[I] * x;
-    if (CZ[I]) r.mz += CZ[I] * x;
-    if (CX[I]) r.xx += x;
-    if (CY[I]) r.yy += x;
-    if (CZ[I]) r.zz += x;
-    if (CX[I] * CY[I]) r.xy += CX[I] * CY[I] * x;
-    if (CX[I] * CZ[I]) r.xz += CX[I] * CZ[I] * x;
-    if (CY[I] * CZ[I]) r.yz += CY[I] * CZ[I] * x;
+  sfor<0, (Q - 1) / 2>([&](auto kc) {
+    constexpr int I = 1 + 2 * decltype(kc)::value;
+    const R a = (R)d[I], b = (R)d[I + 1];
+    const R P = a + b, M = a - b;
+    r.s += P;
+    if (CX[I]) r.mx = CX[I] > 0 ? r.mx + M : r.mx - M;
+    if (CY[I]) r.my = CY[I] > 0 ? r.my + M : r.my - M;
+    if (CZ[I]) r.mz = CZ[I] > 0 ? r.mz + M : r.mz - M;
+    if (CX[I]) r.xx += P;
+    if (CY[I]) r.yy += P;
+    if (CZ[I]) r.zz += P;
+    if (CX[I] * CY[I]) r.xy = CX[I] * CY[I] > 0 ? r.xy + P : r.xy - P;
+    if (CX[I] * CZ[I]) r.xz = CX[I] * CZ[I] > 0 ? r.xz + P : r.xz - P;
+    if (CY[I] * CZ[I]) r.yz = CY[I] * CZ[I] > 0 ? r.yz + P : r.yz - P;
   });
   return r;
+}
+
+// Momentum sum(x c) of the 27 values in FP64, from the opposite-pair
+// differences (exact in FP64): the FP64 projection needs only this moment.
+__device__ __forceinline__ void pair_momentum(const float d[Q], double& mx, double& my, double& mz) {
+  mx = 0.0; my = 0.0; mz = 0.0;
+  sfor<0, (Q - 1) / 2>([&](auto kc) {
+    constexpr int I = 1 + 2 * decltype(kc)::value;
+    const double m = (double)d[I] - (double)d[I + 1];
+    if (CX[I]) mx = CX[I] > 0 ? mx + m : mx - m;
+    if (CY[I]) my = CY[I] > 0 ? my + m : my - m;
+    if (CZ[I]) mz = CZ[I] > 0 ? mz + m : mz - m;
+  });
 }
 
 // Open faces (phi = 1 there): Zou-He inflow / density outflow on nine
@@ -239,6 +261,23 @@ __device__ __forceinline__ bool wall_normal(uint64_t lk, float n[3]) {
   return true;
 }
 
+// c_I . (x, y, z) summed over the nonzero components of c_I, in x, y, z order.
+template <int I, class R>
+__device__ __forceinline__ R cdot(R x, R y, R z) {
+  R r = (R)0;
+  bool any = false;
+  auto add = [&](int ci, R v) {
+    if (ci != 0) {
+      r = any ? (ci > 0 ? r + v : r - v) : (ci > 0 ? v : -v);
+      any = true;
+    }
+  };
+  add(CX[I], x);
+  add(CY[I], y);
+  add(CZ[I], z);
+  return r;
+}
+
 // Collision and store, as in step.hpp (deviation form, optional FP64 momentum
 // projection onto the axis pairs, shift mode 1 conversion).
 template <class S, bool SHW, bool UNI, bool ODD, class R, bool PROJ, int RM>
@@ -259,21 +298,32 @@ __device__ __forceinline__ void collide_store(const Params& p, const Pop<S>& A, 
   // the input momentum for the projection, before d[] is overwritten by the
   // outputs (27 values kept once, not twice)
   double tx = 0.0, ty = 0.0, tz = 0.0;
-  if constexpr (PROJ) {
-    const Sums<double> si = moment_sums<double>(d);
-    tx = si.mx; ty = si.my; tz = si.mz;
-  }
+  if constexpr (PROJ) pair_momentum(d, tx, ty, tz);
   float* o = d;
-  sfor<0, Q>([&](auto ic) {
-    constexpr int I = decltype(ic)::value;
-    const R e = (R)CX[I] * M.ux + (R)CY[I] * M.uy + (R)CZ[I] * M.uz;
-    const R h = (R)CX[I] * M.Fx + (R)CY[I] * M.Fy + (R)CZ[I] * M.Fz;
-    R g = rfma(omC, e * e, rfma(K9, e * h, ev0)) + rfma(omB, e, K3 * h);
-    if (!UNI) g += M.rm1 * ((R)pt[I] - phx);
-    o[I] = (float)rfma(ks * (R)kw(I), g, keep * (R)d[I]);
+  // Directions come in opposite pairs (I odd, I + 1 its opposite): with
+  // e = c_I.u and h = c_I.F the part omega C e^2 + K9 e h + ev0 is shared by
+  // the pair and omega B e + K3 h flips sign, so each pair costs one
+  // evaluation; c.u and c.F take only the nonzero components of c_I.
+  o[0] = (float)rfma(ks * (R)kw(0), UNI ? ev0 : ev0 + M.rm1 * ((R)pt[0] - phx), keep * (R)d[0]);
+  sfor<0, (Q - 1) / 2>([&](auto kc) {
+    constexpr int I = 1 + 2 * decltype(kc)::value;
+    constexpr int J = I + 1;
+    const R e = cdot<I>(M.ux, M.uy, M.uz);
+    const R h = cdot<I>(M.Fx, M.Fy, M.Fz);
+    const R ev = rfma(omC, e * e, rfma(K9, e * h, ev0));
+    const R od = rfma(omB, e, K3 * h);
+    R gi = ev + od, gj = ev - od;
+    if (!UNI) {
+      gi += M.rm1 * ((R)pt[I] - phx);
+      gj += M.rm1 * ((R)pt[J] - phx);
+    }
+    const R kk = ks * (R)kw(I);
+    o[I] = (float)rfma(kk, gi, keep * (R)d[I]);
+    o[J] = (float)rfma(kk, gj, keep * (R)d[J]);
   });
   if constexpr (PROJ) {
-    const Sums<double> so = moment_sums<double>(o);
+    double smx, smy, smz;
+    pair_momentum(o, smx, smy, smz);
     const double U = p.d.U;
     tx += U * (double)M.Fx; ty += U * (double)M.Fy; tz += U * (double)M.Fz;
     if (!UNI) {
@@ -289,7 +339,7 @@ __device__ __forceinline__ void collide_store(const Params& p, const Pop<S>& A, 
       const double kr = p.d.ks * rm1;
       tx += kr * jx; ty += kr * jy; tz += kr * jz;
     }
-    const double rx = 0.5 * (tx - so.mx), ry = 0.5 * (ty - so.my), rz = 0.5 * (tz - so.mz);
+    const double rx = 0.5 * (tx - smx), ry = 0.5 * (ty - smy), rz = 0.5 * (tz - smz);
     o[1] = (float)((double)o[1] + rx); o[2] = (float)((double)o[2] - rx);
     o[3] = (float)((double)o[3] + ry); o[4] = (float)((double)o[4] - ry);
     o[5] = (float)((double)o[5] + rz); o[6] = (float)((double)o[6] - rz);
