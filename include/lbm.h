@@ -103,7 +103,7 @@ typedef enum { LBM_STORE_FP32 = 0, LBM_STORE_FP16 = 1, LBM_STORE_BF16 = 2 } lbm_
  * alternating velocity grows to ~1e-3 of the flow in 20 000 steps); with
  * stochastic rounding the errors have mean zero.  Measured on the 192x128x128
  * aneurysm after 20 000 steps, FP16 velocity relative L2 error: stochastic
- * 2.2e-4, conserving 1.1e-3, nearest 2.4e-3. */
+ * 2.6e-4, conserving 1.1e-3, nearest 2.4e-3. */
 typedef enum { LBM_ROUND_STOCHASTIC = 0, LBM_ROUND_CONSERVE = 1, LBM_ROUND_NEAREST = 2 } lbm_rounding;
 
 /* Arithmetic of the moments, velocity, force and collision (the shear rate and
