@@ -153,10 +153,19 @@ def time_adjoint(torch, case, T: int, ckpt: int):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ok = bool(np.isfinite(J)) and bool(torch.isfinite(g).all().item())
+    # the same call without a gradient output: the forward pass alone (J, no
+    # checkpoints or records), i.e. the initial forward pass that the
+    # algorithmic bytes of the adjoint leave out
+    s.objective(tb, te, T)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Jf = s.objective(tb, te, T)
+    torch.cuda.synchronize()
+    dtf = time.perf_counter() - t0
     s.close()
     del s, g
     torch.cuda.empty_cache()
-    return dt, ok
+    return dt, dtf, ok, Jf == J
 
 
 def _oracle_rate(case, budget_s: float, max_steps: int = 400):
@@ -332,17 +341,25 @@ def main():
         elif aform != "adjoint":
             raise SystemExit(f"unknown adjoint form {aform}")
         log(f"[bench] {aform}: T={T}, checkpoint every {ck}, window [{T // 2}, {T})")
-        dt, ok = time_adjoint(torch, acase, T, ck)
+        dt, dtf, ok, same_j = time_adjoint(torch, acase, T, ck)
         rate = case.n_fluid * T / dt
         gbs = rate * B_ALG_ADJ / 1e9
         bi = B_IMPL_ADJ_1SEG if ck >= T else B_IMPL_ADJ
+        # the gradient part: the whole call less its initial forward pass
+        # (reported, not counted in the algorithmic bytes)
+        dtg = dt - dtf
+        gg = case.n_fluid * T / dtg * B_ALG_ADJ / 1e9
         adjoints[aform] = dict(T=T, ckpt=ck, seconds=round(dt, 4), us_per_step=round(dt / T * 1e6, 1),
                                reverse_cell_steps_per_s=round(rate, 0), bytes_per_update=B_ALG_ADJ,
                                alg_GBps=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4),
                                impl_bytes_per_update=bi, impl_GBps=round(rate * bi / 1e9, 1),
-                               finite=ok)
+                               forward_us_per_step=round(dtf / T * 1e6, 1),
+                               gradient_us_per_step=round(dtg / T * 1e6, 1),
+                               gradient_alg_GBps=round(gg, 1), gradient_frac=round(gg / HBM_PEAK_GBS, 4),
+                               forward_J_equal=same_j, finite=ok)
         log(f"[bench] {aform}: {dt * 1e3:.1f} ms ({dt / T * 1e6:.0f} us per time step), {rate / 1e9:.2f} G "
-            f"reverse cell-steps/s, {gbs:.0f} GB/s algorithmic")
+            f"reverse cell-steps/s, {gbs:.0f} GB/s algorithmic; forward pass alone {dtf / T * 1e6:.0f} us per "
+            f"step, gradient part {dtg / T * 1e6:.0f} us per step ({gg:.0f} GB/s, {gg / HBM_PEAK_GBS:.3f})")
     for form in forms:
         storage, mods, rounding = parse_form(form)
         if "q27" in mods and "hbm" in mods:
