@@ -502,8 +502,9 @@ struct Macro {
 // PF (pure fluid): phi = 1 and no body force.  Then 1/k = 0, so there is no
 // drag, C0 = 1/2 and the denominator of the explicit velocity is 1, and the
 // force vanishes: u = m / rho and F = 0.  The general expressions reduce to
-// these exactly (their extra terms are products with an exact zero and the
-// reciprocals of 1 are 1), so both forms give the same values.
+// these mathematically (their extra terms are products with an exact zero and
+// the reciprocals of 1 are 1); the compiler fuses the remaining terms of the
+// two forms differently, so an output can differ in its last place.
 template <class R, bool AN = false, bool PF = false>
 __device__ __forceinline__ void macro_sums(const Params& p, float phx_f, const Sums<R>& s, float omega_prev,
                                            Macro<R>& M) {
