@@ -138,7 +138,7 @@ def probes(torch, nbytes=4 << 30, reps=10, kinds=("copy", "copy_nt", "read", "wr
     return out
 
 
-def time_adjoint(torch, case, T: int, ckpt: int):
+def time_adjoint(torch, case, T: int, ckpt: int, fp64: bool = False):
     """Wall time of one lbm_adjoint call (forward pass with checkpoints,
     segment recompute and reverse sweep) over T steps, window [T/2, T)."""
     # the call starts from rest by definition (the forward pass is part of it)
@@ -146,10 +146,10 @@ def time_adjoint(torch, case, T: int, ckpt: int):
 
     s = Solver.from_case(case, adjoint_T=T, ckpt=ckpt)
     tb, te = T // 2, T
-    s.adjoint(tb, te, T, ckpt)  # warm-up call
+    s.adjoint(tb, te, T, ckpt, fp64=fp64)  # warm-up call
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    J, g = s.adjoint(tb, te, T, ckpt)
+    J, g = s.adjoint(tb, te, T, ckpt, fp64=fp64)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ok = bool(np.isfinite(J)) and bool(torch.isfinite(g).all().item())
@@ -275,7 +275,7 @@ def make_solver(name: str, case, hbm_case):
 
 
 DEFAULT_FORMS = ("fp16,fp16_conserve,fp16_nearest,bf16,fp32_aniso,fp32_q27,fp16_q27,"
-                 "fp32_hbm,fp16_hbm,bf16_hbm,fp32_slab,fp16_slab,adjoint,adjoint_1seg,adjoint_aniso")
+                 "fp32_hbm,fp16_hbm,bf16_hbm,fp32_slab,fp16_slab,adjoint,adjoint_fp64,adjoint_1seg,adjoint_aniso")
 
 
 def main():
@@ -338,10 +338,10 @@ def main():
             # (T + 1 records of 84 B per cell, 80 GB at T = 400 on the
             # aneurysm), so no step is recomputed
             ck = T
-        elif aform != "adjoint":
+        elif aform not in ("adjoint", "adjoint_fp64"):
             raise SystemExit(f"unknown adjoint form {aform}")
         log(f"[bench] {aform}: T={T}, checkpoint every {ck}, window [{T // 2}, {T})")
-        dt, dtf, ok, same_j = time_adjoint(torch, acase, T, ck)
+        dt, dtf, ok, same_j = time_adjoint(torch, acase, T, ck, fp64=aform == "adjoint_fp64")
         rate = case.n_fluid * T / dt
         gbs = rate * B_ALG_ADJ / 1e9
         bi = B_IMPL_ADJ_1SEG if ck >= T else B_IMPL_ADJ

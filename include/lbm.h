@@ -198,7 +198,15 @@ typedef struct {
  *                         the wall shear stress of lbm_moments (the quantity
  *                         the paper averages over the aneurysm wall). */
 enum { LBM_OBJ_KINETIC = 0, LBM_OBJ_WSS = 1 };
-typedef struct { int t_begin, t_end; int kind; } lbm_objective;
+typedef struct {
+  int t_begin, t_end;
+  int kind;
+  /* nonzero: the reverse sweep stores the adjoint populations in FP64 instead
+   * of FP32 (152 more bytes moved per reverse cell-step; removes the FP32
+   * rounding of those populations, the largest term of the gradient's error
+   * budget).  Needs 19 * 8 bytes per compact cell below 2 GiB. */
+  int fp64_adjoint;
+} lbm_objective;
 
 /* Diagnostics vector (lbm_diagnostics), all FP64, of the current state:
  *   [0] mass  sum_x phi rho            [1..3] momentum sum_x sum_i f_i c_i
@@ -301,7 +309,8 @@ lbm_status lbm_reset(lbm_ctx* ctx);
  * the forward trajectory bit for bit).  The forward passes compute the collision, the shear rate and the Carreau-Yasuda
  * law in FP64 (LBM_ARITH_FP64) whatever the context's arithmetic mode, and
  * store the trajectory in FP32; the reverse steps are FP64 arithmetic with
- * FP32 adjoint populations and an FP64 relaxation-rate adjoint.  Either outflow kind; with the extrapolation outflow
+ * FP32 adjoint populations (FP64 with obj->fp64_adjoint) and an FP64
+ * relaxation-rate adjoint.  Either outflow kind; with the extrapolation outflow
  * the outflow cells' unknowns are state, and their dependence on the previous
  * step's values is part of the reverse sweep.  Needs a workspace sized for
  * (T, ckpt_every) or larger; FP32 storage, shift mode 0, D3Q19 (with or

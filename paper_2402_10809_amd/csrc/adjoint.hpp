@@ -43,8 +43,8 @@ struct AdjBufs {
   const double* wave;     // sampled inflow waveform
   const float* rec;       // record of step n: [19][nc] pulled values (after the fill), [nc] omega_prev
   const float* rho_prev;  // density of step n-1 per compact cell (null for n = 0)
-  const float* ph_next;   // adjoint of the pulled populations of step n+1, [19][nc]
-  float* ph_out;          // adjoint of the pulled populations of step n, [19][nc]
+  const void* ph_next;    // adjoint of the pulled populations of step n+1, [19][nc] (FP32 or FP64)
+  void* ph_out;           // adjoint of the pulled populations of step n, [19][nc] (FP32 or FP64)
   double* omh;            // per cell: in adjoint of omega_n, out adjoint of omega_{n-1}
   double* phih;           // per cell: porosity adjoint accumulator
   const double* aside_in; // extrapolation outflow: per row, adjoints of the 5 c_x = -1 unknowns of step n+1
@@ -64,16 +64,19 @@ __device__ __forceinline__ void gather_to_lds(__amdgpu_buffer_rsrc_t r, float* l
 //
 // Both instantiations are held to 2 waves per SIMD (at most 256 VGPRs; the
 // isotropic one needs 247, the anisotropic one 255, without scratch).
-template <bool AN>
+template <bool AN, class PH = float>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
 void k_adjoint(Params p, AdjBufs a, uint32_t t, float ew, int kind) {
   using R = double;
+  constexpr bool P64 = std::is_same<PH, double>::value;  // FP64 adjoint populations
   // The neighbour gathers (adjoint populations of step n+1, porosities and,
   // for the porosity-jump term, densities of step n-1 at x + c_I) go straight
   // to LDS at the start, so that their latency overlaps the forward recompute
   // at two waves per SIMD without holding registers.  Each wave reads back
   // only the slots its own loads wrote: no barrier, one wait for the loads.
   __shared__ float sq[Q][BLOCK], sp[Q][BLOCK], sr[Q][BLOCK];
+  // FP64 adjoint populations: their high words (the low words go to sq)
+  __shared__ float sqh[P64 ? Q : 1][BLOCK];
   const uint32_t c = xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   if (c >= (uint32_t)p.nc) return;
   const uint32_t lk = a.links[c];
@@ -97,19 +100,23 @@ void k_adjoint(Params p, AdjBufs a, uint32_t t, float ew, int kind) {
   const double omh_in = a.omh[c], phih_in = a.phih[c];
   {
     const uint32_t nb = (uint32_t)p.nc * 4u;
-    const __amdgpu_buffer_rsrc_t rq = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(a.ph_next), (short)0,
-                                                                        (int)(nb * (uint32_t)Q), 0x00020000);
+    constexpr uint32_t PB = sizeof(PH);  // bytes per adjoint population
+    const __amdgpu_buffer_rsrc_t rq = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(a.ph_next), (short)0,
+                                                                        (int)((uint32_t)p.nc * PB * (uint32_t)Q),
+                                                                        0x00020000);
     const __amdgpu_buffer_rsrc_t rp = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(a.phi), (short)0,
                                                                         (int)nb, 0x00020000);
     const __amdgpu_buffer_rsrc_t rr = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(a.rho_prev), (short)0,
                                                                         (int)nb, 0x00020000);
-    gather_to_lds(rq, &sq[0][wb], c * 4u);
+    gather_to_lds(rq, &sq[0][wb], c * PB);
+    if constexpr (P64) gather_to_lds(rq, &sqh[0][wb], c * PB + 4u);
     sfor<1, Q>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
       const bool fl = ((lk >> OPP[I]) & 1u) == 0;  // x + c_I is a fluid cell
       const uint32_t tgt = fl ? src_of<OPP[I]>(p, q) : c;  // x + c_I (the cell itself across a wall)
       const uint32_t e = fl ? (uint32_t)I * (uint32_t)p.nc + tgt : (uint32_t)OPP[I] * (uint32_t)p.nc + c;
-      gather_to_lds(rq, &sq[I][wb], e * 4u);
+      gather_to_lds(rq, &sq[I][wb], e * PB);
+      if constexpr (P64) gather_to_lds(rq, &sqh[I][wb], e * PB + 4u);
       gather_to_lds(rp, &sp[I][wb], tgt * 4u);
       if (a.rho_prev) gather_to_lds(rr, &sr[I][wb], tgt * 4u);
     });
@@ -150,15 +157,25 @@ void k_adjoint(Params p, AdjBufs a, uint32_t t, float ew, int kind) {
 
   // ---- the adjoint of the post-collision populations (staged in LDS) ------
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  float qh[Q];  // as stored (FP32); widened exactly where used, which keeps them in half the registers
-  qh[0] = sq[0][tid];
+  // as stored (FP32 or FP64); FP32 values are widened exactly where used, which
+  // keeps them in half the registers
+  auto rdq = [&](int i) -> PH {
+    if constexpr (P64) {
+      const uint64_t lo = __builtin_bit_cast(uint32_t, sq[i][tid]), hi = __builtin_bit_cast(uint32_t, sqh[i][tid]);
+      return __builtin_bit_cast(double, lo | (hi << 32));
+    } else {
+      return sq[i][tid];
+    }
+  };
+  PH qh[Q];
+  qh[0] = rdq(0);
   uint32_t fmask = 0;
   R sfl = 0.0, sjump = 0.0;
   sfor<1, Q>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
     const bool fl = ((lk >> OPP[I]) & 1u) == 0;  // x + c_I is a fluid cell
     const R pn = (R)sp[I][tid];
-    qh[I] = sq[I][tid];
+    qh[I] = rdq(I);
     const R ai = (R)kw(I) * (1.0 / 36.0) * (R)qh[I];
     sfl += fl ? ai : 0.0;
     sjump += fl ? ai * (pn - phx) : 0.0;
@@ -450,7 +467,7 @@ void k_adjoint(Params p, AdjBufs a, uint32_t t, float ew, int kind) {
     fh[2] = 0.0; fh[8] = 0.0; fh[10] = 0.0; fh[12] = 0.0; fh[14] = 0.0;
   }
 #pragma unroll
-  for (int i = 0; i < Q; ++i) sto(a.ph_out, (uint32_t)i * (uint32_t)p.nc + c, (float)fh[i]);
+  for (int i = 0; i < Q; ++i) sto((PH*)a.ph_out, (uint32_t)i * (uint32_t)p.nc + c, (PH)fh[i]);
   a.omh[c] = omph;
 
   // porosity-jump term of step n-1: q_i(x - c_i) depends on phi(x) when
@@ -470,8 +487,9 @@ void k_adjoint(Params p, AdjBufs a, uint32_t t, float ew, int kind) {
 // Rest state f_i(0, x) = w_i phi(x) on the known links (and on the
 // extrapolation outflow's unknowns, whose adjoints of step 0 are in aside0),
 // then scatter the total into the box-layout gradient.
+template <class PH>
 __global__ __launch_bounds__(BLOCK) void k_adj_final(Params p, const uint32_t* code, const uint32_t* links,
-                                                     const uint32_t* rowbox, const float* ph0, const double* total,
+                                                     const uint32_t* rowbox, const PH* ph0, const double* total,
                                                      const double* aside0, float* grad) {
   const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
   if (c >= (uint32_t)p.nc) return;

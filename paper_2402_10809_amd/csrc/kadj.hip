@@ -27,6 +27,8 @@ extern "C" lbm_status lbm_adjoint(lbm_ctx* c, const lbm_objective* obj, int T, i
   if (c->grid.storage != LBM_STORE_FP32 || c->grid.shift_mode != 0)
     return fail(LBM_E_INVALID, "the adjoint supports FP32 storage with shift mode 0");
   if (c->q != 19) return fail(LBM_E_INVALID, "the adjoint is built for D3Q19");
+  if (obj->fp64_adjoint && (uint64_t)Q * (uint64_t)c->nc * 8u >= (1ull << 31))
+    return fail(LBM_E_INVALID, "FP64 adjoint populations need 19 * 8 bytes per cell below 2 GiB");
   if (obj->kind != LBM_OBJ_KINETIC && obj->kind != LBM_OBJ_WSS) return fail(LBM_E_INVALID, "unknown objective kind");
   if (c->nreg == 0) return fail(LBM_E_INVALID, "the objective region has no fluid cell");
   if (obj->kind == LBM_OBJ_WSS && c->nwss == 0) return fail(LBM_E_INVALID, "the objective region has no wall cell");
@@ -110,10 +112,14 @@ extern "C" lbm_status lbm_adjoint(lbm_ctx* c, const lbm_objective* obj, int T, i
   }
 
   // reverse sweep
-  float* phn = (float*)(c->ws + L.ah0);  // adjoint of the pulled populations of step n+1
-  float* pho = (float*)(c->ws + L.ah1);
-  HIP_TRY(c, hipMemsetAsync(phn, 0, Q * nc * 4, c->stream));
-  HIP_TRY(c, hipMemsetAsync(pho, 0, Q * nc * 4, c->stream));
+  // adjoint of the pulled populations of steps n+1 and n, FP32 or FP64 (the
+  // workspace holds room for FP64)
+  const bool p64 = obj->fp64_adjoint != 0;
+  const size_t pb = p64 ? 8 : 4;
+  void* phn = (void*)(c->ws + L.ah0);
+  void* pho = (void*)(c->ws + L.ah1);
+  HIP_TRY(c, hipMemsetAsync(phn, 0, Q * nc * pb, c->stream));
+  HIP_TRY(c, hipMemsetAsync(pho, 0, Q * nc * pb, c->stream));
   HIP_TRY(c, hipMemsetAsync(omh, 0, nc * 8, c->stream));
   HIP_TRY(c, hipMemsetAsync(phih, 0, nc * 8, c->stream));
   // extrapolation outflow: adjoints of the kept unknowns, per row, by parity
@@ -155,20 +161,31 @@ extern "C" lbm_status lbm_adjoint(lbm_ctx* c, const lbm_objective* obj, int T, i
       ab.aside_in = aside + (size_t)((n + 1) & 1) * c->nrow * 5;
       ab.aside_out = aside + (size_t)(n & 1) * c->nrow * 5;
       const float ewn = (n >= obj->t_begin && n < obj->t_end) ? (float)ew : 0.0f;
-      if (c->P.an_iters > 0)
-        hipLaunchKernelGGL(k_adjoint<true>, dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, ab, (uint32_t)n, ewn,
-                           okind);
+      if (c->P.an_iters > 0 && p64)
+        hipLaunchKernelGGL((k_adjoint<true, double>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, ab, (uint32_t)n,
+                           ewn, okind);
+      else if (c->P.an_iters > 0)
+        hipLaunchKernelGGL((k_adjoint<true, float>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, ab, (uint32_t)n,
+                           ewn, okind);
+      else if (p64)
+        hipLaunchKernelGGL((k_adjoint<false, double>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, ab,
+                           (uint32_t)n, ewn, okind);
       else
-        hipLaunchKernelGGL(k_adjoint<false>, dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, ab, (uint32_t)n, ewn,
-                           okind);
+        hipLaunchKernelGGL((k_adjoint<false, float>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, ab,
+                           (uint32_t)n, ewn, okind);
       HIP_TRY(c, hipGetLastError());
       std::swap(phn, pho);
     }
   }
   HIP_TRY(c, hipMemsetAsync(dJ_dphi, 0, nbox * 4, c->stream));
-  hipLaunchKernelGGL(k_adj_final, dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, ab.code, ab.links,
-                     (const uint32_t*)(c->ws + c->L.rowbox), (const float*)phn, (const double*)phih,
-                     (const double*)aside, dJ_dphi);
+  if (p64)
+    hipLaunchKernelGGL(k_adj_final<double>, dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, ab.code, ab.links,
+                       (const uint32_t*)(c->ws + c->L.rowbox), (const double*)phn, (const double*)phih,
+                       (const double*)aside, dJ_dphi);
+  else
+    hipLaunchKernelGGL(k_adj_final<float>, dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->P, ab.code, ab.links,
+                       (const uint32_t*)(c->ws + c->L.rowbox), (const float*)phn, (const double*)phih,
+                       (const double*)aside, dJ_dphi);
   HIP_TRY(c, hipGetLastError());
   // leave the context at the rest state
   st = launch_init(c);

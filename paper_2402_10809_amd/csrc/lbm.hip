@@ -137,8 +137,8 @@ Layout make_layout(const lbm_grid& g, int64_t nc, int64_t nrow, int T, int ckpt)
     L.ck = take((size_t)L.nck * (Q + 1) * nc * 4);
     L.rec = take((size_t)(ckpt + 1) * (Q + 1) * nc * 4);
     L.rho = take((size_t)(ckpt + 1) * nc * 4);
-    L.ah0 = take(Q * (size_t)nc * 4);
-    L.ah1 = take(Q * (size_t)nc * 4);
+    L.ah0 = take(Q * (size_t)nc * 8);  // adjoint populations: room for FP64
+    L.ah1 = take(Q * (size_t)nc * 8);
     L.omh = take((size_t)nc * 8);
     L.phih = take((size_t)nc * 8);
     L.aside = take((size_t)2 * nrow * 5 * 8);

@@ -52,7 +52,7 @@ class lbm_open(ct.Structure):
 
 
 class lbm_objective(ct.Structure):
-    _fields_ = [("t_begin", ct.c_int), ("t_end", ct.c_int), ("kind", ct.c_int)]
+    _fields_ = [("t_begin", ct.c_int), ("t_end", ct.c_int), ("kind", ct.c_int), ("fp64_adjoint", ct.c_int)]
 
 
 class LBMError(RuntimeError):
@@ -321,17 +321,19 @@ class Solver:
     def objective(self, t_begin: int, t_end: int, T: int, kind: str = "ke") -> float:
         """J alone (forward pass from rest, no gradient); the context ends at rest.
         kind: "ke" (region kinetic energy) or "wss" (WSS over the region's wall)."""
-        obj = lbm_objective(int(t_begin), int(t_end), OBJECTIVE[kind])
+        obj = lbm_objective(int(t_begin), int(t_end), OBJECTIVE[kind], 0)
         J = ct.c_double(0.0)
         check(lib().lbm_adjoint(self.ctx, ct.byref(obj), int(T), 1, ct.byref(J), None))
         return float(J.value)
 
-    def adjoint(self, t_begin: int, t_end: int, T: int, ckpt: Optional[int] = None, kind: str = "ke"):
+    def adjoint(self, t_begin: int, t_end: int, T: int, ckpt: Optional[int] = None, kind: str = "ke",
+                fp64: bool = False):
         """J and dJ/dphi (device tensor, box layout) of the region objective:
-        kind "ke" (kinetic energy) or "wss" (wall shear stress magnitude)."""
+        kind "ke" (kinetic energy) or "wss" (wall shear stress magnitude);
+        fp64: FP64 adjoint populations in the reverse sweep."""
         t = self.torch
         ck = self.ckpt if ckpt is None else int(ckpt)
-        obj = lbm_objective(int(t_begin), int(t_end), OBJECTIVE[kind])
+        obj = lbm_objective(int(t_begin), int(t_end), OBJECTIVE[kind], 1 if fp64 else 0)
         J = ct.c_double(0.0)
         grad = t.empty(self.shape, dtype=t.float32, device=self.device)
         check(lib().lbm_adjoint(self.ctx, ct.byref(obj), int(T), ck, ct.byref(J), ct.c_void_p(grad.data_ptr())))

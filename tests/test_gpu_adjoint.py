@@ -205,14 +205,16 @@ def test_autograd_function_and_objective_only():
     assert s.t == 0
 
 
+@pytest.mark.parametrize("fp64", [False, True])
 @pytest.mark.parametrize("objective", ["ke", "wss"])
-def test_adjoint_full_size_against_stored_references(objective):
+def test_adjoint_full_size_against_stored_references(objective, fp64):
     """The 128x96x96 aneurysm (37 736 fluid cells), 4000 steps, objective over
     the last 1000 (sac kinetic energy, or WSS over the sac's wall), checkpoints
     every 64: GPU gradient vs the oracle's central finite differences and
     dual-number derivative at 16 seeded sac voxels, and vs its FP64 reverse
     sweep over every sac voxel (stored values written by
-    tests/golden/make_adjoint_c4.py [--kind wss])."""
+    tests/golden/make_adjoint_c4.py [--kind wss]).  fp64: the reverse sweep
+    with FP64 adjoint populations."""
     import json
     import os
 
@@ -225,9 +227,10 @@ def test_adjoint_full_size_against_stored_references(objective):
     g_sac_ref = np.load(os.path.join(gdir, stem + "_reverse_sac.npy"))
     case = make_config("c4")
     T, tb, te, ck = ref["T"], ref["t_begin"], ref["t_end"], ref["ckpt"]
-    say(f"adjoint ({objective}) c4 ({case.n_fluid} cells): T={T} window=[{tb},{te}) ckpt={ck}")
+    say(f"adjoint ({objective}, fp64 adjoint populations {fp64}) c4 ({case.n_fluid} cells): T={T} "
+        f"window=[{tb},{te}) ckpt={ck}")
     s = Solver.from_case(case, adjoint_T=T, ckpt=ck)
-    J, g = s.adjoint(tb, te, T, ck, kind=objective)
+    J, g = s.adjoint(tb, te, T, ck, kind=objective, fp64=fp64)
     g = g.cpu().numpy().reshape(-1).astype(np.float64)
     vox = np.asarray(ref["voxels"])
     fd = np.asarray(ref["grad_fd"])
@@ -252,9 +255,13 @@ def test_adjoint_full_size_against_stored_references(objective):
     # reverse sweep is stated in the design notes.
     n_fd = np.linalg.norm(gv - fd) / np.linalg.norm(fd)
     n_dual = np.linalg.norm(gv - dual) / np.linalg.norm(dual)
+    # The same bound with FP64 adjoint populations, which take the measured
+    # worst per-voxel error of the kinetic-energy gradient from 7.1e-5 to
+    # 2.8e-5 (normwise 6.7e-6 to 4.2e-6).
+    bound = 1e-4
     assert abs(J - ref["J"]) <= 1e-6 * abs(ref["J"])
-    assert n_fd < 1e-4 and n_dual < 1e-4
-    assert e_fd.max() < 1e-4 and e_dual.max() < 1e-4
+    assert n_fd < bound and n_dual < bound
+    assert e_fd.max() < bound and e_dual.max() < bound
     assert e_l2 < 1e-5
 
 
