@@ -17,6 +17,7 @@ computed.
 phi is the dense box porosity (nz, ny, nx), FP32, on any device; it must keep
 the solver's solid mask (0 on solid voxels, in (0, 1] on fluid, 1 on open
 faces).  The solver is reset to the rest state by every evaluation.
+fp64=True keeps the adjoint populations of the reverse sweep in FP64.
 """
 
 from __future__ import annotations
@@ -28,12 +29,13 @@ import torch
 
 class RegionObjective(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, phi: torch.Tensor, solver, t_begin: int, t_end: int, T: int, ckpt: Optional[int], kind: str):
+    def forward(ctx, phi: torch.Tensor, solver, t_begin: int, t_end: int, T: int, ckpt: Optional[int], kind: str,
+                fp64: bool = False):
         # device to device: the library reads phi in place (no host copy)
         solver.set_porosity(phi.detach().to(solver.device, torch.float32).contiguous())
         ctx.phi_device = phi.device
         if ctx.needs_input_grad[0]:
-            J, g = solver.adjoint(t_begin, t_end, T, ckpt, kind=kind)
+            J, g = solver.adjoint(t_begin, t_end, T, ckpt, kind=kind, fp64=fp64)
             ctx.save_for_backward(g)
         else:
             J = solver.objective(t_begin, t_end, T, kind=kind)
@@ -43,22 +45,22 @@ class RegionObjective(torch.autograd.Function):
     def backward(ctx, grad_out):
         (g,) = ctx.saved_tensors
         gphi = (grad_out.to(g.device, torch.float64) * g.to(torch.float64)).to(torch.float32)
-        return gphi.to(ctx.phi_device), None, None, None, None, None, None
+        return gphi.to(ctx.phi_device), None, None, None, None, None, None, None
 
 
 def region_objective(phi: torch.Tensor, solver, t_begin: int, t_end: int, T: int,
-                     ckpt: Optional[int] = None, kind: str = "ke") -> torch.Tensor:
+                     ckpt: Optional[int] = None, kind: str = "ke", fp64: bool = False) -> torch.Tensor:
     """Differentiable J(phi); see the module docstring."""
-    return RegionObjective.apply(phi, solver, int(t_begin), int(t_end), int(T), ckpt, kind)
+    return RegionObjective.apply(phi, solver, int(t_begin), int(t_end), int(T), ckpt, kind, bool(fp64))
 
 
 def sac_kinetic_energy(phi: torch.Tensor, solver, t_begin: int, t_end: int, T: int,
-                       ckpt: Optional[int] = None) -> torch.Tensor:
+                       ckpt: Optional[int] = None, fp64: bool = False) -> torch.Tensor:
     """Differentiable time-averaged region kinetic energy."""
-    return region_objective(phi, solver, t_begin, t_end, T, ckpt, "ke")
+    return region_objective(phi, solver, t_begin, t_end, T, ckpt, "ke", fp64)
 
 
 def sac_wall_shear_stress(phi: torch.Tensor, solver, t_begin: int, t_end: int, T: int,
-                          ckpt: Optional[int] = None) -> torch.Tensor:
+                          ckpt: Optional[int] = None, fp64: bool = False) -> torch.Tensor:
     """Differentiable time-averaged WSS magnitude over the region's wall cells."""
-    return region_objective(phi, solver, t_begin, t_end, T, ckpt, "wss")
+    return region_objective(phi, solver, t_begin, t_end, T, ckpt, "wss", fp64)

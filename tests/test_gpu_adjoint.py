@@ -180,9 +180,10 @@ def test_adjoint_small_aneurysm_dual(objective, outlet):
     assert err.max() < 1e-4
 
 
-def test_autograd_function_and_objective_only():
+@pytest.mark.parametrize("fp64", [False, True])
+def test_autograd_function_and_objective_only(fp64):
     """sac_kinetic_energy: J matches the objective-only call bit for bit, and
-    backward returns the adjoint gradient."""
+    backward returns the adjoint gradient (FP32 or FP64 adjoint populations)."""
     import torch
 
     from paper_2402_10809_amd.autograd import sac_kinetic_energy
@@ -190,11 +191,11 @@ def test_autograd_function_and_objective_only():
     case = _tiny("open", 0)
     T, tb, te, ck = 30, 15, 30, 7
     s = Solver.from_case(case, adjoint_T=T, ckpt=ck)
-    J_ref, g_ref = s.adjoint(tb, te, T, ck)
+    J_ref, g_ref = s.adjoint(tb, te, T, ck, fp64=fp64)
     J_only = s.objective(tb, te, T)
     assert J_only == J_ref
     phi = torch.tensor(case.phi, device="cuda", requires_grad=True)
-    J = sac_kinetic_energy(phi, s, tb, te, T, ck)
+    J = sac_kinetic_energy(phi, s, tb, te, T, ck, fp64=fp64)
     assert float(J.detach()) == J_ref
     (3.0 * J).backward()
     assert torch.equal(phi.grad, 3.0 * g_ref.to(torch.float64).to(torch.float32)) or \
